@@ -1,0 +1,377 @@
+"""FP64 CPU oracle for the Hockney free-space particle-mesh Poisson solve.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this module: only the test suite, the smoke check and the CPU-baseline
+leg of the benchmark use it.  It shares no code, constants or tables with the
+HIP library.
+
+What it computes (paper section "FFT Based Particle-Mesh Solver", subsection
+"FFT-based Convolutions"; the open-boundary doubled grid of the same section):
+
+  1. CIC charge assignment of particles to mesh nodes (the "NGP, CIC, TSI"
+     interpolation box of the OPAL/IPPL structure figure).
+  2. The integrated Green's function (IGF): the free-space kernel 1/r of the
+     equation following the convolution solution, integrated over one mesh
+     cell.  Near the origin it is the third mixed difference of a closed-form
+     antiderivative over the cell corners; farther out, where that difference
+     cancels catastrophically in FP64, the Gauss-Legendre product rule over the
+     cell (the integrand is analytic there) with enough points to reach FP64
+     rounding.
+  3. The discrete free-space convolution of the brute-force equation
+     (phi_ijk = sum rho G_{i-i',j-j',k-k'}), done two ways:
+       potential_direct -- the literal O(M^2) double sum (small meshes only);
+       potential_fft    -- cyclic convolution on the zero-padded 2M grid using
+                           numpy.fft as a library step (Hadamard-product form).
+  4. E = -grad(phi) by second-order central differences (the D-operators box
+     of the structure figure).
+  5. CIC interpolation of the mesh field back to the particles.
+
+Readings of the paper adopted where it is silent (each also listed in the
+design notes of the repository):
+  * phi = 1/(4 pi eps0) * sum_j rho_j * G_int(i-j); G_int already integrates
+    over a cell (units m^2), so there is no separate h_x h_y h_z factor.
+  * Nodes are vertex-centred: x_i = x0 + i*h, i = 0..n-1.
+  * phi is returned on the extended box [-1, n] per axis (a one-node ghost
+    layer), which the doubled grid gives exactly when the kernel value at
+    offset n is the true G_int(n).
+  * The in/out-of-mesh and cell-index decision of a particle is taken on
+    s = (x - x0) * (1/h) evaluated in the run's dtype with two correctly
+    rounded operations (difference, then product), because floating point
+    decides an integer there; everything after that decision is FP64.
+  * eps0 = 8.8541878128e-12 F/m (CODATA 2018).
+"""
+
+import math
+
+import numpy as np
+
+EPS0 = 8.8541878128e-12  # F/m, CODATA 2018
+COULOMB_K = 1.0 / (4.0 * math.pi * EPS0)
+
+
+# --------------------------------------------------------------------------
+# Mesh geometry
+# --------------------------------------------------------------------------
+
+def centred_origin(n, h):
+    """Origin of an explicit-h mesh centred at 0: x0 = -(n-1) h / 2."""
+    return tuple(-0.5 * (nd - 1) * hd for nd, hd in zip(n, h))
+
+
+def fit_mesh(x, y, z, n):
+    """Particle-fitted cubic mesh (the mesh-spacing remark of the PM section).
+
+    h = max_d (hi_d - lo_d) / (n_d - 3); the origin centres the bounding box,
+    x0_d = (lo_d + hi_d)/2 - (n_d - 1) h / 2, which leaves at least one empty
+    node of margin on each side.  With no particles, or all particles at one
+    point, h = 1 m and the box sits at the origin (lo = hi = 0 without
+    particles).  Bounding-box values are the inputs as given (FP32 inputs are
+    widened exactly); h and the origin are FP64.
+    Returns (h, (x0, y0, z0)).
+    """
+    coords = [np.asarray(c, dtype=np.float64) for c in (x, y, z)]
+    if coords[0].size == 0:
+        lo = [0.0, 0.0, 0.0]
+        hi = [0.0, 0.0, 0.0]
+    else:
+        lo = [float(c.min()) for c in coords]
+        hi = [float(c.max()) for c in coords]
+    h = 0.0
+    for d in range(3):
+        h = max(h, (hi[d] - lo[d]) / (n[d] - 3))
+    if not h > 0.0:
+        h = 1.0
+    origin = tuple(0.5 * (lo[d] + hi[d]) - 0.5 * (n[d] - 1) * h for d in range(3))
+    return h, origin
+
+
+def cell_coordinates(pos, origin, h, dtype):
+    """s = (pos - origin) * (1/h) in `dtype`, two rounded operations, as FP64."""
+    dt = np.dtype(dtype)
+    x0 = dt.type(origin)
+    inv = dt.type(1.0 / h)
+    s = (np.asarray(pos).astype(dt) - x0) * inv
+    return s.astype(np.float64)
+
+
+def cic_stencil(x, y, z, n, h, origin, dtype):
+    """CIC cell index and fractional offsets of each particle.
+
+    Returns (inside mask, i[3] int64 lower node index, f[3] float64 fraction).
+    A particle is outside when s_d < 0 or s_d > n_d - 1 on any axis.  The
+    lower node is min(floor(s), n-2), so a particle exactly on the last node
+    goes entirely to it with f = 1.
+    """
+    s = [cell_coordinates(c, o, hd, dtype) for c, o, hd in zip((x, y, z), origin, h)]
+    inside = np.ones(s[0].shape, dtype=bool)
+    for d in range(3):
+        inside &= (s[d] >= 0.0) & (s[d] <= n[d] - 1)
+    idx, frac = [], []
+    for d in range(3):
+        sd = np.where(inside, s[d], 0.0)
+        i = np.minimum(np.floor(sd), n[d] - 2).astype(np.int64)
+        idx.append(i)
+        frac.append(sd - i)
+    return inside, idx, frac
+
+
+def _corner_weights(frac):
+    """The eight trilinear weights, keyed by corner offset (cz, cy, cx)."""
+    fx, fy, fz = frac
+    wx = (1.0 - fx, fx)
+    wy = (1.0 - fy, fy)
+    wz = (1.0 - fz, fz)
+    out = {}
+    for cz in (0, 1):
+        for cy in (0, 1):
+            for cx in (0, 1):
+                out[(cz, cy, cx)] = wz[cz] * wy[cy] * wx[cx]
+    return out
+
+
+# --------------------------------------------------------------------------
+# 1. CIC deposit
+# --------------------------------------------------------------------------
+
+def deposit_cic(x, y, z, q, n, h, origin, dtype=np.float64):
+    """Charge per node Q[nz, ny, nx] (coulomb) from particles of charge q each.
+
+    Each inside particle adds q * w_x w_y w_z to the eight nodes around it.
+    Returns (Q, n_outside).  rho = Q / (h_x h_y h_z).
+    """
+    nx, ny, nz = n
+    inside, (ix, iy, iz), frac = cic_stencil(x, y, z, n, h, origin, dtype)
+    Q = np.zeros(nx * ny * nz, dtype=np.float64)
+    sel = np.nonzero(inside)[0]
+    ix, iy, iz = ix[sel], iy[sel], iz[sel]
+    w = _corner_weights([f[sel] for f in frac])
+    for (cz, cy, cx), wc in w.items():
+        node = ((iz + cz) * ny + (iy + cy)) * nx + (ix + cx)
+        Q += np.bincount(node, weights=q * wc, minlength=nx * ny * nz)
+    return Q.reshape(nz, ny, nx), int(inside.size - sel.size)
+
+
+# --------------------------------------------------------------------------
+# 2. Integrated Green's function
+# --------------------------------------------------------------------------
+
+def _antiderivative(x, y, z):
+    """F with d^3F/dxdydz = 1/sqrt(x^2+y^2+z^2), valid where no coordinate is 0."""
+    r = np.sqrt(x * x + y * y + z * z)
+    return (y * z * np.log(x + r) + x * z * np.log(y + r) + x * y * np.log(z + r)
+            - 0.5 * x * x * np.arctan(y * z / (x * r))
+            - 0.5 * y * y * np.arctan(x * z / (y * r))
+            - 0.5 * z * z * np.arctan(x * y / (z * r)))
+
+
+# Gauss-Legendre bands: (lower bound of D, points per axis).  D is the
+# distance of the cell centre from the origin in units of the largest cell
+# side.  Below D = 2 the closed form is used.
+_GL_BANDS = ((2.0, 10), (4.0, 8), (8.0, 6), (16.0, 5), (32.0, 4))
+
+
+def igf_closed_form(a, b, c, h):
+    """G_int at integer offsets (arrays broadcast) from the antiderivative.
+
+    G_int(a,b,c) = third mixed difference of F over the corners
+    ((a -+ 1/2) hx, (b -+ 1/2) hy, (c -+ 1/2) hz).  Exact in exact arithmetic,
+    but in FP64 it loses digits to cancellation as the offset grows
+    (about 1e-10 relative at 64 cells, 1e-7 at 256).
+    """
+    hx, hy, hz = h
+    a = np.abs(np.asarray(a, dtype=np.float64))
+    b = np.abs(np.asarray(b, dtype=np.float64))
+    c = np.abs(np.asarray(c, dtype=np.float64))
+    total = 0.0
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                sign = (-1.0) ** (3 - dx - dy - dz)
+                total = total + sign * _antiderivative((a - 0.5 + dx) * hx,
+                                                       (b - 0.5 + dy) * hy,
+                                                       (c - 0.5 + dz) * hz)
+    return total
+
+
+def igf_gauss_legendre(a, b, c, h, m):
+    """G_int by the m x m x m Gauss-Legendre product rule over the cell."""
+    hx, hy, hz = h
+    a = np.abs(np.asarray(a, dtype=np.float64))
+    b = np.abs(np.asarray(b, dtype=np.float64))
+    c = np.abs(np.asarray(c, dtype=np.float64))
+    t, w = np.polynomial.legendre.leggauss(m)
+    total = np.zeros(np.broadcast(a, b, c).shape)
+    for i in range(m):
+        xi = (a + 0.5 * t[i]) * hx
+        for j in range(m):
+            yj = (b + 0.5 * t[j]) * hy
+            for k in range(m):
+                zk = (c + 0.5 * t[k]) * hz
+                total += (w[i] * w[j] * w[k]) / np.sqrt(xi * xi + yj * yj + zk * zk)
+    return total * (hx * hy * hz / 8.0)
+
+
+def igf_at(a, b, c, h):
+    """G_int(a, b, c): the integral of 1/r over the cell centred at (a hx, b hy, c hz).
+
+    Closed form where the cell centre is within 2 largest-cell-sides of the
+    origin; elsewhere the integrand is analytic on the cell and the
+    Gauss-Legendre product rule of the band reaches FP64 rounding.
+    """
+    a, b, c = np.broadcast_arrays(*(np.abs(np.asarray(v, dtype=np.float64)) for v in (a, b, c)))
+    hmax = max(h)
+    D = np.sqrt((a * h[0]) ** 2 + (b * h[1]) ** 2 + (c * h[2]) ** 2) / hmax
+    out = np.empty(a.shape, dtype=np.float64)
+    near = D < _GL_BANDS[0][0]
+    out[near] = igf_closed_form(a[near], b[near], c[near], h)
+    for idx, (lo, m) in enumerate(_GL_BANDS):
+        hi = _GL_BANDS[idx + 1][0] if idx + 1 < len(_GL_BANDS) else np.inf
+        sel = (D >= lo) & (D < hi)
+        if np.any(sel):
+            out[sel] = igf_gauss_legendre(a[sel], b[sel], c[sel], h, m)
+    return out
+
+
+def igf_octant(n, h):
+    """G_int(a, b, c) for a in [0, nx], b in [0, ny], c in [0, nz]; array [c, b, a]."""
+    nx, ny, nz = n
+    c, b, a = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    return igf_at(a, b, c, h)
+
+
+# --------------------------------------------------------------------------
+# 3. Discrete free-space convolution on the extended box [-1, n]^3
+# --------------------------------------------------------------------------
+
+def potential_direct(rho, h):
+    """Literal double sum: phi_i = K sum_j rho_j G_int(i - j), i in [-1, n]^3.
+
+    rho is [nz, ny, nx] in C/m^3; returns phi_ext [nz+2, ny+2, nx+2] in volts,
+    phi_ext[k+1, j+1, i+1] = phi at node (i, j, k).  O(M^2): small meshes only.
+    """
+    nz, ny, nx = rho.shape
+    G = igf_octant((nx + 1, ny + 1, nz + 1), h)  # offsets up to n+1 are needed
+    phi = np.zeros((nz + 2, ny + 2, nx + 2), dtype=np.float64)
+    ti = np.arange(-1, nx + 1)
+    tj = np.arange(-1, ny + 1)
+    tk = np.arange(-1, nz + 1)
+    src = np.argwhere(rho != 0.0)
+    for (k, j, i) in src:
+        dz = np.abs(tk - k)[:, None, None]
+        dy = np.abs(tj - j)[None, :, None]
+        dx = np.abs(ti - i)[None, None, :]
+        phi += rho[k, j, i] * G[dz, dy, dx]
+    return COULOMB_K * phi
+
+
+def doubled_kernel(n, h):
+    """K on the 2n grid: K[a] = G_int(min(a, 2n - a)) per axis (K[n] = G_int(n))."""
+    nx, ny, nz = n
+    G = igf_octant(n, h)
+    ax = np.minimum(np.arange(2 * nx), 2 * nx - np.arange(2 * nx))
+    ay = np.minimum(np.arange(2 * ny), 2 * ny - np.arange(2 * ny))
+    az = np.minimum(np.arange(2 * nz), 2 * nz - np.arange(2 * nz))
+    return G[az[:, None, None], ay[None, :, None], ax[None, None, :]]
+
+
+def potential_fft(rho, h):
+    """Hadamard-product form on the zero-padded 2n grid; phi_ext on [-1, n]^3.
+
+    Cyclic convolution of rho (zero-padded to 2n) with K; for target indices
+    -1..n every wrapped offset lands on its true |offset| <= n, so the result
+    equals the literal sum there.
+    """
+    nz, ny, nx = rho.shape
+    K = doubled_kernel((nx, ny, nz), h)
+    shape = (2 * nz, 2 * ny, 2 * nx)
+    Rk = np.fft.rfftn(rho, s=shape, axes=(0, 1, 2))
+    Kk = np.fft.rfftn(K)
+    full = np.fft.irfftn(Rk * Kk, s=shape, axes=(0, 1, 2))
+    idz = np.r_[2 * nz - 1, np.arange(nz + 1)]
+    idy = np.r_[2 * ny - 1, np.arange(ny + 1)]
+    idx = np.r_[2 * nx - 1, np.arange(nx + 1)]
+    return COULOMB_K * full[np.ix_(idz, idy, idx)]
+
+
+# --------------------------------------------------------------------------
+# 4. Central-difference field
+# --------------------------------------------------------------------------
+
+def gradient(phi_ext, h):
+    """E_d(i) = -(phi(i + e_d) - phi(i - e_d)) / (2 h_d), i in [0, n)^3.
+
+    Returns E [3, nz, ny, nx] ordered (Ex, Ey, Ez), V/m.
+    """
+    hx, hy, hz = h
+    Ex = -(phi_ext[1:-1, 1:-1, 2:] - phi_ext[1:-1, 1:-1, :-2]) / (2.0 * hx)
+    Ey = -(phi_ext[1:-1, 2:, 1:-1] - phi_ext[1:-1, :-2, 1:-1]) / (2.0 * hy)
+    Ez = -(phi_ext[2:, 1:-1, 1:-1] - phi_ext[:-2, 1:-1, 1:-1]) / (2.0 * hz)
+    return np.stack([Ex, Ey, Ez])
+
+
+# --------------------------------------------------------------------------
+# 5. CIC gather
+# --------------------------------------------------------------------------
+
+def gather_cic(E, x, y, z, n, h, origin, dtype=np.float64):
+    """E at the particles: sum over the 8 nodes of w * E(node); 0 outside."""
+    nx, ny, nz = n
+    inside, (ix, iy, iz), frac = cic_stencil(x, y, z, n, h, origin, dtype)
+    w = _corner_weights(frac)
+    out = np.zeros((3, inside.size), dtype=np.float64)
+    ixc = np.where(inside, ix, 0)
+    iyc = np.where(inside, iy, 0)
+    izc = np.where(inside, iz, 0)
+    for (cz, cy, cx), wc in w.items():
+        for d in range(3):
+            out[d] += wc * E[d][izc + cz, iyc + cy, ixc + cx]
+    out[:, ~inside] = 0.0
+    return out
+
+
+# --------------------------------------------------------------------------
+# Whole path
+# --------------------------------------------------------------------------
+
+def solve_rho(rho, h, method="fft"):
+    """rho [nz,ny,nx] (C/m^3) -> (phi_ext [nz+2,ny+2,nx+2], E [3,nz,ny,nx])."""
+    rho = np.asarray(rho, dtype=np.float64)
+    phi_ext = potential_fft(rho, h) if method == "fft" else potential_direct(rho, h)
+    return phi_ext, gradient(phi_ext, h)
+
+
+def solve_particles(x, y, z, q, n, h=None, origin=None, dtype=np.float64, method="fft"):
+    """Particles (SoA) of charge q each -> field at the particles.
+
+    h=None selects the particle-fitted cubic mesh; otherwise h is a 3-tuple and
+    origin defaults to the mesh centred at 0.  Returns a dict with Q, rho,
+    phi_ext, E_mesh, E (3 x Np), n_outside, h, origin.
+    """
+    if h is None:
+        hc, origin = fit_mesh(x, y, z, n)
+        h = (hc, hc, hc)
+    elif origin is None:
+        origin = centred_origin(n, h)
+    Q, n_out = deposit_cic(x, y, z, q, n, h, origin, dtype)
+    rho = Q / (h[0] * h[1] * h[2])
+    phi_ext, E_mesh = solve_rho(rho, h, method)
+    E = gather_cic(E_mesh, x, y, z, n, h, origin, dtype)
+    return dict(Q=Q, rho=rho, phi_ext=phi_ext, E_mesh=E_mesh, E=E,
+                n_outside=n_out, h=tuple(h), origin=tuple(origin))
+
+
+def potential_at(rho, h, targets):
+    """phi at a few target nodes (k, j, i) by the literal sum over all sources.
+
+    Each target costs one pass over the whole mesh; use for sampled checks of
+    large meshes.  Offsets may be -1..n (ghost layer).
+    """
+    nz, ny, nx = rho.shape
+    G = igf_octant((nx + 1, ny + 1, nz + 1), h)
+    out = []
+    kk = np.arange(nz)[:, None, None]
+    jj = np.arange(ny)[None, :, None]
+    ii = np.arange(nx)[None, None, :]
+    for (k, j, i) in targets:
+        out.append(np.sum(rho * G[np.abs(kk - k), np.abs(jj - j), np.abs(ii - i)]))
+    return COULOMB_K * np.asarray(out)
