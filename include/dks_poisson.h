@@ -1,0 +1,187 @@
+/*
+ * dks_poisson.h -- C ABI of the MI355X free-space particle-mesh Poisson solver.
+ *
+ * The library computes the open-boundary potential of a charge distribution
+ * by Hockney's method as the paper states it (section "FFT Based
+ * Particle-Mesh Solver"): charge is assigned to a regular 3-D mesh by
+ * cloud-in-cell, the mesh is zero-padded to twice its size per axis, the
+ * potential is the discrete convolution with the Green's function of the
+ * free-space Poisson equation (the brute-force sum equation, computed as the
+ * Hadamard product of forward FFTs followed by an inverse FFT), the field is
+ * the negative central-difference gradient, and it is interpolated back to the
+ * particles by cloud-in-cell.  The Green's function is the cell-integrated
+ * 1/r kernel, computed in FP64 on the device.
+ *
+ * Conventions shared by every entry point
+ *  - Memory: the caller owns every buffer, including the workspace, and
+ *    allocates it (the paper's DKS leaves memory management to the user,
+ *    section "DKS" and its usage example).  Pointers marked "device" must be
+ *    device memory of the current HIP device; the library never frees them.
+ *  - Layout: meshes are C-contiguous [nz][ny][nx] (x fastest); a mesh vector
+ *    field is [3][nz][ny][nx] ordered (x, y, z) components.  Particles are
+ *    structure-of-arrays: separate x, y, z arrays of np elements.
+ *  - Types: every array has the plan's dtype (float for DKS_F32, double for
+ *    DKS_F64).  Every host scalar is double.  Units are SI (m, C, V, V/m).
+ *  - Streams: every device operation is enqueued asynchronously on the
+ *    caller's stream (NULL = the default stream), with no host
+ *    synchronisation, so a solve can be captured into a HIP graph.  The only
+ *    exception is dks_poisson_geometry, which synchronises the stream.
+ *  - Mesh: node (i, j, k) sits at origin + (i hx, j hy, k hz).  An
+ *    explicit-h plan is centred at 0 unless dks_poisson_set_origin moves it.
+ *    A fitted plan (hx = hy = hz = 0) re-fits a cubic mesh to the particles
+ *    of every particle solve: h = max_d extent_d / (n_d - 3), origin centring
+ *    the particles' bounding box (at least one empty node on each side); with
+ *    no particles or a zero extent, h = 1 m.
+ *  - Particles outside the mesh (a cell coordinate (x - x0) * (1/h), taken
+ *    in the plan's dtype, below 0 or above n - 1 on any axis) deposit
+ *    nothing, receive E = 0 and are counted.
+ *  - Errors: every entry point returns a dks_status.  Arguments are checked
+ *    on the host before any device work; no C++ exception crosses the ABI.
+ *    HIP failures are reported as DKS_EHIP.  A plan is not thread-safe;
+ *    distinct plans may run concurrently on distinct streams.
+ */
+#ifndef DKS_POISSON_H
+#define DKS_POISSON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DKS_OK = 0,
+  DKS_EINVAL = -1,        /* bad argument: null pointer, size or spacing out of range */
+  DKS_EUNSUPPORTED = -2,  /* a doubled extent 2n is not of the form 2^a 3^b, or too large */
+  DKS_ENOMEM = -3,        /* host allocation failed */
+  DKS_EHIP = -4,          /* a HIP runtime call or kernel launch failed */
+  DKS_EWORKSPACE = -5,    /* workspace missing, too small or misaligned */
+  DKS_ESTATE = -6         /* call out of order (e.g. solve before prepare) */
+} dks_status;
+
+typedef enum { DKS_F32 = 0, DKS_F64 = 1 } dks_dtype;
+
+typedef struct dks_poisson_plan_s* dks_poisson_plan_t;
+
+/* A hipStream_t passed as an opaque pointer (NULL = default stream). */
+typedef void* dks_stream_t;
+
+/* Create a plan for an nx x ny x nz node mesh (section "FFT Based
+ * Particle-Mesh Solver": the M_x x M_y x M_z mesh, solved on the doubled
+ * 2M grid).
+ *   nx, ny, nz : nodes per axis, each >= 2 (>= 4 for a fitted plan); each
+ *                2 n_d must factor as 2^a 3^b and be <= 4096.
+ *   hx, hy, hz : cell sizes in metres, all > 0 (explicit mesh), or all
+ *                exactly 0 (particle-fitted cubic mesh).
+ *   dtype      : arithmetic type of the bulk path and of every array.
+ *   out        : receives the plan handle (host memory owned by the library
+ *                until dks_poisson_destroy).
+ * Host-only; touches no device. */
+dks_status dks_poisson_plan(int nx, int ny, int nz, double hx, double hy, double hz,
+                            dks_dtype dtype, dks_poisson_plan_t* out);
+
+/* Move an explicit-h mesh: node (0,0,0) at (x0, y0, z0) metres.  Takes effect
+ * from the next solve.  DKS_ESTATE on a fitted plan. */
+dks_status dks_poisson_set_origin(dks_poisson_plan_t plan, double x0, double y0, double z0);
+
+/* Bytes of device workspace the plan needs: its resident state (Green's
+ * spectrum octant, twiddle tables, geometry block) plus the scratch of one
+ * solve.  Alignment required: 256 bytes. */
+dks_status dks_poisson_workspace_bytes(dks_poisson_plan_t plan, size_t* bytes);
+
+/* Bytes of per-element scratch a batched solve needs for `batch` elements,
+ * on top of the plan workspace. */
+dks_status dks_poisson_batch_scratch_bytes(dks_poisson_plan_t plan, int batch, size_t* bytes);
+
+/* Attach caller-owned device workspace (at least dks_poisson_workspace_bytes,
+ * 256-byte aligned).  The plan keeps the pointer; the caller keeps it alive
+ * and must call dks_poisson_prepare again after attaching a new one. */
+dks_status dks_poisson_set_workspace(dks_poisson_plan_t plan, void* workspace, size_t bytes);
+
+/* Build the resident state on the device, on `stream`: the FP64 twiddle
+ * tables (rounded to the dtype) and the Green's function spectrum.  The
+ * spectrum is the DFT over the doubled grid of the cell-integrated 1/r kernel
+ * (the G of the convolution-solution equation, integrated over a cell; FFT of
+ * G in the paper's sequence diagram), evaluated and transformed in FP64, with
+ * the 1/(Nx Ny Nz) inverse-transform factor folded in, then rounded to the
+ * dtype.  Because the kernel is even, its spectrum is real and even, and only
+ * the octant [0..nx] x [0..ny] x [0..nz] is stored.  Must precede any solve;
+ * a fitted plan computes it once for h = 1 m and scales it by h^2 per solve. */
+dks_status dks_poisson_prepare(dks_poisson_plan_t plan, dks_stream_t stream);
+
+/* Potential (and field) of a mesh charge density (the brute-force sum
+ * equation and its FFT form; E = -grad phi by central differences, the
+ * D-operator of the OPAL structure figure).  Explicit-h plans only
+ * (DKS_ESTATE on a fitted plan).
+ *   rho    : device [nz][ny][nx], C/m^3, read only.
+ *   phi    : device [nz][ny][nx], volts, written; may be NULL.
+ *   E_mesh : device [3][nz][ny][nx], V/m, written; may be NULL.
+ * At least one of phi, E_mesh must be non-NULL. */
+dks_status dks_poisson_solve_rho(dks_poisson_plan_t plan, const void* rho, void* phi,
+                                 void* E_mesh, dks_stream_t stream);
+
+/* One full particle step: (fit the mesh,) CIC deposit, free-space potential,
+ * central-difference field, CIC gather back to the particles.
+ *   x, y, z    : device [np] particle positions in metres, read only.
+ *   np         : number of particles, >= 0.
+ *   q          : charge of each particle in coulombs.
+ *   Ex, Ey, Ez : device [np] field at the particles, V/m, written (np > 0).
+ *   phi        : device [nz][ny][nx] mesh potential, volts; may be NULL.
+ *   n_outside  : device int64 counter of particles outside the mesh, written
+ *                (not accumulated); may be NULL. */
+dks_status dks_poisson_solve_particles(dks_poisson_plan_t plan, const void* x, const void* y,
+                                       const void* z, int64_t np, double q, void* Ex, void* Ey,
+                                       void* Ez, void* phi, int64_t* n_outside,
+                                       dks_stream_t stream);
+
+/* The same step for `batch` independent particle sets of the plan's shape
+ * and dtype, each kernel launched once over the whole batch (the batch index
+ * is part of the grid).  On a fitted plan every element gets its own mesh fit;
+ * the cached spectrum is scaled per element by h_b^2.
+ *   batch           : 1 .. 16 elements.
+ *   x, y, z, Ex, Ey, Ez : host arrays of `batch` device pointers.
+ *   np, q           : host arrays of `batch` counts and per-particle charges.
+ *   phi             : host array of `batch` device pointers (entries may be
+ *                     NULL), or NULL.
+ *   scratch         : device, >= dks_poisson_batch_scratch_bytes(batch),
+ *                     256-byte aligned, caller-owned.
+ *   n_outside       : device int64[batch], written; may be NULL. */
+dks_status dks_poisson_solve_particles_batched(
+    dks_poisson_plan_t plan, int batch, const void* const* x, const void* const* y,
+    const void* const* z, const int64_t* np, const double* q, void* const* Ex, void* const* Ey,
+    void* const* Ez, void* const* phi, void* scratch, size_t scratch_bytes, int64_t* n_outside,
+    dks_stream_t stream);
+
+/* Charge deposit alone (CIC assignment, the "NGP, CIC, TSI" box of the OPAL
+ * structure figure), including the mesh fit of a fitted plan.
+ *   rho       : device [nz][ny][nx], written with the charge density, C/m^3.
+ *   n_outside : device int64 counter, written; may be NULL. */
+dks_status dks_poisson_deposit(dks_poisson_plan_t plan, const void* x, const void* y,
+                               const void* z, int64_t np, double q, void* rho,
+                               int64_t* n_outside, dks_stream_t stream);
+
+/* Field interpolation alone (CIC gather) from a mesh field, using the
+ * plan's current geometry (the explicit mesh, or the last fit).
+ *   E_mesh     : device [3][nz][ny][nx], V/m, read only.
+ *   Ex, Ey, Ez : device [np], written. */
+dks_status dks_poisson_gather(dks_poisson_plan_t plan, const void* E_mesh, const void* x,
+                              const void* y, const void* z, int64_t np, void* Ex, void* Ey,
+                              void* Ez, dks_stream_t stream);
+
+/* Read back the geometry of the last solve (or the explicit mesh):
+ * h[3] cell sizes and origin[3] in metres, FP64.  Synchronises `stream`. */
+dks_status dks_poisson_geometry(dks_poisson_plan_t plan, dks_stream_t stream, double* h,
+                                double* origin);
+
+/* Release the plan's host state.  Does not touch the caller's workspace. */
+dks_status dks_poisson_destroy(dks_poisson_plan_t plan);
+
+/* Static, NUL-terminated description of a status code. */
+const char* dks_status_string(dks_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DKS_POISSON_H */

@@ -1,0 +1,557 @@
+// Pruned 3-D real-to-complex / complex-to-real FFT passes of the doubled-grid
+// convolution (Hockney's open-boundary method, section "FFT Based
+// Particle-Mesh Solver": phi = FT^-1{FT{rho} (Hadamard) FT{G}}, the Green's
+// multiply fused between the forward and inverse z transforms).
+//
+// Every pass works on a tile of W pencils held in LDS as [element][pencil]
+// (pencil index fastest).  A mixed-radix Stockham transform (radices 8, 4, 2,
+// 3) runs over the tile: each pass loads its butterfly inputs from LDS into
+// registers, synchronises, applies twiddles and the radix-R DFT and writes
+// the outputs back in Stockham order.  The first pass of a transform can take
+// its inputs straight from HBM (the y and z passes) and the last pass can
+// hand its outputs straight to HBM, so a transform of P passes costs P - 1
+// LDS round trips.  Lanes are mapped pencil-fastest so that a wavefront's 64
+// lanes read and write W contiguous complex values per row: 128-byte HBM
+// segments and conflict-free LDS rows.
+//
+// Zero padding is never stored: the forward x transform reads the nx real
+// values of a row, the forward y and z transforms read only the first half of
+// their pencils, and the inverse transforms store only the outputs in
+// [-1, n] per axis (the physical mesh plus one ghost node on each side).
+
+#include <type_traits>
+
+#include "dks_internal.h"
+
+namespace dks {
+
+template <typename T> struct alignas(2 * sizeof(T)) cpx {
+  T x, y;
+};
+template <typename T> struct Cplx { using type = cpx<T>; };
+
+// Register budget per thread: the tile holds at most kLdsBytes / sizeof(C)
+// complex values spread over the block's threads (512 for FP32, 256 for
+// FP64), i.e. 16 complex values per thread either way.
+template <typename T> struct RegCfg {
+  static constexpr int THREADS = sizeof(T) == 4 ? 512 : 256;
+  static constexpr int EMAX = kLdsBytes / (2 * (int)sizeof(T)) / THREADS;
+  static constexpr int ARR = EMAX + 2;     // ceil(EMAX / R) * R <= EMAX + 2 for R in {2,3,4,8}
+};
+
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+
+// (x + iy) * (-i) in the forward direction, * (+i) in the inverse one.
+template <bool INV, typename C> __device__ __forceinline__ C mul_mi(C a) {
+  return INV ? C{-a.y, a.x} : C{a.y, -a.x};
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void dft2(C* v) {
+  const C a = v[0];
+  v[0] = cadd(a, v[1]);
+  v[1] = csub(a, v[1]);
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void dft4(C* v) {
+  const C a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+  const C a2 = cadd(v[1], v[3]), a3 = mul_mi<INV>(csub(v[1], v[3]));
+  v[0] = cadd(a0, a2);
+  v[2] = csub(a0, a2);
+  v[1] = cadd(a1, a3);
+  v[3] = csub(a1, a3);
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void dft8(C* v) {
+  using T = decltype(C::x);
+  C e[4] = {v[0], v[2], v[4], v[6]};
+  C o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<INV>(e);
+  dft4<INV>(o);
+  const T s = (T)0.70710678118654752440;   // cos(pi/4), rounded from the FP64 value
+  // o[k] *= w8^k with w8 = exp(-+ i pi / 4)
+  {
+    const C a = o[1];
+    o[1] = INV ? C{s * (a.x - a.y), s * (a.x + a.y)} : C{s * (a.x + a.y), s * (a.y - a.x)};
+  }
+  o[2] = mul_mi<INV>(o[2]);
+  {
+    const C a = o[3];
+    o[3] = INV ? C{-s * (a.x + a.y), s * (a.x - a.y)} : C{s * (a.y - a.x), -s * (a.x + a.y)};
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = cadd(e[k], o[k]);
+    v[k + 4] = csub(e[k], o[k]);
+  }
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void dft3(C* v) {
+  using T = decltype(C::x);
+  const T sn = INV ? (T)0.86602540378443864676 : (T)-0.86602540378443864676;   // sin(-+2pi/3)
+  const C t = cadd(v[1], v[2]);
+  const C d = csub(v[1], v[2]);
+  const C m = C{v[0].x - (T)0.5 * t.x, v[0].y - (T)0.5 * t.y};
+  v[0] = cadd(v[0], t);
+  const C si = C{-sn * d.y, sn * d.x};
+  v[1] = cadd(m, si);
+  v[2] = csub(m, si);
+}
+
+template <int R, bool INV, typename C> __device__ __forceinline__ void dft(C* v) {
+  if constexpr (R == 2) dft2<INV>(v);
+  else if constexpr (R == 3) dft3<INV>(v);
+  else if constexpr (R == 4) dft4<INV>(v);
+  else dft8<INV>(v);
+}
+
+template <class F> __device__ __forceinline__ void radix_dispatch(int R, F&& f) {
+  switch (R) {
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    default: f(std::integral_constant<int, 3>{}); break;
+  }
+}
+
+// One Stockham pass of radix R over the tile.  Every butterfly (pencil c,
+// index j) this thread owns takes its R inputs j + r N/R from in(c, idx);
+// after the optional barrier (needed when the pass reads and writes the LDS
+// tile in place) the twiddles w^(r t), t = j mod Ns, and the radix-R DFT are
+// applied and out(R, c, j, base, Ns, vals) receives the R outputs, whose
+// positions are base + r Ns.  The register array is local to this pass.
+template <typename T, bool INV, int R, bool SYNC, class In, class Out>
+__device__ __forceinline__ void fft_pass(const FFTPlan* __restrict__ P, int p, In in, Out out) {
+  using C = typename Cplx<T>::type;
+  constexpr int TH = RegCfg<T>::THREADS;
+  constexpr int K = (RegCfg<T>::EMAX + R - 1) / R;
+  const int W = P->W, logW = P->logW, NR = P->N / R, nbf = W * NR, Ns = P->Ns[p];
+  C v[K * R];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int b = (int)threadIdx.x + k * TH;
+    if (b < nbf) {
+      const int c = b & (W - 1), j = b >> logW;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[k * R + r] = in(c, j + r * NR);
+    }
+  }
+  if (SYNC) __syncthreads();
+  const C* tw = (const C*)P->tw + P->tw_off[p];
+  const unsigned magic = P->magic[p];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int b = (int)threadIdx.x + k * TH;
+    if (b < nbf) {
+      const int c = b & (W - 1), j = b >> logW;
+      int base;
+      if (Ns > 1) {
+        const int q = (int)__umulhi((unsigned)j, magic);
+        const int t = j - q * Ns;
+        const C* w = tw + t * (R - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C wr = w[r - 1];
+          if (INV) wr.y = -wr.y;
+          v[k * R + r] = cmul(v[k * R + r], wr);
+        }
+        base = q * Ns * R + t;
+      } else {
+        base = j * R;
+      }
+      dft<R, INV>(&v[k * R]);
+      out(std::integral_constant<int, R>{}, c, j, base, Ns, &v[k * R]);
+    }
+  }
+}
+
+// Runs passes [p0, npass) of plan P over the LDS tile.  Pass p0 reads
+// first_in (the LDS tile itself when FIRST_LDS, so it synchronises before
+// overwriting it); later passes read the tile.  The last pass hands its
+// butterflies to last_out; earlier ones write the tile.  A barrier follows
+// every pass that wrote the tile, except the last.
+template <typename T, bool INV, bool FIRST_LDS, class FirstIn, class LastOut>
+__device__ __forceinline__ void run_fft(typename Cplx<T>::type* lds, const FFTPlan* __restrict__ P, int p0,
+                                        FirstIn first_in, LastOut last_out) {
+  using C = typename Cplx<T>::type;
+  const int LD = P->LD;
+  auto lds_in = [&](int c, int idx) { return lds[idx * LD + c]; };
+  auto lds_out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
+#pragma unroll
+    for (int r = 0; r < RC.value; ++r) lds[(base + r * Ns) * LD + c] = vals[r];
+  };
+  const int np = P->npass;
+  for (int p = p0; p < np; ++p) {
+    const bool first = p == p0, last = p == np - 1;
+    radix_dispatch(P->R[p], [&](auto RC) {
+      constexpr int R = RC.value;
+      if (first && last) fft_pass<T, INV, R, FIRST_LDS>(P, p, first_in, last_out);
+      else if (first) fft_pass<T, INV, R, FIRST_LDS>(P, p, first_in, lds_out);
+      else if (last) fft_pass<T, INV, R, true>(P, p, lds_in, last_out);
+      else fft_pass<T, INV, R, true>(P, p, lds_in, lds_out);
+    });
+    if (!last) __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x forward: real rows of nx values (zero-padded to 2 nx) -> nx + 1 complex.
+// A length-2nx real transform is done as a length-nx complex transform of
+// z[m] = x[2m] + i x[2m+1], then X[k] = (Z[k] + conj Z[nx-k]) / 2
+// - i w^k (Z[k] - conj Z[nx-k]) / 2 with w = exp(-2 pi i / 2nx).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __restrict__ in, size_t in_stride,
+                                                        typename Cplx<T>::type* __restrict__ out,
+                                                        size_t out_stride, MeshDims m, const FFTPlan* __restrict__ P,
+                                                        const typename Cplx<T>::type* __restrict__ post,
+                                                        int nrows, int logTX) {
+  using C = typename Cplx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  const T* src = in + blockIdx.y * in_stride;
+  C* dst = out + blockIdx.y * out_stride;
+  const int row0 = blockIdx.x * P->W;
+  const int nvalid = min(P->W, nrows - row0);
+  const int nx = m.nx, M = P->N;
+  const int TX = 1 << logTX;
+  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> logTX, TY = RegCfg<T>::THREADS >> logTX;
+  for (int p = ty; p < nvalid; p += TY) {
+    const T* row = src + (size_t)(row0 + p) * nx;
+    for (int x = tx; x < nx; x += TX) {
+      T* slot = reinterpret_cast<T*>(&lds[(x >> 1) * P->LD + p]);
+      slot[x & 1] = row[x];
+      if ((x & 1) == 0 && x == nx - 1) slot[1] = (T)0;
+    }
+  }
+  __syncthreads();
+  {
+    const int nnz = (nx + 1) >> 1;
+    const int LD = P->LD;
+    auto in = [&](int c, int idx) { return idx < nnz ? lds[idx * LD + c] : C{0, 0}; };
+    auto out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
+#pragma unroll
+      for (int r = 0; r < RC.value; ++r) lds[(base + r * Ns) * LD + c] = vals[r];
+    };
+    run_fft<T, false, true>(lds, P, 0, in, out);
+  }
+  __syncthreads();
+  const int ncols = nx + 1;
+  for (int p = ty; p < nvalid; p += TY) {
+    C* orow = dst + (size_t)(row0 + p) * m.cs;
+    for (int k = tx; k < ncols; k += TX) {
+      const C zk = lds[(k == M ? 0 : k) * P->LD + p];
+      C zc = lds[(k == 0 ? 0 : M - k) * P->LD + p];
+      zc.y = -zc.y;
+      const C s = cadd(zk, zc), d = csub(zk, zc);
+      const C wd = cmul(post[k], d);
+      orow[k] = C{(T)0.5 * (s.x + wd.y), (T)0.5 * (s.y - wd.x)};
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y forward: pencils along y of the x-transformed rows.  Input A[z][y][kx]
+// (y < ny), output B[z][ky][kx] (ky < 2 ny).  Grid: (column tiles, nz, batch).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_fwd(const typename Cplx<T>::type* __restrict__ A,
+                                                        typename Cplx<T>::type* __restrict__ B,
+                                                        size_t stride, MeshDims m, const FFTPlan* __restrict__ P) {
+  using C = typename Cplx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  const int c0 = blockIdx.x * P->W;
+  const int ncol = min(P->W, m.ncols - c0);
+  const C* src = A + blockIdx.z * stride + (size_t)blockIdx.y * m.ny * m.cs + c0;
+  C* dst = B + blockIdx.z * stride + (size_t)blockIdx.y * m.Ny * m.cs + c0;
+  const int ny = m.ny, cs = m.cs;
+  auto in = [&](int c, int idx) { return (idx < ny && c < ncol) ? src[(size_t)idx * cs + c] : C{0, 0}; };
+  auto out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
+    if (c < ncol) {
+#pragma unroll
+      for (int r = 0; r < RC.value; ++r) dst[(size_t)(base + r * Ns) * cs + c] = vals[r];
+    }
+  };
+  run_fft<T, false, false>(lds, P, 0, in, out);
+}
+
+// ---------------------------------------------------------------------------
+// z: forward transform of each (kx, ky) pencil over its nz non-zero inputs,
+// multiply by the real Green's spectrum times the solve's scale, inverse
+// transform, keep z in [-1, nz].  Input B[z][ky][kx] (z < nz), output
+// C[z + 1][ky][kx] for z in [-1, nz].  Grid: (column tiles, 2 ny, batch).
+// The inverse plan's radices are the forward's reversed, so the last forward
+// pass and the first inverse pass share a butterfly layout and the multiply
+// happens in registers between them.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
+    const typename Cplx<T>::type* __restrict__ B, typename Cplx<T>::type* __restrict__ Cout,
+    size_t stride, const T* __restrict__ G, const Geometry* __restrict__ geo, size_t geo_stride,
+    MeshDims m, const FFTPlan* __restrict__ Pf, const FFTPlan* __restrict__ Pi) {
+  using C = typename Cplx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  const int c0 = blockIdx.x * Pf->W;
+  const int ky = blockIdx.y;
+  const int ncol = min(Pf->W, m.ncols - c0);
+  const size_t plane_in = (size_t)m.Ny * m.cs;     // one z plane of B or C
+  const C* src = B + blockIdx.z * stride + (size_t)ky * m.cs + c0;
+  C* dst = Cout + blockIdx.z * stride + (size_t)ky * m.cs + c0;
+  const Geometry* g = reinterpret_cast<const Geometry*>(reinterpret_cast<const char*>(geo) +
+                                                        blockIdx.z * geo_stride);
+  const T scale = Geo<T>::scale(g);
+  const int kyr = min(ky, m.Ny - ky);
+  const T* grow = G + (size_t)kyr * (m.nz + 1) * m.cs + c0;
+  const int nz = m.nz, Nz = m.Nz, cs = m.cs, LD = Pf->LD;
+  auto in = [&](int c, int idx) { return (idx < nz && c < ncol) ? src[(size_t)idx * plane_in + c] : C{0, 0}; };
+  // Final inverse outputs: keep z = -1 (index Nz - 1) and z = 0 .. nz as row z + 1.
+  auto store_z = [&](int c, int idx, C val) {
+    int zo = -1;
+    if (idx <= nz) zo = idx + 1;
+    else if (idx == Nz - 1) zo = 0;
+    if (zo >= 0 && c < ncol) dst[(size_t)zo * plane_in + c] = val;
+  };
+  const bool inv_single = Pi->npass == 1;
+  // Last forward pass: its outputs sit at kz = j + r Ns, exactly the inputs of
+  // the first inverse butterfly j (radix R, span 1, no twiddles).
+  auto mid = [&](auto RC, int c, int j, int base, int Ns, C* vals) {
+    constexpr int R = RC.value;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int kz = base + r * Ns;
+      const int kzr = min(kz, Nz - kz);
+      const T gv = (c < ncol) ? grow[(size_t)kzr * cs + c] * scale : (T)0;
+      vals[r].x *= gv;
+      vals[r].y *= gv;
+    }
+    dft<R, true>(vals);
+    if (inv_single) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) store_z(c, j * R + r, vals[r]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[(j * R + r) * LD + c] = vals[r];
+    }
+  };
+  run_fft<T, false, false>(lds, Pf, 0, in, mid);
+  if (!inv_single) {
+    __syncthreads();
+    auto lds_in = [&](int c, int idx) { return lds[idx * LD + c]; };
+    auto out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
+#pragma unroll
+      for (int r = 0; r < RC.value; ++r) store_z(c, base + r * Ns, vals[r]);
+    };
+    run_fft<T, true, true>(lds, Pi, 1, lds_in, out);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y inverse: C[z'][ky][kx] -> D[z'][y + 1][kx] for y in [-1, ny].
+// Grid: (column tiles, nz + 2, batch).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_inv(const typename Cplx<T>::type* __restrict__ Cin,
+                                                        typename Cplx<T>::type* __restrict__ D,
+                                                        size_t stride, MeshDims m, const FFTPlan* __restrict__ P) {
+  using C = typename Cplx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  const int c0 = blockIdx.x * P->W;
+  const int ncol = min(P->W, m.ncols - c0);
+  const C* src = Cin + blockIdx.z * stride + (size_t)blockIdx.y * m.Ny * m.cs + c0;
+  C* dst = D + blockIdx.z * stride + (size_t)blockIdx.y * (m.ny + 2) * m.cs + c0;
+  const int ny = m.ny, Ny = m.Ny, cs = m.cs;
+  auto in = [&](int c, int idx) { return c < ncol ? src[(size_t)idx * cs + c] : C{0, 0}; };
+  auto out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
+#pragma unroll
+    for (int r = 0; r < RC.value; ++r) {
+      const int idx = base + r * Ns;
+      int yo = -1;
+      if (idx <= ny) yo = idx + 1;
+      else if (idx == Ny - 1) yo = 0;
+      if (yo >= 0 && c < ncol) dst[(size_t)yo * cs + c] = vals[r];
+    }
+  };
+  run_fft<T, true, false>(lds, P, 0, in, out);
+}
+
+// ---------------------------------------------------------------------------
+// x inverse: rows of nx + 1 complex (half spectrum of a real length-2nx row)
+// -> real values at x in [-1, nx] (row of nx + 2, ghost nodes included).
+// Z'[k] = (X[k] + conj X[nx-k]) + i w^-k (X[k] - conj X[nx-k]); the length-nx
+// inverse transform of Z' gives 2nx * (x[2m] + i x[2m+1]) unnormalised; the
+// normalisation is folded into the Green's spectrum.  Optionally also writes
+// the physical part of phi to a [nz][ny][nx] array.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_inv(const typename Cplx<T>::type* __restrict__ D,
+                                                        size_t in_stride, T* __restrict__ phi_ext,
+                                                        size_t out_stride, PtrBatch phi_user,
+                                                        MeshDims m, const FFTPlan* __restrict__ P,
+                                                        const typename Cplx<T>::type* __restrict__ post,
+                                                        int nrows, int logTX) {
+  using C = typename Cplx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  const C* src = D + blockIdx.y * in_stride;
+  T* dst = phi_ext + blockIdx.y * out_stride;
+  T* user = reinterpret_cast<T*>(phi_user.p[blockIdx.y]);
+  const int row0 = blockIdx.x * P->W;
+  const int nvalid = min(P->W, nrows - row0);
+  const int nx = m.nx, M = P->N;
+  const int TX = 1 << logTX;
+  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> logTX, TY = RegCfg<T>::THREADS >> logTX;
+  for (int p = ty; p < nvalid; p += TY) {
+    const C* row = src + (size_t)(row0 + p) * m.cs;
+    for (int k = tx; k < M; k += TX) {
+      const C xk = row[k];
+      C xc = row[M - k];
+      xc.y = -xc.y;
+      const C s = cadd(xk, xc), d = csub(xk, xc);
+      C w = post[k];
+      w.y = -w.y;
+      const C wd = cmul(w, d);
+      lds[k * P->LD + p] = C{s.x - wd.y, s.y + wd.x};
+    }
+  }
+  __syncthreads();
+  {
+    const int LD = P->LD;
+    auto in = [&](int c, int idx) { return lds[idx * LD + c]; };
+    auto out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
+#pragma unroll
+      for (int r = 0; r < RC.value; ++r) lds[(base + r * Ns) * LD + c] = vals[r];
+    };
+    run_fft<T, true, true>(lds, P, 0, in, out);
+  }
+  __syncthreads();
+  const int nout = nx + 2;
+  const int ny2 = m.ny + 2;
+  for (int p = ty; p < nvalid; p += TY) {
+    const int r = row0 + p;          // row index z' * (ny + 2) + y'
+    T* orow = dst + (size_t)r * nout;
+    const int zp = r / ny2, yp = r - zp * ny2;
+    const bool phys = user && zp >= 1 && zp <= m.nz && yp >= 1 && yp <= m.ny;
+    const size_t ubase = phys ? ((size_t)(zp - 1) * m.ny + (yp - 1)) * nx : 0;
+    for (int xo = tx; xo < nout; xo += TX) {
+      const int x = xo - 1;
+      T val;
+      if (x < 0) {
+        val = lds[(M - 1) * P->LD + p].y;
+      } else {
+        const C zv = lds[(x >> 1) * P->LD + p];
+        val = (x & 1) ? zv.y : zv.x;
+      }
+      orow[xo] = val;
+      if (phys && xo >= 1 && xo <= nx) user[ubase + xo - 1] = val;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+static inline int log2_floor(int v) {
+  int l = 0;
+  while ((1 << (l + 1)) <= v) ++l;
+  return l;
+}
+
+template <typename T>
+static size_t lds_bytes(const FFTPlan& P) {
+  return (size_t)P.N * P.LD * sizeof(typename Cplx<T>::type);
+}
+
+template <typename T>
+hipError_t launch_fft_x_fwd(const void* in, size_t in_stride, void* out, size_t out_stride, const MeshDims& m,
+                            const PlanRef& P, const void* post, int batch, hipStream_t s) {
+  using C = typename Cplx<T>::type;
+  const int nrows = m.ny * m.nz;
+  const int logTX = log2_floor(std::min(256, std::max(1, m.nx)));
+  dim3 grid((nrows + P.host.W - 1) / P.host.W, batch);
+  hipLaunchKernelGGL(k_fft_x_fwd<T>, grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s, (const T*)in,
+                     in_stride, (C*)out, out_stride, m, P.dev, (const C*)post, nrows, logTX);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_y_fwd(const void* A, void* B, size_t stride, const MeshDims& m, const PlanRef& P, int batch,
+                            hipStream_t s) {
+  using C = typename Cplx<T>::type;
+  dim3 grid((m.ncols + P.host.W - 1) / P.host.W, m.nz, batch);
+  hipLaunchKernelGGL(k_fft_y_fwd<T>, grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s, (const C*)A, (C*)B,
+                     stride, m, P.dev);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_z_conv(const void* B, void* Cout, size_t stride, const void* G, const Geometry* geo,
+                             size_t geo_stride, const MeshDims& m, const PlanRef& Pf, const PlanRef& Pi, int batch,
+                             hipStream_t s) {
+  using C = typename Cplx<T>::type;
+  dim3 grid((m.ncols + Pf.host.W - 1) / Pf.host.W, m.Ny, batch);
+  hipLaunchKernelGGL(k_fft_z_conv<T>, grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(Pf.host), s, (const C*)B,
+                     (C*)Cout, stride, (const T*)G, geo, geo_stride, m, Pf.dev, Pi.dev);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_y_inv(const void* Cin, void* D, size_t stride, const MeshDims& m, const PlanRef& P, int batch,
+                            hipStream_t s) {
+  using C = typename Cplx<T>::type;
+  dim3 grid((m.ncols + P.host.W - 1) / P.host.W, m.nz + 2, batch);
+  hipLaunchKernelGGL(k_fft_y_inv<T>, grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s, (const C*)Cin, (C*)D,
+                     stride, m, P.dev);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_x_inv(const void* D, size_t in_stride, void* phi_ext, size_t out_stride,
+                            const PtrBatch& phi_user, const MeshDims& m, const PlanRef& P, const void* post,
+                            int batch, hipStream_t s) {
+  using C = typename Cplx<T>::type;
+  const int nrows = (m.ny + 2) * (m.nz + 2);
+  const int logTX = log2_floor(std::min(256, std::max(1, m.nx + 2)));
+  dim3 grid((nrows + P.host.W - 1) / P.host.W, batch);
+  hipLaunchKernelGGL(k_fft_x_inv<T>, grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s, (const C*)D,
+                     in_stride, (T*)phi_ext, out_stride, phi_user, m, P.dev, (const C*)post, nrows, logTX);
+  return hipGetLastError();
+}
+
+// Copies the host-built plans into device memory (kernel arguments are
+// copied at launch, so this is safe inside stream capture).
+__global__ void k_store_plans(FFTPlan a, FFTPlan b, FFTPlan c, FFTPlan d, FFTPlan* out) {
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+    out[2] = c;
+    out[3] = d;
+  }
+}
+
+hipError_t launch_store_plans(const FFTPlan* four, FFTPlan* dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_store_plans, dim3(1), dim3(64), 0, s, four[0], four[1], four[2], four[3], dev);
+  return hipGetLastError();
+}
+
+#define DKS_INSTANTIATE(T)                                                                                     \
+  template hipError_t launch_fft_x_fwd<T>(const void*, size_t, void*, size_t, const MeshDims&, const PlanRef&, \
+                                          const void*, int, hipStream_t);                                      \
+  template hipError_t launch_fft_y_fwd<T>(const void*, void*, size_t, const MeshDims&, const PlanRef&, int,    \
+                                          hipStream_t);                                                        \
+  template hipError_t launch_fft_z_conv<T>(const void*, void*, size_t, const void*, const Geometry*, size_t,   \
+                                           const MeshDims&, const PlanRef&, const PlanRef&, int, hipStream_t); \
+  template hipError_t launch_fft_y_inv<T>(const void*, void*, size_t, const MeshDims&, const PlanRef&, int,    \
+                                          hipStream_t);                                                        \
+  template hipError_t launch_fft_x_inv<T>(const void*, size_t, void*, size_t, const PtrBatch&, const MeshDims&, \
+                                          const PlanRef&, const void*, int, hipStream_t);
+DKS_INSTANTIATE(float)
+DKS_INSTANTIATE(double)
+#undef DKS_INSTANTIATE
+
+}  // namespace dks

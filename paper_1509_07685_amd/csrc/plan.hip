@@ -1,0 +1,638 @@
+// Plan objects and the C ABI (include/dks_poisson.h): argument validation,
+// radix plans of the three transforms, workspace layout, and the launch
+// sequences of the plan-time Green's spectrum and of each solve.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dks_internal.h"
+
+namespace dks {
+
+// Launchers defined in the kernel translation units.
+template <typename T> hipError_t launch_fft_x_fwd(const void*, size_t, void*, size_t, const MeshDims&,
+                                                  const PlanRef&, const void*, int, hipStream_t);
+template <typename T> hipError_t launch_fft_y_fwd(const void*, void*, size_t, const MeshDims&, const PlanRef&,
+                                                  int, hipStream_t);
+template <typename T> hipError_t launch_fft_z_conv(const void*, void*, size_t, const void*, const Geometry*,
+                                                   size_t, const MeshDims&, const PlanRef&, const PlanRef&, int,
+                                                   hipStream_t);
+template <typename T> hipError_t launch_fft_y_inv(const void*, void*, size_t, const MeshDims&, const PlanRef&,
+                                                  int, hipStream_t);
+template <typename T> hipError_t launch_fft_x_inv(const void*, size_t, void*, size_t, const PtrBatch&,
+                                                  const MeshDims&, const PlanRef&, const void*, int,
+                                                  hipStream_t);
+hipError_t launch_store_plans(const FFTPlan* four, FFTPlan* dev, hipStream_t s);
+template <typename T> hipError_t launch_bbox(const PtrBatch&, const PtrBatch&, const PtrBatch&,
+                                             const BatchScalars&, int, double*, size_t, int*, hipStream_t);
+hipError_t launch_geometry(const double*, size_t, Geometry*, size_t, const GeoArgs&, const BatchScalars&,
+                           const PtrBatch&, int, hipStream_t);
+hipError_t launch_zero(void*, size_t, size_t, int, hipStream_t);
+template <typename T> hipError_t launch_deposit(const PtrBatch&, const PtrBatch&, const PtrBatch&,
+                                                const BatchScalars&, int, void*, size_t, const Geometry*, size_t,
+                                                const MeshDims&, const PtrBatch&, hipStream_t);
+template <typename T> hipError_t launch_weights_to_density(const void*, void*, size_t, const Geometry*, double,
+                                                           hipStream_t);
+template <typename T, bool I> hipError_t launch_gradient(const void*, size_t, void*, size_t, const Geometry*,
+                                                         size_t, const MeshDims&, int, hipStream_t);
+template <typename T, bool I> hipError_t launch_gather(const void*, size_t, const PtrBatch&, const PtrBatch&,
+                                                       const PtrBatch&, const PtrBatch&, const PtrBatch&,
+                                                       const PtrBatch&, const BatchScalars&, int,
+                                                       const Geometry*, size_t, const MeshDims&, hipStream_t);
+template <typename T> hipError_t launch_twiddle_pass(void*, int, int, hipStream_t);
+template <typename T> hipError_t launch_twiddle_line(void*, int, int, hipStream_t);
+hipError_t launch_igf_octant(double*, const int*, const double*, const GLBands&, hipStream_t);
+hipError_t launch_cos_matrix(double*, int, hipStream_t);
+hipError_t launch_apply_axis(const double*, double*, const double*, const int*, int, hipStream_t);
+template <typename T> hipError_t launch_green_pack(const double*, void*, const int*, int, double, hipStream_t);
+
+static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static bool factor23(int N) {
+  if (N < 1) return false;
+  while (N % 2 == 0) N /= 2;
+  while (N % 3 == 0) N /= 3;
+  return N == 1;
+}
+
+// Radix-8 passes first, then one radix-4 or radix-2 pass for the remaining
+// powers of two, then radix-3 passes; pass 0 is even whenever N is.
+static std::vector<int> radices_for(int N) {
+  int a = 0, b = 0;
+  while (N % 2 == 0) { N /= 2; ++a; }
+  while (N % 3 == 0) { N /= 3; ++b; }
+  std::vector<int> r;
+  while (a >= 3) { r.push_back(8); a -= 3; }
+  if (a == 2) r.push_back(4);
+  if (a == 1) r.push_back(2);
+  for (int i = 0; i < b; ++i) r.push_back(3);
+  return r;
+}
+
+static int pick_width(int N, size_t csize, bool padded, int wmax) {
+  int W = wmax;
+  while (W > 1 && (size_t)N * (size_t)(padded ? W + 1 : W) * csize > (size_t)kLdsBytes) W >>= 1;
+  return W;
+}
+
+static void build_fft(FFTPlanHost& P, int N, const std::vector<int>& R, int W, bool padded) {
+  std::memset(&P, 0, sizeof(P));
+  P.dev.N = N;
+  P.dev.npass = (int)R.size();
+  P.dev.W = W;
+  int lw = 0;
+  while ((1 << lw) < W) ++lw;
+  P.dev.logW = lw;
+  P.dev.LD = padded ? W + 1 : W;
+  int Ns = 1, off = 0;
+  for (size_t p = 0; p < R.size(); ++p) {
+    P.dev.R[p] = R[p];
+    P.dev.Ns[p] = Ns;
+    P.dev.magic[p] = Ns >= 2 ? (unsigned)(((1ull << 32) + (unsigned long long)Ns - 1) / (unsigned long long)Ns) : 0u;
+    P.dev.tw_off[p] = off;
+    if (p > 0) off += Ns * (R[p] - 1);
+    Ns *= R[p];
+  }
+  P.tw_count = off;
+}
+
+// Nodes and weights of the m-point Gauss-Legendre rule on [-1, 1] (Newton
+// iteration on the three-term Legendre recurrence).
+static void gauss_legendre(int m, double* x, double* w) {
+  for (int i = 0; i < m; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (m + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= m; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = m * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= m; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = m * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+static GLBands make_bands() {
+  GLBands g;
+  std::memset(&g, 0, sizeof(g));
+  const double lo[5] = {2.0, 4.0, 8.0, 16.0, 32.0};
+  const int m[5] = {10, 8, 6, 5, 4};
+  g.nb = 5;
+  for (int i = 0; i < 5; ++i) {
+    g.lo[i] = lo[i];
+    g.m[i] = m[i];
+    gauss_legendre(m[i], g.t[i], g.w[i]);
+  }
+  return g;
+}
+
+}  // namespace dks
+
+using namespace dks;
+
+struct dks_poisson_plan_s {
+  int n[3];
+  double h[3];
+  double origin[3];
+  bool fitted;
+  dks_dtype dtype;
+  size_t rsize;     // sizeof(real)
+  size_t csize;     // sizeof(complex)
+  MeshDims md;
+  FFTPlanHost px, py, pz, pzi;
+  size_t off_plans;                                        // four device FFTPlan copies
+  size_t tw_px, tw_py, tw_pz, tw_pzi, tw_post, tw_bytes;   // byte offsets in the twiddle region
+  size_t off_green, green_bytes, off_slot;
+  // slot layout (bytes from slot start)
+  size_t s_bbox, s_r1, s_r2, s_r3, slot_bytes;
+  size_t bytes_W, bytes_phi_ext, bytes_E4;
+  size_t ws_total;
+  char* ws;
+  size_t ws_bytes;
+  bool prepared;
+  bool has_geometry;
+};
+
+namespace {
+
+dks_status hip_status(hipError_t e) { return e == hipSuccess ? DKS_OK : DKS_EHIP; }
+
+#define DKS_CK(call)                              \
+  do {                                            \
+    const hipError_t e_ = (call);                 \
+    if (e_ != hipSuccess) return DKS_EHIP;        \
+  } while (0)
+
+void layout(dks_poisson_plan_s* p) {
+  const int nx = p->n[0], ny = p->n[1], nz = p->n[2];
+  const size_t s = p->rsize, c = p->csize;
+  const int wmax = (int)(128 / c);    // 128-byte column tiles
+  MeshDims& m = p->md;
+  m.nx = nx; m.ny = ny; m.nz = nz;
+  m.Nx = 2 * nx; m.Ny = 2 * ny; m.Nz = 2 * nz;
+  m.ncols = nx + 1;
+  m.cs = (nx + 1 + wmax - 1) / wmax * wmax;
+  const int Wx = pick_width(nx, c, true, wmax);
+  const int Wy = pick_width(m.Ny, c, false, wmax);
+  const int Wz = pick_width(m.Nz, c, false, wmax);
+  build_fft(p->px, nx, radices_for(nx), Wx, true);
+  build_fft(p->py, m.Ny, radices_for(m.Ny), Wy, false);
+  std::vector<int> rz = radices_for(m.Nz);
+  build_fft(p->pz, m.Nz, rz, Wz, false);
+  std::reverse(rz.begin(), rz.end());
+  build_fft(p->pzi, m.Nz, rz, Wz, false);
+  size_t off = 0;
+  p->off_plans = off; off = align256(off + 4 * sizeof(FFTPlan));
+  p->tw_px = off; off = align256(off + p->px.tw_count * c);
+  p->tw_py = off; off = align256(off + p->py.tw_count * c);
+  p->tw_pz = off; off = align256(off + p->pz.tw_count * c);
+  p->tw_pzi = off; off = align256(off + p->pzi.tw_count * c);
+  p->tw_post = off; off = align256(off + (size_t)(nx + 1) * c);
+  p->tw_bytes = off;
+  p->off_green = off;
+  p->green_bytes = (size_t)(ny + 1) * (nz + 1) * m.cs * s;
+  p->off_slot = align256(p->off_green + p->green_bytes);
+  const size_t cs = (size_t)m.cs;
+  const size_t A = (size_t)ny * nz * cs * c;
+  const size_t B = (size_t)m.Ny * nz * cs * c;
+  const size_t C = (size_t)m.Ny * (nz + 2) * cs * c;
+  const size_t D = (size_t)(ny + 2) * (nz + 2) * cs * c;
+  p->bytes_W = (size_t)nx * ny * nz * s;
+  p->bytes_phi_ext = (size_t)(nx + 2) * (ny + 2) * (nz + 2) * s;
+  p->bytes_E4 = (size_t)4 * nx * ny * nz * s;
+  const size_t G64 = (size_t)(nx + 1) * (ny + 1) * (nz + 1) * sizeof(double);
+  const size_t COS = ((size_t)(nx + 1) * (nx + 1) + (size_t)(ny + 1) * (ny + 1) + (size_t)(nz + 1) * (nz + 1)) *
+                     sizeof(double);
+  const size_t r1 = std::max({A, C, p->bytes_E4, G64});
+  const size_t r2 = std::max({B, D, G64});
+  const size_t r3 = std::max({p->bytes_W, p->bytes_phi_ext, COS + 256});
+  size_t so = align256(sizeof(Geometry));
+  p->s_bbox = so; so = align256(so + (size_t)kBboxBlocks * 6 * sizeof(double));
+  p->s_r1 = so; so = align256(so + r1);
+  p->s_r2 = so; so = align256(so + r2);
+  p->s_r3 = so; so = align256(so + r3);
+  p->slot_bytes = so;
+  p->ws_total = p->off_slot + p->slot_bytes;
+}
+
+// idx: 0 = x, 1 = y, 2 = z forward, 3 = z inverse.
+PlanRef planref(const dks_poisson_plan_s* p, int idx) {
+  const FFTPlanHost* hs[4] = {&p->px, &p->py, &p->pz, &p->pzi};
+  const size_t offs[4] = {p->tw_px, p->tw_py, p->tw_pz, p->tw_pzi};
+  PlanRef r;
+  r.host = hs[idx]->dev;
+  r.host.tw = p->ws + offs[idx];
+  r.dev = reinterpret_cast<const FFTPlan*>(p->ws + p->off_plans) + idx;
+  return r;
+}
+
+struct Slots {
+  char* base;
+  size_t stride;   // bytes between consecutive elements
+  Geometry* geo() const { return reinterpret_cast<Geometry*>(base); }
+};
+
+// rho (in `src`, element stride in_stride) -> phi_ext in R3 (+ user phi) via the five passes.
+template <typename T>
+dks_status convolve(const dks_poisson_plan_s* p, const void* src, size_t in_stride, int batch, const Slots& sl,
+                    const PtrBatch& phi_user, hipStream_t st) {
+  const MeshDims& m = p->md;
+  const size_t cstride = sl.stride / p->csize;
+  const size_t rstride = sl.stride / p->rsize;
+  char* R1 = sl.base + p->s_r1;
+  char* R2 = sl.base + p->s_r2;
+  char* R3 = sl.base + p->s_r3;
+  const PlanRef fx = planref(p, 0);
+  const PlanRef fy = planref(p, 1);
+  const PlanRef fz = planref(p, 2);
+  const PlanRef fzi = planref(p, 3);
+  const void* post = p->ws + p->tw_post;
+  const void* G = p->ws + p->off_green;
+  DKS_CK(launch_fft_x_fwd<T>(src, in_stride, R1, cstride, m, fx, post, batch, st));
+  DKS_CK(launch_fft_y_fwd<T>(R1, R2, cstride, m, fy, batch, st));
+  DKS_CK(launch_fft_z_conv<T>(R2, R1, cstride, G, sl.geo(), sl.stride, m, fz, fzi, batch, st));
+  DKS_CK(launch_fft_y_inv<T>(R1, R2, cstride, m, fy, batch, st));
+  DKS_CK(launch_fft_x_inv<T>(R2, cstride, R3, rstride, phi_user, m, fx, post, batch, st));
+  return DKS_OK;
+}
+
+GeoArgs geo_args(const dks_poisson_plan_s* p, int mode, int nblocks) {
+  GeoArgs a;
+  std::memset(&a, 0, sizeof(a));
+  for (int d = 0; d < 3; ++d) {
+    a.n[d] = p->n[d];
+    a.h[d] = p->h[d];
+    a.origin[d] = p->origin[d];
+  }
+  a.fitted = p->fitted ? 1 : 0;
+  a.nblocks = nblocks;
+  a.mode = mode;
+  return a;
+}
+
+// Mesh fit (fitted plans), geometry, zero W, deposit: leaves W in R3.
+template <typename T>
+dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl, const PtrBatch& X,
+                         const PtrBatch& Y, const PtrBatch& Z, const BatchScalars& bs, const PtrBatch& cnt,
+                         hipStream_t st) {
+  int nb = 0;
+  double* bbox = reinterpret_cast<double*>(sl.base + p->s_bbox);
+  if (p->fitted) DKS_CK(launch_bbox<T>(X, Y, Z, bs, batch, bbox, sl.stride / sizeof(double), &nb, st));
+  const GeoArgs ga = geo_args(p, 1, nb);
+  DKS_CK(launch_geometry(bbox, sl.stride / sizeof(double), sl.geo(), sl.stride, ga, bs, cnt, batch, st));
+  DKS_CK(launch_zero(sl.base + p->s_r3, sl.stride, p->bytes_W, batch, st));
+  DKS_CK(launch_deposit<T>(X, Y, Z, bs, batch, sl.base + p->s_r3, sl.stride / sizeof(T), sl.geo(), sl.stride,
+                           p->md, cnt, st));
+  return DKS_OK;
+}
+
+template <typename T>
+dks_status solve_particles_t(const dks_poisson_plan_s* p, int batch, const Slots& sl, const PtrBatch& X,
+                             const PtrBatch& Y, const PtrBatch& Z, const PtrBatch& EX, const PtrBatch& EY,
+                             const PtrBatch& EZ, const PtrBatch& PHI, const BatchScalars& bs,
+                             const PtrBatch& cnt, hipStream_t st) {
+  dks_status r = deposit_stage<T>(p, batch, sl, X, Y, Z, bs, cnt, st);
+  if (r != DKS_OK) return r;
+  r = convolve<T>(p, sl.base + p->s_r3, sl.stride / sizeof(T), batch, sl, PHI, st);
+  if (r != DKS_OK) return r;
+  const size_t rstride = sl.stride / sizeof(T);
+  DKS_CK((launch_gradient<T, true>(sl.base + p->s_r3, rstride, sl.base + p->s_r1, rstride, sl.geo(), sl.stride,
+                                   p->md, batch, st)));
+  DKS_CK((launch_gather<T, true>(sl.base + p->s_r1, rstride, X, Y, Z, EX, EY, EZ, bs, batch, sl.geo(), sl.stride,
+                                 p->md, st)));
+  return DKS_OK;
+}
+
+template <typename T>
+dks_status prepare_t(dks_poisson_plan_s* p, hipStream_t st) {
+  const size_t c = p->csize;
+  (void)c;
+  const FFTPlanHost* plans[4] = {&p->px, &p->py, &p->pz, &p->pzi};
+  const size_t offs[4] = {p->tw_px, p->tw_py, p->tw_pz, p->tw_pzi};
+  for (int i = 0; i < 4; ++i) {
+    const FFTPlan& f = plans[i]->dev;
+    for (int q = 1; q < f.npass; ++q)
+      DKS_CK(launch_twiddle_pass<T>(p->ws + offs[i] + (size_t)f.tw_off[q] * p->csize, f.Ns[q], f.R[q], st));
+  }
+  DKS_CK(launch_twiddle_line<T>(p->ws + p->tw_post, 2 * p->n[0], p->n[0] + 1, st));
+  FFTPlan four[4];
+  for (int i = 0; i < 4; ++i) four[i] = planref(p, i).host;
+  DKS_CK(launch_store_plans(four, reinterpret_cast<FFTPlan*>(p->ws + p->off_plans), st));
+  char* slot = p->ws + p->off_slot;
+  double* g1 = reinterpret_cast<double*>(slot + p->s_r1);
+  double* g2 = reinterpret_cast<double*>(slot + p->s_r2);
+  double* cosm = reinterpret_cast<double*>(slot + p->s_r3);
+  double* cos_axis[3];
+  cos_axis[0] = cosm;
+  cos_axis[1] = cos_axis[0] + (size_t)(p->n[0] + 1) * (p->n[0] + 1);
+  cos_axis[2] = cos_axis[1] + (size_t)(p->n[1] + 1) * (p->n[1] + 1);
+  const double hg[3] = {p->fitted ? 1.0 : p->h[0], p->fitted ? 1.0 : p->h[1], p->fitted ? 1.0 : p->h[2]};
+  const GLBands gl = make_bands();
+  DKS_CK(launch_igf_octant(g1, p->n, hg, gl, st));
+  for (int d = 0; d < 3; ++d) DKS_CK(launch_cos_matrix(cos_axis[d], p->n[d], st));
+  DKS_CK(launch_apply_axis(g1, g2, cos_axis[0], p->n, 0, st));
+  DKS_CK(launch_apply_axis(g2, g1, cos_axis[1], p->n, 1, st));
+  DKS_CK(launch_apply_axis(g1, g2, cos_axis[2], p->n, 2, st));
+  const double inv_ntot = 1.0 / ((double)(2 * p->n[0]) * (double)(2 * p->n[1]) * (double)(2 * p->n[2]));
+  DKS_CK(launch_green_pack<T>(g2, p->ws + p->off_green, p->n, p->md.cs, inv_ntot, st));
+  if (!p->fitted) {
+    BatchScalars bs;
+    std::memset(&bs, 0, sizeof(bs));
+    PtrBatch cnt;
+    std::memset(&cnt, 0, sizeof(cnt));
+    const GeoArgs ga = geo_args(p, 0, 0);
+    DKS_CK(launch_geometry(nullptr, 0, reinterpret_cast<Geometry*>(slot), 0, ga, bs, cnt, 1, st));
+  }
+  return DKS_OK;
+}
+
+bool ws_ready(const dks_poisson_plan_s* p) { return p->ws != nullptr && p->ws_bytes >= p->ws_total; }
+
+PtrBatch one(const void* v) {
+  PtrBatch b;
+  std::memset(&b, 0, sizeof(b));
+  b.p[0] = const_cast<void*>(v);
+  return b;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* dks_status_string(dks_status s) {
+  switch (s) {
+    case DKS_OK: return "success";
+    case DKS_EINVAL: return "invalid argument";
+    case DKS_EUNSUPPORTED: return "unsupported mesh size (each 2n must be 2^a 3^b and <= 4096)";
+    case DKS_ENOMEM: return "host allocation failed";
+    case DKS_EHIP: return "HIP runtime error";
+    case DKS_EWORKSPACE: return "workspace missing, too small or misaligned";
+    case DKS_ESTATE: return "call out of order for this plan";
+  }
+  return "unknown status";
+}
+
+dks_status dks_poisson_plan(int nx, int ny, int nz, double hx, double hy, double hz, dks_dtype dtype,
+                            dks_poisson_plan_t* out) {
+  if (!out) return DKS_EINVAL;
+  *out = nullptr;
+  if (dtype != DKS_F32 && dtype != DKS_F64) return DKS_EINVAL;
+  const bool fitted = (hx == 0.0 && hy == 0.0 && hz == 0.0);
+  const double hs[3] = {hx, hy, hz};
+  if (!fitted)
+    for (double h : hs)
+      if (!(h > 0.0) || !std::isfinite(h)) return DKS_EINVAL;
+  const int ns[3] = {nx, ny, nz};
+  for (int n : ns) {
+    if (n < (fitted ? 4 : 2)) return DKS_EINVAL;
+    if (n > kMaxLength / 2 || !factor23(2 * n)) return DKS_EUNSUPPORTED;
+  }
+  dks_poisson_plan_s* p = new (std::nothrow) dks_poisson_plan_s;
+  if (!p) return DKS_ENOMEM;
+  std::memset(p, 0, sizeof(*p));
+  for (int d = 0; d < 3; ++d) {
+    p->n[d] = ns[d];
+    p->h[d] = fitted ? 1.0 : hs[d];
+    p->origin[d] = fitted ? 0.0 : -0.5 * (ns[d] - 1) * hs[d];
+  }
+  p->fitted = fitted;
+  p->dtype = dtype;
+  p->rsize = dtype == DKS_F32 ? sizeof(float) : sizeof(double);
+  p->csize = 2 * p->rsize;
+  try {
+    layout(p);
+  } catch (...) {
+    delete p;
+    return DKS_ENOMEM;
+  }
+  *out = p;
+  return DKS_OK;
+}
+
+dks_status dks_poisson_set_origin(dks_poisson_plan_t p, double x0, double y0, double z0) {
+  if (!p) return DKS_EINVAL;
+  if (p->fitted) return DKS_ESTATE;
+  if (!std::isfinite(x0) || !std::isfinite(y0) || !std::isfinite(z0)) return DKS_EINVAL;
+  p->origin[0] = x0;
+  p->origin[1] = y0;
+  p->origin[2] = z0;
+  return DKS_OK;
+}
+
+dks_status dks_poisson_workspace_bytes(dks_poisson_plan_t p, size_t* bytes) {
+  if (!p || !bytes) return DKS_EINVAL;
+  *bytes = p->ws_total;
+  return DKS_OK;
+}
+
+dks_status dks_poisson_batch_scratch_bytes(dks_poisson_plan_t p, int batch, size_t* bytes) {
+  if (!p || !bytes || batch < 1 || batch > kMaxBatch) return DKS_EINVAL;
+  *bytes = (size_t)batch * p->slot_bytes;
+  return DKS_OK;
+}
+
+dks_status dks_poisson_set_workspace(dks_poisson_plan_t p, void* ws, size_t bytes) {
+  if (!p) return DKS_EINVAL;
+  if (!ws || bytes < p->ws_total || (reinterpret_cast<uintptr_t>(ws) & 255u)) return DKS_EWORKSPACE;
+  p->ws = static_cast<char*>(ws);
+  p->ws_bytes = bytes;
+  p->prepared = false;
+  p->has_geometry = false;
+  return DKS_OK;
+}
+
+dks_status dks_poisson_prepare(dks_poisson_plan_t p, dks_stream_t stream) {
+  if (!p) return DKS_EINVAL;
+  if (!ws_ready(p)) return DKS_EWORKSPACE;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const dks_status r = p->dtype == DKS_F32 ? prepare_t<float>(p, st) : prepare_t<double>(p, st);
+  if (r == DKS_OK) {
+    p->prepared = true;
+    p->has_geometry = !p->fitted;
+  }
+  return r;
+}
+
+dks_status dks_poisson_solve_rho(dks_poisson_plan_t p, const void* rho, void* phi, void* E_mesh,
+                                 dks_stream_t stream) {
+  if (!p || !rho || (!phi && !E_mesh)) return DKS_EINVAL;
+  if (p->fitted) return DKS_ESTATE;
+  if (!ws_ready(p)) return DKS_EWORKSPACE;
+  if (!p->prepared) return DKS_ESTATE;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  Slots sl{p->ws + p->off_slot, p->slot_bytes};
+  BatchScalars bs;
+  std::memset(&bs, 0, sizeof(bs));
+  PtrBatch none;
+  std::memset(&none, 0, sizeof(none));
+  const GeoArgs ga = geo_args(p, 0, 0);
+  if (launch_geometry(nullptr, 0, sl.geo(), sl.stride, ga, bs, none, 1, st) != hipSuccess) return DKS_EHIP;
+  dks_status r;
+  if (p->dtype == DKS_F32) {
+    r = convolve<float>(p, rho, 0, 1, sl, one(phi), st);
+    if (r == DKS_OK && E_mesh)
+      r = hip_status(launch_gradient<float, false>(sl.base + p->s_r3, 0, E_mesh, 0, sl.geo(), 0, p->md, 1, st));
+  } else {
+    r = convolve<double>(p, rho, 0, 1, sl, one(phi), st);
+    if (r == DKS_OK && E_mesh)
+      r = hip_status(launch_gradient<double, false>(sl.base + p->s_r3, 0, E_mesh, 0, sl.geo(), 0, p->md, 1, st));
+  }
+  if (r == DKS_OK) p->has_geometry = true;
+  return r;
+}
+
+dks_status dks_poisson_solve_particles(dks_poisson_plan_t p, const void* x, const void* y, const void* z,
+                                       int64_t np, double q, void* Ex, void* Ey, void* Ez, void* phi,
+                                       int64_t* n_outside, dks_stream_t stream) {
+  if (!p || np < 0 || !std::isfinite(q)) return DKS_EINVAL;
+  if (np > 0 && (!x || !y || !z || !Ex || !Ey || !Ez)) return DKS_EINVAL;
+  if (!ws_ready(p)) return DKS_EWORKSPACE;
+  if (!p->prepared) return DKS_ESTATE;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  Slots sl{p->ws + p->off_slot, p->slot_bytes};
+  BatchScalars bs;
+  std::memset(&bs, 0, sizeof(bs));
+  bs.np[0] = np;
+  bs.q[0] = q;
+  const dks_status r =
+      p->dtype == DKS_F32
+          ? solve_particles_t<float>(p, 1, sl, one(x), one(y), one(z), one(Ex), one(Ey), one(Ez), one(phi), bs,
+                                     one(n_outside), st)
+          : solve_particles_t<double>(p, 1, sl, one(x), one(y), one(z), one(Ex), one(Ey), one(Ez), one(phi), bs,
+                                      one(n_outside), st);
+  if (r == DKS_OK) p->has_geometry = true;
+  return r;
+}
+
+dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, const void* const* x,
+                                               const void* const* y, const void* const* z, const int64_t* np,
+                                               const double* q, void* const* Ex, void* const* Ey,
+                                               void* const* Ez, void* const* phi, void* scratch,
+                                               size_t scratch_bytes, int64_t* n_outside, dks_stream_t stream) {
+  if (!p || batch < 1 || batch > kMaxBatch || !x || !y || !z || !np || !q || !Ex || !Ey || !Ez)
+    return DKS_EINVAL;
+  if (!ws_ready(p)) return DKS_EWORKSPACE;
+  if (!p->prepared) return DKS_ESTATE;
+  if (!scratch || scratch_bytes < (size_t)batch * p->slot_bytes || (reinterpret_cast<uintptr_t>(scratch) & 255u))
+    return DKS_EWORKSPACE;
+  PtrBatch X, Y, Z, EX, EY, EZ, PHI, CNT;
+  BatchScalars bs;
+  std::memset(&X, 0, sizeof(X)); std::memset(&Y, 0, sizeof(Y)); std::memset(&Z, 0, sizeof(Z));
+  std::memset(&EX, 0, sizeof(EX)); std::memset(&EY, 0, sizeof(EY)); std::memset(&EZ, 0, sizeof(EZ));
+  std::memset(&PHI, 0, sizeof(PHI)); std::memset(&CNT, 0, sizeof(CNT)); std::memset(&bs, 0, sizeof(bs));
+  for (int b = 0; b < batch; ++b) {
+    if (np[b] < 0 || !std::isfinite(q[b])) return DKS_EINVAL;
+    if (np[b] > 0 && (!x[b] || !y[b] || !z[b] || !Ex[b] || !Ey[b] || !Ez[b])) return DKS_EINVAL;
+    X.p[b] = const_cast<void*>(x[b]);
+    Y.p[b] = const_cast<void*>(y[b]);
+    Z.p[b] = const_cast<void*>(z[b]);
+    EX.p[b] = Ex[b];
+    EY.p[b] = Ey[b];
+    EZ.p[b] = Ez[b];
+    PHI.p[b] = phi ? phi[b] : nullptr;
+    CNT.p[b] = n_outside ? n_outside + b : nullptr;
+    bs.np[b] = np[b];
+    bs.q[b] = q[b];
+  }
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  Slots sl{static_cast<char*>(scratch), p->slot_bytes};
+  return p->dtype == DKS_F32 ? solve_particles_t<float>(p, batch, sl, X, Y, Z, EX, EY, EZ, PHI, bs, CNT, st)
+                             : solve_particles_t<double>(p, batch, sl, X, Y, Z, EX, EY, EZ, PHI, bs, CNT, st);
+}
+
+dks_status dks_poisson_deposit(dks_poisson_plan_t p, const void* x, const void* y, const void* z, int64_t np,
+                               double q, void* rho, int64_t* n_outside, dks_stream_t stream) {
+  if (!p || !rho || np < 0 || !std::isfinite(q)) return DKS_EINVAL;
+  if (np > 0 && (!x || !y || !z)) return DKS_EINVAL;
+  if (!ws_ready(p)) return DKS_EWORKSPACE;
+  if (!p->prepared) return DKS_ESTATE;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  Slots sl{p->ws + p->off_slot, p->slot_bytes};
+  BatchScalars bs;
+  std::memset(&bs, 0, sizeof(bs));
+  bs.np[0] = np;
+  bs.q[0] = q;
+  const size_t nmesh = (size_t)p->n[0] * p->n[1] * p->n[2];
+  dks_status r;
+  if (p->dtype == DKS_F32) {
+    r = deposit_stage<float>(p, 1, sl, one(x), one(y), one(z), bs, one(n_outside), st);
+    if (r == DKS_OK) r = hip_status(launch_weights_to_density<float>(sl.base + p->s_r3, rho, nmesh, sl.geo(), q, st));
+  } else {
+    r = deposit_stage<double>(p, 1, sl, one(x), one(y), one(z), bs, one(n_outside), st);
+    if (r == DKS_OK) r = hip_status(launch_weights_to_density<double>(sl.base + p->s_r3, rho, nmesh, sl.geo(), q, st));
+  }
+  if (r == DKS_OK) p->has_geometry = true;
+  return r;
+}
+
+dks_status dks_poisson_gather(dks_poisson_plan_t p, const void* E_mesh, const void* x, const void* y,
+                              const void* z, int64_t np, void* Ex, void* Ey, void* Ez, dks_stream_t stream) {
+  if (!p || !E_mesh || np < 0) return DKS_EINVAL;
+  if (np > 0 && (!x || !y || !z || !Ex || !Ey || !Ez)) return DKS_EINVAL;
+  if (!ws_ready(p)) return DKS_EWORKSPACE;
+  if (!p->prepared) return DKS_ESTATE;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  Slots sl{p->ws + p->off_slot, p->slot_bytes};
+  if (!p->fitted) {
+    BatchScalars bs;
+    std::memset(&bs, 0, sizeof(bs));
+    PtrBatch none;
+    std::memset(&none, 0, sizeof(none));
+    const GeoArgs ga = geo_args(p, 0, 0);
+    if (launch_geometry(nullptr, 0, sl.geo(), sl.stride, ga, bs, none, 1, st) != hipSuccess) return DKS_EHIP;
+  } else if (!p->has_geometry) {
+    return DKS_ESTATE;
+  }
+  BatchScalars bs;
+  std::memset(&bs, 0, sizeof(bs));
+  bs.np[0] = np;
+  if (p->dtype == DKS_F32)
+    return hip_status(launch_gather<float, false>(E_mesh, 0, one(x), one(y), one(z), one(Ex), one(Ey), one(Ez), bs,
+                                                  1, sl.geo(), 0, p->md, st));
+  return hip_status(launch_gather<double, false>(E_mesh, 0, one(x), one(y), one(z), one(Ex), one(Ey), one(Ez), bs, 1,
+                                                 sl.geo(), 0, p->md, st));
+}
+
+dks_status dks_poisson_geometry(dks_poisson_plan_t p, dks_stream_t stream, double* h, double* origin) {
+  if (!p || !h || !origin) return DKS_EINVAL;
+  if (!ws_ready(p)) return DKS_EWORKSPACE;
+  if (!p->has_geometry) return DKS_ESTATE;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  Geometry g;
+  if (hipMemcpyAsync(&g, p->ws + p->off_slot, sizeof(Geometry), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return DKS_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return DKS_EHIP;
+  for (int d = 0; d < 3; ++d) {
+    h[d] = g.h[d];
+    origin[d] = g.origin[d];
+  }
+  return DKS_OK;
+}
+
+dks_status dks_poisson_destroy(dks_poisson_plan_t p) {
+  if (!p) return DKS_EINVAL;
+  delete p;
+  return DKS_OK;
+}
+
+}  // extern "C"

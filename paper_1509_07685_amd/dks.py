@@ -1,0 +1,299 @@
+"""ctypes binding of libdks_poisson.so (include/dks_poisson.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+The module-level functions carry the C names and signatures; `PoissonPlan`
+wraps a plan with torch-owned device memory (PyTorch supplies allocations
+and streams, nothing else).  Importing this module fails loudly if the
+library has not been built.
+"""
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdks_poisson.so")
+
+DKS_OK = 0
+DKS_EINVAL = -1
+DKS_EUNSUPPORTED = -2
+DKS_ENOMEM = -3
+DKS_EHIP = -4
+DKS_EWORKSPACE = -5
+DKS_ESTATE = -6
+DKS_F32 = 0
+DKS_F64 = 1
+
+EXPORTS = (
+    "dks_poisson_plan", "dks_poisson_set_origin", "dks_poisson_workspace_bytes",
+    "dks_poisson_batch_scratch_bytes", "dks_poisson_set_workspace", "dks_poisson_prepare",
+    "dks_poisson_solve_rho", "dks_poisson_solve_particles", "dks_poisson_solve_particles_batched",
+    "dks_poisson_deposit", "dks_poisson_gather", "dks_poisson_geometry", "dks_poisson_destroy",
+    "dks_status_string",
+)
+
+
+class DKSError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {dks_status_string(status)} ({status})")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1509_07685_amd.build`")
+    return ctypes.CDLL(LIB_PATH)
+
+
+_lib = _load()
+
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_i64 = ctypes.c_int64
+_d = ctypes.c_double
+_i = ctypes.c_int
+_PLAN = ctypes.c_void_p
+
+_SIGS = {
+    "dks_poisson_plan": (_i, [_i, _i, _i, _d, _d, _d, _i, ctypes.POINTER(_PLAN)]),
+    "dks_poisson_set_origin": (_i, [_PLAN, _d, _d, _d]),
+    "dks_poisson_workspace_bytes": (_i, [_PLAN, ctypes.POINTER(_sz)]),
+    "dks_poisson_batch_scratch_bytes": (_i, [_PLAN, _i, ctypes.POINTER(_sz)]),
+    "dks_poisson_set_workspace": (_i, [_PLAN, _vp, _sz]),
+    "dks_poisson_prepare": (_i, [_PLAN, _vp]),
+    "dks_poisson_solve_rho": (_i, [_PLAN, _vp, _vp, _vp, _vp]),
+    "dks_poisson_solve_particles": (_i, [_PLAN, _vp, _vp, _vp, _i64, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "dks_poisson_solve_particles_batched": (_i, [_PLAN, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                                 _vp, _sz, _vp, _vp]),
+    "dks_poisson_deposit": (_i, [_PLAN, _vp, _vp, _vp, _i64, _d, _vp, _vp, _vp]),
+    "dks_poisson_gather": (_i, [_PLAN, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
+    "dks_poisson_geometry": (_i, [_PLAN, _vp, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+    "dks_poisson_destroy": (_i, [_PLAN]),
+    "dks_status_string": (ctypes.c_char_p, [_i]),
+}
+
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def dks_status_string(status):
+    return _lib.dks_status_string(int(status)).decode()
+
+
+def _check(status, what):
+    if status != DKS_OK:
+        raise DKSError(status, what)
+
+
+def dks_poisson_plan(nx, ny, nz, hx, hy, hz, dtype):
+    plan = _PLAN()
+    _check(_lib.dks_poisson_plan(nx, ny, nz, hx, hy, hz, dtype, ctypes.byref(plan)), "dks_poisson_plan")
+    return plan
+
+
+def dks_poisson_set_origin(plan, x0, y0, z0):
+    _check(_lib.dks_poisson_set_origin(plan, x0, y0, z0), "dks_poisson_set_origin")
+
+
+def dks_poisson_workspace_bytes(plan):
+    out = _sz()
+    _check(_lib.dks_poisson_workspace_bytes(plan, ctypes.byref(out)), "dks_poisson_workspace_bytes")
+    return out.value
+
+
+def dks_poisson_batch_scratch_bytes(plan, batch):
+    out = _sz()
+    _check(_lib.dks_poisson_batch_scratch_bytes(plan, batch, ctypes.byref(out)),
+           "dks_poisson_batch_scratch_bytes")
+    return out.value
+
+
+def dks_poisson_set_workspace(plan, ptr, nbytes):
+    _check(_lib.dks_poisson_set_workspace(plan, ptr, nbytes), "dks_poisson_set_workspace")
+
+
+def dks_poisson_prepare(plan, stream):
+    _check(_lib.dks_poisson_prepare(plan, stream), "dks_poisson_prepare")
+
+
+def dks_poisson_solve_rho(plan, rho, phi, E_mesh, stream):
+    _check(_lib.dks_poisson_solve_rho(plan, rho, phi, E_mesh, stream), "dks_poisson_solve_rho")
+
+
+def dks_poisson_solve_particles(plan, x, y, z, np_, q, Ex, Ey, Ez, phi, n_outside, stream):
+    _check(_lib.dks_poisson_solve_particles(plan, x, y, z, np_, q, Ex, Ey, Ez, phi, n_outside, stream),
+           "dks_poisson_solve_particles")
+
+
+def _ptr_array(ptrs):
+    arr = (_vp * len(ptrs))(*[p or None for p in ptrs])
+    return arr
+
+
+def dks_poisson_solve_particles_batched(plan, batch, x, y, z, np_, q, Ex, Ey, Ez, phi, scratch,
+                                        scratch_bytes, n_outside, stream):
+    keep = [_ptr_array(a) for a in (x, y, z, Ex, Ey, Ez)]
+    phi_arr = _ptr_array(phi) if phi is not None else None
+    nps = (_i64 * batch)(*np_)
+    qs = (_d * batch)(*q)
+    st = _lib.dks_poisson_solve_particles_batched(
+        plan, batch, *[ctypes.cast(a, _vp) for a in keep[:3]], ctypes.cast(nps, _vp),
+        ctypes.cast(qs, _vp), *[ctypes.cast(a, _vp) for a in keep[3:]],
+        ctypes.cast(phi_arr, _vp) if phi_arr is not None else None, scratch, scratch_bytes, n_outside,
+        stream)
+    _check(st, "dks_poisson_solve_particles_batched")
+
+
+def dks_poisson_deposit(plan, x, y, z, np_, q, rho, n_outside, stream):
+    _check(_lib.dks_poisson_deposit(plan, x, y, z, np_, q, rho, n_outside, stream), "dks_poisson_deposit")
+
+
+def dks_poisson_gather(plan, E_mesh, x, y, z, np_, Ex, Ey, Ez, stream):
+    _check(_lib.dks_poisson_gather(plan, E_mesh, x, y, z, np_, Ex, Ey, Ez, stream), "dks_poisson_gather")
+
+
+def dks_poisson_geometry(plan, stream):
+    h = (_d * 3)()
+    o = (_d * 3)()
+    _check(_lib.dks_poisson_geometry(plan, stream, h, o), "dks_poisson_geometry")
+    return tuple(h), tuple(o)
+
+
+def dks_poisson_destroy(plan):
+    _check(_lib.dks_poisson_destroy(plan), "dks_poisson_destroy")
+
+
+# --------------------------------------------------------------------------
+# torch-facing convenience wrapper
+# --------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(dtype):
+    torch = _torch()
+    if dtype in ("f32", torch.float32):
+        return DKS_F32, torch.float32
+    if dtype in ("f64", torch.float64):
+        return DKS_F64, torch.float64
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class PoissonPlan:
+    """A plan plus its torch-allocated device workspace.
+
+    n = (nx, ny, nz) nodes; h = (hx, hy, hz) metres or None for the
+    particle-fitted cubic mesh; dtype "f32"/"f64" (or torch dtype).
+    """
+
+    def __init__(self, n, h=None, dtype="f32", device="cuda", stream=None, prepare=True):
+        torch = _torch()
+        self.n = tuple(int(v) for v in n)
+        self.fitted = h is None
+        self.h = (0.0, 0.0, 0.0) if h is None else tuple(float(v) for v in h)
+        self.code, self.dtype = _dtype_code(dtype)
+        self.device = torch.device(device)
+        self.handle = dks_poisson_plan(*self.n, *self.h, self.code)
+        self.workspace_bytes = dks_poisson_workspace_bytes(self.handle)
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        dks_poisson_set_workspace(self.handle, _ptr(self.workspace), self.workspace_bytes)
+        if prepare:
+            self.prepare(stream)
+
+    def prepare(self, stream=None):
+        dks_poisson_prepare(self.handle, _stream_handle(stream))
+
+    def set_origin(self, origin):
+        dks_poisson_set_origin(self.handle, *[float(v) for v in origin])
+
+    def mesh_shape(self):
+        nx, ny, nz = self.n
+        return (nz, ny, nx)
+
+    def _check_tensor(self, t, shape, name):
+        if t.dtype != self.dtype or not t.is_contiguous() or t.device.type != "cuda":
+            raise ValueError(f"{name} must be a contiguous {self.dtype} CUDA tensor")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+    def solve_rho(self, rho, want_phi=True, want_E=True, stream=None):
+        torch = _torch()
+        self._check_tensor(rho, self.mesh_shape(), "rho")
+        phi = torch.empty(self.mesh_shape(), dtype=self.dtype, device=rho.device) if want_phi else None
+        E = torch.empty((3,) + self.mesh_shape(), dtype=self.dtype, device=rho.device) if want_E else None
+        dks_poisson_solve_rho(self.handle, _ptr(rho), _ptr(phi), _ptr(E), _stream_handle(stream))
+        return phi, E
+
+    def solve_particles(self, x, y, z, q, want_phi=False, out=None, stream=None):
+        torch = _torch()
+        npart = x.numel()
+        for name, t in (("x", x), ("y", y), ("z", z)):
+            self._check_tensor(t, (npart,), name)
+        if out is None:
+            Ex, Ey, Ez = (torch.empty(npart, dtype=self.dtype, device=x.device) for _ in range(3))
+            cnt = torch.zeros(1, dtype=torch.int64, device=x.device)
+        else:
+            Ex, Ey, Ez, cnt = out
+        phi = torch.empty(self.mesh_shape(), dtype=self.dtype, device=x.device) if want_phi else None
+        dks_poisson_solve_particles(self.handle, _ptr(x), _ptr(y), _ptr(z), npart, float(q), _ptr(Ex),
+                                    _ptr(Ey), _ptr(Ez), _ptr(phi), _ptr(cnt), _stream_handle(stream))
+        return (Ex, Ey, Ez), phi, cnt
+
+    def deposit(self, x, y, z, q, stream=None):
+        torch = _torch()
+        npart = x.numel()
+        rho = torch.empty(self.mesh_shape(), dtype=self.dtype, device=x.device)
+        cnt = torch.zeros(1, dtype=torch.int64, device=x.device)
+        dks_poisson_deposit(self.handle, _ptr(x), _ptr(y), _ptr(z), npart, float(q), _ptr(rho), _ptr(cnt),
+                            _stream_handle(stream))
+        return rho, cnt
+
+    def gather(self, E_mesh, x, y, z, stream=None):
+        torch = _torch()
+        npart = x.numel()
+        self._check_tensor(E_mesh, (3,) + self.mesh_shape(), "E_mesh")
+        Ex, Ey, Ez = (torch.empty(npart, dtype=self.dtype, device=x.device) for _ in range(3))
+        dks_poisson_gather(self.handle, _ptr(E_mesh), _ptr(x), _ptr(y), _ptr(z), npart, _ptr(Ex), _ptr(Ey),
+                           _ptr(Ez), _stream_handle(stream))
+        return Ex, Ey, Ez
+
+    def geometry(self, stream=None):
+        return dks_poisson_geometry(self.handle, _stream_handle(stream))
+
+    def batch_scratch(self, batch):
+        torch = _torch()
+        nbytes = dks_poisson_batch_scratch_bytes(self.handle, batch)
+        return torch.empty(nbytes, dtype=torch.uint8, device=self.device), nbytes
+
+    def solve_particles_batched(self, xs, ys, zs, qs, scratch, outs, n_outside=None, phis=None, stream=None):
+        batch = len(xs)
+        buf, nbytes = scratch
+        dks_poisson_solve_particles_batched(
+            self.handle, batch, [t.data_ptr() for t in xs], [t.data_ptr() for t in ys],
+            [t.data_ptr() for t in zs], [t.numel() for t in xs], [float(q) for q in qs],
+            [o[0].data_ptr() for o in outs], [o[1].data_ptr() for o in outs], [o[2].data_ptr() for o in outs],
+            None if phis is None else [p.data_ptr() if p is not None else 0 for p in phis],
+            _ptr(buf), nbytes, _ptr(n_outside), _stream_handle(stream))
+
+    def close(self):
+        if self.handle is not None:
+            dks_poisson_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,145 @@
+"""C ABI contract checks that need no GPU: the library loads, exports every
+entry point the header declares, and rejects bad arguments on the host
+before any device work."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dks_poisson.h")
+LIB = os.path.join(ROOT, "paper_1509_07685_amd", "libdks_poisson.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libdks_poisson.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dks_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("dks_poisson_plan", "dks_poisson_solve_rho", "dks_poisson_solve_particles",
+                     "dks_poisson_solve_particles_batched", "dks_poisson_prepare", "dks_poisson_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header():
+    from paper_1509_07685_amd import dks
+    assert sorted(dks.EXPORTS) == declared_functions()
+    for name in declared_functions():
+        assert callable(getattr(dks, name))
+
+
+@pytest.fixture()
+def dks():
+    from paper_1509_07685_amd import dks as mod
+    return mod
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+def test_plan_validation(dks):
+    lib = dks._lib
+    plan = ctypes.c_void_p()
+    # good plans
+    assert lib.dks_poisson_plan(32, 32, 32, 1e-4, 1e-4, 1e-4, dks.DKS_F64, ctypes.byref(plan)) == dks.DKS_OK
+    assert lib.dks_poisson_destroy(plan) == dks.DKS_OK
+    assert lib.dks_poisson_plan(96, 96, 192, 0.0, 0.0, 0.0, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_OK
+    assert lib.dks_poisson_destroy(plan) == dks.DKS_OK
+    # 2n = 2^a 3^b only
+    assert lib.dks_poisson_plan(5, 8, 8, 1.0, 1.0, 1.0, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_EUNSUPPORTED
+    assert lib.dks_poisson_plan(8, 8, 2049, 1.0, 1.0, 1.0, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_EUNSUPPORTED
+    # sizes, spacings, dtype, output pointer
+    assert lib.dks_poisson_plan(1, 8, 8, 1.0, 1.0, 1.0, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_EINVAL
+    assert lib.dks_poisson_plan(3, 8, 8, 0.0, 0.0, 0.0, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_EINVAL
+    assert lib.dks_poisson_plan(8, 8, 8, 1.0, 0.0, 1.0, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_EINVAL
+    assert lib.dks_poisson_plan(8, 8, 8, -1.0, 1.0, 1.0, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_EINVAL
+    assert lib.dks_poisson_plan(8, 8, 8, float("nan"), 1.0, 1.0, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_EINVAL
+    assert lib.dks_poisson_plan(8, 8, 8, 1.0, 1.0, 1.0, 7, ctypes.byref(plan)) == dks.DKS_EINVAL
+    assert lib.dks_poisson_plan(8, 8, 8, 1.0, 1.0, 1.0, dks.DKS_F32, None) == dks.DKS_EINVAL
+
+
+def test_workspace_and_state_checks(dks):
+    lib = dks._lib
+    plan = dks.dks_poisson_plan(16, 12, 9, 1e-4, 1e-4, 2e-4, dks.DKS_F32)
+    try:
+        nbytes = dks.dks_poisson_workspace_bytes(plan)
+        assert nbytes > 0
+        per = dks.dks_poisson_batch_scratch_bytes(plan, 1)
+        assert dks.dks_poisson_batch_scratch_bytes(plan, 4) == 4 * per
+        assert per < nbytes
+        assert lib.dks_poisson_batch_scratch_bytes(plan, 0, ctypes.byref(ctypes.c_size_t())) == dks.DKS_EINVAL
+        assert lib.dks_poisson_batch_scratch_bytes(plan, 17, ctypes.byref(ctypes.c_size_t())) == dks.DKS_EINVAL
+        # no workspace yet
+        fake = ctypes.c_void_p(0x100000)
+        assert lib.dks_poisson_solve_rho(plan, fake, fake, None, None) == dks.DKS_EWORKSPACE
+        assert lib.dks_poisson_prepare(plan, None) == dks.DKS_EWORKSPACE
+        # too small, misaligned, null
+        assert lib.dks_poisson_set_workspace(plan, fake, nbytes - 1) == dks.DKS_EWORKSPACE
+        assert lib.dks_poisson_set_workspace(plan, ctypes.c_void_p(0x100010), nbytes) == dks.DKS_EWORKSPACE
+        assert lib.dks_poisson_set_workspace(plan, None, nbytes) == dks.DKS_EWORKSPACE
+        # attached but not prepared: solves are refused before touching the device
+        assert lib.dks_poisson_set_workspace(plan, fake, nbytes) == dks.DKS_OK
+        assert lib.dks_poisson_solve_rho(plan, fake, fake, None, None) == dks.DKS_ESTATE
+        assert lib.dks_poisson_solve_particles(plan, fake, fake, fake, 10, 1e-15, fake, fake, fake,
+                                               None, None, None) == dks.DKS_ESTATE
+        assert lib.dks_poisson_geometry(plan, None, (ctypes.c_double * 3)(),
+                                        (ctypes.c_double * 3)()) == dks.DKS_ESTATE
+        # argument errors come first
+        assert lib.dks_poisson_solve_rho(plan, None, fake, None, None) == dks.DKS_EINVAL
+        assert lib.dks_poisson_solve_rho(plan, fake, None, None, None) == dks.DKS_EINVAL
+        assert lib.dks_poisson_solve_particles(plan, fake, fake, fake, -1, 1e-15, fake, fake, fake,
+                                               None, None, None) == dks.DKS_EINVAL
+        assert lib.dks_poisson_solve_particles(plan, None, fake, fake, 10, 1e-15, fake, fake, fake,
+                                               None, None, None) == dks.DKS_EINVAL
+        assert lib.dks_poisson_solve_particles(plan, fake, fake, fake, 1, float("inf"), fake, fake, fake,
+                                               None, None, None) == dks.DKS_EINVAL
+        assert lib.dks_poisson_set_origin(plan, 0.0, 1.0, float("nan")) == dks.DKS_EINVAL
+        assert lib.dks_poisson_set_origin(plan, 0.0, 1.0, 2.0) == dks.DKS_OK
+    finally:
+        dks.dks_poisson_destroy(plan)
+
+
+def test_fitted_plan_rejects_mesh_density_and_origin(dks):
+    lib = dks._lib
+    plan = dks.dks_poisson_plan(16, 16, 16, 0.0, 0.0, 0.0, dks.DKS_F64)
+    try:
+        assert lib.dks_poisson_set_origin(plan, 0.0, 0.0, 0.0) == dks.DKS_ESTATE
+        fake = ctypes.c_void_p(0x100000)
+        assert lib.dks_poisson_solve_rho(plan, fake, fake, None, None) == dks.DKS_ESTATE
+    finally:
+        dks.dks_poisson_destroy(plan)
+
+
+def test_status_strings(dks):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert dks.dks_status_string(code)
+    assert dks.dks_status_string(12345) == "unknown status"
+    with pytest.raises(dks.DKSError):
+        dks.dks_poisson_plan(5, 5, 5, 1.0, 1.0, 1.0, dks.DKS_F32)
+
+
+def test_workspace_grows_with_mesh_and_dtype(dks):
+    sizes = {}
+    for n in (16, 32, 64):
+        for code in (dks.DKS_F32, dks.DKS_F64):
+            p = dks.dks_poisson_plan(n, n, n, 1.0, 1.0, 1.0, code)
+            sizes[(n, code)] = dks.dks_poisson_workspace_bytes(p)
+            dks.dks_poisson_destroy(p)
+    assert sizes[(32, dks.DKS_F32)] > sizes[(16, dks.DKS_F32)]
+    assert sizes[(64, dks.DKS_F64)] > sizes[(64, dks.DKS_F32)]
+    # about 27 sizeof(real) x 8 per node for the doubled-grid intermediates, well under 64x
+    assert sizes[(64, dks.DKS_F32)] < 64 * 4 * 64 ** 3 * 8

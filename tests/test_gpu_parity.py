@@ -1,0 +1,279 @@
+"""Parity of the HIP path with the FP64 oracle, through the C ABI.
+
+Tolerances (relative L2 over the compared set): 1e-12 for the FP64 path and
+2e-5 for the FP32 path, for phi and for E.  Integer results (out-of-mesh
+counts) must match exactly; the fitted mesh geometry (FP64 on both sides,
+same formula) must match to the last bit.  Inputs are seeded and synthetic;
+FP32 runs feed the oracle the same FP32 values, and both sides take the
+in/out-of-mesh decision in FP32.
+"""
+
+import functools
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import poisson_oracle as orc  # noqa: E402
+from paper_1509_07685_amd import workloads as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 2e-5, "f64": 1e-12}
+NP_DT = {"f32": np.float32, "f64": np.float64}
+
+
+def dks():
+    from paper_1509_07685_amd import dks as mod
+    return mod
+
+
+def tdt(dt):
+    return torch.float32 if dt == "f32" else torch.float64
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(a, dt):
+    return torch.from_numpy(np.ascontiguousarray(a.astype(NP_DT[dt]))).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+# --------------------------------------------------------------------------
+# mesh density -> potential and field
+# --------------------------------------------------------------------------
+
+RHO_CASES = [
+    ((2, 2, 2), (1e-4, 1e-4, 1e-4)),      # smallest mesh
+    ((3, 4, 6), (1.0, 2.0, 0.5)),         # odd, single-radix-3 x transform
+    ((8, 8, 8), (1e-4, 1e-4, 1e-4)),
+    ((12, 12, 12), (1e-4, 1e-4, 1e-4)),   # radix-3 passes
+    ((6, 8, 10), (5e-5, 5e-5, 2e-4)),     # anisotropic cells
+    ((32, 24, 18), (1e-4, 2e-4, 1.5e-4)),
+    ((48, 36, 27), (1e-4, 1e-4, 1e-4)),   # several column tiles, ragged tails, 3^3 z
+    ((64, 64, 64), (1e-4, 1e-4, 1e-4)),
+]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n,h", RHO_CASES)
+def test_solve_rho_matches_oracle(n, h, dt):
+    g = np.random.default_rng(100 + n[0] + 7 * n[1] + 13 * n[2])
+    rho = g.standard_normal((n[2], n[1], n[0])).astype(NP_DT[dt])
+    plan = dks().PoissonPlan(n, h, dt)
+    phi, E = plan.solve_rho(dev(rho, dt))
+    phi_ref, E_ref = orc.solve_rho(rho.astype(np.float64), h)
+    assert rel_l2(host(phi), phi_ref[1:-1, 1:-1, 1:-1]) <= TOL[dt]
+    assert rel_l2(host(E), E_ref) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_solve_rho_phi_only_and_field_only(dt):
+    n, h = (16, 18, 24), (1e-4, 1e-4, 1e-4)
+    rho = np.random.default_rng(5).random((24, 18, 16))
+    plan = dks().PoissonPlan(n, h, dt)
+    phi, E = plan.solve_rho(dev(rho, dt), want_phi=True, want_E=False)
+    assert E is None
+    phi2, E2 = plan.solve_rho(dev(rho, dt), want_phi=False, want_E=True)
+    assert phi2 is None
+    phi_ref, E_ref = orc.solve_rho(rho, h)
+    assert rel_l2(host(phi), phi_ref[1:-1, 1:-1, 1:-1]) <= TOL[dt]
+    assert rel_l2(host(E2), E_ref) <= TOL[dt]
+
+
+def test_solve_rho_moved_origin_is_translation_invariant():
+    n, h = (16, 16, 16), (1e-4, 1e-4, 1e-4)
+    rho = np.random.default_rng(9).random((16, 16, 16))
+    plan = dks().PoissonPlan(n, h, "f64")
+    phi0, _ = plan.solve_rho(dev(rho, "f64"))
+    plan.set_origin((1.0, -2.0, 3.0))
+    phi1, _ = plan.solve_rho(dev(rho, "f64"))
+    assert plan.geometry()[1] == (1.0, -2.0, 3.0)
+    np.testing.assert_array_equal(host(phi0), host(phi1))
+
+
+# --------------------------------------------------------------------------
+# deposit and gather alone
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_deposit_matches_oracle_explicit_mesh(dt):
+    cfg = wl.SMALL_GAUSSIAN
+    x, y, z = wl.particles_for(cfg, dtype=dt)
+    plan = dks().PoissonPlan(cfg.n, cfg.h, dt)
+    rho, cnt = plan.deposit(dev(x, dt), dev(y, dt), dev(z, dt), cfg.charge_per_particle)
+    origin = orc.centred_origin(cfg.n, cfg.h)
+    Q, n_out = orc.deposit_cic(x, y, z, cfg.charge_per_particle, cfg.n, cfg.h, origin, NP_DT[dt])
+    V = cfg.h[0] * cfg.h[1] * cfg.h[2]
+    assert int(host(cnt)[0]) == n_out
+    assert rel_l2(host(rho), Q / V) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_deposit_matches_oracle_fitted_mesh(dt):
+    cfg = wl.UNIFORM_SPHERE
+    x, y, z = wl.particles_for(cfg, dtype=dt)
+    plan = dks().PoissonPlan(cfg.n, None, dt)
+    rho, cnt = plan.deposit(dev(x, dt), dev(y, dt), dev(z, dt), cfg.charge_per_particle)
+    hc, origin = orc.fit_mesh(x, y, z, cfg.n)
+    hg, og = plan.geometry()
+    assert hg == (hc, hc, hc)
+    assert og == origin
+    Q, n_out = orc.deposit_cic(x, y, z, cfg.charge_per_particle, cfg.n, (hc,) * 3, origin, NP_DT[dt])
+    assert n_out == 0 and int(host(cnt)[0]) == 0
+    assert rel_l2(host(rho), Q / hc ** 3) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_gather_matches_oracle(dt):
+    n, h = (20, 18, 27), (1e-4, 1.2e-4, 0.8e-4)
+    origin = orc.centred_origin(n, h)
+    g = np.random.default_rng(21)
+    E = g.standard_normal((3, n[2], n[1], n[0]))
+    num = 50_000
+    # include particles outside the mesh and exactly on the last node
+    x = g.uniform(origin[0] - 2 * h[0], origin[0] + (n[0] + 1) * h[0], num)
+    y = g.uniform(origin[1] - 2 * h[1], origin[1] + (n[1] + 1) * h[1], num)
+    z = g.uniform(origin[2] - 2 * h[2], origin[2] + (n[2] + 1) * h[2], num)
+    x[:3] = origin[0] + (n[0] - 1) * h[0]
+    x, y, z = (a.astype(NP_DT[dt]) for a in (x, y, z))
+    plan = dks().PoissonPlan(n, h, dt)
+    out = plan.gather(dev(E, dt), dev(x, dt), dev(y, dt), dev(z, dt))
+    ref = orc.gather_cic(E.astype(NP_DT[dt]).astype(np.float64), x, y, z, n, h, origin, NP_DT[dt])
+    got = np.stack([host(t) for t in out])
+    assert rel_l2(got, ref) <= TOL[dt]
+    outside = ~orc.cic_stencil(x, y, z, n, h, origin, NP_DT[dt])[0]
+    assert outside.sum() > 1000
+    assert np.all(got[:, outside] == 0.0)
+
+
+# --------------------------------------------------------------------------
+# full particle step
+# --------------------------------------------------------------------------
+
+def _full_step(cfg, dt, num=None):
+    x, y, z = wl.particles_for(cfg, dtype=dt, num=num)
+    num = x.size
+    q = wl.TOTAL_CHARGE / num
+    plan = dks().PoissonPlan(cfg.n, cfg.h, dt)
+    (Ex, Ey, Ez), phi, cnt = plan.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), q, want_phi=True)
+    ref = orc.solve_particles(x, y, z, q, cfg.n, cfg.h, dtype=NP_DT[dt])
+    got_E = np.stack([host(Ex), host(Ey), host(Ez)])
+    return plan, host(phi), got_E, int(host(cnt)[0]), ref
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_small_gaussian_full_step(dt):
+    plan, phi, E, n_out, ref = _full_step(wl.SMALL_GAUSSIAN, dt)
+    assert n_out == ref["n_outside"] > 0
+    assert rel_l2(phi, ref["phi_ext"][1:-1, 1:-1, 1:-1]) <= TOL[dt]
+    assert rel_l2(E, ref["E"]) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_uniform_sphere_full_step(dt):
+    cfg = wl.UNIFORM_SPHERE
+    plan, phi, E, n_out, ref = _full_step(cfg, dt)
+    assert n_out == 0
+    assert plan.geometry()[0] == ref["h"]
+    assert rel_l2(phi, ref["phi_ext"][1:-1, 1:-1, 1:-1]) <= TOL[dt]
+    assert rel_l2(E, ref["E"]) <= TOL[dt]
+    # and against the analytic uniform sphere (shot-noise limited)
+    R, Q = 2.5e-3, wl.TOTAL_CHARGE
+    h = ref["h"][0]
+    o = ref["origin"]
+    c = [o[d] + np.arange(cfg.n[d]) * h for d in range(3)]
+    Zg, Yg, Xg = np.meshgrid(c[2], c[1], c[0], indexing="ij")
+    r = np.sqrt(Xg ** 2 + Yg ** 2 + Zg ** 2)
+    eps0 = 8.8541878128e-12
+    rho0 = Q / (4.0 / 3.0 * math.pi * R ** 3)
+    ana = np.where(r < R, rho0 * (3 * R * R - r * r) / (6 * eps0), Q / (4 * math.pi * eps0 * np.maximum(r, 1e-30)))
+    assert rel_l2(phi, ana) < 3e-3
+
+
+def test_elongated_bunch_full_step_f32():
+    """128 x 128 x 256 mesh, anisotropic cells, 1e7 particles, FP32 bulk with the
+    FP64-built Green's spectrum: the whole deposit-solve-gather step."""
+    plan, phi, E, n_out, ref = _full_step(wl.ELONGATED, "f32")
+    assert n_out == ref["n_outside"]
+    assert 0.005 < n_out / wl.ELONGATED.num_particles < 0.03
+    assert rel_l2(phi, ref["phi_ext"][1:-1, 1:-1, 1:-1]) <= TOL["f32"]
+    assert rel_l2(E, ref["E"]) <= TOL["f32"]
+
+
+def test_empty_and_single_particle():
+    d = dks()
+    plan = d.PoissonPlan((8, 8, 8), None, "f64")
+    empty = torch.empty(0, dtype=torch.float64, device="cuda")
+    (Ex, Ey, Ez), phi, cnt = plan.solve_particles(empty, empty, empty, 1e-12, want_phi=True)
+    assert host(phi).max() == 0.0 and host(phi).min() == 0.0
+    assert int(host(cnt)[0]) == 0
+    assert plan.geometry()[0] == (1.0, 1.0, 1.0)
+    one = torch.tensor([1e-3], dtype=torch.float64, device="cuda")
+    (Ex, Ey, Ez), phi, cnt = plan.solve_particles(one, one, one, 1e-12, want_phi=True)
+    ref = orc.solve_particles(np.array([1e-3]), np.array([1e-3]), np.array([1e-3]), 1e-12, (8, 8, 8))
+    assert rel_l2(host(phi), ref["phi_ext"][1:-1, 1:-1, 1:-1]) <= 1e-12
+    # a lone particle on a node feels no field from itself
+    assert abs(float(host(Ex)[0])) <= 1e-12 * np.abs(ref["E_mesh"]).max()
+
+
+# --------------------------------------------------------------------------
+# the 256^3 workload at full size
+# --------------------------------------------------------------------------
+
+def test_halo_gaussian_full_size_properties():
+    """1e8 particles on the fitted 256^3 mesh in FP32, in the launch
+    configuration the benchmark times: mesh fit identical to the oracle's,
+    nobody outside, charge conserved, and the total self-force of the bunch
+    vanishes (CIC deposit/gather with a symmetric Green's function and
+    antisymmetric central differences conserve momentum)."""
+    cfg = wl.HALO_GAUSSIAN
+    x, y, z = wl.particles_for(cfg, dtype="f32")
+    q = cfg.charge_per_particle
+    plan = dks().PoissonPlan(cfg.n, None, "f32")
+    tx, ty, tz = dev(x, "f32"), dev(y, "f32"), dev(z, "f32")
+    (Ex, Ey, Ez), _, cnt = plan.solve_particles(tx, ty, tz, q)
+    hc, origin = orc.fit_mesh(x, y, z, cfg.n)
+    hg, og = plan.geometry()
+    assert hg == (hc, hc, hc) and og == origin
+    assert int(host(cnt)[0]) == 0
+    rho, _ = plan.deposit(tx, ty, tz, q)
+    total = float(torch.sum(rho.double()).item()) * hc ** 3
+    assert total == pytest.approx(wl.TOTAL_CHARGE, rel=2e-5)
+    for comp in (Ex, Ey, Ez):
+        c = comp.double()
+        assert abs(float(c.sum())) <= 2e-5 * float(c.abs().sum())
+
+
+def test_full_size_mesh_solve_sampled_f32():
+    """The 256^3 FP32 convolution (the benchmark's dominant kernels, same
+    launch configuration) on a sparse random density: phi at sampled nodes,
+    ghost nodes included, against the oracle's literal sum over the sources."""
+    n, h = (256, 256, 256), (1e-5, 1e-5, 1e-5)
+    g = np.random.default_rng(44)
+    idx = g.integers(0, 256, (2000, 3))
+    vals = g.standard_normal(2000)
+    rho = np.zeros((256, 256, 256), dtype=np.float32)
+    rho[idx[:, 2], idx[:, 1], idx[:, 0]] = vals.astype(np.float32)
+    plan = dks().PoissonPlan(n, h, "f32")
+    phi, E = plan.solve_rho(dev(rho, "f32"))
+    phi_h = host(phi)
+    src = np.argwhere(rho != 0)     # (k, j, i)
+    w = rho[src[:, 0], src[:, 1], src[:, 2]].astype(np.float64)
+    targets = np.concatenate([g.integers(0, 256, (48, 3)), [[0, 0, 0], [255, 255, 255], [0, 255, 128]]])
+    got, want = [], []
+    for (k, j, i) in targets:
+        G = orc.igf_at(i - src[:, 2], j - src[:, 1], k - src[:, 0], h)
+        want.append(orc.COULOMB_K * float(np.sum(w * G)))
+        got.append(phi_h[k, j, i])
+    assert rel_l2(got, want) <= TOL["f32"]
