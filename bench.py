@@ -1,0 +1,216 @@
+"""Benchmark of the free-space PM Poisson step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+
+Workload (one "step" = the whole hot path once): the 256^3 particle-fitted
+mesh (512^3 doubled grid) with 1e8 particles from a 3-D Gaussian plus a 10%
+uniform halo out to 5 sigma, FP32 bulk path with the FP64-built Green's
+spectrum: mesh fit, CIC deposit, the five pruned FFT passes with the fused
+Green's multiply, central-difference field and CIC gather.  Inputs are
+synthetic, seeded, resident in HBM before the clock starts.
+
+Prints one JSON line: value = mesh points per second of the full step
+(256^3 x steps / time).  It also carries the per-kernel breakdown measured
+with HIP events on the library's stream, the roofline of the dominant
+kernel, the mesh-only solve rates in FP32 and FP64, the CPU oracle timed on
+a bounded sample of the same workload, and, when the serving loop is
+available, the mixed-size request stream.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
+
+
+def algorithmic_bytes(n, num_particles, s, kernel):
+    """Bytes a kernel must move per launch (compulsory traffic of the design)."""
+    nx, ny, nz = n
+    c = 2 * s
+    mesh = nx * ny * nz
+    model = {
+        "bbox": 3 * s * num_particles,
+        "geometry": 0,
+        "zero_mesh": s * mesh,
+        "deposit": 3 * s * num_particles + s * mesh,
+        "fft_x_fwd": s * mesh + c * (nx + 1) * ny * nz,
+        "fft_y_fwd": c * (nx + 1) * ny * nz + c * (nx + 1) * 2 * ny * nz,
+        "fft_z_conv": (c * (nx + 1) * 2 * ny * nz + s * (nx + 1) * (ny + 1) * (nz + 1)
+                       + c * (nx + 1) * 2 * ny * (nz + 2)),
+        "fft_y_inv": c * (nx + 1) * 2 * ny * (nz + 2) + c * (nx + 1) * (ny + 2) * (nz + 2),
+        "fft_x_inv": c * (nx + 1) * (ny + 2) * (nz + 2) + s * (nx + 2) * (ny + 2) * (nz + 2),
+        "gradient": s * (nx + 2) * (ny + 2) * (nz + 2) + 3 * s * mesh,
+        "gather": 3 * s * num_particles + 3 * s * mesh + 3 * s * num_particles,
+    }
+    return model[kernel]
+
+
+def conv_bytes(n, s):
+    return sum(algorithmic_bytes(n, 0, s, k) for k in
+               ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv"))
+
+
+def time_loop(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def cpu_baseline():
+    """The oracle as it stands on a bounded sample: the full particle step on a
+    128^3 fitted mesh with 1e6 particles of the same halo-Gaussian bunch, twice."""
+    import numpy as np
+    from oracle import poisson_oracle as orc
+    from paper_1509_07685_amd import workloads as wl
+    x, y, z = wl.halo_gaussian(1_000_000, 1e-3, 0.1, 5e-3, 4, np.float32)
+    reps, n = 2, (128, 128, 128)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        orc.solve_particles(x, y, z, wl.TOTAL_CHARGE / x.size, n, dtype=np.float32)
+    dt = (time.perf_counter() - t0) / reps
+    return {"value": n[0] * n[1] * n[2] / dt, "unit": "mesh-pts/s", "cores": 1, "kind": "oracle",
+            "sample": "FP64 numpy oracle, full particle step (fit, CIC deposit, IGF, doubled-grid FFT "
+                      "convolution, gradient, gather) on a 128^3 fitted mesh with 1e6 particles of the "
+                      "halo-Gaussian bunch, mean of 2 runs; numpy's FFT and bincount are single-threaded",
+            "seconds_per_step": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--particles", type=int, default=100_000_000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-extra", action="store_true", help="skip the mesh-only and serving legs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); nothing in this build "
+              f"spans GPUs.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1509_07685_amd import dks, workloads as wl
+
+    cfg = wl.HALO_GAUSSIAN
+    n = cfg.n
+    num = args.particles
+    x, y, z = wl.particles_for(cfg, dtype="f32", num=num)
+    tx, ty, tz = (torch.from_numpy(a).cuda() for a in (x, y, z))
+    del x, y, z
+    q = wl.TOTAL_CHARGE / num
+    plan = dks.PoissonPlan(n, None, "f32")
+    out = tuple(torch.empty(num, dtype=torch.float32, device="cuda") for _ in range(3))
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    bufs = out + (cnt,)
+
+    def step():
+        plan.solve_particles(tx, ty, tz, q, out=bufs)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    dks.dks_timing_enable(True)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(args.steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    ms_per_step = a.elapsed_time(b) / args.steps
+    kt = dks.dks_timing_read()
+    dks.dks_timing_enable(False)
+    mesh_pts = n[0] * n[1] * n[2]
+    value = mesh_pts / (ms_per_step * 1e-3)
+
+    kernels = {}
+    for name, (launches, total, mn, mx) in kt.items():
+        avg = total / launches
+        alg = algorithmic_bytes(n, num, 4, name)
+        kernels[name] = {"launches": launches, "avg_ms": avg, "min_ms": mn, "max_ms": mx,
+                         "alg_bytes": alg, "GB_s": alg / (avg * 1e-3) / 1e9 if alg else None}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
+    dk = kernels[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dk["GB_s"] / HBM_PEAK_GBS, "traffic": None}
+    conv_names = ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv")
+    conv_ms = sum(kernels[k]["avg_ms"] for k in conv_names if k in kernels)
+    conv = {"ms": conv_ms, "alg_bytes": conv_bytes(n, 4),
+            "GB_s": conv_bytes(n, 4) / (conv_ms * 1e-3) / 1e9,
+            "mesh_pts_per_s": mesh_pts / (conv_ms * 1e-3)}
+    conv["frac"] = conv["GB_s"] / HBM_PEAK_GBS
+
+    extra = {}
+    if not args.no_extra:
+        del tx, ty, tz, out, bufs
+        torch.cuda.empty_cache()
+        # mesh-only solves (rho -> phi and E) at 256^3 in FP32 and FP64
+        for dt_name, tdt in (("f32", torch.float32), ("f64", torch.float64)):
+            mp = dks.PoissonPlan(n, (1e-5, 1e-5, 1e-5), dt_name)
+            rho = torch.rand((n[2], n[1], n[0]), dtype=tdt, device="cuda")
+            phi = torch.empty_like(rho)
+            dks.dks_timing_enable(True)
+            ms = time_loop(torch, lambda: dks.dks_poisson_solve_rho(
+                mp.handle, dks._ptr(rho), dks._ptr(phi), None, dks._stream_handle(None)), 10, 2)
+            kk = dks.dks_timing_read()
+            dks.dks_timing_enable(False)
+            s = 4 if dt_name == "f32" else 8
+            cms = sum(kk[k][1] / kk[k][0] for k in conv_names if k in kk)
+            extra[f"solve_{dt_name}"] = {"ms": ms, "mesh_pts_per_s": mesh_pts / (ms * 1e-3),
+                                         "conv_GB_s": conv_bytes(n, s) / (cms * 1e-3) / 1e9,
+                                         "conv_frac": conv_bytes(n, s) / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            del mp, rho, phi
+            torch.cuda.empty_cache()
+        try:
+            from paper_1509_07685_amd import serve
+            extra["serving"] = serve.bench_stream(torch)
+        except ImportError:
+            extra["serving"] = None
+
+    cpu = None if args.no_cpu else cpu_baseline()
+    line = {
+        "metric": "Poisson solve mesh-pts/s (FP32 vs FP64) + served solves/s at p50/p99 latency",
+        "value": value,
+        "unit": "mesh-pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "halo_gaussian_256cubed_1e8_f32: 256^3 fitted mesh (512^3 doubled), "
+                               f"{num} particles (90% Gaussian sigma 1 mm + 10% uniform halo to 5 sigma), "
+                               "full particle step per solve, Green's spectrum cached",
+                   "mesh": list(n), "particles": num},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "convolution": conv,
+        **extra,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -174,6 +174,26 @@ dks_status dks_poisson_gather(dks_poisson_plan_t plan, const void* E_mesh, const
 dks_status dks_poisson_geometry(dks_poisson_plan_t plan, dks_stream_t stream, double* h,
                                 double* origin);
 
+/* Kernel timing (instrumentation of the library itself, not a step of the
+ * method).  While enabled, every kernel a solve, deposit, gather or prepare
+ * launches is bracketed by two HIP events recorded on the stream it runs on.
+ * Enabling or disabling discards the records.  Not for use inside HIP graph
+ * capture.  Library-wide; protected by a mutex. */
+typedef struct {
+  char name[40];       /* kernel name, NUL-terminated */
+  int64_t launches;    /* launches recorded since timing was enabled */
+  double total_ms;     /* summed event-to-event time */
+  double min_ms;
+  double max_ms;
+} dks_kernel_time;
+
+dks_status dks_timing_enable(int enable);
+
+/* Wait for the recorded events, aggregate them per kernel name into
+ * out[0 .. *count) (host memory, capacity entries), and drop the records.
+ * DKS_EINVAL if capacity is too small (then *count is the number needed). */
+dks_status dks_timing_read(dks_kernel_time* out, int capacity, int* count);
+
 /* Release the plan's host state.  Does not touch the caller's workspace. */
 dks_status dks_poisson_destroy(dks_poisson_plan_t plan);
 

@@ -5,7 +5,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "dks_internal.h"
@@ -174,10 +177,79 @@ namespace {
 
 dks_status hip_status(hipError_t e) { return e == hipSuccess ? DKS_OK : DKS_EHIP; }
 
+// Optional per-kernel event timing (dks_timing_enable / dks_timing_read).
+struct TimingState {
+  std::mutex mu;
+  bool on = false;
+  struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void release_all() {
+    for (auto& r : recs) {
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    recs.clear();
+  }
+};
+
+TimingState& timing() {
+  static TimingState t;
+  return t;
+}
+
+// Records an event before the launch and one after it, when timing is on.
+class Timed {
+ public:
+  Timed(const char* name, hipStream_t st) : name_(name), st_(st) {
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lock(t.mu);
+    if (!t.on) return;
+    a_ = t.take();
+    if (a_ && hipEventRecord(a_, st_) == hipSuccess) active_ = true;
+  }
+  void done() {
+    if (!active_) return;
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lock(t.mu);
+    hipEvent_t b = t.take();
+    if (b && hipEventRecord(b, st_) == hipSuccess) t.recs.push_back({name_, a_, b});
+    active_ = false;
+  }
+
+ private:
+  const char* name_;
+  hipStream_t st_;
+  hipEvent_t a_ = nullptr;
+  bool active_ = false;
+};
+
 #define DKS_CK(call)                              \
   do {                                            \
     const hipError_t e_ = (call);                 \
     if (e_ != hipSuccess) return DKS_EHIP;        \
+  } while (0)
+
+// Launch `call` on stream `st` under the kernel name `name` for the timing records.
+#define DKS_TK(name, call)                        \
+  do {                                            \
+    Timed tm_(name, st);                          \
+    const hipError_t e_ = (call);                 \
+    if (e_ != hipSuccess) return DKS_EHIP;        \
+    tm_.done();                                   \
   } while (0)
 
 void layout(dks_poisson_plan_s* p) {
@@ -265,11 +337,11 @@ dks_status convolve(const dks_poisson_plan_s* p, const void* src, size_t in_stri
   const PlanRef fzi = planref(p, 3);
   const void* post = p->ws + p->tw_post;
   const void* G = p->ws + p->off_green;
-  DKS_CK(launch_fft_x_fwd<T>(src, in_stride, R1, cstride, m, fx, post, batch, st));
-  DKS_CK(launch_fft_y_fwd<T>(R1, R2, cstride, m, fy, batch, st));
-  DKS_CK(launch_fft_z_conv<T>(R2, R1, cstride, G, sl.geo(), sl.stride, m, fz, fzi, batch, st));
-  DKS_CK(launch_fft_y_inv<T>(R1, R2, cstride, m, fy, batch, st));
-  DKS_CK(launch_fft_x_inv<T>(R2, cstride, R3, rstride, phi_user, m, fx, post, batch, st));
+  DKS_TK("fft_x_fwd", launch_fft_x_fwd<T>(src, in_stride, R1, cstride, m, fx, post, batch, st));
+  DKS_TK("fft_y_fwd", launch_fft_y_fwd<T>(R1, R2, cstride, m, fy, batch, st));
+  DKS_TK("fft_z_conv", launch_fft_z_conv<T>(R2, R1, cstride, G, sl.geo(), sl.stride, m, fz, fzi, batch, st));
+  DKS_TK("fft_y_inv", launch_fft_y_inv<T>(R1, R2, cstride, m, fy, batch, st));
+  DKS_TK("fft_x_inv", launch_fft_x_inv<T>(R2, cstride, R3, rstride, phi_user, m, fx, post, batch, st));
   return DKS_OK;
 }
 
@@ -294,11 +366,11 @@ dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl
                          hipStream_t st) {
   int nb = 0;
   double* bbox = reinterpret_cast<double*>(sl.base + p->s_bbox);
-  if (p->fitted) DKS_CK(launch_bbox<T>(X, Y, Z, bs, batch, bbox, sl.stride / sizeof(double), &nb, st));
+  if (p->fitted) DKS_TK("bbox", launch_bbox<T>(X, Y, Z, bs, batch, bbox, sl.stride / sizeof(double), &nb, st));
   const GeoArgs ga = geo_args(p, 1, nb);
-  DKS_CK(launch_geometry(bbox, sl.stride / sizeof(double), sl.geo(), sl.stride, ga, bs, cnt, batch, st));
-  DKS_CK(launch_zero(sl.base + p->s_r3, sl.stride, p->bytes_W, batch, st));
-  DKS_CK(launch_deposit<T>(X, Y, Z, bs, batch, sl.base + p->s_r3, sl.stride / sizeof(T), sl.geo(), sl.stride,
+  DKS_TK("geometry", launch_geometry(bbox, sl.stride / sizeof(double), sl.geo(), sl.stride, ga, bs, cnt, batch, st));
+  DKS_TK("zero_mesh", launch_zero(sl.base + p->s_r3, sl.stride, p->bytes_W, batch, st));
+  DKS_TK("deposit", launch_deposit<T>(X, Y, Z, bs, batch, sl.base + p->s_r3, sl.stride / sizeof(T), sl.geo(), sl.stride,
                            p->md, cnt, st));
   return DKS_OK;
 }
@@ -313,9 +385,9 @@ dks_status solve_particles_t(const dks_poisson_plan_s* p, int batch, const Slots
   r = convolve<T>(p, sl.base + p->s_r3, sl.stride / sizeof(T), batch, sl, PHI, st);
   if (r != DKS_OK) return r;
   const size_t rstride = sl.stride / sizeof(T);
-  DKS_CK((launch_gradient<T, true>(sl.base + p->s_r3, rstride, sl.base + p->s_r1, rstride, sl.geo(), sl.stride,
+  DKS_TK("gradient", (launch_gradient<T, true>(sl.base + p->s_r3, rstride, sl.base + p->s_r1, rstride, sl.geo(), sl.stride,
                                    p->md, batch, st)));
-  DKS_CK((launch_gather<T, true>(sl.base + p->s_r1, rstride, X, Y, Z, EX, EY, EZ, bs, batch, sl.geo(), sl.stride,
+  DKS_TK("gather", (launch_gather<T, true>(sl.base + p->s_r1, rstride, X, Y, Z, EX, EY, EZ, bs, batch, sl.geo(), sl.stride,
                                  p->md, st)));
   return DKS_OK;
 }
@@ -490,12 +562,18 @@ dks_status dks_poisson_solve_rho(dks_poisson_plan_t p, const void* rho, void* ph
   dks_status r;
   if (p->dtype == DKS_F32) {
     r = convolve<float>(p, rho, 0, 1, sl, one(phi), st);
-    if (r == DKS_OK && E_mesh)
+    if (r == DKS_OK && E_mesh) {
+      Timed tm("gradient", st);
       r = hip_status(launch_gradient<float, false>(sl.base + p->s_r3, 0, E_mesh, 0, sl.geo(), 0, p->md, 1, st));
+      tm.done();
+    }
   } else {
     r = convolve<double>(p, rho, 0, 1, sl, one(phi), st);
-    if (r == DKS_OK && E_mesh)
+    if (r == DKS_OK && E_mesh) {
+      Timed tm("gradient", st);
       r = hip_status(launch_gradient<double, false>(sl.base + p->s_r3, 0, E_mesh, 0, sl.geo(), 0, p->md, 1, st));
+      tm.done();
+    }
   }
   if (r == DKS_OK) p->has_geometry = true;
   return r;
@@ -626,6 +704,47 @@ dks_status dks_poisson_geometry(dks_poisson_plan_t p, dks_stream_t stream, doubl
     h[d] = g.h[d];
     origin[d] = g.origin[d];
   }
+  return DKS_OK;
+}
+
+dks_status dks_timing_enable(int enable) {
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> lock(t.mu);
+  for (auto& r : t.recs) hipEventSynchronize(r.b);
+  t.release_all();
+  t.on = enable != 0;
+  return DKS_OK;
+}
+
+dks_status dks_timing_read(dks_kernel_time* out, int capacity, int* count) {
+  if (!count || capacity < 0 || (capacity > 0 && !out)) return DKS_EINVAL;
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> lock(t.mu);
+  std::map<std::string, dks_kernel_time> agg;
+  std::vector<std::string> order;
+  for (auto& r : t.recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return DKS_EHIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return DKS_EHIP;
+    auto it = agg.find(r.name);
+    if (it == agg.end()) {
+      dks_kernel_time k;
+      std::memset(&k, 0, sizeof(k));
+      std::strncpy(k.name, r.name, sizeof(k.name) - 1);
+      k.min_ms = ms;
+      k.max_ms = ms;
+      it = agg.emplace(r.name, k).first;
+      order.push_back(r.name);
+    }
+    it->second.launches += 1;
+    it->second.total_ms += ms;
+    it->second.min_ms = std::min(it->second.min_ms, (double)ms);
+    it->second.max_ms = std::max(it->second.max_ms, (double)ms);
+  }
+  *count = (int)order.size();
+  if ((int)order.size() > capacity) return DKS_EINVAL;
+  for (size_t i = 0; i < order.size(); ++i) out[i] = agg[order[i]];
+  t.release_all();
   return DKS_OK;
 }
 

@@ -27,7 +27,7 @@ EXPORTS = (
     "dks_poisson_batch_scratch_bytes", "dks_poisson_set_workspace", "dks_poisson_prepare",
     "dks_poisson_solve_rho", "dks_poisson_solve_particles", "dks_poisson_solve_particles_batched",
     "dks_poisson_deposit", "dks_poisson_gather", "dks_poisson_geometry", "dks_poisson_destroy",
-    "dks_status_string",
+    "dks_status_string", "dks_timing_enable", "dks_timing_read",
 )
 
 
@@ -68,7 +68,14 @@ _SIGS = {
     "dks_poisson_geometry": (_i, [_PLAN, _vp, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "dks_poisson_destroy": (_i, [_PLAN]),
     "dks_status_string": (ctypes.c_char_p, [_i]),
+    "dks_timing_enable": (_i, [_i]),
+    "dks_timing_read": (_i, [_vp, _i, ctypes.POINTER(_i)]),
 }
+
+
+class dks_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
 
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -157,6 +164,19 @@ def dks_poisson_geometry(plan, stream):
     o = (_d * 3)()
     _check(_lib.dks_poisson_geometry(plan, stream, h, o), "dks_poisson_geometry")
     return tuple(h), tuple(o)
+
+
+def dks_timing_enable(enable):
+    _check(_lib.dks_timing_enable(1 if enable else 0), "dks_timing_enable")
+
+
+def dks_timing_read(capacity=64):
+    """{kernel name: (launches, total_ms, min_ms, max_ms)} since timing was enabled."""
+    arr = (dks_kernel_time * capacity)()
+    count = _i()
+    _check(_lib.dks_timing_read(ctypes.cast(arr, _vp), capacity, ctypes.byref(count)), "dks_timing_read")
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms, arr[i].min_ms, arr[i].max_ms)
+            for i in range(count.value)}
 
 
 def dks_poisson_destroy(plan):

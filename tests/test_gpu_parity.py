@@ -58,7 +58,7 @@ RHO_CASES = [
     ((3, 4, 6), (1.0, 2.0, 0.5)),         # odd, single-radix-3 x transform
     ((8, 8, 8), (1e-4, 1e-4, 1e-4)),
     ((12, 12, 12), (1e-4, 1e-4, 1e-4)),   # radix-3 passes
-    ((6, 8, 10), (5e-5, 5e-5, 2e-4)),     # anisotropic cells
+    ((6, 8, 9), (5e-5, 5e-5, 2e-4)),      # anisotropic cells
     ((32, 24, 18), (1e-4, 2e-4, 1.5e-4)),
     ((48, 36, 27), (1e-4, 1e-4, 1e-4)),   # several column tiles, ragged tails, 3^3 z
     ((64, 64, 64), (1e-4, 1e-4, 1e-4)),
@@ -136,7 +136,7 @@ def test_deposit_matches_oracle_fitted_mesh(dt):
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_gather_matches_oracle(dt):
-    n, h = (20, 18, 27), (1e-4, 1.2e-4, 0.8e-4)
+    n, h = (24, 18, 27), (1e-4, 1.2e-4, 0.8e-4)
     origin = orc.centred_origin(n, h)
     g = np.random.default_rng(21)
     E = g.standard_normal((3, n[2], n[1], n[0]))
