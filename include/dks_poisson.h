@@ -90,9 +90,22 @@ dks_status dks_poisson_set_origin(dks_poisson_plan_t plan, double x0, double y0,
  * solve.  Alignment required: 256 bytes. */
 dks_status dks_poisson_workspace_bytes(dks_poisson_plan_t plan, size_t* bytes);
 
-/* Bytes of per-element scratch a batched solve needs for `batch` elements,
- * on top of the plan workspace. */
-dks_status dks_poisson_batch_scratch_bytes(dks_poisson_plan_t plan, int batch, size_t* bytes);
+/* Bytes of per-element scratch a batched solve needs for `batch` elements
+ * of at most max_np particles each, on top of the plan workspace: each
+ * element's mesh intermediates and its binned particle records. */
+dks_status dks_poisson_batch_scratch_bytes(dks_poisson_plan_t plan, int batch, int64_t max_np,
+                                           size_t* bytes);
+
+/* Particle solves and the deposit group the particles by mesh tile before
+ * depositing (so that charge accumulates in on-chip memory rather than by
+ * contended device-wide atomics) and need a caller-owned device scratch of
+ * dks_poisson_particle_scratch_bytes(np) bytes for np particles (16 bytes per
+ * particle in FP32, 32 in FP64, rounded up to 256), attached with
+ * dks_poisson_set_particle_scratch (256-byte aligned; NULL with 0 bytes
+ * detaches).  A solve of more particles than the attached scratch holds
+ * returns DKS_EWORKSPACE.  np must be < 2^32. */
+dks_status dks_poisson_particle_scratch_bytes(dks_poisson_plan_t plan, int64_t np, size_t* bytes);
+dks_status dks_poisson_set_particle_scratch(dks_poisson_plan_t plan, void* scratch, size_t bytes);
 
 /* Attach caller-owned device workspace (at least dks_poisson_workspace_bytes,
  * 256-byte aligned).  The plan keeps the pointer; the caller keeps it alive
@@ -144,8 +157,9 @@ dks_status dks_poisson_solve_particles(dks_poisson_plan_t plan, const void* x, c
  *   np, q           : host arrays of `batch` counts and per-particle charges.
  *   phi             : host array of `batch` device pointers (entries may be
  *                     NULL), or NULL.
- *   scratch         : device, >= dks_poisson_batch_scratch_bytes(batch),
- *                     256-byte aligned, caller-owned.
+ *   scratch         : device, >= dks_poisson_batch_scratch_bytes(batch, max np),
+ *                     256-byte aligned, caller-owned; element b uses the
+ *                     b-th of `batch` equal parts (rounded down to 256 bytes).
  *   n_outside       : device int64[batch], written; may be NULL. */
 dks_status dks_poisson_solve_particles_batched(
     dks_poisson_plan_t plan, int batch, const void* const* x, const void* const* y,

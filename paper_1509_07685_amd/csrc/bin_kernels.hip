@@ -1,0 +1,458 @@
+// Spatially binned cloud-in-cell deposit and gather.
+//
+// A compact bunch puts hundreds of particles in each central cell, so a
+// deposit that adds every particle's eight weights straight into the mesh
+// with device-wide atomics serialises on the hot nodes, and a gather over
+// unsorted particles reads the mesh at random.  Both steps here work on the
+// particles grouped by the 16^3-cell tile that holds their CIC cell:
+//
+//   count    per-tile histogram (LDS-privatised, flushed with one atomic per
+//            touched tile per workgroup)
+//   scan     tile offsets, reservation cursors and the work-item list
+//            (a work item is up to kItem particles of one tile)
+//   scatter  each workgroup reserves one contiguous range per tile and writes
+//            its particles there as packed (x, y, z, original index)
+//   deposit  per work item: accumulate the weights of the tile's particles in
+//            an LDS copy of its 17^3 nodes with LDS atomics, then merge the
+//            copy into the mesh with one device atomic per non-zero node
+//   gather   per work item: stage phi of the tile plus a two-node apron
+//            (19^3 values) in LDS, form the central-difference field at the
+//            eight nodes of each particle and interpolate it with the
+//            deposit's weights; write E at the particle's original index
+//
+// Particles outside the mesh fall in an extra tile K: they deposit nothing,
+// get E = 0 and their count is the out-of-mesh count.  The cell decision is
+// made from the same (x - x0) * (1/h) in the dtype as everywhere else, so the
+// tile a particle is filed under always contains its whole stencil.
+
+#include <math.h>
+
+#include "dks_internal.h"
+
+namespace dks {
+
+constexpr int kTile = 16;          // cells per tile edge
+constexpr int kTileN = kTile + 1;  // deposit accumulator nodes per edge
+constexpr int kApron = kTile + 3;  // staged phi values per edge (nodes -1 .. 17)
+
+template <typename T> struct Packed;
+template <> struct Packed<float> { using type = float4; };
+template <> struct Packed<double> { using type = double4; };
+
+__device__ __forceinline__ float cc(float x, float x0, float ih) { return __fmul_rn(__fsub_rn(x, x0), ih); }
+__device__ __forceinline__ double cc(double x, double x0, double ih) { return __dmul_rn(__dsub_rn(x, x0), ih); }
+
+__device__ __forceinline__ const Geometry* geo_of(const Geometry* base, size_t stride, int b) {
+  return reinterpret_cast<const Geometry*>(reinterpret_cast<const char*>(base) + (size_t)b * stride);
+}
+
+__device__ __forceinline__ BinState bin_state(char* slot_base, size_t stride, size_t off, int b, int K) {
+  BinState s;
+  unsigned* p = reinterpret_cast<unsigned*>(slot_base + (size_t)b * stride + off);
+  s.count = p;
+  s.offset = p + (K + 1);
+  s.cursor = p + 2 * (K + 1) + 1;
+  s.item_off = p + 3 * (K + 1) + 1;
+  s.misc = p + 4 * (K + 1) + 2;
+  return s;
+}
+
+// Cell decision of one particle: returns its tile (K if outside) and the
+// lower CIC node and fractions.
+template <typename T>
+struct Cell {
+  int key;
+  int jx, jy, jz;
+  T fx, fy, fz;
+};
+
+template <typename T>
+__device__ __forceinline__ Cell<T> locate(T x, T y, T z, const Geometry* g, const MeshDims& m, const BinGeom& bg) {
+  Cell<T> c;
+  const T sx = cc(x, Geo<T>::origin(g, 0), Geo<T>::inv_h(g, 0));
+  const T sy = cc(y, Geo<T>::origin(g, 1), Geo<T>::inv_h(g, 1));
+  const T sz = cc(z, Geo<T>::origin(g, 2), Geo<T>::inv_h(g, 2));
+  if (sx >= (T)0 && sx <= (T)(m.nx - 1) && sy >= (T)0 && sy <= (T)(m.ny - 1) && sz >= (T)0 &&
+      sz <= (T)(m.nz - 1)) {
+    c.jx = min((int)floor(sx), m.nx - 2);
+    c.jy = min((int)floor(sy), m.ny - 2);
+    c.jz = min((int)floor(sz), m.nz - 2);
+    c.fx = sx - (T)c.jx;
+    c.fy = sy - (T)c.jy;
+    c.fz = sz - (T)c.jz;
+    c.key = ((c.jz / kTile) * bg.ty + (c.jy / kTile)) * bg.tx + (c.jx / kTile);
+  } else {
+    c.key = bg.K;
+    c.jx = c.jy = c.jz = 0;
+    c.fx = c.fy = c.fz = (T)0;
+  }
+  return c;
+}
+
+// Chunk of batch element b handled by count/scatter block `blk` of `nblk`.
+__device__ __forceinline__ void chunk_of(int64_t n, int blk, int nblk, int64_t* start, int64_t* end) {
+  const int64_t ch = (n + nblk - 1) / nblk;
+  *start = min((int64_t)blk * ch, n);
+  *end = min(*start + ch, n);
+}
+
+// ---------------------------------------------------------------------------
+// count
+// ---------------------------------------------------------------------------
+template <typename T, bool LDSHIST>
+__global__ __launch_bounds__(256) void k_bin_count(PtrBatch xs, PtrBatch ys, PtrBatch zs, BatchScalars bs,
+                                                   const Geometry* geo, size_t stride, char* slot_base,
+                                                   size_t bins_off, MeshDims m, BinGeom bg) {
+  extern __shared__ unsigned hist[];
+  const int b = blockIdx.y;
+  const T* px = (const T*)xs.p[b];
+  const T* py = (const T*)ys.p[b];
+  const T* pz = (const T*)zs.p[b];
+  const Geometry* g = geo_of(geo, stride, b);
+  BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
+  int64_t start, end;
+  chunk_of(bs.np[b], blockIdx.x, gridDim.x, &start, &end);
+  if (LDSHIST) {
+    for (int k = threadIdx.x; k <= bg.K; k += blockDim.x) hist[k] = 0;
+    __syncthreads();
+  }
+  for (int64_t i = start + threadIdx.x; i < end; i += blockDim.x) {
+    const int key = locate<T>(px[i], py[i], pz[i], g, m, bg).key;
+    if (LDSHIST) atomicAdd(&hist[key], 1u);
+    else atomicAdd(&st.count[key], 1u);
+  }
+  if (LDSHIST) {
+    __syncthreads();
+    for (int k = threadIdx.x; k <= bg.K; k += blockDim.x)
+      if (hist[k]) atomicAdd(&st.count[k], hist[k]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// scan: offsets (exclusive prefix of counts), cursors, work items.  One block
+// of 1024 threads per batch element.  Also publishes the out-of-mesh count.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_bin_scan(const Geometry* geo, size_t stride, char* slot_base,
+                                                   size_t bins_off, BinGeom bg, PtrBatch counters) {
+  __shared__ unsigned s_cnt[1024];
+  __shared__ unsigned s_itm[1024];
+  const int b = blockIdx.x;
+  BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
+  const int L = bg.K + 1;
+  const int per = (L + 1023) / 1024;
+  const int lo = min((int)threadIdx.x * per, L), hi = min(lo + per, L);
+  unsigned sc = 0, si = 0;
+  for (int k = lo; k < hi; ++k) {
+    const unsigned c = st.count[k];
+    sc += c;
+    si += (c + bg.item - 1) / bg.item;
+  }
+  s_cnt[threadIdx.x] = sc;
+  s_itm[threadIdx.x] = si;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    unsigned a = 0, c = 0;
+    if ((int)threadIdx.x >= d) {
+      a = s_cnt[threadIdx.x - d];
+      c = s_itm[threadIdx.x - d];
+    }
+    __syncthreads();
+    s_cnt[threadIdx.x] += a;
+    s_itm[threadIdx.x] += c;
+    __syncthreads();
+  }
+  unsigned oc = s_cnt[threadIdx.x] - sc, oi = s_itm[threadIdx.x] - si;
+  for (int k = lo; k < hi; ++k) {
+    const unsigned c = st.count[k];
+    st.offset[k] = oc;
+    st.cursor[k] = oc;
+    st.item_off[k] = oi;
+    oc += c;
+    oi += (c + bg.item - 1) / bg.item;
+  }
+  if (threadIdx.x == 1023) {
+    st.offset[L] = s_cnt[1023];
+    st.item_off[L] = s_itm[1023];
+    st.misc[0] = s_itm[1023];
+    const unsigned long long outside = st.count[bg.K];
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters.p[b]);
+    Geometry* gw = const_cast<Geometry*>(geo_of(geo, stride, b));
+    gw->n_outside = outside;
+    if (cnt) *cnt = outside;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// scatter: reserve one range per tile per block, then write packed particles.
+// ---------------------------------------------------------------------------
+template <typename T, bool LDSHIST>
+__global__ __launch_bounds__(256) void k_bin_scatter(PtrBatch xs, PtrBatch ys, PtrBatch zs, BatchScalars bs,
+                                                     const Geometry* geo, size_t stride, char* slot_base,
+                                                     size_t bins_off, char* sorted_base, size_t sorted_stride,
+                                                     MeshDims m, BinGeom bg) {
+  extern __shared__ unsigned lds[];
+  unsigned* lcnt = lds;
+  unsigned* lbase = lds + (bg.K + 1);
+  using P4 = typename Packed<T>::type;
+  const int b = blockIdx.y;
+  const T* px = (const T*)xs.p[b];
+  const T* py = (const T*)ys.p[b];
+  const T* pz = (const T*)zs.p[b];
+  const Geometry* g = geo_of(geo, stride, b);
+  BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
+  P4* out = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
+  int64_t start, end;
+  chunk_of(bs.np[b], blockIdx.x, gridDim.x, &start, &end);
+  if (LDSHIST) {
+    for (int k = threadIdx.x; k <= bg.K; k += blockDim.x) lcnt[k] = 0;
+    __syncthreads();
+    for (int64_t i = start + threadIdx.x; i < end; i += blockDim.x)
+      atomicAdd(&lcnt[locate<T>(px[i], py[i], pz[i], g, m, bg).key], 1u);
+    __syncthreads();
+    for (int k = threadIdx.x; k <= bg.K; k += blockDim.x) {
+      const unsigned c = lcnt[k];
+      lbase[k] = c ? atomicAdd(&st.cursor[k], c) : 0u;
+      lcnt[k] = 0;
+    }
+    __syncthreads();
+  }
+  for (int64_t i = start + threadIdx.x; i < end; i += blockDim.x) {
+    const T x = px[i], y = py[i], z = pz[i];
+    const int key = locate<T>(x, y, z, g, m, bg).key;
+    const unsigned dst = LDSHIST ? lbase[key] + atomicAdd(&lcnt[key], 1u) : atomicAdd(&st.cursor[key], 1u);
+    P4 v;
+    v.x = x;
+    v.y = y;
+    v.z = z;
+    if constexpr (sizeof(T) == 4) v.w = __uint_as_float((unsigned)i);
+    else v.w = (double)i;
+    out[dst] = v;
+  }
+}
+
+// Work item t -> (tile, first particle, one past the last).
+__device__ __forceinline__ void decode_item(const BinState& st, int K, int item, unsigned t, int* tile,
+                                            unsigned* start, unsigned* end) {
+  int lo = 0, hi = K + 1;   // item_off[lo] <= t < item_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (st.item_off[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  *tile = lo;
+  *start = st.offset[lo] + (t - st.item_off[lo]) * (unsigned)item;
+  *end = min(*start + (unsigned)item, st.offset[lo + 1]);
+}
+
+// ---------------------------------------------------------------------------
+// deposit: LDS-privatised accumulation per work item, then merge.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_deposit_binned(const Geometry* geo, size_t stride, char* slot_base,
+                                                        size_t bins_off, const char* sorted_base,
+                                                        size_t sorted_stride, T* W, size_t w_stride, MeshDims m,
+                                                        BinGeom bg) {
+  __shared__ T acc[kTileN * kTileN * kTileN];
+  using P4 = typename Packed<T>::type;
+  const int b = blockIdx.y;
+  const Geometry* g = geo_of(geo, stride, b);
+  BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
+  const P4* part = reinterpret_cast<const P4*>(sorted_base + (size_t)b * sorted_stride);
+  T* w = W + (size_t)b * w_stride;
+  const unsigned nitems = st.misc[0];
+  constexpr int NN = kTileN * kTileN * kTileN;
+  for (unsigned t = blockIdx.x; t < nitems; t += gridDim.x) {
+    int tile;
+    unsigned s0, s1;
+    decode_item(st, bg.K, bg.item, t, &tile, &s0, &s1);
+    if (tile == bg.K) continue;                      // outside particles deposit nothing
+    const int tx = tile % bg.tx, ty = (tile / bg.tx) % bg.ty, tz = tile / (bg.tx * bg.ty);
+    const int bx = tx * kTile, by = ty * kTile, bz = tz * kTile;
+    for (int e = threadIdx.x; e < NN; e += blockDim.x) acc[e] = (T)0;
+    __syncthreads();
+    for (unsigned i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+      const P4 p = part[i];
+      const Cell<T> c = locate<T>(p.x, p.y, p.z, g, m, bg);
+      const T gx = (T)1 - c.fx, gy = (T)1 - c.fy, gz = (T)1 - c.fz;
+      T* a = acc + ((c.jz - bz) * kTileN + (c.jy - by)) * kTileN + (c.jx - bx);
+      constexpr int SY = kTileN, SZ = kTileN * kTileN;
+      atomicAdd(a, gz * gy * gx);
+      atomicAdd(a + 1, gz * gy * c.fx);
+      atomicAdd(a + SY, gz * c.fy * gx);
+      atomicAdd(a + SY + 1, gz * c.fy * c.fx);
+      atomicAdd(a + SZ, c.fz * gy * gx);
+      atomicAdd(a + SZ + 1, c.fz * gy * c.fx);
+      atomicAdd(a + SZ + SY, c.fz * c.fy * gx);
+      atomicAdd(a + SZ + SY + 1, c.fz * c.fy * c.fx);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NN; e += blockDim.x) {
+      const T v = acc[e];
+      if (v != (T)0) {
+        const int ex = e % kTileN, ey = (e / kTileN) % kTileN, ez = e / (kTileN * kTileN);
+        const int x = bx + ex, y = by + ey, z = bz + ez;
+        if (x < m.nx && y < m.ny && z < m.nz) unsafeAtomicAdd(&w[((size_t)z * m.ny + y) * m.nx + x], v);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gather with the central-difference field formed on the fly from staged phi.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_binned(const Geometry* geo, size_t stride, char* slot_base,
+                                                       size_t bins_off, const char* sorted_base,
+                                                       size_t sorted_stride, const T* __restrict__ phi_ext,
+                                                       size_t phi_stride, PtrBatch exs, PtrBatch eys,
+                                                       PtrBatch ezs, MeshDims m, BinGeom bg) {
+  __shared__ T ph[kApron * kApron * kApron];
+  using P4 = typename Packed<T>::type;
+  const int b = blockIdx.y;
+  const Geometry* g = geo_of(geo, stride, b);
+  BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
+  const P4* part = reinterpret_cast<const P4*>(sorted_base + (size_t)b * sorted_stride);
+  const T* phi = phi_ext + (size_t)b * phi_stride;
+  T* qx = (T*)exs.p[b];
+  T* qy = (T*)eys.p[b];
+  T* qz = (T*)ezs.p[b];
+  const T cx = Geo<T>::grad(g, 0), cy = Geo<T>::grad(g, 1), cz = Geo<T>::grad(g, 2);
+  const int nx2 = m.nx + 2, ny2 = m.ny + 2, nz2 = m.nz + 2;
+  const unsigned nitems = st.misc[0];
+  constexpr int A = kApron, NA = kApron * kApron * kApron;
+  for (unsigned t = blockIdx.x; t < nitems; t += gridDim.x) {
+    int tile;
+    unsigned s0, s1;
+    decode_item(st, bg.K, bg.item, t, &tile, &s0, &s1);
+    if (tile == bg.K) {
+      for (unsigned i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+        const P4 p = part[i];
+        size_t idx;
+        if constexpr (sizeof(T) == 4) idx = __float_as_uint(p.w);
+        else idx = (size_t)p.w;
+        qx[idx] = (T)0;
+        qy[idx] = (T)0;
+        qz[idx] = (T)0;
+      }
+      continue;
+    }
+    const int tx = tile % bg.tx, ty = (tile / bg.tx) % bg.ty, tz = tile / (bg.tx * bg.ty);
+    const int bx = tx * kTile, by = ty * kTile, bz = tz * kTile;
+    // phi_ext indices bx .. bx + 18 hold nodes bx - 1 .. bx + 17
+    for (int e = threadIdx.x; e < NA; e += blockDim.x) {
+      const int ex = e % A, ey = (e / A) % A, ez = e / (A * A);
+      const int x = bx + ex, y = by + ey, z = bz + ez;
+      ph[e] = (x < nx2 && y < ny2 && z < nz2) ? phi[((size_t)z * ny2 + y) * nx2 + x] : (T)0;
+    }
+    __syncthreads();
+    for (unsigned i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+      const P4 p = part[i];
+      const Cell<T> c = locate<T>(p.x, p.y, p.z, g, m, bg);
+      const T wx[2] = {(T)1 - c.fx, c.fx}, wy[2] = {(T)1 - c.fy, c.fy}, wz[2] = {(T)1 - c.fz, c.fz};
+      // staged index of node (jx, jy, jz): (node - tile base) + 1 per axis
+      const T* o = ph + ((c.jz - bz + 1) * A + (c.jy - by + 1)) * A + (c.jx - bx + 1);
+      T ax = 0, ay = 0, az = 0;
+#pragma unroll
+      for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+        for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+          for (int kx = 0; kx < 2; ++kx) {
+            const T* q = o + (kz * A + ky) * A + kx;
+            const T ex = cx * (q[1] - q[-1]);
+            const T ey = cy * (q[A] - q[-A]);
+            const T ez = cz * (q[A * A] - q[-A * A]);
+            const T wgt = wz[kz] * wy[ky] * wx[kx];
+            ax += wgt * ex;
+            ay += wgt * ey;
+            az += wgt * ez;
+          }
+      size_t idx;
+      if constexpr (sizeof(T) == 4) idx = __float_as_uint(p.w);
+      else idx = (size_t)p.w;
+      qx[idx] = ax;
+      qy[idx] = ay;
+      qz[idx] = az;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_bin_count(const PtrBatch& xs, const PtrBatch& ys, const PtrBatch& zs, const BatchScalars& bs,
+                            int batch, const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
+                            const MeshDims& m, const BinGeom& bg, int nblk, hipStream_t s) {
+  const bool lh = bg.lds_hist != 0;
+  const size_t lds = lh ? (size_t)(bg.K + 1) * sizeof(unsigned) : 0;
+  if (lh)
+    hipLaunchKernelGGL((k_bin_count<T, true>), dim3(nblk, batch), dim3(256), lds, s, xs, ys, zs, bs, geo, stride,
+                       slot_base, bins_off, m, bg);
+  else
+    hipLaunchKernelGGL((k_bin_count<T, false>), dim3(nblk, batch), dim3(256), 0, s, xs, ys, zs, bs, geo, stride,
+                       slot_base, bins_off, m, bg);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_scan(const Geometry* geo, size_t stride, char* slot_base, size_t bins_off, const BinGeom& bg,
+                           const PtrBatch& counters, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_bin_scan, dim3(batch), dim3(1024), 0, s, geo, stride, slot_base, bins_off, bg, counters);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bin_scatter(const PtrBatch& xs, const PtrBatch& ys, const PtrBatch& zs, const BatchScalars& bs,
+                              int batch, const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
+                              char* sorted_base, size_t sorted_stride, const MeshDims& m, const BinGeom& bg,
+                              int nblk, hipStream_t s) {
+  const bool lh = bg.lds_hist != 0;
+  const size_t lds = lh ? 2 * (size_t)(bg.K + 1) * sizeof(unsigned) : 0;
+  if (lh)
+    hipLaunchKernelGGL((k_bin_scatter<T, true>), dim3(nblk, batch), dim3(256), lds, s, xs, ys, zs, bs, geo, stride,
+                       slot_base, bins_off, sorted_base, sorted_stride, m, bg);
+  else
+    hipLaunchKernelGGL((k_bin_scatter<T, false>), dim3(nblk, batch), dim3(256), 0, s, xs, ys, zs, bs, geo, stride,
+                       slot_base, bins_off, sorted_base, sorted_stride, m, bg);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_deposit_binned(const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
+                                 const char* sorted_base, size_t sorted_stride, void* W, size_t w_stride,
+                                 const MeshDims& m, const BinGeom& bg, int nblk, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_deposit_binned<T>, dim3(nblk, batch), dim3(256), 0, s, geo, stride, slot_base, bins_off,
+                     sorted_base, sorted_stride, (T*)W, w_stride, m, bg);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather_binned(const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
+                                const char* sorted_base, size_t sorted_stride, const void* phi_ext,
+                                size_t phi_stride, const PtrBatch& exs, const PtrBatch& eys, const PtrBatch& ezs,
+                                const MeshDims& m, const BinGeom& bg, int nblk, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_binned<T>, dim3(nblk, batch), dim3(256), 0, s, geo, stride, slot_base, bins_off,
+                     sorted_base, sorted_stride, (const T*)phi_ext, phi_stride, exs, eys, ezs, m, bg);
+  return hipGetLastError();
+}
+
+#define DKS_INSTANTIATE(T)                                                                                         \
+  template hipError_t launch_bin_count<T>(const PtrBatch&, const PtrBatch&, const PtrBatch&, const BatchScalars&,  \
+                                          int, const Geometry*, size_t, char*, size_t, const MeshDims&,            \
+                                          const BinGeom&, int, hipStream_t);                                       \
+  template hipError_t launch_bin_scatter<T>(const PtrBatch&, const PtrBatch&, const PtrBatch&,                     \
+                                            const BatchScalars&, int, const Geometry*, size_t, char*, size_t,      \
+                                            char*, size_t, const MeshDims&, const BinGeom&, int, hipStream_t);     \
+  template hipError_t launch_deposit_binned<T>(const Geometry*, size_t, char*, size_t, const char*, size_t, void*, \
+                                               size_t, const MeshDims&, const BinGeom&, int, int, hipStream_t);    \
+  template hipError_t launch_gather_binned<T>(const Geometry*, size_t, char*, size_t, const char*, size_t,         \
+                                              const void*, size_t, const PtrBatch&, const PtrBatch&,               \
+                                              const PtrBatch&, const MeshDims&, const BinGeom&, int, int,          \
+                                              hipStream_t);
+DKS_INSTANTIATE(float)
+DKS_INSTANTIATE(double)
+#undef DKS_INSTANTIATE
+
+}  // namespace dks

@@ -104,6 +104,26 @@ struct GeoArgs {
   int mode;            // 0: mesh density input, 1: particles
   double h[3];         // explicit cell sizes
   double origin[3];    // explicit origin
+  size_t zero_off;     // slot offset of a uint32 array cleared by the kernel
+  int zero_len;        // its length (0: none)
+};
+
+// Particle binning: 16^3-cell tiles, tile K collects out-of-mesh particles.
+struct BinGeom {
+  int tx, ty, tz;      // tiles per axis
+  int K;               // tx * ty * tz
+  int item;            // particles per deposit/gather work item
+  int lds_hist;        // 1: per-block tile histograms fit in LDS
+};
+
+// Per-slot bin bookkeeping (uint32): count[K+1], offset[K+2], cursor[K+1],
+// item_off[K+2], misc[4] (misc[0] = number of work items).
+struct BinState {
+  unsigned* count;
+  unsigned* offset;
+  unsigned* cursor;
+  unsigned* item_off;
+  unsigned* misc;
 };
 
 // Gauss-Legendre product rules of the Green's function bands: band i covers

@@ -84,6 +84,10 @@ __global__ __launch_bounds__(256) void k_geometry(const double* partial, size_t 
 #pragma clang fp contract(off)
   const int b = blockIdx.x;
   Geometry* g = reinterpret_cast<Geometry*>(reinterpret_cast<char*>(geo) + (size_t)b * geo_stride);
+  if (a.zero_len > 0) {
+    unsigned* z = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(g) + a.zero_off);
+    for (int i = threadIdx.x; i < a.zero_len; i += blockDim.x) z[i] = 0u;
+  }
   __shared__ double red[6][256];
   if (a.fitted) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -168,63 +172,6 @@ __global__ __launch_bounds__(256) void k_zero(void* base, size_t stride_bytes, s
   if (blockIdx.x == 0 && threadIdx.x < tail) p[n16 * 16 + threadIdx.x] = 0;
 }
 
-// ---------------------------------------------------------------------------
-// CIC deposit of dimensionless weights W (charge = q W) with hardware
-// floating-point atomics.  Out-of-mesh particles are counted per wavefront.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_deposit(PtrBatch xs, PtrBatch ys, PtrBatch zs, BatchScalars bs,
-                                                 T* W, size_t w_stride, const Geometry* geo,
-                                                 size_t geo_stride, MeshDims m, PtrBatch counters) {
-  const int b = blockIdx.y;
-  const T* px = (const T*)xs.p[b];
-  const T* py = (const T*)ys.p[b];
-  const T* pz = (const T*)zs.p[b];
-  T* w = W + (size_t)b * w_stride;
-  const Geometry* g = geo_at(geo, geo_stride, b);
-  const T ox = Geo<T>::origin(g, 0), oy = Geo<T>::origin(g, 1), oz = Geo<T>::origin(g, 2);
-  const T ix = Geo<T>::inv_h(g, 0), iy = Geo<T>::inv_h(g, 1), iz = Geo<T>::inv_h(g, 2);
-  unsigned long long* cnt = counters.p[b] ? reinterpret_cast<unsigned long long*>(counters.p[b])
-                                          : &const_cast<Geometry*>(g)->n_outside;
-  const int64_t n = bs.np[b];
-  const int nx = m.nx, ny = m.ny, nz = m.nz;
-  const T ux = (T)(nx - 1), uy = (T)(ny - 1), uz = (T)(nz - 1);
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = i0 + threadIdx.x;
-    bool outside = false;
-    if (i < n) {
-      const T sx = cell_coord(px[i], ox, ix);
-      const T sy = cell_coord(py[i], oy, iy);
-      const T sz = cell_coord(pz[i], oz, iz);
-      if (sx >= (T)0 && sx <= ux && sy >= (T)0 && sy <= uy && sz >= (T)0 && sz <= uz) {
-        const int jx = min((int)floor(sx), nx - 2);
-        const int jy = min((int)floor(sy), ny - 2);
-        const int jz = min((int)floor(sz), nz - 2);
-        const T fx = sx - (T)jx, fy = sy - (T)jy, fz = sz - (T)jz;
-        const T gx = (T)1 - fx, gy = (T)1 - fy, gz = (T)1 - fz;
-        T* base = w + ((size_t)jz * ny + jy) * nx + jx;
-        const size_t sy_ = nx, sz_ = (size_t)nx * ny;
-        unsafeAtomicAdd(base, gz * gy * gx);
-        unsafeAtomicAdd(base + 1, gz * gy * fx);
-        unsafeAtomicAdd(base + sy_, gz * fy * gx);
-        unsafeAtomicAdd(base + sy_ + 1, gz * fy * fx);
-        unsafeAtomicAdd(base + sz_, fz * gy * gx);
-        unsafeAtomicAdd(base + sz_ + 1, fz * gy * fx);
-        unsafeAtomicAdd(base + sz_ + sy_, fz * fy * gx);
-        unsafeAtomicAdd(base + sz_ + sy_ + 1, fz * fy * fx);
-      } else {
-        outside = true;
-      }
-    }
-    const unsigned long long out_mask = __ballot(outside);
-    if (out_mask != 0ull) {
-      const unsigned long long active = __ballot(1);
-      if ((int)(threadIdx.x & 63) == __ffsll((long long)active) - 1)
-        atomicAdd(cnt, (unsigned long long)__popcll(out_mask));
-    }
-  }
-}
-
 // rho = W * q / V for the deposit-only entry point (factor formed in FP64).
 template <typename T>
 __global__ __launch_bounds__(256) void k_weights_to_density(const T* W, T* rho, size_t n, const Geometry* g,
@@ -237,65 +184,37 @@ __global__ __launch_bounds__(256) void k_weights_to_density(const T* W, T* rho, 
 
 // ---------------------------------------------------------------------------
 // Central-difference field from phi with its ghost layer: E_d = -(phi(+e_d)
-// - phi(-e_d)) / (2 h_d) on the physical nodes.  INTERLEAVED writes
-// [node][4] (x, y, z, 0) for the gather; otherwise [3][nz][ny][nx].
+// - phi(-e_d)) / (2 h_d) on the physical nodes, written [3][nz][ny][nx].
 // ---------------------------------------------------------------------------
-template <typename T, bool INTERLEAVED>
-__global__ __launch_bounds__(256) void k_gradient(const T* __restrict__ phi, size_t phi_stride,
-                                                  T* __restrict__ out, size_t out_stride,
-                                                  const Geometry* geo, size_t geo_stride, MeshDims m) {
-  const int b = blockIdx.z;
+template <typename T>
+__global__ __launch_bounds__(256) void k_gradient(const T* __restrict__ phi, T* __restrict__ out,
+                                                  const Geometry* g, MeshDims m) {
   const int z = blockIdx.y;
   const int nx = m.nx, ny = m.ny, nz = m.nz;
   const int i2 = blockIdx.x * blockDim.x + threadIdx.x;    // y * nx + x within plane z
   if (i2 >= nx * ny) return;
   const int y = i2 / nx, x = i2 - y * nx;
-  const T* p = phi + (size_t)b * phi_stride;
-  T* o = out + (size_t)b * out_stride;
-  const Geometry* g = geo_at(geo, geo_stride, b);
   const T cx = Geo<T>::grad(g, 0), cy = Geo<T>::grad(g, 1), cz = Geo<T>::grad(g, 2);
   const size_t py = (size_t)nx + 2, pz = (size_t)(nx + 2) * (ny + 2);
   const size_t c = (size_t)(z + 1) * pz + (size_t)(y + 1) * py + (size_t)(x + 1);
-  const T ex = cx * (p[c + 1] - p[c - 1]);
-  const T ey = cy * (p[c + py] - p[c - py]);
-  const T ez = cz * (p[c + pz] - p[c - pz]);
   const size_t i = (size_t)z * nx * ny + i2;
-  if (INTERLEAVED) {
-    typename Vec4<T>::type e;
-    e.x = ex;
-    e.y = ey;
-    e.z = ez;
-    e.w = (T)0;
-    reinterpret_cast<typename Vec4<T>::type*>(o)[i] = e;
-  } else {
-    const size_t total = (size_t)nx * ny * nz;
-    o[i] = ex;
-    o[total + i] = ey;
-    o[2 * total + i] = ez;
-  }
+  const size_t total = (size_t)nx * ny * nz;
+  out[i] = cx * (phi[c + 1] - phi[c - 1]);
+  out[total + i] = cy * (phi[c + py] - phi[c - py]);
+  out[2 * total + i] = cz * (phi[c + pz] - phi[c - pz]);
 }
 
 // ---------------------------------------------------------------------------
-// CIC gather with the deposit's weights.  INTERLEAVED reads [node][4];
-// otherwise [3][nz][ny][nx].  Outside particles receive 0.
+// CIC gather of a [3][nz][ny][nx] mesh field at unsorted particles (the
+// stand-alone gather entry point).  Outside particles receive 0.
 // ---------------------------------------------------------------------------
-template <typename T, bool INTERLEAVED>
-__global__ __launch_bounds__(256) void k_gather(const T* __restrict__ E, size_t e_stride, PtrBatch xs,
-                                                PtrBatch ys, PtrBatch zs, PtrBatch exs, PtrBatch eys,
-                                                PtrBatch ezs, BatchScalars bs, const Geometry* geo,
-                                                size_t geo_stride, MeshDims m) {
-  const int b = blockIdx.y;
-  const T* px = (const T*)xs.p[b];
-  const T* py = (const T*)ys.p[b];
-  const T* pz = (const T*)zs.p[b];
-  T* qx = (T*)exs.p[b];
-  T* qy = (T*)eys.p[b];
-  T* qz = (T*)ezs.p[b];
-  const T* e = E + (size_t)b * e_stride;
-  const Geometry* g = geo_at(geo, geo_stride, b);
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(const T* __restrict__ E, const T* __restrict__ px,
+                                                const T* __restrict__ py, const T* __restrict__ pz,
+                                                T* __restrict__ qx, T* __restrict__ qy, T* __restrict__ qz,
+                                                int64_t n, const Geometry* g, MeshDims m) {
   const T ox = Geo<T>::origin(g, 0), oy = Geo<T>::origin(g, 1), oz = Geo<T>::origin(g, 2);
   const T ix = Geo<T>::inv_h(g, 0), iy = Geo<T>::inv_h(g, 1), iz = Geo<T>::inv_h(g, 2);
-  const int64_t n = bs.np[b];
   const int nx = m.nx, ny = m.ny, nz = m.nz;
   const T ux = (T)(nx - 1), uy = (T)(ny - 1), uz = (T)(nz - 1);
   const size_t total = (size_t)nx * ny * nz;
@@ -318,16 +237,9 @@ __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ E, size_t 
           for (int cx = 0; cx < 2; ++cx) {
             const size_t node = ((size_t)(jz + cz) * ny + (jy + cy)) * nx + (jx + cx);
             const T wgt = wz[cz] * wy[cy] * wx[cx];
-            if (INTERLEAVED) {
-              const typename Vec4<T>::type v = reinterpret_cast<const typename Vec4<T>::type*>(e)[node];
-              ax += wgt * v.x;
-              ay += wgt * v.y;
-              az += wgt * v.z;
-            } else {
-              ax += wgt * e[node];
-              ay += wgt * e[total + node];
-              az += wgt * e[2 * total + node];
-            }
+            ax += wgt * E[node];
+            ay += wgt * E[total + node];
+            az += wgt * E[2 * total + node];
           }
     }
     qx[i] = ax;
@@ -370,19 +282,6 @@ hipError_t launch_zero(void* base, size_t stride_bytes, size_t bytes, int batch,
 }
 
 template <typename T>
-hipError_t launch_deposit(const PtrBatch& xs, const PtrBatch& ys, const PtrBatch& zs, const BatchScalars& bs,
-                          int batch, void* W, size_t w_stride, const Geometry* geo, size_t geo_stride,
-                          const MeshDims& m, const PtrBatch& counters, hipStream_t s) {
-  int64_t maxn = 0;
-  for (int b = 0; b < batch; ++b) maxn = std::max(maxn, bs.np[b]);
-  if (maxn == 0) return hipSuccess;
-  const unsigned nb = grid_for(maxn, 65535u * 4);
-  hipLaunchKernelGGL(k_deposit<T>, dim3(nb, batch), dim3(256), 0, s, xs, ys, zs, bs, (T*)W, w_stride, geo,
-                     geo_stride, m, counters);
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_weights_to_density(const void* W, void* rho, size_t n, const Geometry* g, double q,
                                      hipStream_t s) {
   hipLaunchKernelGGL(k_weights_to_density<T>, dim3(grid_for((int64_t)n, 8192)), dim3(256), 0, s, (const T*)W,
@@ -390,48 +289,30 @@ hipError_t launch_weights_to_density(const void* W, void* rho, size_t n, const G
   return hipGetLastError();
 }
 
-template <typename T, bool INTERLEAVED>
-hipError_t launch_gradient(const void* phi, size_t phi_stride, void* out, size_t out_stride, const Geometry* geo,
-                           size_t geo_stride, const MeshDims& m, int batch, hipStream_t s) {
+template <typename T>
+hipError_t launch_gradient(const void* phi, void* out, const Geometry* g, const MeshDims& m, hipStream_t s) {
   const unsigned gx = (unsigned)(((int64_t)m.nx * m.ny + 255) / 256);
-  hipLaunchKernelGGL((k_gradient<T, INTERLEAVED>), dim3(gx, m.nz, batch), dim3(256), 0, s,
-                     (const T*)phi, phi_stride, (T*)out, out_stride, geo, geo_stride, m);
+  hipLaunchKernelGGL(k_gradient<T>, dim3(gx, m.nz), dim3(256), 0, s, (const T*)phi, (T*)out, g, m);
   return hipGetLastError();
 }
 
-template <typename T, bool INTERLEAVED>
-hipError_t launch_gather(const void* E, size_t e_stride, const PtrBatch& xs, const PtrBatch& ys,
-                         const PtrBatch& zs, const PtrBatch& exs, const PtrBatch& eys, const PtrBatch& ezs,
-                         const BatchScalars& bs, int batch, const Geometry* geo, size_t geo_stride,
-                         const MeshDims& m, hipStream_t s) {
-  int64_t maxn = 0;
-  for (int b = 0; b < batch; ++b) maxn = std::max(maxn, bs.np[b]);
-  if (maxn == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gather<T, INTERLEAVED>), dim3(grid_for(maxn, 65535u * 4), batch), dim3(256), 0, s,
-                     (const T*)E, e_stride, xs, ys, zs, exs, eys, ezs, bs, geo, geo_stride, m);
+template <typename T>
+hipError_t launch_gather(const void* E, const void* x, const void* y, const void* z, void* ex, void* ey, void* ez,
+                         int64_t n, const Geometry* g, const MeshDims& m, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather<T>, dim3(grid_for(n, 65535u * 4)), dim3(256), 0, s, (const T*)E, (const T*)x,
+                     (const T*)y, (const T*)z, (T*)ex, (T*)ey, (T*)ez, n, g, m);
   return hipGetLastError();
 }
 
 #define DKS_INSTANTIATE(T)                                                                                   \
   template hipError_t launch_bbox<T>(const PtrBatch&, const PtrBatch&, const PtrBatch&, const BatchScalars&, \
                                      int, double*, size_t, int*, hipStream_t);                               \
-  template hipError_t launch_deposit<T>(const PtrBatch&, const PtrBatch&, const PtrBatch&,                   \
-                                        const BatchScalars&, int, void*, size_t, const Geometry*, size_t,    \
-                                        const MeshDims&, const PtrBatch&, hipStream_t);                      \
   template hipError_t launch_weights_to_density<T>(const void*, void*, size_t, const Geometry*, double,      \
                                                    hipStream_t);                                             \
-  template hipError_t launch_gradient<T, true>(const void*, size_t, void*, size_t, const Geometry*, size_t,  \
-                                               const MeshDims&, int, hipStream_t);                           \
-  template hipError_t launch_gradient<T, false>(const void*, size_t, void*, size_t, const Geometry*, size_t, \
-                                                const MeshDims&, int, hipStream_t);                          \
-  template hipError_t launch_gather<T, true>(const void*, size_t, const PtrBatch&, const PtrBatch&,          \
-                                             const PtrBatch&, const PtrBatch&, const PtrBatch&,              \
-                                             const PtrBatch&, const BatchScalars&, int, const Geometry*,     \
-                                             size_t, const MeshDims&, hipStream_t);                          \
-  template hipError_t launch_gather<T, false>(const void*, size_t, const PtrBatch&, const PtrBatch&,         \
-                                              const PtrBatch&, const PtrBatch&, const PtrBatch&,             \
-                                              const PtrBatch&, const BatchScalars&, int, const Geometry*,    \
-                                              size_t, const MeshDims&, hipStream_t);
+  template hipError_t launch_gradient<T>(const void*, void*, const Geometry*, const MeshDims&, hipStream_t); \
+  template hipError_t launch_gather<T>(const void*, const void*, const void*, const void*, void*, void*,     \
+                                       void*, int64_t, const Geometry*, const MeshDims&, hipStream_t);
 DKS_INSTANTIATE(float)
 DKS_INSTANTIATE(double)
 #undef DKS_INSTANTIATE

@@ -34,17 +34,26 @@ template <typename T> hipError_t launch_bbox(const PtrBatch&, const PtrBatch&, c
 hipError_t launch_geometry(const double*, size_t, Geometry*, size_t, const GeoArgs&, const BatchScalars&,
                            const PtrBatch&, int, hipStream_t);
 hipError_t launch_zero(void*, size_t, size_t, int, hipStream_t);
-template <typename T> hipError_t launch_deposit(const PtrBatch&, const PtrBatch&, const PtrBatch&,
-                                                const BatchScalars&, int, void*, size_t, const Geometry*, size_t,
-                                                const MeshDims&, const PtrBatch&, hipStream_t);
 template <typename T> hipError_t launch_weights_to_density(const void*, void*, size_t, const Geometry*, double,
                                                            hipStream_t);
-template <typename T, bool I> hipError_t launch_gradient(const void*, size_t, void*, size_t, const Geometry*,
-                                                         size_t, const MeshDims&, int, hipStream_t);
-template <typename T, bool I> hipError_t launch_gather(const void*, size_t, const PtrBatch&, const PtrBatch&,
-                                                       const PtrBatch&, const PtrBatch&, const PtrBatch&,
-                                                       const PtrBatch&, const BatchScalars&, int,
-                                                       const Geometry*, size_t, const MeshDims&, hipStream_t);
+template <typename T> hipError_t launch_gradient(const void*, void*, const Geometry*, const MeshDims&, hipStream_t);
+template <typename T> hipError_t launch_gather(const void*, const void*, const void*, const void*, void*, void*,
+                                               void*, int64_t, const Geometry*, const MeshDims&, hipStream_t);
+template <typename T> hipError_t launch_bin_count(const PtrBatch&, const PtrBatch&, const PtrBatch&,
+                                                  const BatchScalars&, int, const Geometry*, size_t, char*, size_t,
+                                                  const MeshDims&, const BinGeom&, int, hipStream_t);
+hipError_t launch_bin_scan(const Geometry*, size_t, char*, size_t, const BinGeom&, const PtrBatch&, int, hipStream_t);
+template <typename T> hipError_t launch_bin_scatter(const PtrBatch&, const PtrBatch&, const PtrBatch&,
+                                                    const BatchScalars&, int, const Geometry*, size_t, char*,
+                                                    size_t, char*, size_t, const MeshDims&, const BinGeom&, int,
+                                                    hipStream_t);
+template <typename T> hipError_t launch_deposit_binned(const Geometry*, size_t, char*, size_t, const char*, size_t,
+                                                       void*, size_t, const MeshDims&, const BinGeom&, int, int,
+                                                       hipStream_t);
+template <typename T> hipError_t launch_gather_binned(const Geometry*, size_t, char*, size_t, const char*, size_t,
+                                                      const void*, size_t, const PtrBatch&, const PtrBatch&,
+                                                      const PtrBatch&, const MeshDims&, const BinGeom&, int, int,
+                                                      hipStream_t);
 template <typename T> hipError_t launch_twiddle_pass(void*, int, int, hipStream_t);
 template <typename T> hipError_t launch_twiddle_line(void*, int, int, hipStream_t);
 hipError_t launch_igf_octant(double*, const int*, const double*, const GLBands&, hipStream_t);
@@ -164,11 +173,16 @@ struct dks_poisson_plan_s {
   size_t tw_px, tw_py, tw_pz, tw_pzi, tw_post, tw_bytes;   // byte offsets in the twiddle region
   size_t off_green, green_bytes, off_slot;
   // slot layout (bytes from slot start)
-  size_t s_bbox, s_r1, s_r2, s_r3, slot_bytes;
-  size_t bytes_W, bytes_phi_ext, bytes_E4;
+  size_t s_bbox, s_bins, s_r1, s_r2, s_r3, slot_bytes;
+  size_t bytes_W, bytes_phi_ext;
+  BinGeom bg;          // tiles of the binned deposit/gather (item set per solve)
+  int bins_len;        // uint32 entries of the bin bookkeeping
+  size_t part_elem;    // bytes per binned particle record
   size_t ws_total;
   char* ws;
   size_t ws_bytes;
+  char* pscratch;      // caller-owned binned-particle scratch of single solves
+  size_t pscratch_bytes;
   bool prepared;
   bool has_geometry;
 };
@@ -288,15 +302,24 @@ void layout(dks_poisson_plan_s* p) {
   const size_t D = (size_t)(ny + 2) * (nz + 2) * cs * c;
   p->bytes_W = (size_t)nx * ny * nz * s;
   p->bytes_phi_ext = (size_t)(nx + 2) * (ny + 2) * (nz + 2) * s;
-  p->bytes_E4 = (size_t)4 * nx * ny * nz * s;
   const size_t G64 = (size_t)(nx + 1) * (ny + 1) * (nz + 1) * sizeof(double);
   const size_t COS = ((size_t)(nx + 1) * (nx + 1) + (size_t)(ny + 1) * (ny + 1) + (size_t)(nz + 1) * (nz + 1)) *
                      sizeof(double);
-  const size_t r1 = std::max({A, C, p->bytes_E4, G64});
+  const size_t r1 = std::max({A, C, G64});
   const size_t r2 = std::max({B, D, G64});
   const size_t r3 = std::max({p->bytes_W, p->bytes_phi_ext, COS + 256});
+  BinGeom& bg = p->bg;
+  bg.tx = (nx - 1 + 15) / 16;    // cells per axis = n - 1, 16 per tile
+  bg.ty = (ny - 1 + 15) / 16;
+  bg.tz = (nz - 1 + 15) / 16;
+  bg.K = bg.tx * bg.ty * bg.tz;
+  bg.item = 65536;
+  bg.lds_hist = 2 * (size_t)(bg.K + 1) * sizeof(unsigned) <= 65536 ? 1 : 0;
+  p->bins_len = 4 * (bg.K + 1) + 6;
+  p->part_elem = 4 * s;
   size_t so = align256(sizeof(Geometry));
   p->s_bbox = so; so = align256(so + (size_t)kBboxBlocks * 6 * sizeof(double));
+  p->s_bins = so; so = align256(so + (size_t)p->bins_len * sizeof(unsigned));
   p->s_r1 = so; so = align256(so + r1);
   p->s_r2 = so; so = align256(so + r2);
   p->s_r3 = so; so = align256(so + r3);
@@ -356,22 +379,52 @@ GeoArgs geo_args(const dks_poisson_plan_s* p, int mode, int nblocks) {
   a.fitted = p->fitted ? 1 : 0;
   a.nblocks = nblocks;
   a.mode = mode;
+  a.zero_off = 0;
+  a.zero_len = 0;
   return a;
 }
 
-// Mesh fit (fitted plans), geometry, zero W, deposit: leaves W in R3.
+// Work split of one (batched) particle solve.
+struct PartWork {
+  BinGeom bg;
+  int count_blocks;   // blocks of the count and scatter kernels (same chunking)
+  int item_blocks;    // blocks of the deposit and gather kernels (loop over work items)
+};
+
+PartWork part_work(const dks_poisson_plan_s* p, const BatchScalars& bs, int batch) {
+  int64_t maxn = 0;
+  for (int b = 0; b < batch; ++b) maxn = std::max(maxn, bs.np[b]);
+  PartWork w;
+  w.bg = p->bg;
+  w.bg.item = (int)std::min<int64_t>(65536, std::max<int64_t>(8192, maxn / 512));
+  w.count_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (maxn + 8191) / 8192));
+  const int64_t items = (maxn + w.bg.item - 1) / w.bg.item + w.bg.K + 1;
+  w.item_blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(1, items));
+  return w;
+}
+
+// Mesh fit (fitted plans), geometry, particle binning and the binned deposit:
+// leaves the weights W in R3 and the binned particles in `sorted`.
 template <typename T>
 dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl, const PtrBatch& X,
                          const PtrBatch& Y, const PtrBatch& Z, const BatchScalars& bs, const PtrBatch& cnt,
-                         hipStream_t st) {
+                         char* sorted, size_t sorted_stride, const PartWork& w, hipStream_t st) {
   int nb = 0;
   double* bbox = reinterpret_cast<double*>(sl.base + p->s_bbox);
   if (p->fitted) DKS_TK("bbox", launch_bbox<T>(X, Y, Z, bs, batch, bbox, sl.stride / sizeof(double), &nb, st));
-  const GeoArgs ga = geo_args(p, 1, nb);
+  GeoArgs ga = geo_args(p, 1, nb);
+  ga.zero_off = p->s_bins;
+  ga.zero_len = p->bg.K + 1;
   DKS_TK("geometry", launch_geometry(bbox, sl.stride / sizeof(double), sl.geo(), sl.stride, ga, bs, cnt, batch, st));
   DKS_TK("zero_mesh", launch_zero(sl.base + p->s_r3, sl.stride, p->bytes_W, batch, st));
-  DKS_TK("deposit", launch_deposit<T>(X, Y, Z, bs, batch, sl.base + p->s_r3, sl.stride / sizeof(T), sl.geo(), sl.stride,
-                           p->md, cnt, st));
+  DKS_TK("bin_count", launch_bin_count<T>(X, Y, Z, bs, batch, sl.geo(), sl.stride, sl.base, p->s_bins, p->md, w.bg,
+                                          w.count_blocks, st));
+  DKS_TK("bin_scan", launch_bin_scan(sl.geo(), sl.stride, sl.base, p->s_bins, w.bg, cnt, batch, st));
+  DKS_TK("bin_scatter", launch_bin_scatter<T>(X, Y, Z, bs, batch, sl.geo(), sl.stride, sl.base, p->s_bins, sorted,
+                                              sorted_stride, p->md, w.bg, w.count_blocks, st));
+  DKS_TK("deposit", launch_deposit_binned<T>(sl.geo(), sl.stride, sl.base, p->s_bins, sorted, sorted_stride,
+                                             sl.base + p->s_r3, sl.stride / sizeof(T), p->md, w.bg, w.item_blocks,
+                                             batch, st));
   return DKS_OK;
 }
 
@@ -379,16 +432,15 @@ template <typename T>
 dks_status solve_particles_t(const dks_poisson_plan_s* p, int batch, const Slots& sl, const PtrBatch& X,
                              const PtrBatch& Y, const PtrBatch& Z, const PtrBatch& EX, const PtrBatch& EY,
                              const PtrBatch& EZ, const PtrBatch& PHI, const BatchScalars& bs,
-                             const PtrBatch& cnt, hipStream_t st) {
-  dks_status r = deposit_stage<T>(p, batch, sl, X, Y, Z, bs, cnt, st);
+                             const PtrBatch& cnt, char* sorted, size_t sorted_stride, hipStream_t st) {
+  const PartWork w = part_work(p, bs, batch);
+  dks_status r = deposit_stage<T>(p, batch, sl, X, Y, Z, bs, cnt, sorted, sorted_stride, w, st);
   if (r != DKS_OK) return r;
   r = convolve<T>(p, sl.base + p->s_r3, sl.stride / sizeof(T), batch, sl, PHI, st);
   if (r != DKS_OK) return r;
-  const size_t rstride = sl.stride / sizeof(T);
-  DKS_TK("gradient", (launch_gradient<T, true>(sl.base + p->s_r3, rstride, sl.base + p->s_r1, rstride, sl.geo(), sl.stride,
-                                   p->md, batch, st)));
-  DKS_TK("gather", (launch_gather<T, true>(sl.base + p->s_r1, rstride, X, Y, Z, EX, EY, EZ, bs, batch, sl.geo(), sl.stride,
-                                 p->md, st)));
+  DKS_TK("gather", launch_gather_binned<T>(sl.geo(), sl.stride, sl.base, p->s_bins, sorted, sorted_stride,
+                                           sl.base + p->s_r3, sl.stride / sizeof(T), EX, EY, EZ, p->md, w.bg,
+                                           w.item_blocks, batch, st));
   return DKS_OK;
 }
 
@@ -517,9 +569,24 @@ dks_status dks_poisson_workspace_bytes(dks_poisson_plan_t p, size_t* bytes) {
   return DKS_OK;
 }
 
-dks_status dks_poisson_batch_scratch_bytes(dks_poisson_plan_t p, int batch, size_t* bytes) {
-  if (!p || !bytes || batch < 1 || batch > kMaxBatch) return DKS_EINVAL;
-  *bytes = (size_t)batch * p->slot_bytes;
+dks_status dks_poisson_particle_scratch_bytes(dks_poisson_plan_t p, int64_t np, size_t* bytes) {
+  if (!p || !bytes || np < 0 || np > (int64_t)UINT32_MAX) return DKS_EINVAL;
+  *bytes = align256((size_t)np * p->part_elem);
+  return DKS_OK;
+}
+
+dks_status dks_poisson_set_particle_scratch(dks_poisson_plan_t p, void* scratch, size_t bytes) {
+  if (!p) return DKS_EINVAL;
+  if (bytes > 0 && (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255u))) return DKS_EWORKSPACE;
+  p->pscratch = static_cast<char*>(scratch);
+  p->pscratch_bytes = scratch ? bytes : 0;
+  return DKS_OK;
+}
+
+dks_status dks_poisson_batch_scratch_bytes(dks_poisson_plan_t p, int batch, int64_t max_np, size_t* bytes) {
+  if (!p || !bytes || batch < 1 || batch > kMaxBatch || max_np < 0 || max_np > (int64_t)UINT32_MAX)
+    return DKS_EINVAL;
+  *bytes = (size_t)batch * (p->slot_bytes + align256((size_t)max_np * p->part_elem));
   return DKS_OK;
 }
 
@@ -564,14 +631,14 @@ dks_status dks_poisson_solve_rho(dks_poisson_plan_t p, const void* rho, void* ph
     r = convolve<float>(p, rho, 0, 1, sl, one(phi), st);
     if (r == DKS_OK && E_mesh) {
       Timed tm("gradient", st);
-      r = hip_status(launch_gradient<float, false>(sl.base + p->s_r3, 0, E_mesh, 0, sl.geo(), 0, p->md, 1, st));
+      r = hip_status(launch_gradient<float>(sl.base + p->s_r3, E_mesh, sl.geo(), p->md, st));
       tm.done();
     }
   } else {
     r = convolve<double>(p, rho, 0, 1, sl, one(phi), st);
     if (r == DKS_OK && E_mesh) {
       Timed tm("gradient", st);
-      r = hip_status(launch_gradient<double, false>(sl.base + p->s_r3, 0, E_mesh, 0, sl.geo(), 0, p->md, 1, st));
+      r = hip_status(launch_gradient<double>(sl.base + p->s_r3, E_mesh, sl.geo(), p->md, st));
       tm.done();
     }
   }
@@ -582,9 +649,10 @@ dks_status dks_poisson_solve_rho(dks_poisson_plan_t p, const void* rho, void* ph
 dks_status dks_poisson_solve_particles(dks_poisson_plan_t p, const void* x, const void* y, const void* z,
                                        int64_t np, double q, void* Ex, void* Ey, void* Ez, void* phi,
                                        int64_t* n_outside, dks_stream_t stream) {
-  if (!p || np < 0 || !std::isfinite(q)) return DKS_EINVAL;
+  if (!p || np < 0 || np > (int64_t)UINT32_MAX || !std::isfinite(q)) return DKS_EINVAL;
   if (np > 0 && (!x || !y || !z || !Ex || !Ey || !Ez)) return DKS_EINVAL;
   if (!ws_ready(p)) return DKS_EWORKSPACE;
+  if ((size_t)np * p->part_elem > p->pscratch_bytes) return DKS_EWORKSPACE;
   if (!p->prepared) return DKS_ESTATE;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   Slots sl{p->ws + p->off_slot, p->slot_bytes};
@@ -595,9 +663,9 @@ dks_status dks_poisson_solve_particles(dks_poisson_plan_t p, const void* x, cons
   const dks_status r =
       p->dtype == DKS_F32
           ? solve_particles_t<float>(p, 1, sl, one(x), one(y), one(z), one(Ex), one(Ey), one(Ez), one(phi), bs,
-                                     one(n_outside), st)
+                                     one(n_outside), p->pscratch, 0, st)
           : solve_particles_t<double>(p, 1, sl, one(x), one(y), one(z), one(Ex), one(Ey), one(Ez), one(phi), bs,
-                                      one(n_outside), st);
+                                      one(n_outside), p->pscratch, 0, st);
   if (r == DKS_OK) p->has_geometry = true;
   return r;
 }
@@ -611,15 +679,19 @@ dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, 
     return DKS_EINVAL;
   if (!ws_ready(p)) return DKS_EWORKSPACE;
   if (!p->prepared) return DKS_ESTATE;
-  if (!scratch || scratch_bytes < (size_t)batch * p->slot_bytes || (reinterpret_cast<uintptr_t>(scratch) & 255u))
-    return DKS_EWORKSPACE;
+  if (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255u)) return DKS_EWORKSPACE;
+  // Element b owns [b * stride, (b + 1) * stride): its slot, then its binned particles.
+  const size_t stride = (scratch_bytes / (size_t)batch) & ~(size_t)255;
+  if (stride < p->slot_bytes) return DKS_EWORKSPACE;
+  const size_t part_cap = (stride - p->slot_bytes) / p->part_elem;
   PtrBatch X, Y, Z, EX, EY, EZ, PHI, CNT;
   BatchScalars bs;
   std::memset(&X, 0, sizeof(X)); std::memset(&Y, 0, sizeof(Y)); std::memset(&Z, 0, sizeof(Z));
   std::memset(&EX, 0, sizeof(EX)); std::memset(&EY, 0, sizeof(EY)); std::memset(&EZ, 0, sizeof(EZ));
   std::memset(&PHI, 0, sizeof(PHI)); std::memset(&CNT, 0, sizeof(CNT)); std::memset(&bs, 0, sizeof(bs));
   for (int b = 0; b < batch; ++b) {
-    if (np[b] < 0 || !std::isfinite(q[b])) return DKS_EINVAL;
+    if (np[b] < 0 || np[b] > (int64_t)UINT32_MAX || !std::isfinite(q[b])) return DKS_EINVAL;
+    if ((size_t)np[b] > part_cap) return DKS_EWORKSPACE;
     if (np[b] > 0 && (!x[b] || !y[b] || !z[b] || !Ex[b] || !Ey[b] || !Ez[b])) return DKS_EINVAL;
     X.p[b] = const_cast<void*>(x[b]);
     Y.p[b] = const_cast<void*>(y[b]);
@@ -633,16 +705,19 @@ dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, 
     bs.q[b] = q[b];
   }
   const hipStream_t st = static_cast<hipStream_t>(stream);
-  Slots sl{static_cast<char*>(scratch), p->slot_bytes};
-  return p->dtype == DKS_F32 ? solve_particles_t<float>(p, batch, sl, X, Y, Z, EX, EY, EZ, PHI, bs, CNT, st)
-                             : solve_particles_t<double>(p, batch, sl, X, Y, Z, EX, EY, EZ, PHI, bs, CNT, st);
+  Slots sl{static_cast<char*>(scratch), stride};
+  char* sorted = static_cast<char*>(scratch) + p->slot_bytes;
+  return p->dtype == DKS_F32
+             ? solve_particles_t<float>(p, batch, sl, X, Y, Z, EX, EY, EZ, PHI, bs, CNT, sorted, stride, st)
+             : solve_particles_t<double>(p, batch, sl, X, Y, Z, EX, EY, EZ, PHI, bs, CNT, sorted, stride, st);
 }
 
 dks_status dks_poisson_deposit(dks_poisson_plan_t p, const void* x, const void* y, const void* z, int64_t np,
                                double q, void* rho, int64_t* n_outside, dks_stream_t stream) {
-  if (!p || !rho || np < 0 || !std::isfinite(q)) return DKS_EINVAL;
+  if (!p || !rho || np < 0 || np > (int64_t)UINT32_MAX || !std::isfinite(q)) return DKS_EINVAL;
   if (np > 0 && (!x || !y || !z)) return DKS_EINVAL;
   if (!ws_ready(p)) return DKS_EWORKSPACE;
+  if ((size_t)np * p->part_elem > p->pscratch_bytes) return DKS_EWORKSPACE;
   if (!p->prepared) return DKS_ESTATE;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   Slots sl{p->ws + p->off_slot, p->slot_bytes};
@@ -650,13 +725,14 @@ dks_status dks_poisson_deposit(dks_poisson_plan_t p, const void* x, const void* 
   std::memset(&bs, 0, sizeof(bs));
   bs.np[0] = np;
   bs.q[0] = q;
+  const PartWork w = part_work(p, bs, 1);
   const size_t nmesh = (size_t)p->n[0] * p->n[1] * p->n[2];
   dks_status r;
   if (p->dtype == DKS_F32) {
-    r = deposit_stage<float>(p, 1, sl, one(x), one(y), one(z), bs, one(n_outside), st);
+    r = deposit_stage<float>(p, 1, sl, one(x), one(y), one(z), bs, one(n_outside), p->pscratch, 0, w, st);
     if (r == DKS_OK) r = hip_status(launch_weights_to_density<float>(sl.base + p->s_r3, rho, nmesh, sl.geo(), q, st));
   } else {
-    r = deposit_stage<double>(p, 1, sl, one(x), one(y), one(z), bs, one(n_outside), st);
+    r = deposit_stage<double>(p, 1, sl, one(x), one(y), one(z), bs, one(n_outside), p->pscratch, 0, w, st);
     if (r == DKS_OK) r = hip_status(launch_weights_to_density<double>(sl.base + p->s_r3, rho, nmesh, sl.geo(), q, st));
   }
   if (r == DKS_OK) p->has_geometry = true;
@@ -681,14 +757,9 @@ dks_status dks_poisson_gather(dks_poisson_plan_t p, const void* E_mesh, const vo
   } else if (!p->has_geometry) {
     return DKS_ESTATE;
   }
-  BatchScalars bs;
-  std::memset(&bs, 0, sizeof(bs));
-  bs.np[0] = np;
   if (p->dtype == DKS_F32)
-    return hip_status(launch_gather<float, false>(E_mesh, 0, one(x), one(y), one(z), one(Ex), one(Ey), one(Ez), bs,
-                                                  1, sl.geo(), 0, p->md, st));
-  return hip_status(launch_gather<double, false>(E_mesh, 0, one(x), one(y), one(z), one(Ex), one(Ey), one(Ez), bs, 1,
-                                                 sl.geo(), 0, p->md, st));
+    return hip_status(launch_gather<float>(E_mesh, x, y, z, Ex, Ey, Ez, np, sl.geo(), p->md, st));
+  return hip_status(launch_gather<double>(E_mesh, x, y, z, Ex, Ey, Ez, np, sl.geo(), p->md, st));
 }
 
 dks_status dks_poisson_geometry(dks_poisson_plan_t p, dks_stream_t stream, double* h, double* origin) {

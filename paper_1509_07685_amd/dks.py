@@ -24,7 +24,8 @@ DKS_F64 = 1
 
 EXPORTS = (
     "dks_poisson_plan", "dks_poisson_set_origin", "dks_poisson_workspace_bytes",
-    "dks_poisson_batch_scratch_bytes", "dks_poisson_set_workspace", "dks_poisson_prepare",
+    "dks_poisson_batch_scratch_bytes", "dks_poisson_particle_scratch_bytes",
+    "dks_poisson_set_particle_scratch", "dks_poisson_set_workspace", "dks_poisson_prepare",
     "dks_poisson_solve_rho", "dks_poisson_solve_particles", "dks_poisson_solve_particles_batched",
     "dks_poisson_deposit", "dks_poisson_gather", "dks_poisson_geometry", "dks_poisson_destroy",
     "dks_status_string", "dks_timing_enable", "dks_timing_read",
@@ -56,7 +57,9 @@ _SIGS = {
     "dks_poisson_plan": (_i, [_i, _i, _i, _d, _d, _d, _i, ctypes.POINTER(_PLAN)]),
     "dks_poisson_set_origin": (_i, [_PLAN, _d, _d, _d]),
     "dks_poisson_workspace_bytes": (_i, [_PLAN, ctypes.POINTER(_sz)]),
-    "dks_poisson_batch_scratch_bytes": (_i, [_PLAN, _i, ctypes.POINTER(_sz)]),
+    "dks_poisson_batch_scratch_bytes": (_i, [_PLAN, _i, _i64, ctypes.POINTER(_sz)]),
+    "dks_poisson_particle_scratch_bytes": (_i, [_PLAN, _i64, ctypes.POINTER(_sz)]),
+    "dks_poisson_set_particle_scratch": (_i, [_PLAN, _vp, _sz]),
     "dks_poisson_set_workspace": (_i, [_PLAN, _vp, _sz]),
     "dks_poisson_prepare": (_i, [_PLAN, _vp]),
     "dks_poisson_solve_rho": (_i, [_PLAN, _vp, _vp, _vp, _vp]),
@@ -108,11 +111,22 @@ def dks_poisson_workspace_bytes(plan):
     return out.value
 
 
-def dks_poisson_batch_scratch_bytes(plan, batch):
+def dks_poisson_batch_scratch_bytes(plan, batch, max_np):
     out = _sz()
-    _check(_lib.dks_poisson_batch_scratch_bytes(plan, batch, ctypes.byref(out)),
+    _check(_lib.dks_poisson_batch_scratch_bytes(plan, batch, max_np, ctypes.byref(out)),
            "dks_poisson_batch_scratch_bytes")
     return out.value
+
+
+def dks_poisson_particle_scratch_bytes(plan, np_):
+    out = _sz()
+    _check(_lib.dks_poisson_particle_scratch_bytes(plan, np_, ctypes.byref(out)),
+           "dks_poisson_particle_scratch_bytes")
+    return out.value
+
+
+def dks_poisson_set_particle_scratch(plan, ptr, nbytes):
+    _check(_lib.dks_poisson_set_particle_scratch(plan, ptr, nbytes), "dks_poisson_set_particle_scratch")
 
 
 def dks_poisson_set_workspace(plan, ptr, nbytes):
@@ -229,6 +243,7 @@ class PoissonPlan:
         self.workspace_bytes = dks_poisson_workspace_bytes(self.handle)
         self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
         dks_poisson_set_workspace(self.handle, _ptr(self.workspace), self.workspace_bytes)
+        self.particle_scratch = None
         if prepare:
             self.prepare(stream)
 
@@ -256,9 +271,19 @@ class PoissonPlan:
         dks_poisson_solve_rho(self.handle, _ptr(rho), _ptr(phi), _ptr(E), _stream_handle(stream))
         return phi, E
 
+    def reserve_particles(self, npart):
+        """Attach (growing if needed) the binned-particle scratch for npart particles."""
+        torch = _torch()
+        need = dks_poisson_particle_scratch_bytes(self.handle, npart)
+        if self.particle_scratch is None or self.particle_scratch.numel() < need:
+            self.particle_scratch = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+            dks_poisson_set_particle_scratch(self.handle, _ptr(self.particle_scratch),
+                                             self.particle_scratch.numel())
+
     def solve_particles(self, x, y, z, q, want_phi=False, out=None, stream=None):
         torch = _torch()
         npart = x.numel()
+        self.reserve_particles(npart)
         for name, t in (("x", x), ("y", y), ("z", z)):
             self._check_tensor(t, (npart,), name)
         if out is None:
@@ -274,6 +299,7 @@ class PoissonPlan:
     def deposit(self, x, y, z, q, stream=None):
         torch = _torch()
         npart = x.numel()
+        self.reserve_particles(npart)
         rho = torch.empty(self.mesh_shape(), dtype=self.dtype, device=x.device)
         cnt = torch.zeros(1, dtype=torch.int64, device=x.device)
         dks_poisson_deposit(self.handle, _ptr(x), _ptr(y), _ptr(z), npart, float(q), _ptr(rho), _ptr(cnt),
@@ -292,9 +318,9 @@ class PoissonPlan:
     def geometry(self, stream=None):
         return dks_poisson_geometry(self.handle, _stream_handle(stream))
 
-    def batch_scratch(self, batch):
+    def batch_scratch(self, batch, max_np):
         torch = _torch()
-        nbytes = dks_poisson_batch_scratch_bytes(self.handle, batch)
+        nbytes = dks_poisson_batch_scratch_bytes(self.handle, batch, max_np)
         return torch.empty(nbytes, dtype=torch.uint8, device=self.device), nbytes
 
     def solve_particles_batched(self, xs, ys, zs, qs, scratch, outs, n_outside=None, phis=None, stream=None):

@@ -277,3 +277,67 @@ def test_full_size_mesh_solve_sampled_f32():
         want.append(orc.COULOMB_K * float(np.sum(w * G)))
         got.append(phi_h[k, j, i])
     assert rel_l2(got, want) <= TOL["f32"]
+
+
+# --------------------------------------------------------------------------
+# binned deposit/gather edge cases
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_dense_tile_spans_many_work_items(dt):
+    """150k particles packed into one 16^3-cell tile of an explicit 48^3 mesh:
+    the tile is split over many work items whose partial meshes are merged."""
+    n, h = (48, 48, 48), (1e-4, 1e-4, 1e-4)
+    origin = orc.centred_origin(n, h)
+    g = np.random.default_rng(31)
+    num = 150_000
+    pos = [origin[d] + (17.0 + 14.0 * g.random(num)) * h[d] for d in range(3)]
+    x, y, z = (a.astype(NP_DT[dt]) for a in pos)
+    q = 1e-15
+    plan = dks().PoissonPlan(n, h, dt)
+    rho, cnt = plan.deposit(dev(x, dt), dev(y, dt), dev(z, dt), q)
+    Q, n_out = orc.deposit_cic(x, y, z, q, n, h, origin, NP_DT[dt])
+    assert int(host(cnt)[0]) == n_out == 0
+    assert rel_l2(host(rho), Q / (h[0] * h[1] * h[2])) <= TOL[dt]
+    (Ex, Ey, Ez), phi, _ = plan.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), q, want_phi=True)
+    ref = orc.solve_particles(x, y, z, q, n, h, dtype=NP_DT[dt])
+    assert rel_l2(np.stack([host(Ex), host(Ey), host(Ez)]), ref["E"]) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_particles_on_tile_boundaries_and_mesh_edges(dt):
+    """Particles exactly on nodes at tile boundaries (cell coordinate 16, 32),
+    on the last node (n - 1), on the first node, and just outside."""
+    n, h = (40, 34, 33), (1.0, 1.0, 1.0)
+    origin = (0.0, 0.0, 0.0)
+    g = np.random.default_rng(8)
+    grid = np.array([0.0, 15.5, 16.0, 31.999, 32.0, 32.5])
+    xs, ys, zs = np.meshgrid(np.r_[grid, 39.0, -0.001, 39.001], np.r_[grid, 33.0], np.r_[grid, 32.0],
+                             indexing="ij")
+    x, y, z = (a.ravel().astype(NP_DT[dt]) for a in (xs, ys, zs))
+    extra = [g.uniform(0, nd - 1, 5000) for nd in n]
+    x, y, z = (np.concatenate([a, b.astype(NP_DT[dt])]) for a, b in zip((x, y, z), extra))
+    plan = dks().PoissonPlan(n, h, dt)
+    plan.set_origin(origin)
+    (Ex, Ey, Ez), phi, cnt = plan.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), 1e-12, want_phi=True)
+    ref = orc.solve_particles(x, y, z, 1e-12, n, h, origin=origin, dtype=NP_DT[dt])
+    assert int(host(cnt)[0]) == ref["n_outside"] > 0
+    assert rel_l2(host(phi), ref["phi_ext"][1:-1, 1:-1, 1:-1]) <= TOL[dt]
+    assert rel_l2(np.stack([host(Ex), host(Ey), host(Ez)]), ref["E"]) <= TOL[dt]
+
+
+def test_repeated_solves_reuse_state():
+    """Ten solves in a row on one plan give the same answer each time (to FP32
+    atomics reordering), with n_outside rewritten, not accumulated."""
+    cfg = wl.SMALL_GAUSSIAN
+    x, y, z = wl.particles_for(cfg, dtype="f32")
+    plan = dks().PoissonPlan(cfg.n, cfg.h, "f32")
+    tx, ty, tz = dev(x, "f32"), dev(y, "f32"), dev(z, "f32")
+    first = None
+    for _ in range(10):
+        (Ex, Ey, Ez), _, cnt = plan.solve_particles(tx, ty, tz, cfg.charge_per_particle)
+        e = np.stack([host(Ex), host(Ey), host(Ez)])
+        if first is None:
+            first, n0 = e, int(host(cnt)[0])
+        assert int(host(cnt)[0]) == n0
+        assert rel_l2(e, first) <= 1e-6
