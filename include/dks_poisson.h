@@ -151,21 +151,26 @@ dks_status dks_poisson_solve_particles(dks_poisson_plan_t plan, const void* x, c
 /* The same step for `batch` independent particle sets of the plan's shape
  * and dtype, each kernel launched once over the whole batch (the batch index
  * is part of the grid).  On a fitted plan every element gets its own mesh fit;
- * the cached spectrum is scaled per element by h_b^2.
+ * the cached spectrum is scaled per element by h_b^2.  Counts and charges are
+ * read from device memory when the kernels run, so a captured HIP graph of
+ * this call can be replayed with new counts, charges and particle data (at
+ * the same addresses).
  *   batch           : 1 .. 16 elements.
  *   x, y, z, Ex, Ey, Ez : host arrays of `batch` device pointers.
- *   np, q           : host arrays of `batch` counts and per-particle charges.
+ *   np              : device int64[batch] particle counts.
+ *   q               : device double[batch] charge per particle of each element.
+ *   max_np          : host bound on every np[b]; larger counts are clamped to it.
  *   phi             : host array of `batch` device pointers (entries may be
  *                     NULL), or NULL.
- *   scratch         : device, >= dks_poisson_batch_scratch_bytes(batch, max np),
+ *   scratch         : device, >= dks_poisson_batch_scratch_bytes(batch, max_np),
  *                     256-byte aligned, caller-owned; element b uses the
  *                     b-th of `batch` equal parts (rounded down to 256 bytes).
  *   n_outside       : device int64[batch], written; may be NULL. */
 dks_status dks_poisson_solve_particles_batched(
     dks_poisson_plan_t plan, int batch, const void* const* x, const void* const* y,
-    const void* const* z, const int64_t* np, const double* q, void* const* Ex, void* const* Ey,
-    void* const* Ez, void* const* phi, void* scratch, size_t scratch_bytes, int64_t* n_outside,
-    dks_stream_t stream);
+    const void* const* z, const int64_t* np, const double* q, int64_t max_np, void* const* Ex,
+    void* const* Ey, void* const* Ez, void* const* phi, void* scratch, size_t scratch_bytes,
+    int64_t* n_outside, dks_stream_t stream);
 
 /* Charge deposit alone (CIC assignment, the "NGP, CIC, TSI" box of the OPAL
  * structure figure), including the mesh fit of a fitted plan.

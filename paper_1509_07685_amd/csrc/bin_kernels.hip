@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_bin_count(PtrBatch xs, PtrBatch ys, Ptr
   const Geometry* g = geo_of(geo, stride, b);
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
   int64_t start, end;
-  chunk_of(bs.np[b], blockIdx.x, gridDim.x, &start, &end);
+  chunk_of(bs.n(b), blockIdx.x, gridDim.x, &start, &end);
   if (LDSHIST) {
     for (int k = threadIdx.x; k <= bg.K; k += blockDim.x) hist[k] = 0;
     __syncthreads();
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(PtrBatch xs, PtrBatch ys, P
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
   P4* out = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
   int64_t start, end;
-  chunk_of(bs.np[b], blockIdx.x, gridDim.x, &start, &end);
+  chunk_of(bs.n(b), blockIdx.x, gridDim.x, &start, &end);
   if (LDSHIST) {
     for (int k = threadIdx.x; k <= bg.K; k += blockDim.x) lcnt[k] = 0;
     __syncthreads();

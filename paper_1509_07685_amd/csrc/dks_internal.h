@@ -90,10 +90,22 @@ struct PtrBatch {
   void* p[kMaxBatch];
 };
 
-// Per-element particle counts and charges of a (batched) particle solve.
+// Per-element particle counts and charges of a (batched) particle solve:
+// by value, or (np_dev / q_dev set) read from device memory when the kernels
+// run, so that a captured graph can be replayed with new counts.  max_np
+// bounds every count; it sizes the launches on the host.
 struct BatchScalars {
   int64_t np[kMaxBatch];
   double q[kMaxBatch];
+  const int64_t* np_dev;
+  const double* q_dev;
+  int64_t max_np;
+  __device__ __forceinline__ int64_t n(int b) const {
+    if (!np_dev) return np[b];
+    const int64_t v = np_dev[b];
+    return v < 0 ? 0 : (v > max_np ? max_np : v);
+  }
+  __device__ __forceinline__ double charge(int b) const { return q_dev ? q_dev[b] : q[b]; }
 };
 
 // Arguments of the per-solve geometry kernel.

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void k_bbox(PtrBatch xs, PtrBatch ys, PtrBatch
                                               double* partial, size_t partial_stride) {
   const int b = blockIdx.y;
   const T* p[3] = {(const T*)xs.p[b], (const T*)ys.p[b], (const T*)zs.p[b]};
-  const int64_t n = bs.np[b];
+  const int64_t n = bs.n(b);
   T lo[3], hi[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_geometry(const double* partial, size_t 
   double h[3], origin[3];
   if (a.fitted) {
     double lo[3], hi[3];
-    const bool empty = bs.np[b] <= 0;
+    const bool empty = bs.n(b) <= 0;
     for (int d = 0; d < 3; ++d) {
       lo[d] = empty ? 0.0 : red[d][0];
       hi[d] = empty ? 0.0 : red[3 + d][0];
@@ -143,8 +143,8 @@ __global__ __launch_bounds__(256) void k_geometry(const double* partial, size_t 
   const double coulomb = 1.0 / (4.0 * M_PI * kEps0);
   double scale;
   if (a.mode == 0) scale = coulomb;                                   // rho given in C/m^3
-  else if (a.fitted) scale = coulomb * bs.q[b] / h[0];                // spectrum built for h = 1 m
-  else scale = coulomb * bs.q[b] / (h[0] * h[1] * h[2]);             // rho = q W / V
+  else if (a.fitted) scale = coulomb * bs.charge(b) / h[0];                // spectrum built for h = 1 m
+  else scale = coulomb * bs.charge(b) / (h[0] * h[1] * h[2]);             // rho = q W / V
   for (int d = 0; d < 3; ++d) {
     g->h[d] = h[d];
     g->origin[d] = origin[d];
@@ -259,9 +259,7 @@ static inline unsigned grid_for(int64_t n, unsigned cap) {
 template <typename T>
 hipError_t launch_bbox(const PtrBatch& xs, const PtrBatch& ys, const PtrBatch& zs, const BatchScalars& bs,
                        int batch, double* partial, size_t partial_stride, int* nblocks_out, hipStream_t s) {
-  int64_t maxn = 0;
-  for (int b = 0; b < batch; ++b) maxn = std::max(maxn, bs.np[b]);
-  const unsigned nb = grid_for(maxn, kBboxBlocks);
+  const unsigned nb = grid_for(bs.max_np, kBboxBlocks);
   *nblocks_out = (int)nb;
   hipLaunchKernelGGL(k_bbox<T>, dim3(nb, batch), dim3(256), 0, s, xs, ys, zs, bs, partial, partial_stride);
   return hipGetLastError();

@@ -392,8 +392,7 @@ struct PartWork {
 };
 
 PartWork part_work(const dks_poisson_plan_s* p, const BatchScalars& bs, int batch) {
-  int64_t maxn = 0;
-  for (int b = 0; b < batch; ++b) maxn = std::max(maxn, bs.np[b]);
+  const int64_t maxn = bs.max_np;
   PartWork w;
   w.bg = p->bg;
   w.bg.item = (int)std::min<int64_t>(65536, std::max<int64_t>(8192, maxn / 512));
@@ -660,6 +659,7 @@ dks_status dks_poisson_solve_particles(dks_poisson_plan_t p, const void* x, cons
   std::memset(&bs, 0, sizeof(bs));
   bs.np[0] = np;
   bs.q[0] = q;
+  bs.max_np = np;
   const dks_status r =
       p->dtype == DKS_F32
           ? solve_particles_t<float>(p, 1, sl, one(x), one(y), one(z), one(Ex), one(Ey), one(Ez), one(phi), bs,
@@ -672,27 +672,25 @@ dks_status dks_poisson_solve_particles(dks_poisson_plan_t p, const void* x, cons
 
 dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, const void* const* x,
                                                const void* const* y, const void* const* z, const int64_t* np,
-                                               const double* q, void* const* Ex, void* const* Ey,
+                                               const double* q, int64_t max_np, void* const* Ex, void* const* Ey,
                                                void* const* Ez, void* const* phi, void* scratch,
                                                size_t scratch_bytes, int64_t* n_outside, dks_stream_t stream) {
   if (!p || batch < 1 || batch > kMaxBatch || !x || !y || !z || !np || !q || !Ex || !Ey || !Ez)
     return DKS_EINVAL;
+  if (max_np < 0 || max_np > (int64_t)UINT32_MAX) return DKS_EINVAL;
   if (!ws_ready(p)) return DKS_EWORKSPACE;
   if (!p->prepared) return DKS_ESTATE;
   if (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255u)) return DKS_EWORKSPACE;
   // Element b owns [b * stride, (b + 1) * stride): its slot, then its binned particles.
   const size_t stride = (scratch_bytes / (size_t)batch) & ~(size_t)255;
-  if (stride < p->slot_bytes) return DKS_EWORKSPACE;
-  const size_t part_cap = (stride - p->slot_bytes) / p->part_elem;
+  if (stride < p->slot_bytes || (stride - p->slot_bytes) / p->part_elem < (size_t)max_np) return DKS_EWORKSPACE;
   PtrBatch X, Y, Z, EX, EY, EZ, PHI, CNT;
   BatchScalars bs;
   std::memset(&X, 0, sizeof(X)); std::memset(&Y, 0, sizeof(Y)); std::memset(&Z, 0, sizeof(Z));
   std::memset(&EX, 0, sizeof(EX)); std::memset(&EY, 0, sizeof(EY)); std::memset(&EZ, 0, sizeof(EZ));
   std::memset(&PHI, 0, sizeof(PHI)); std::memset(&CNT, 0, sizeof(CNT)); std::memset(&bs, 0, sizeof(bs));
   for (int b = 0; b < batch; ++b) {
-    if (np[b] < 0 || np[b] > (int64_t)UINT32_MAX || !std::isfinite(q[b])) return DKS_EINVAL;
-    if ((size_t)np[b] > part_cap) return DKS_EWORKSPACE;
-    if (np[b] > 0 && (!x[b] || !y[b] || !z[b] || !Ex[b] || !Ey[b] || !Ez[b])) return DKS_EINVAL;
+    if (max_np > 0 && (!x[b] || !y[b] || !z[b] || !Ex[b] || !Ey[b] || !Ez[b])) return DKS_EINVAL;
     X.p[b] = const_cast<void*>(x[b]);
     Y.p[b] = const_cast<void*>(y[b]);
     Z.p[b] = const_cast<void*>(z[b]);
@@ -701,9 +699,10 @@ dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, 
     EZ.p[b] = Ez[b];
     PHI.p[b] = phi ? phi[b] : nullptr;
     CNT.p[b] = n_outside ? n_outside + b : nullptr;
-    bs.np[b] = np[b];
-    bs.q[b] = q[b];
   }
+  bs.np_dev = np;
+  bs.q_dev = q;
+  bs.max_np = max_np;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   Slots sl{static_cast<char*>(scratch), stride};
   char* sorted = static_cast<char*>(scratch) + p->slot_bytes;
@@ -725,6 +724,7 @@ dks_status dks_poisson_deposit(dks_poisson_plan_t p, const void* x, const void* 
   std::memset(&bs, 0, sizeof(bs));
   bs.np[0] = np;
   bs.q[0] = q;
+  bs.max_np = np;
   const PartWork w = part_work(p, bs, 1);
   const size_t nmesh = (size_t)p->n[0] * p->n[1] * p->n[2];
   dks_status r;

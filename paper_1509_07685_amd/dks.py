@@ -64,8 +64,8 @@ _SIGS = {
     "dks_poisson_prepare": (_i, [_PLAN, _vp]),
     "dks_poisson_solve_rho": (_i, [_PLAN, _vp, _vp, _vp, _vp]),
     "dks_poisson_solve_particles": (_i, [_PLAN, _vp, _vp, _vp, _i64, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
-    "dks_poisson_solve_particles_batched": (_i, [_PLAN, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                                                 _vp, _sz, _vp, _vp]),
+    "dks_poisson_solve_particles_batched": (_i, [_PLAN, _i, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp,
+                                                 _vp, _vp, _sz, _vp, _vp]),
     "dks_poisson_deposit": (_i, [_PLAN, _vp, _vp, _vp, _i64, _d, _vp, _vp, _vp]),
     "dks_poisson_gather": (_i, [_PLAN, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
     "dks_poisson_geometry": (_i, [_PLAN, _vp, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
@@ -151,15 +151,14 @@ def _ptr_array(ptrs):
     return arr
 
 
-def dks_poisson_solve_particles_batched(plan, batch, x, y, z, np_, q, Ex, Ey, Ez, phi, scratch,
-                                        scratch_bytes, n_outside, stream):
-    keep = [_ptr_array(a) for a in (x, y, z, Ex, Ey, Ez)]
+def dks_poisson_solve_particles_batched(plan, batch, x, y, z, np_dev, q_dev, max_np, Ex, Ey, Ez, phi,
+                                        scratch, scratch_bytes, n_outside, stream):
+    """x..Ez, phi: sequences of device addresses (ints); np_dev, q_dev: device pointers."""
+    arrs = [_ptr_array(a) for a in (x, y, z, Ex, Ey, Ez)]
     phi_arr = _ptr_array(phi) if phi is not None else None
-    nps = (_i64 * batch)(*np_)
-    qs = (_d * batch)(*q)
     st = _lib.dks_poisson_solve_particles_batched(
-        plan, batch, *[ctypes.cast(a, _vp) for a in keep[:3]], ctypes.cast(nps, _vp),
-        ctypes.cast(qs, _vp), *[ctypes.cast(a, _vp) for a in keep[3:]],
+        plan, batch, *[ctypes.cast(a, _vp) for a in arrs[:3]], np_dev, q_dev, max_np,
+        *[ctypes.cast(a, _vp) for a in arrs[3:]],
         ctypes.cast(phi_arr, _vp) if phi_arr is not None else None, scratch, scratch_bytes, n_outside,
         stream)
     _check(st, "dks_poisson_solve_particles_batched")
@@ -323,12 +322,16 @@ class PoissonPlan:
         nbytes = dks_poisson_batch_scratch_bytes(self.handle, batch, max_np)
         return torch.empty(nbytes, dtype=torch.uint8, device=self.device), nbytes
 
-    def solve_particles_batched(self, xs, ys, zs, qs, scratch, outs, n_outside=None, phis=None, stream=None):
+    def solve_particles_batched(self, xs, ys, zs, np_dev, q_dev, max_np, outs, scratch, n_outside=None,
+                                phis=None, stream=None):
+        """One batched launch; xs..zs and outs[b] = (Ex, Ey, Ez) are device tensors
+        (fixed addresses if the call is captured), np_dev / q_dev device tensors
+        (int64 / float64) holding each element's count and per-particle charge."""
         batch = len(xs)
         buf, nbytes = scratch
         dks_poisson_solve_particles_batched(
             self.handle, batch, [t.data_ptr() for t in xs], [t.data_ptr() for t in ys],
-            [t.data_ptr() for t in zs], [t.numel() for t in xs], [float(q) for q in qs],
+            [t.data_ptr() for t in zs], _ptr(np_dev), _ptr(q_dev), int(max_np),
             [o[0].data_ptr() for o in outs], [o[1].data_ptr() for o in outs], [o[2].data_ptr() for o in outs],
             None if phis is None else [p.data_ptr() if p is not None else 0 for p in phis],
             _ptr(buf), nbytes, _ptr(n_outside), _stream_handle(stream))

@@ -1,0 +1,436 @@
+"""Continuous-batching server for free-space Poisson solves of mixed sizes.
+
+Requests (mesh shape, dtype, particles already on the device, charge) arrive
+on a clock.  The scheduler:
+
+  * keeps one prepared plan per (shape, dtype) resident: twiddles and the
+    FP64-built Green's spectrum are computed once and reused by every request
+    of that shape (a fitted cubic mesh scales the cached spectrum by h^2);
+  * admits work by an HBM byte budget: executors (staging buffers, batch
+    scratch, outputs) are created lazily while the budget allows, idle ones
+    are evicted least-recently-used when another shape needs the room, and a
+    request whose executor can never fit is refused;
+  * forms batches continuously: whenever a stream and an idle executor are
+    free, all waiting requests of the shape whose oldest request has waited
+    longest (up to the batch cap) go out as one batched launch, i.e. every
+    kernel of the step runs once over the batch;
+  * replays a HIP graph captured once per (shape, dtype, batch size) for that
+    launch, on one of several streams, so batches of different shapes overlap
+    on the device;
+  * records latency = completion observed - scheduled arrival, and reports
+    p50/p99 beside throughput.
+
+The scheduler is plain Python and talks to a backend; `GpuBackend` drives
+the HIP library through its C ABI (all solve work runs in the library's
+kernels; torch supplies memory, streams, events and graph capture), and the
+CPU tests drive the same scheduler with a modelled backend.
+"""
+
+import collections
+import dataclasses
+import math
+import time
+
+GiB = 1 << 30
+
+
+@dataclasses.dataclass
+class Job:
+    rid: int
+    arrival_s: float
+    key: tuple            # (shape, dtype)
+    num_particles: int
+    charge: float
+    payload: object = None       # backend-specific (device tensors)
+    start_s: float = None
+    done_s: float = None
+    batch_size: int = None
+    status: str = "waiting"      # waiting | running | done | refused | failed
+
+
+@dataclasses.dataclass
+class Stats:
+    completed: int
+    refused: int
+    failed: int
+    wall_s: float
+    throughput: float
+    p50_ms: float
+    p99_ms: float
+    mean_ms: float
+    batch_hist: dict
+    executors_created: int
+    evictions: int
+    peak_bytes: int
+
+    def as_dict(self):
+        return dataclasses.asdict(self)
+
+
+def percentile(values, q):
+    if not values:
+        return float("nan")
+    v = sorted(values)
+    k = (len(v) - 1) * q
+    lo, hi = math.floor(k), math.ceil(k)
+    return v[lo] + (v[hi] - v[lo]) * (k - lo)
+
+
+class Scheduler:
+    """Continuous batching over a backend.
+
+    backend must provide:
+      executor_bytes(key) -> int          device bytes an executor of `key` holds
+      plan_bytes(key) -> int              bytes of the resident plan of `key`
+      create_executor(key) -> ex          allocate (and prepare) an executor
+      destroy_executor(ex)
+      launch(ex, jobs, stream) -> token   enqueue one batched solve, non-blocking
+      done(token) -> bool                 has the launch completed
+      error(token) -> str or None
+      num_streams, max_batch
+    """
+
+    def __init__(self, backend, budget_bytes=64 * GiB, clock=time.perf_counter, idle_wait_s=0.0):
+        self.be = backend
+        self.budget = budget_bytes
+        self.clock = clock
+        self.idle_wait_s = idle_wait_s
+        self.plans = {}                              # key -> bytes (resident plans)
+        self.idle = collections.defaultdict(list)    # key -> [executor]
+        self.busy = {}                               # token -> (executor, jobs, stream)
+        self.lru = collections.OrderedDict()         # executor id -> (key, executor) of idle executors
+        self.used = 0
+        self.peak = 0
+        self.created = 0
+        self.evictions = 0
+
+    # -- memory -------------------------------------------------------------
+    def _reserve(self, nbytes):
+        if self.used + nbytes > self.budget:
+            return False
+        self.used += nbytes
+        self.peak = max(self.peak, self.used)
+        return True
+
+    def _evict_one(self, keep_key):
+        for exid, (key, ex) in list(self.lru.items()):
+            if key == keep_key:
+                continue
+            self.lru.pop(exid)
+            self.idle[key].remove(ex)
+            self.be.destroy_executor(ex)
+            self.used -= self.be.executor_bytes(key)
+            self.evictions += 1
+            return True
+        return False
+
+    def _executor_for(self, key):
+        """An idle executor of `key`, creating one within the budget; None if not now."""
+        if self.idle[key]:
+            ex = self.idle[key].pop()
+            self.lru.pop(id(ex), None)
+            return ex
+        if key not in self.plans:
+            need = self.be.plan_bytes(key)
+            while not self._reserve(need):
+                if not self._evict_one(key):
+                    return None
+            self.plans[key] = need
+        need = self.be.executor_bytes(key)
+        while not self._reserve(need):
+            if not self._evict_one(key):
+                return None
+        self.created += 1
+        return self.be.create_executor(key)
+
+    def _fits_ever(self, key):
+        return self.be.plan_bytes(key) + self.be.executor_bytes(key) <= self.budget
+
+    # -- main loop ----------------------------------------------------------
+    def run(self, jobs):
+        """Serve `jobs` (sorted by arrival) to completion; returns Stats."""
+        pending = collections.deque(sorted(jobs, key=lambda j: j.arrival_s))
+        queues = collections.defaultdict(collections.deque)   # key -> waiting jobs
+        free_streams = list(range(self.be.num_streams))
+        finished = []
+        t0 = self.clock()
+        while pending or any(queues.values()) or self.busy:
+            now = self.clock() - t0
+            while pending and pending[0].arrival_s <= now:
+                j = pending.popleft()
+                if not self._fits_ever(j.key):
+                    j.status = "refused"
+                    finished.append(j)
+                    continue
+                queues[j.key].append(j)
+            progressed = False
+            for token in list(self.busy):
+                if self.be.done(token):
+                    ex, batch, stream = self.busy.pop(token)
+                    t_done = self.clock() - t0
+                    err = self.be.error(token)
+                    for j in batch:
+                        j.done_s = t_done
+                        j.status = "failed" if err else "done"
+                        finished.append(j)
+                    self.idle[ex.key].append(ex)
+                    self.lru[id(ex)] = (ex.key, ex)
+                    free_streams.append(stream)
+                    progressed = True
+            while free_streams:
+                ready = [(q[0].arrival_s, q[0].rid, k) for k, q in queues.items() if q]
+                if not ready:
+                    break
+                launched = False
+                for _, _, key in sorted(ready):
+                    ex = self._executor_for(key)
+                    if ex is None:
+                        continue
+                    q = queues[key]
+                    batch = [q.popleft() for _ in range(min(len(q), self.be.max_batch))]
+                    stream = free_streams.pop()
+                    t_start = self.clock() - t0
+                    for j in batch:
+                        j.start_s = t_start
+                        j.batch_size = len(batch)
+                        j.status = "running"
+                    token = self.be.launch(ex, batch, stream)
+                    self.busy[token] = (ex, batch, stream)
+                    launched = progressed = True
+                    break
+                if not launched:
+                    break
+            if not progressed and self.idle_wait_s:
+                time.sleep(self.idle_wait_s)
+        wall = self.clock() - t0
+        done = [j for j in finished if j.status == "done"]
+        lat = [(j.done_s - j.arrival_s) * 1e3 for j in done]
+        hist = collections.Counter(j.batch_size for j in done)
+        span = max((j.done_s for j in done), default=0.0) - min((j.arrival_s for j in jobs), default=0.0)
+        return Stats(completed=len(done), refused=sum(j.status == "refused" for j in finished),
+                     failed=sum(j.status == "failed" for j in finished), wall_s=wall,
+                     throughput=len(done) / span if span > 0 else float("nan"),
+                     p50_ms=percentile(lat, 0.5), p99_ms=percentile(lat, 0.99),
+                     mean_ms=sum(lat) / len(lat) if lat else float("nan"),
+                     batch_hist=dict(sorted(hist.items())), executors_created=self.created,
+                     evictions=self.evictions, peak_bytes=self.peak)
+
+
+# --------------------------------------------------------------------------
+# GPU backend
+# --------------------------------------------------------------------------
+
+class Executor:
+    """Fixed device buffers for up to `max_batch` requests of one (shape, dtype)
+    and the HIP graphs captured over them, one per batch size."""
+
+    def __init__(self, backend, key):
+        torch = backend.torch
+        self.key = key
+        shape, dt = key
+        self.plan = backend.plan(key)
+        self.tdtype = torch.float32 if dt == "f32" else torch.float64
+        B, M = backend.max_batch, backend.max_np
+        dev = backend.device
+        self.x = [torch.zeros(M, dtype=self.tdtype, device=dev) for _ in range(B)]
+        self.y = [torch.zeros(M, dtype=self.tdtype, device=dev) for _ in range(B)]
+        self.z = [torch.zeros(M, dtype=self.tdtype, device=dev) for _ in range(B)]
+        self.out = [tuple(torch.zeros(M, dtype=self.tdtype, device=dev) for _ in range(3)) for _ in range(B)]
+        self.np_dev = torch.zeros(B, dtype=torch.int64, device=dev)
+        self.q_dev = torch.zeros(B, dtype=torch.float64, device=dev)
+        self.np_host = torch.zeros(B, dtype=torch.int64).pin_memory()
+        self.q_host = torch.zeros(B, dtype=torch.float64).pin_memory()
+        self.cnt = torch.zeros(B, dtype=torch.int64, device=dev)
+        self.scratch = self.plan.batch_scratch(B, M)
+        self.graphs = {}
+        self.use_graphs = backend.use_graphs
+        self.max_np = M
+
+    def _solve(self, b):
+        self.plan.solve_particles_batched(self.x[:b], self.y[:b], self.z[:b], self.np_dev, self.q_dev,
+                                          self.max_np, self.out[:b], self.scratch, n_outside=self.cnt)
+
+    def run(self, b, stream, torch):
+        """Solve the first b staged elements on `stream` (graph replay when enabled)."""
+        if not self.use_graphs:
+            with torch.cuda.stream(stream):
+                self._solve(b)
+            return
+        g = self.graphs.get(b)
+        if g is None:
+            cap = torch.cuda.Stream()
+            cap.wait_stream(stream)
+            with torch.cuda.stream(cap):
+                self._solve(b)                     # eager warm-up on the capture stream
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cap):
+                self._solve(b)
+            stream.wait_stream(cap)
+            self.graphs[b] = g
+        with torch.cuda.stream(stream):
+            g.replay()
+
+
+class GpuBackend:
+    def __init__(self, torch, max_batch=8, num_streams=4, max_np=1_000_000, use_graphs=True, device="cuda"):
+        from paper_1509_07685_amd import dks
+        self.torch = torch
+        self.dks = dks
+        self.max_batch = max_batch
+        self.num_streams = num_streams
+        self.max_np = max_np
+        self.use_graphs = use_graphs
+        self.device = device
+        self.streams = [torch.cuda.Stream() for _ in range(num_streams)]
+        self._plans = {}
+        self._tokens = {}
+        self._next = 0
+        self._sizes = {}
+
+    # sizes ------------------------------------------------------------------
+    def plan(self, key):
+        p = self._plans.get(key)
+        if p is None:
+            shape, dt = key
+            p = self.dks.PoissonPlan(shape, None, dt, device=self.device)
+            self._plans[key] = p
+        return p
+
+    def _size(self, key):
+        if key not in self._sizes:
+            shape, dt = key
+            d = self.dks
+            h = d.dks_poisson_plan(*shape, 0.0, 0.0, 0.0, d.DKS_F32 if dt == "f32" else d.DKS_F64)
+            try:
+                ws = d.dks_poisson_workspace_bytes(h) + d.dks_poisson_particle_scratch_bytes(h, self.max_np)
+                scratch = d.dks_poisson_batch_scratch_bytes(h, self.max_batch, self.max_np)
+            finally:
+                d.dks_poisson_destroy(h)
+            s = 4 if dt == "f32" else 8
+            self._sizes[key] = (ws, scratch + self.max_batch * self.max_np * s * 6 + 64 * self.max_batch)
+        return self._sizes[key]
+
+    def plan_bytes(self, key):
+        return self._size(key)[0]
+
+    def executor_bytes(self, key):
+        return self._size(key)[1]
+
+    # lifecycle --------------------------------------------------------------
+    def create_executor(self, key):
+        return Executor(self, key)
+
+    def destroy_executor(self, ex):
+        ex.graphs.clear()
+        del ex
+
+    def launch(self, ex, jobs, stream_id):
+        torch = self.torch
+        s = self.streams[stream_id]
+        b = len(jobs)
+        for i, j in enumerate(jobs):
+            x, y, z, outs = j.payload
+            n = j.num_particles
+            ex.np_host[i] = n
+            ex.q_host[i] = j.charge
+            with torch.cuda.stream(s):
+                ex.x[i][:n].copy_(x, non_blocking=True)
+                ex.y[i][:n].copy_(y, non_blocking=True)
+                ex.z[i][:n].copy_(z, non_blocking=True)
+        with torch.cuda.stream(s):
+            ex.np_dev[:b].copy_(ex.np_host[:b], non_blocking=True)
+            ex.q_dev[:b].copy_(ex.q_host[:b], non_blocking=True)
+        ex.run(b, s, torch)
+        with torch.cuda.stream(s):
+            for i, j in enumerate(jobs):
+                n = j.num_particles
+                outs = j.payload[3]
+                for d in range(3):
+                    outs[d].copy_(ex.out[i][d][:n], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        token = self._next
+        self._next += 1
+        self._tokens[token] = ev
+        return token
+
+    def done(self, token):
+        ev = self._tokens[token]
+        if ev.query():
+            del self._tokens[token]
+            return True
+        return False
+
+    def error(self, token):
+        return None
+
+
+def make_jobs(torch, requests, device="cuda", dtype_override=None):
+    """Device-resident inputs and outputs for each request (staged before the clock)."""
+    from paper_1509_07685_amd import workloads as wl
+    jobs = []
+    for r in requests:
+        dt = dtype_override or r.dtype
+        tdt = torch.float32 if dt == "f32" else torch.float64
+        x, y, z = wl.gaussian_bunch_torch(torch, r.num_particles, r.sigma, r.seed, tdt, device)
+        outs = tuple(torch.empty(r.num_particles, dtype=tdt, device=device) for _ in range(3))
+        jobs.append(Job(r.rid, r.arrival_s, (tuple(r.n), dt), r.num_particles, r.charge_per_particle,
+                        payload=(x, y, z, outs)))
+    return jobs
+
+
+def serve_sequential(torch, jobs, clock=time.perf_counter, device="cuda"):
+    """Baseline: one solve at a time in arrival order, one stream, no batching
+    or graphs (plans are still cached per shape)."""
+    from paper_1509_07685_amd import dks
+    plans = {}
+    cnt = torch.zeros(1, dtype=torch.int64, device=device)
+    t0 = clock()
+    s = torch.cuda.current_stream()
+    for j in sorted(jobs, key=lambda j: j.arrival_s):
+        while clock() - t0 < j.arrival_s:
+            pass
+        p = plans.get(j.key)
+        if p is None:
+            p = plans[j.key] = dks.PoissonPlan(j.key[0], None, j.key[1], device=device)
+            p.reserve_particles(1_000_000)
+        x, y, z, outs = j.payload
+        j.start_s = clock() - t0
+        p.solve_particles(x, y, z, j.charge, out=(outs[0], outs[1], outs[2], cnt), stream=s)
+        s.synchronize()
+        j.done_s = clock() - t0
+        j.status = "done"
+        j.batch_size = 1
+    lat = [(j.done_s - j.arrival_s) * 1e3 for j in jobs]
+    span = max(j.done_s for j in jobs) - min(j.arrival_s for j in jobs)
+    return {"completed": len(jobs), "throughput": len(jobs) / span, "p50_ms": percentile(lat, 0.5),
+            "p99_ms": percentile(lat, 0.99), "mean_ms": sum(lat) / len(lat), "wall_s": clock() - t0}
+
+
+def bench_stream(torch, num_requests=2000, rate_hz=500.0, seed=5, budget_bytes=64 * GiB):
+    """The mixed-size request stream: batched server vs the one-at-a-time FP64 path."""
+    from paper_1509_07685_amd import workloads as wl
+    reqs = wl.serving_stream(num_requests, rate_hz, seed)
+    backend = GpuBackend(torch)
+    # warm every plan and executor graph shape once, off the clock
+    warm = make_jobs(torch, [dataclasses.replace(r, arrival_s=0.0, num_particles=1000)
+                             for r in reqs[:60]])
+    Scheduler(backend, budget_bytes).run(warm)
+    torch.cuda.synchronize()
+    jobs = make_jobs(torch, reqs)
+    torch.cuda.synchronize()
+    stats = Scheduler(backend, budget_bytes).run(jobs)
+    torch.cuda.synchronize()
+    del jobs
+    torch.cuda.empty_cache()
+    base_jobs = make_jobs(torch, reqs, dtype_override="f64")
+    torch.cuda.synchronize()
+    serve_sequential(torch, make_jobs(torch, [dataclasses.replace(r, arrival_s=0.0, num_particles=1000)
+                                                 for r in reqs[:20]], dtype_override="f64"))
+    base = serve_sequential(torch, base_jobs)
+    del base_jobs
+    torch.cuda.empty_cache()
+    out = stats.as_dict()
+    out.update({"requests": num_requests, "rate_hz": rate_hz, "budget_GiB": budget_bytes / GiB,
+                "baseline_fp64_one_at_a_time": base})
+    return out

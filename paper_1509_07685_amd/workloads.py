@@ -142,3 +142,13 @@ def serving_stream(num_requests=2000, rate_hz=500.0, seed=5,
 def request_particles(req):
     dt = np.float32 if req.dtype == "f32" else np.float64
     return gaussian_bunch(req.num_particles, req.sigma, req.seed, dt)
+
+
+def gaussian_bunch_torch(torch, num, sigma, seed, dtype, device="cuda"):
+    """SoA Gaussian bunch drawn directly on the device with a seeded torch
+    generator (used for the request stream, whose hundreds of millions of
+    particles would take minutes to draw on the host)."""
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    pts = torch.randn((3, num), generator=g, dtype=torch.float64, device=device)
+    return tuple((pts[d] * sigma[d]).to(dtype).contiguous() for d in range(3))

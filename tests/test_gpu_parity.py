@@ -341,3 +341,41 @@ def test_repeated_solves_reuse_state():
             first, n0 = e, int(host(cnt)[0])
         assert int(host(cnt)[0]) == n0
         assert rel_l2(e, first) <= 1e-6
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_batched_solve_matches_single_solves(dt):
+    """One batched launch over elements with different particle counts and
+    charges equals the elements solved one by one (and the oracle)."""
+    d = dks()
+    n = (32, 24, 36)
+    plan = d.PoissonPlan(n, None, dt)
+    counts = [5000, 0, 12345, 1, 30000]
+    charges = [1e-13, 2e-13, 5e-14, 1e-12, 3e-14]
+    sig = [(1e-3, 1e-3, 1e-3), (1e-3, 1e-3, 1e-3), (0.5e-3, 1.5e-3, 1e-3), (1e-3, 1e-3, 1e-3), (2e-3, 1e-3, 1e-3)]
+    parts = [wl.gaussian_bunch(c, s, 50 + i, NP_DT[dt]) for i, (c, s) in enumerate(zip(counts, sig))]
+    max_np = max(counts)
+    xs, ys, zs, outs = [], [], [], []
+    for (x, y, z), c in zip(parts, counts):
+        pad = lambda a: np.concatenate([a, np.full(max_np - c, 7.0, dtype=a.dtype)])   # beyond np: ignored
+        xs.append(dev(pad(x), dt)); ys.append(dev(pad(y), dt)); zs.append(dev(pad(z), dt))
+        outs.append(tuple(torch.full((max_np,), -1.0, dtype=tdt(dt), device="cuda") for _ in range(3)))
+    np_dev = torch.tensor(counts, dtype=torch.int64, device="cuda")
+    q_dev = torch.tensor(charges, dtype=torch.float64, device="cuda")
+    cnt = torch.zeros(len(counts), dtype=torch.int64, device="cuda")
+    scratch = plan.batch_scratch(len(counts), max_np)
+    plan.solve_particles_batched(xs, ys, zs, np_dev, q_dev, max_np, outs, scratch, n_outside=cnt)
+    cnts = host(cnt)
+    for b, ((x, y, z), c, q) in enumerate(zip(parts, counts, charges)):
+        got = np.stack([host(t)[:c] for t in outs[b]])
+        assert np.all(host(outs[b][0])[c:] == -1.0)     # nothing written past np
+        single = d.PoissonPlan(n, None, dt)
+        (Ex, Ey, Ez), _, sc = single.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), q)
+        alone = np.stack([host(Ex), host(Ey), host(Ez)])
+        assert int(cnts[b]) == int(host(sc)[0]) == 0
+        if c > 1:
+            assert rel_l2(got, alone) <= TOL[dt]
+            ref = orc.solve_particles(x, y, z, q, n, dtype=NP_DT[dt])
+            assert rel_l2(got, ref["E"]) <= TOL[dt]
+        elif c == 1:
+            assert np.allclose(got, alone, rtol=0, atol=1e-6 * (np.abs(alone).max() + 1e-30))

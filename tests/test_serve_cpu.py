@@ -1,0 +1,146 @@
+"""The serving scheduler on a modelled backend (no GPU): admission by byte
+budget, continuous batching, no starvation, refusal, eviction, latency."""
+
+import pytest
+
+from paper_1509_07685_amd import serve
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        self.t += 1e-5          # every look at the clock advances it 10 us
+        return self.t
+
+
+class FakeEx:
+    def __init__(self, key):
+        self.key = key
+
+
+class FakeBackend:
+    """Solve time = 0.2 ms + 1 ns per mesh point per element of the batch."""
+
+    def __init__(self, clock, max_batch=4, num_streams=2, exec_bytes=None, plan_bytes=1 << 20):
+        self.clock = clock
+        self.max_batch = max_batch
+        self.num_streams = num_streams
+        self.exec_bytes = exec_bytes or {}
+        self.pbytes = plan_bytes
+        self.inflight = {}
+        self.launches = []
+        self.created = []
+        self.destroyed = []
+        self.live = 0
+        self.max_live_streams = 0
+        self.n = 0
+
+    def executor_bytes(self, key):
+        return self.exec_bytes.get(key, 100 << 20)
+
+    def plan_bytes(self, key):
+        return self.pbytes
+
+    def create_executor(self, key):
+        self.created.append(key)
+        return FakeEx(key)
+
+    def destroy_executor(self, ex):
+        self.destroyed.append(ex.key)
+
+    def launch(self, ex, jobs, stream):
+        shape = ex.key[0]
+        dur = 2e-4 + 1e-9 * shape[0] * shape[1] * shape[2] * len(jobs)
+        self.n += 1
+        self.inflight[self.n] = self.clock.t + dur
+        self.launches.append((ex.key, [j.rid for j in jobs], stream))
+        self.live += 1
+        self.max_live_streams = max(self.max_live_streams, self.live)
+        return self.n
+
+    def done(self, token):
+        if self.clock.t >= self.inflight[token]:
+            self.live -= 1
+            return True
+        return False
+
+    def error(self, token):
+        return None
+
+
+def jobs_from(spec):
+    return [serve.Job(i, t, key, 1000, 1e-15) for i, (t, key) in enumerate(spec)]
+
+
+A = ((32, 32, 32), "f32")
+B = ((64, 64, 64), "f64")
+C = ((128, 128, 128), "f32")
+
+
+def test_every_request_completes_and_batches_form():
+    clock = FakeClock()
+    be = FakeBackend(clock)
+    spec = [(0.0001 * i, A if i % 3 else B) for i in range(200)]
+    stats = serve.Scheduler(be, budget_bytes=1 << 40, clock=clock).run(jobs_from(spec))
+    assert stats.completed == 200 and stats.refused == 0 and stats.failed == 0
+    assert max(stats.batch_hist) > 1                      # continuous batching merged requests
+    assert all(len(r) <= be.max_batch for _, r, _ in be.launches)
+    for key, rids, _ in be.launches:                     # a batch never mixes shapes
+        assert all((spec[r][1] == key) for r in rids)
+    assert be.max_live_streams <= be.num_streams
+    assert stats.p99_ms >= stats.p50_ms > 0
+
+
+def test_fifo_within_a_shape_and_no_starvation():
+    """A steady stream of one shape cannot starve a request of another: the
+    oldest waiting request's shape goes next whenever a stream frees."""
+    clock = FakeClock()
+    be = FakeBackend(clock, max_batch=2, num_streams=1)
+    spec = [(0.0002 * i, A) for i in range(300)] + [(0.001, B)]
+    stats = serve.Scheduler(be, budget_bytes=1 << 40, clock=clock).run(jobs_from(spec))
+    assert stats.completed == 301
+    order = [r for _, rids, _ in be.launches for r in rids]
+    a_order = [r for r in order if r < 300]
+    assert a_order == sorted(a_order)
+    b_pos = order.index(300)
+    # everything launched before B arrived before it (plus at most one batch in flight)
+    assert all(spec[r][0] <= 0.001 + 1e-12 for r in order[:max(0, b_pos - 2)])
+    assert b_pos < 40
+
+
+def test_budget_is_never_exceeded_and_idle_executors_are_evicted():
+    clock = FakeClock()
+    be = FakeBackend(clock, num_streams=1, exec_bytes={A: 300 << 20, B: 300 << 20}, plan_bytes=10 << 20)
+    budget = 700 << 20       # room for two plans and two executors at once
+    spec = [(0.001 * i, A) for i in range(10)] + [(0.05 + 0.001 * i, B) for i in range(10)] + \
+           [(0.1 + 0.001 * i, A) for i in range(10)]
+    sch = serve.Scheduler(be, budget_bytes=budget, clock=clock)
+    stats = sch.run(jobs_from(spec))
+    assert stats.completed == 30
+    assert stats.peak_bytes <= budget
+    assert sch.used <= budget
+
+
+def test_request_that_can_never_fit_is_refused():
+    clock = FakeClock()
+    be = FakeBackend(clock, exec_bytes={C: 10 << 30})
+    spec = [(0.0, A), (0.0, C), (0.001, A)]
+    stats = serve.Scheduler(be, budget_bytes=4 << 30, clock=clock).run(jobs_from(spec))
+    assert stats.completed == 2 and stats.refused == 1
+
+
+def test_waits_for_memory_instead_of_failing():
+    """Two shapes whose executors cannot coexist: the second waits until the
+    first's executor is idle, evicts it, and proceeds."""
+    clock = FakeClock()
+    be = FakeBackend(clock, num_streams=2, exec_bytes={A: 600 << 20, B: 600 << 20}, plan_bytes=1 << 20)
+    spec = [(0.0, A)] * 3 + [(0.0, B)] * 3
+    stats = serve.Scheduler(be, budget_bytes=700 << 20, clock=clock).run(jobs_from(spec))
+    assert stats.completed == 6 and stats.evictions >= 1
+
+
+def test_percentile():
+    assert serve.percentile([1, 2, 3, 4], 0.5) == 2.5
+    assert serve.percentile(list(range(101)), 0.99) == pytest.approx(99.0)
