@@ -14,6 +14,12 @@
 // lanes read and write W contiguous complex values per row: 128-byte HBM
 // segments and conflict-free LDS rows.
 //
+// The two intermediates the z pass reads and writes (B after the y forward
+// pass, C after the z pass) are z-blocked: element (z, ky, kx) sits in row
+// ((z / 16) * 2ny + ky) * 16 + z % 16, so a z pencil spans 16-17 blocks of
+// 16 adjacent rows instead of one row per plane, and a y pencil of one plane
+// steps by 16 rows.
+//
 // Zero padding is never stored: the forward x transform reads the nx real
 // values of a row, the forward y and z transforms read only the first half of
 // their pencils, and the inverse transforms store only the outputs in
@@ -266,14 +272,16 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_fwd(const typename
   C* lds = reinterpret_cast<C*>(smem);
   const int c0 = blockIdx.x * P->W;
   const int ncol = min(P->W, m.ncols - c0);
-  const C* src = A + blockIdx.z * stride + (size_t)blockIdx.y * m.ny * m.cs + c0;
-  C* dst = B + blockIdx.z * stride + (size_t)blockIdx.y * m.Ny * m.cs + c0;
+  const int z = blockIdx.y;
+  const C* src = A + blockIdx.z * stride + (size_t)z * m.ny * m.cs + c0;
+  C* dst = B + blockIdx.z * stride + ((size_t)(z >> 4) * m.Ny * 16 + (z & 15)) * m.cs + c0;
   const int ny = m.ny, cs = m.cs;
+  const size_t ostep = (size_t)16 * cs;       // next ky row of this plane
   auto in = [&](int c, int idx) { return (idx < ny && c < ncol) ? src[(size_t)idx * cs + c] : C{0, 0}; };
   auto out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
     if (c < ncol) {
 #pragma unroll
-      for (int r = 0; r < RC.value; ++r) dst[(size_t)(base + r * Ns) * cs + c] = vals[r];
+      for (int r = 0; r < RC.value; ++r) dst[(size_t)(base + r * Ns) * ostep + c] = vals[r];
     }
   };
   run_fft<T, false, false>(lds, P, 0, in, out);
@@ -299,22 +307,23 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
   const int c0 = blockIdx.x * Pf->W;
   const int ky = blockIdx.y;
   const int ncol = min(Pf->W, m.ncols - c0);
-  const size_t plane_in = (size_t)m.Ny * m.cs;     // one z plane of B or C
-  const C* src = B + blockIdx.z * stride + (size_t)ky * m.cs + c0;
-  C* dst = Cout + blockIdx.z * stride + (size_t)ky * m.cs + c0;
+  const size_t zblock = (size_t)m.Ny * 16 * m.cs;   // one block of 16 z rows of B or C
+  const C* src = B + blockIdx.z * stride + (size_t)ky * 16 * m.cs + c0;
+  C* dst = Cout + blockIdx.z * stride + (size_t)ky * 16 * m.cs + c0;
   const Geometry* g = reinterpret_cast<const Geometry*>(reinterpret_cast<const char*>(geo) +
                                                         blockIdx.z * geo_stride);
   const T scale = Geo<T>::scale(g);
   const int kyr = min(ky, m.Ny - ky);
   const T* grow = G + (size_t)kyr * (m.nz + 1) * m.cs + c0;
   const int nz = m.nz, Nz = m.Nz, cs = m.cs, LD = Pf->LD;
-  auto in = [&](int c, int idx) { return (idx < nz && c < ncol) ? src[(size_t)idx * plane_in + c] : C{0, 0}; };
+  auto zoff = [&](int z) { return (size_t)(z >> 4) * zblock + (size_t)(z & 15) * cs; };
+  auto in = [&](int c, int idx) { return (idx < nz && c < ncol) ? src[zoff(idx) + c] : C{0, 0}; };
   // Final inverse outputs: keep z = -1 (index Nz - 1) and z = 0 .. nz as row z + 1.
   auto store_z = [&](int c, int idx, C val) {
     int zo = -1;
     if (idx <= nz) zo = idx + 1;
     else if (idx == Nz - 1) zo = 0;
-    if (zo >= 0 && c < ncol) dst[(size_t)zo * plane_in + c] = val;
+    if (zo >= 0 && c < ncol) dst[zoff(zo) + c] = val;
   };
   const bool inv_single = Pi->npass == 1;
   // Last forward pass: its outputs sit at kz = j + r Ns, exactly the inputs of
@@ -363,10 +372,12 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_inv(const typename
   C* lds = reinterpret_cast<C*>(smem);
   const int c0 = blockIdx.x * P->W;
   const int ncol = min(P->W, m.ncols - c0);
-  const C* src = Cin + blockIdx.z * stride + (size_t)blockIdx.y * m.Ny * m.cs + c0;
-  C* dst = D + blockIdx.z * stride + (size_t)blockIdx.y * (m.ny + 2) * m.cs + c0;
+  const int zp = blockIdx.y;
+  const C* src = Cin + blockIdx.z * stride + ((size_t)(zp >> 4) * m.Ny * 16 + (zp & 15)) * m.cs + c0;
+  C* dst = D + blockIdx.z * stride + (size_t)zp * (m.ny + 2) * m.cs + c0;
   const int ny = m.ny, Ny = m.Ny, cs = m.cs;
-  auto in = [&](int c, int idx) { return c < ncol ? src[(size_t)idx * cs + c] : C{0, 0}; };
+  const size_t istep = (size_t)16 * cs;       // next ky row of this plane
+  auto in = [&](int c, int idx) { return c < ncol ? src[(size_t)idx * istep + c] : C{0, 0}; };
   auto out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
 #pragma unroll
     for (int r = 0; r < RC.value; ++r) {

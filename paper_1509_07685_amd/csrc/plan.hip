@@ -297,8 +297,9 @@ void layout(dks_poisson_plan_s* p) {
   p->off_slot = align256(p->off_green + p->green_bytes);
   const size_t cs = (size_t)m.cs;
   const size_t A = (size_t)ny * nz * cs * c;
-  const size_t B = (size_t)m.Ny * nz * cs * c;
-  const size_t C = (size_t)m.Ny * (nz + 2) * cs * c;
+  // B and C are z-blocked in groups of 16 rows (partial last block allocated in full)
+  const size_t B = (size_t)m.Ny * ((nz + 15) / 16 * 16) * cs * c;
+  const size_t C = (size_t)m.Ny * ((nz + 2 + 15) / 16 * 16) * cs * c;
   const size_t D = (size_t)(ny + 2) * (nz + 2) * cs * c;
   p->bytes_W = (size_t)nx * ny * nz * s;
   p->bytes_phi_ext = (size_t)(nx + 2) * (ny + 2) * (nz + 2) * s;
