@@ -39,7 +39,10 @@ def algorithmic_bytes(n, num_particles, s, kernel):
         "bbox": 3 * s * num_particles,
         "geometry": 0,
         "zero_mesh": s * mesh,
-        "deposit": 3 * s * num_particles + s * mesh,
+        "bin_count": 3 * s * num_particles,
+        "bin_scan": 0,
+        "bin_scatter": 3 * s * num_particles + 4 * s * num_particles,
+        "deposit": 4 * s * num_particles + s * mesh,
         "fft_x_fwd": s * mesh + c * (nx + 1) * ny * nz,
         "fft_y_fwd": c * (nx + 1) * ny * nz + c * (nx + 1) * 2 * ny * nz,
         "fft_z_conv": (c * (nx + 1) * 2 * ny * nz + s * (nx + 1) * (ny + 1) * (nz + 1)
@@ -47,7 +50,7 @@ def algorithmic_bytes(n, num_particles, s, kernel):
         "fft_y_inv": c * (nx + 1) * 2 * ny * (nz + 2) + c * (nx + 1) * (ny + 2) * (nz + 2),
         "fft_x_inv": c * (nx + 1) * (ny + 2) * (nz + 2) + s * (nx + 2) * (ny + 2) * (nz + 2),
         "gradient": s * (nx + 2) * (ny + 2) * (nz + 2) + 3 * s * mesh,
-        "gather": 3 * s * num_particles + 3 * s * mesh + 3 * s * num_particles,
+        "gather": 4 * s * num_particles + 3 * s * num_particles + s * (nx + 2) * (ny + 2) * (nz + 2),
     }
     return model[kernel]
 
@@ -98,6 +101,8 @@ def main():
     ap.add_argument("--particles", type=int, default=100_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the mesh-only and serving legs")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); nothing in this build "
@@ -107,6 +112,13 @@ def main():
     import numpy as np
     import torch
     from paper_1509_07685_amd import dks, workloads as wl
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cfg = wl.HALO_GAUSSIAN
     n = cfg.n

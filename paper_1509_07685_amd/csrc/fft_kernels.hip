@@ -135,7 +135,10 @@ __device__ __forceinline__ void fft_pass(const FFTPlan* __restrict__ P, int p, I
   constexpr int TH = RegCfg<T>::THREADS;
   constexpr int K = (RegCfg<T>::EMAX + R - 1) / R;
   const int W = P->W, logW = P->logW, NR = P->N / R, nbf = W * NR, Ns = P->Ns[p];
+  const C* tw = (const C*)P->tw + P->tw_off[p];
+  const unsigned magic = P->magic[p];
   C v[K * R];
+  C w[K * (R - 1)];   // twiddles, fetched with the inputs so their latency hides under the barrier
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int b = (int)threadIdx.x + k * TH;
@@ -143,11 +146,15 @@ __device__ __forceinline__ void fft_pass(const FFTPlan* __restrict__ P, int p, I
       const int c = b & (W - 1), j = b >> logW;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[k * R + r] = in(c, j + r * NR);
+      if (Ns > 1) {
+        const int q = (int)__umulhi((unsigned)j, magic);
+        const C* wt = tw + (j - q * Ns) * (R - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[k * (R - 1) + r - 1] = wt[r - 1];
+      }
     }
   }
   if (SYNC) __syncthreads();
-  const C* tw = (const C*)P->tw + P->tw_off[p];
-  const unsigned magic = P->magic[p];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int b = (int)threadIdx.x + k * TH;
@@ -157,10 +164,9 @@ __device__ __forceinline__ void fft_pass(const FFTPlan* __restrict__ P, int p, I
       if (Ns > 1) {
         const int q = (int)__umulhi((unsigned)j, magic);
         const int t = j - q * Ns;
-        const C* w = tw + t * (R - 1);
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          C wr = w[r - 1];
+          C wr = w[k * (R - 1) + r - 1];
           if (INV) wr.y = -wr.y;
           v[k * R + r] = cmul(v[k * R + r], wr);
         }

@@ -308,11 +308,11 @@ def test_dense_tile_spans_many_work_items(dt):
 def test_particles_on_tile_boundaries_and_mesh_edges(dt):
     """Particles exactly on nodes at tile boundaries (cell coordinate 16, 32),
     on the last node (n - 1), on the first node, and just outside."""
-    n, h = (40, 34, 33), (1.0, 1.0, 1.0)
+    n, h = (48, 36, 54), (1.0, 1.0, 1.0)
     origin = (0.0, 0.0, 0.0)
     g = np.random.default_rng(8)
     grid = np.array([0.0, 15.5, 16.0, 31.999, 32.0, 32.5])
-    xs, ys, zs = np.meshgrid(np.r_[grid, 39.0, -0.001, 39.001], np.r_[grid, 33.0], np.r_[grid, 32.0],
+    xs, ys, zs = np.meshgrid(np.r_[grid, 47.0, -0.001, 47.001], np.r_[grid, 35.0], np.r_[grid, 48.0, 53.0],
                              indexing="ij")
     x, y, z = (a.ravel().astype(NP_DT[dt]) for a in (xs, ys, zs))
     extra = [g.uniform(0, nd - 1, 5000) for nd in n]
