@@ -11,14 +11,23 @@
 //   scan     tile offsets, reservation cursors and the work-item list
 //            (a work item is up to kItem particles of one tile)
 //   scatter  each workgroup reserves one contiguous range per tile and writes
-//            its particles there as packed (x, y, z, original index)
+//            its particles there as packed (x, y, z, original index); the
+//            inverse permutation (original index -> binned slot) is written
+//            alongside, in original order
 //   deposit  per work item: accumulate the weights of the tile's particles in
-//            an LDS copy of its 17^3 nodes with LDS atomics, then merge the
-//            copy into the mesh with one device atomic per non-zero node
+//            an LDS copy of its 17^3 nodes with integer LDS atomics on a fixed-
+//            point scale (exact and order independent; floating-point LDS
+//            atomics run an order of magnitude slower), then merge the copy
+//            into the mesh with one device atomic per non-zero node
 //   gather   per work item: stage phi of the tile plus a two-node apron
 //            (19^3 values) in LDS, form the central-difference field at the
 //            eight nodes of each particle and interpolate it with the
-//            deposit's weights; write E at the particle's original index
+//            deposit's weights; the field overwrites the particle's binned
+//            record in place
+//   unsort   in original particle order, read each field through the inverse
+//            permutation and write the three field arrays contiguously
+//            (scattered 4-byte writes to the original indices cost ten times
+//            more than one scattered 16-byte read)
 //
 // Particles outside the mesh fall in an extra tile K: they deposit nothing,
 // get E = 0 and their count is the out-of-mesh count.  The cell decision is
@@ -26,6 +35,8 @@
 // tile a particle is filed under always contains its whole stencil.
 
 #include <math.h>
+
+#include <algorithm>
 
 #include "dks_internal.h"
 
@@ -38,6 +49,20 @@ constexpr int kApron = kTile + 3;  // staged phi values per edge (nodes -1 .. 17
 template <typename T> struct Packed;
 template <> struct Packed<float> { using type = float4; };
 template <> struct Packed<double> { using type = double4; };
+
+// Fixed-point scale of the deposit accumulators: a weight is at most 1 and a
+// work item holds at most 2^16 (FP32) or 2^14 (FP64) particles, so a node sum
+// stays below 2^48 resp. 2^63 in 64 bits; the scale keeps 2^-32 resp. 2^-49
+// resolution, finer than the dtype's rounding of the weight products.
+template <typename T> struct Fixed;
+template <> struct Fixed<float> {
+  static __device__ __forceinline__ unsigned long long to(float w) { return __float2ull_rn(w * 4294967296.0f); }
+  static __device__ __forceinline__ float from(unsigned long long v) { return (float)v * 2.3283064365386963e-10f; }
+};
+template <> struct Fixed<double> {
+  static __device__ __forceinline__ unsigned long long to(double w) { return __double2ull_rn(w * 562949953421312.0); }
+  static __device__ __forceinline__ double from(unsigned long long v) { return (double)v * 1.7763568394002505e-15; }
+};
 
 __device__ __forceinline__ float cc(float x, float x0, float ih) { return __fmul_rn(__fsub_rn(x, x0), ih); }
 __device__ __forceinline__ double cc(double x, double x0, double ih) { return __dmul_rn(__dsub_rn(x, x0), ih); }
@@ -189,7 +214,7 @@ template <typename T, bool LDSHIST>
 __global__ __launch_bounds__(256) void k_bin_scatter(PtrBatch xs, PtrBatch ys, PtrBatch zs, BatchScalars bs,
                                                      const Geometry* geo, size_t stride, char* slot_base,
                                                      size_t bins_off, char* sorted_base, size_t sorted_stride,
-                                                     MeshDims m, BinGeom bg) {
+                                                     size_t inv_off, MeshDims m, BinGeom bg) {
   extern __shared__ unsigned lds[];
   unsigned* lcnt = lds;
   unsigned* lbase = lds + (bg.K + 1);
@@ -201,6 +226,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(PtrBatch xs, PtrBatch ys, P
   const Geometry* g = geo_of(geo, stride, b);
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
   P4* out = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
+  unsigned* inv = reinterpret_cast<unsigned*>(sorted_base + (size_t)b * sorted_stride + inv_off);
   int64_t start, end;
   chunk_of(bs.n(b), blockIdx.x, gridDim.x, &start, &end);
   if (LDSHIST) {
@@ -227,6 +253,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(PtrBatch xs, PtrBatch ys, P
     if constexpr (sizeof(T) == 4) v.w = __uint_as_float((unsigned)i);
     else v.w = (double)i;
     out[dst] = v;
+    inv[i] = dst;
   }
 }
 
@@ -252,7 +279,7 @@ __global__ __launch_bounds__(256) void k_deposit_binned(const Geometry* geo, siz
                                                         size_t bins_off, const char* sorted_base,
                                                         size_t sorted_stride, T* W, size_t w_stride, MeshDims m,
                                                         BinGeom bg) {
-  __shared__ T acc[kTileN * kTileN * kTileN];
+  __shared__ unsigned long long acc[kTileN * kTileN * kTileN];
   using P4 = typename Packed<T>::type;
   const int b = blockIdx.y;
   const Geometry* g = geo_of(geo, stride, b);
@@ -268,27 +295,28 @@ __global__ __launch_bounds__(256) void k_deposit_binned(const Geometry* geo, siz
     if (tile == bg.K) continue;                      // outside particles deposit nothing
     const int tx = tile % bg.tx, ty = (tile / bg.tx) % bg.ty, tz = tile / (bg.tx * bg.ty);
     const int bx = tx * kTile, by = ty * kTile, bz = tz * kTile;
-    for (int e = threadIdx.x; e < NN; e += blockDim.x) acc[e] = (T)0;
+    for (int e = threadIdx.x; e < NN; e += blockDim.x) acc[e] = 0ull;
     __syncthreads();
     for (unsigned i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
       const P4 p = part[i];
       const Cell<T> c = locate<T>(p.x, p.y, p.z, g, m, bg);
       const T gx = (T)1 - c.fx, gy = (T)1 - c.fy, gz = (T)1 - c.fz;
-      T* a = acc + ((c.jz - bz) * kTileN + (c.jy - by)) * kTileN + (c.jx - bx);
+      unsigned long long* a = acc + ((c.jz - bz) * kTileN + (c.jy - by)) * kTileN + (c.jx - bx);
       constexpr int SY = kTileN, SZ = kTileN * kTileN;
-      atomicAdd(a, gz * gy * gx);
-      atomicAdd(a + 1, gz * gy * c.fx);
-      atomicAdd(a + SY, gz * c.fy * gx);
-      atomicAdd(a + SY + 1, gz * c.fy * c.fx);
-      atomicAdd(a + SZ, c.fz * gy * gx);
-      atomicAdd(a + SZ + 1, c.fz * gy * c.fx);
-      atomicAdd(a + SZ + SY, c.fz * c.fy * gx);
-      atomicAdd(a + SZ + SY + 1, c.fz * c.fy * c.fx);
+      atomicAdd(a, Fixed<T>::to(gz * gy * gx));
+      atomicAdd(a + 1, Fixed<T>::to(gz * gy * c.fx));
+      atomicAdd(a + SY, Fixed<T>::to(gz * c.fy * gx));
+      atomicAdd(a + SY + 1, Fixed<T>::to(gz * c.fy * c.fx));
+      atomicAdd(a + SZ, Fixed<T>::to(c.fz * gy * gx));
+      atomicAdd(a + SZ + 1, Fixed<T>::to(c.fz * gy * c.fx));
+      atomicAdd(a + SZ + SY, Fixed<T>::to(c.fz * c.fy * gx));
+      atomicAdd(a + SZ + SY + 1, Fixed<T>::to(c.fz * c.fy * c.fx));
     }
     __syncthreads();
     for (int e = threadIdx.x; e < NN; e += blockDim.x) {
-      const T v = acc[e];
-      if (v != (T)0) {
+      const unsigned long long fv = acc[e];
+      if (fv != 0ull) {
+        const T v = Fixed<T>::from(fv);
         const int ex = e % kTileN, ey = (e / kTileN) % kTileN, ez = e / (kTileN * kTileN);
         const int x = bx + ex, y = by + ey, z = bz + ez;
         if (x < m.nx && y < m.ny && z < m.nz) unsafeAtomicAdd(&w[((size_t)z * m.ny + y) * m.nx + x], v);
@@ -303,20 +331,16 @@ __global__ __launch_bounds__(256) void k_deposit_binned(const Geometry* geo, siz
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather_binned(const Geometry* geo, size_t stride, char* slot_base,
-                                                       size_t bins_off, const char* sorted_base,
-                                                       size_t sorted_stride, const T* __restrict__ phi_ext,
-                                                       size_t phi_stride, PtrBatch exs, PtrBatch eys,
-                                                       PtrBatch ezs, MeshDims m, BinGeom bg) {
+                                                       size_t bins_off, char* sorted_base, size_t sorted_stride,
+                                                       const T* __restrict__ phi_ext, size_t phi_stride,
+                                                       MeshDims m, BinGeom bg) {
   __shared__ T ph[kApron * kApron * kApron];
   using P4 = typename Packed<T>::type;
   const int b = blockIdx.y;
   const Geometry* g = geo_of(geo, stride, b);
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
-  const P4* part = reinterpret_cast<const P4*>(sorted_base + (size_t)b * sorted_stride);
+  P4* part = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
   const T* phi = phi_ext + (size_t)b * phi_stride;
-  T* qx = (T*)exs.p[b];
-  T* qy = (T*)eys.p[b];
-  T* qz = (T*)ezs.p[b];
   const T cx = Geo<T>::grad(g, 0), cy = Geo<T>::grad(g, 1), cz = Geo<T>::grad(g, 2);
   const int nx2 = m.nx + 2, ny2 = m.ny + 2, nz2 = m.nz + 2;
   const unsigned nitems = st.misc[0];
@@ -327,13 +351,11 @@ __global__ __launch_bounds__(256) void k_gather_binned(const Geometry* geo, size
     decode_item(st, bg.K, bg.item, t, &tile, &s0, &s1);
     if (tile == bg.K) {
       for (unsigned i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-        const P4 p = part[i];
-        size_t idx;
-        if constexpr (sizeof(T) == 4) idx = __float_as_uint(p.w);
-        else idx = (size_t)p.w;
-        qx[idx] = (T)0;
-        qy[idx] = (T)0;
-        qz[idx] = (T)0;
+        P4 e = part[i];
+        e.x = (T)0;
+        e.y = (T)0;
+        e.z = (T)0;
+        part[i] = e;
       }
       continue;
     }
@@ -368,14 +390,35 @@ __global__ __launch_bounds__(256) void k_gather_binned(const Geometry* geo, size
             ay += wgt * ey;
             az += wgt * ez;
           }
-      size_t idx;
-      if constexpr (sizeof(T) == 4) idx = __float_as_uint(p.w);
-      else idx = (size_t)p.w;
-      qx[idx] = ax;
-      qy[idx] = ay;
-      qz[idx] = az;
+      P4 e = p;
+      e.x = ax;
+      e.y = ay;
+      e.z = az;
+      part[i] = e;
     }
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// unsort: E at the particles in their original order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_unsort(BatchScalars bs, const char* sorted_base, size_t sorted_stride,
+                                                size_t inv_off, PtrBatch exs, PtrBatch eys, PtrBatch ezs) {
+  using P4 = typename Packed<T>::type;
+  const int b = blockIdx.y;
+  const P4* part = reinterpret_cast<const P4*>(sorted_base + (size_t)b * sorted_stride);
+  const unsigned* inv = reinterpret_cast<const unsigned*>(sorted_base + (size_t)b * sorted_stride + inv_off);
+  T* qx = (T*)exs.p[b];
+  T* qy = (T*)eys.p[b];
+  T* qz = (T*)ezs.p[b];
+  const int64_t n = bs.n(b);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const P4 e = part[inv[i]];
+    qx[i] = e.x;
+    qy[i] = e.y;
+    qz[i] = e.z;
   }
 }
 
@@ -406,16 +449,16 @@ hipError_t launch_bin_scan(const Geometry* geo, size_t stride, char* slot_base, 
 template <typename T>
 hipError_t launch_bin_scatter(const PtrBatch& xs, const PtrBatch& ys, const PtrBatch& zs, const BatchScalars& bs,
                               int batch, const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
-                              char* sorted_base, size_t sorted_stride, const MeshDims& m, const BinGeom& bg,
-                              int nblk, hipStream_t s) {
+                              char* sorted_base, size_t sorted_stride, size_t inv_off, const MeshDims& m,
+                              const BinGeom& bg, int nblk, hipStream_t s) {
   const bool lh = bg.lds_hist != 0;
   const size_t lds = lh ? 2 * (size_t)(bg.K + 1) * sizeof(unsigned) : 0;
   if (lh)
     hipLaunchKernelGGL((k_bin_scatter<T, true>), dim3(nblk, batch), dim3(256), lds, s, xs, ys, zs, bs, geo, stride,
-                       slot_base, bins_off, sorted_base, sorted_stride, m, bg);
+                       slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
   else
     hipLaunchKernelGGL((k_bin_scatter<T, false>), dim3(nblk, batch), dim3(256), 0, s, xs, ys, zs, bs, geo, stride,
-                       slot_base, bins_off, sorted_base, sorted_stride, m, bg);
+                       slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
   return hipGetLastError();
 }
 
@@ -430,11 +473,21 @@ hipError_t launch_deposit_binned(const Geometry* geo, size_t stride, char* slot_
 
 template <typename T>
 hipError_t launch_gather_binned(const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
-                                const char* sorted_base, size_t sorted_stride, const void* phi_ext,
-                                size_t phi_stride, const PtrBatch& exs, const PtrBatch& eys, const PtrBatch& ezs,
+                                char* sorted_base, size_t sorted_stride, const void* phi_ext, size_t phi_stride,
                                 const MeshDims& m, const BinGeom& bg, int nblk, int batch, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_binned<T>, dim3(nblk, batch), dim3(256), 0, s, geo, stride, slot_base, bins_off,
-                     sorted_base, sorted_stride, (const T*)phi_ext, phi_stride, exs, eys, ezs, m, bg);
+                     sorted_base, sorted_stride, (const T*)phi_ext, phi_stride, m, bg);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_unsort(const BatchScalars& bs, int batch, const char* sorted_base, size_t sorted_stride,
+                         size_t inv_off, const PtrBatch& exs, const PtrBatch& eys, const PtrBatch& ezs,
+                         hipStream_t s) {
+  if (bs.max_np == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((bs.max_np + 255) / 256, 65535 * 4);
+  hipLaunchKernelGGL(k_unsort<T>, dim3((unsigned)blocks, batch), dim3(256), 0, s, bs, sorted_base, sorted_stride,
+                     inv_off, exs, eys, ezs);
   return hipGetLastError();
 }
 
@@ -444,13 +497,15 @@ hipError_t launch_gather_binned(const Geometry* geo, size_t stride, char* slot_b
                                           const BinGeom&, int, hipStream_t);                                       \
   template hipError_t launch_bin_scatter<T>(const PtrBatch&, const PtrBatch&, const PtrBatch&,                     \
                                             const BatchScalars&, int, const Geometry*, size_t, char*, size_t,      \
-                                            char*, size_t, const MeshDims&, const BinGeom&, int, hipStream_t);     \
+                                            char*, size_t, size_t, const MeshDims&, const BinGeom&, int,           \
+                                            hipStream_t);                                                          \
   template hipError_t launch_deposit_binned<T>(const Geometry*, size_t, char*, size_t, const char*, size_t, void*, \
                                                size_t, const MeshDims&, const BinGeom&, int, int, hipStream_t);    \
-  template hipError_t launch_gather_binned<T>(const Geometry*, size_t, char*, size_t, const char*, size_t,         \
-                                              const void*, size_t, const PtrBatch&, const PtrBatch&,               \
-                                              const PtrBatch&, const MeshDims&, const BinGeom&, int, int,          \
-                                              hipStream_t);
+  template hipError_t launch_gather_binned<T>(const Geometry*, size_t, char*, size_t, char*, size_t,               \
+                                              const void*, size_t, const MeshDims&, const BinGeom&, int, int,      \
+                                              hipStream_t);                                                        \
+  template hipError_t launch_unsort<T>(const BatchScalars&, int, const char*, size_t, size_t, const PtrBatch&,     \
+                                       const PtrBatch&, const PtrBatch&, hipStream_t);
 DKS_INSTANTIATE(float)
 DKS_INSTANTIATE(double)
 #undef DKS_INSTANTIATE

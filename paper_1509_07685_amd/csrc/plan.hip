@@ -45,15 +45,16 @@ template <typename T> hipError_t launch_bin_count(const PtrBatch&, const PtrBatc
 hipError_t launch_bin_scan(const Geometry*, size_t, char*, size_t, const BinGeom&, const PtrBatch&, int, hipStream_t);
 template <typename T> hipError_t launch_bin_scatter(const PtrBatch&, const PtrBatch&, const PtrBatch&,
                                                     const BatchScalars&, int, const Geometry*, size_t, char*,
-                                                    size_t, char*, size_t, const MeshDims&, const BinGeom&, int,
-                                                    hipStream_t);
+                                                    size_t, char*, size_t, size_t, const MeshDims&, const BinGeom&,
+                                                    int, hipStream_t);
 template <typename T> hipError_t launch_deposit_binned(const Geometry*, size_t, char*, size_t, const char*, size_t,
                                                        void*, size_t, const MeshDims&, const BinGeom&, int, int,
                                                        hipStream_t);
-template <typename T> hipError_t launch_gather_binned(const Geometry*, size_t, char*, size_t, const char*, size_t,
-                                                      const void*, size_t, const PtrBatch&, const PtrBatch&,
-                                                      const PtrBatch&, const MeshDims&, const BinGeom&, int, int,
+template <typename T> hipError_t launch_gather_binned(const Geometry*, size_t, char*, size_t, char*, size_t,
+                                                      const void*, size_t, const MeshDims&, const BinGeom&, int, int,
                                                       hipStream_t);
+template <typename T> hipError_t launch_unsort(const BatchScalars&, int, const char*, size_t, size_t,
+                                               const PtrBatch&, const PtrBatch&, const PtrBatch&, hipStream_t);
 template <typename T> hipError_t launch_twiddle_pass(void*, int, int, hipStream_t);
 template <typename T> hipError_t launch_twiddle_line(void*, int, int, hipStream_t);
 hipError_t launch_igf_octant(double*, const int*, const double*, const GLBands&, hipStream_t);
@@ -177,7 +178,7 @@ struct dks_poisson_plan_s {
   size_t bytes_W, bytes_phi_ext;
   BinGeom bg;          // tiles of the binned deposit/gather (item set per solve)
   int bins_len;        // uint32 entries of the bin bookkeeping
-  size_t part_elem;    // bytes per binned particle record
+  size_t part_elem;    // bytes per binned particle record (x, y, z, index; later the field)
   size_t ws_total;
   char* ws;
   size_t ws_bytes;
@@ -190,6 +191,13 @@ struct dks_poisson_plan_s {
 namespace {
 
 dks_status hip_status(hipError_t e) { return e == hipSuccess ? DKS_OK : DKS_EHIP; }
+
+// Particle scratch of np particles: the binned records, then the inverse
+// permutation (uint32 per particle).
+size_t inv_offset(const dks_poisson_plan_s* p, int64_t np) { return align256((size_t)np * p->part_elem); }
+size_t particle_bytes(const dks_poisson_plan_s* p, int64_t np) {
+  return inv_offset(p, np) + align256((size_t)np * sizeof(unsigned));
+}
 
 // Optional per-kernel event timing (dks_timing_enable / dks_timing_read).
 struct TimingState {
@@ -396,7 +404,9 @@ PartWork part_work(const dks_poisson_plan_s* p, const BatchScalars& bs, int batc
   const int64_t maxn = bs.max_np;
   PartWork w;
   w.bg = p->bg;
-  w.bg.item = (int)std::min<int64_t>(65536, std::max<int64_t>(8192, maxn / 512));
+  // Work items bound the fixed-point deposit sums: <= 2^16 particles (FP32), 2^14 (FP64).
+  const int64_t item_cap = p->dtype == DKS_F32 ? 65536 : 16384;
+  w.bg.item = (int)std::min<int64_t>(item_cap, std::max<int64_t>(8192, maxn / 512));
   w.count_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (maxn + 8191) / 8192));
   const int64_t items = (maxn + w.bg.item - 1) / w.bg.item + w.bg.K + 1;
   w.item_blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(1, items));
@@ -408,7 +418,8 @@ PartWork part_work(const dks_poisson_plan_s* p, const BatchScalars& bs, int batc
 template <typename T>
 dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl, const PtrBatch& X,
                          const PtrBatch& Y, const PtrBatch& Z, const BatchScalars& bs, const PtrBatch& cnt,
-                         char* sorted, size_t sorted_stride, const PartWork& w, hipStream_t st) {
+                         char* sorted, size_t sorted_stride, size_t inv_off, const PartWork& w,
+                         hipStream_t st) {
   int nb = 0;
   double* bbox = reinterpret_cast<double*>(sl.base + p->s_bbox);
   if (p->fitted) DKS_TK("bbox", launch_bbox<T>(X, Y, Z, bs, batch, bbox, sl.stride / sizeof(double), &nb, st));
@@ -421,7 +432,7 @@ dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl
                                           w.count_blocks, st));
   DKS_TK("bin_scan", launch_bin_scan(sl.geo(), sl.stride, sl.base, p->s_bins, w.bg, cnt, batch, st));
   DKS_TK("bin_scatter", launch_bin_scatter<T>(X, Y, Z, bs, batch, sl.geo(), sl.stride, sl.base, p->s_bins, sorted,
-                                              sorted_stride, p->md, w.bg, w.count_blocks, st));
+                                              sorted_stride, inv_off, p->md, w.bg, w.count_blocks, st));
   DKS_TK("deposit", launch_deposit_binned<T>(sl.geo(), sl.stride, sl.base, p->s_bins, sorted, sorted_stride,
                                              sl.base + p->s_r3, sl.stride / sizeof(T), p->md, w.bg, w.item_blocks,
                                              batch, st));
@@ -434,13 +445,15 @@ dks_status solve_particles_t(const dks_poisson_plan_s* p, int batch, const Slots
                              const PtrBatch& EZ, const PtrBatch& PHI, const BatchScalars& bs,
                              const PtrBatch& cnt, char* sorted, size_t sorted_stride, hipStream_t st) {
   const PartWork w = part_work(p, bs, batch);
-  dks_status r = deposit_stage<T>(p, batch, sl, X, Y, Z, bs, cnt, sorted, sorted_stride, w, st);
+  const size_t inv_off = inv_offset(p, bs.max_np);
+  dks_status r = deposit_stage<T>(p, batch, sl, X, Y, Z, bs, cnt, sorted, sorted_stride, inv_off, w, st);
   if (r != DKS_OK) return r;
   r = convolve<T>(p, sl.base + p->s_r3, sl.stride / sizeof(T), batch, sl, PHI, st);
   if (r != DKS_OK) return r;
   DKS_TK("gather", launch_gather_binned<T>(sl.geo(), sl.stride, sl.base, p->s_bins, sorted, sorted_stride,
-                                           sl.base + p->s_r3, sl.stride / sizeof(T), EX, EY, EZ, p->md, w.bg,
-                                           w.item_blocks, batch, st));
+                                           sl.base + p->s_r3, sl.stride / sizeof(T), p->md, w.bg, w.item_blocks,
+                                           batch, st));
+  DKS_TK("unsort", launch_unsort<T>(bs, batch, sorted, sorted_stride, inv_off, EX, EY, EZ, st));
   return DKS_OK;
 }
 
@@ -571,7 +584,7 @@ dks_status dks_poisson_workspace_bytes(dks_poisson_plan_t p, size_t* bytes) {
 
 dks_status dks_poisson_particle_scratch_bytes(dks_poisson_plan_t p, int64_t np, size_t* bytes) {
   if (!p || !bytes || np < 0 || np > (int64_t)UINT32_MAX) return DKS_EINVAL;
-  *bytes = align256((size_t)np * p->part_elem);
+  *bytes = particle_bytes(p, np);
   return DKS_OK;
 }
 
@@ -586,7 +599,7 @@ dks_status dks_poisson_set_particle_scratch(dks_poisson_plan_t p, void* scratch,
 dks_status dks_poisson_batch_scratch_bytes(dks_poisson_plan_t p, int batch, int64_t max_np, size_t* bytes) {
   if (!p || !bytes || batch < 1 || batch > kMaxBatch || max_np < 0 || max_np > (int64_t)UINT32_MAX)
     return DKS_EINVAL;
-  *bytes = (size_t)batch * (p->slot_bytes + align256((size_t)max_np * p->part_elem));
+  *bytes = (size_t)batch * (p->slot_bytes + particle_bytes(p, max_np));
   return DKS_OK;
 }
 
@@ -652,7 +665,7 @@ dks_status dks_poisson_solve_particles(dks_poisson_plan_t p, const void* x, cons
   if (!p || np < 0 || np > (int64_t)UINT32_MAX || !std::isfinite(q)) return DKS_EINVAL;
   if (np > 0 && (!x || !y || !z || !Ex || !Ey || !Ez)) return DKS_EINVAL;
   if (!ws_ready(p)) return DKS_EWORKSPACE;
-  if ((size_t)np * p->part_elem > p->pscratch_bytes) return DKS_EWORKSPACE;
+  if (particle_bytes(p, np) > p->pscratch_bytes) return DKS_EWORKSPACE;
   if (!p->prepared) return DKS_ESTATE;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   Slots sl{p->ws + p->off_slot, p->slot_bytes};
@@ -684,7 +697,7 @@ dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, 
   if (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255u)) return DKS_EWORKSPACE;
   // Element b owns [b * stride, (b + 1) * stride): its slot, then its binned particles.
   const size_t stride = (scratch_bytes / (size_t)batch) & ~(size_t)255;
-  if (stride < p->slot_bytes || (stride - p->slot_bytes) / p->part_elem < (size_t)max_np) return DKS_EWORKSPACE;
+  if (stride < p->slot_bytes + particle_bytes(p, max_np)) return DKS_EWORKSPACE;
   PtrBatch X, Y, Z, EX, EY, EZ, PHI, CNT;
   BatchScalars bs;
   std::memset(&X, 0, sizeof(X)); std::memset(&Y, 0, sizeof(Y)); std::memset(&Z, 0, sizeof(Z));
@@ -717,7 +730,7 @@ dks_status dks_poisson_deposit(dks_poisson_plan_t p, const void* x, const void* 
   if (!p || !rho || np < 0 || np > (int64_t)UINT32_MAX || !std::isfinite(q)) return DKS_EINVAL;
   if (np > 0 && (!x || !y || !z)) return DKS_EINVAL;
   if (!ws_ready(p)) return DKS_EWORKSPACE;
-  if ((size_t)np * p->part_elem > p->pscratch_bytes) return DKS_EWORKSPACE;
+  if (particle_bytes(p, np) > p->pscratch_bytes) return DKS_EWORKSPACE;
   if (!p->prepared) return DKS_ESTATE;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   Slots sl{p->ws + p->off_slot, p->slot_bytes};
@@ -730,10 +743,12 @@ dks_status dks_poisson_deposit(dks_poisson_plan_t p, const void* x, const void* 
   const size_t nmesh = (size_t)p->n[0] * p->n[1] * p->n[2];
   dks_status r;
   if (p->dtype == DKS_F32) {
-    r = deposit_stage<float>(p, 1, sl, one(x), one(y), one(z), bs, one(n_outside), p->pscratch, 0, w, st);
+    r = deposit_stage<float>(p, 1, sl, one(x), one(y), one(z), bs, one(n_outside), p->pscratch, 0,
+                             inv_offset(p, np), w, st);
     if (r == DKS_OK) r = hip_status(launch_weights_to_density<float>(sl.base + p->s_r3, rho, nmesh, sl.geo(), q, st));
   } else {
-    r = deposit_stage<double>(p, 1, sl, one(x), one(y), one(z), bs, one(n_outside), p->pscratch, 0, w, st);
+    r = deposit_stage<double>(p, 1, sl, one(x), one(y), one(z), bs, one(n_outside), p->pscratch, 0,
+                              inv_offset(p, np), w, st);
     if (r == DKS_OK) r = hip_status(launch_weights_to_density<double>(sl.base + p->s_r3, rho, nmesh, sl.geo(), q, st));
   }
   if (r == DKS_OK) p->has_geometry = true;
