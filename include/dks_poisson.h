@@ -149,29 +149,42 @@ dks_status dks_poisson_solve_particles(dks_poisson_plan_t plan, const void* x, c
                                        void* Ez, void* phi, int64_t* n_outside,
                                        dks_stream_t stream);
 
-/* The same step for `batch` independent particle sets of the plan's shape
- * and dtype, each kernel launched once over the whole batch (the batch index
- * is part of the grid).  On a fitted plan every element gets its own mesh fit;
- * the cached spectrum is scaled per element by h_b^2.  Counts and charges are
- * read from device memory when the kernels run, so a captured HIP graph of
- * this call can be replayed with new counts, charges and particle data (at
- * the same addresses).
- *   batch           : 1 .. 16 elements.
- *   x, y, z, Ex, Ey, Ez : host arrays of `batch` device pointers.
- *   np              : device int64[batch] particle counts.
- *   q               : device double[batch] charge per particle of each element.
- *   max_np          : host bound on every np[b]; larger counts are clamped to it.
- *   phi             : host array of `batch` device pointers (entries may be
- *                     NULL), or NULL.
- *   scratch         : device, >= dks_poisson_batch_scratch_bytes(batch, max_np),
- *                     256-byte aligned, caller-owned; element b uses the
- *                     b-th of `batch` equal parts (rounded down to 256 bytes).
- *   n_outside       : device int64[batch], written; may be NULL. */
-dks_status dks_poisson_solve_particles_batched(
-    dks_poisson_plan_t plan, int batch, const void* const* x, const void* const* y,
-    const void* const* z, const int64_t* np, const double* q, int64_t max_np, void* const* Ex,
-    void* const* Ey, void* const* Ez, void* const* phi, void* scratch, size_t scratch_bytes,
-    int64_t* n_outside, dks_stream_t stream);
+/* One element of a batched particle solve.  The table of elements lives in
+ * device memory and is read by the kernels when they run, so a HIP graph
+ * captured over dks_poisson_solve_particles_batched can be replayed for new
+ * particle sets by rewriting the table (same table address, same batch).
+ * Every field is 8 bytes; the struct is 80 bytes. */
+typedef struct {
+  const void* x;         /* device [np] positions, metres */
+  const void* y;
+  const void* z;
+  void* Ex;              /* device [np] field at the particles, V/m, written */
+  void* Ey;
+  void* Ez;
+  void* phi;             /* device [nz][ny][nx] potential, volts, or NULL */
+  int64_t* n_outside;    /* device counter of particles outside the mesh, or NULL */
+  int64_t np;            /* particle count; clamped to [0, max_np] */
+  double q;              /* charge of each particle, coulombs */
+} dks_particle_set;
+
+/* The particle step for `batch` independent particle sets of the plan's
+ * shape and dtype, each kernel launched once over the whole batch (the batch
+ * index is part of the grid).  On a fitted plan every element gets its own
+ * mesh fit, and the cached unit-spacing spectrum is rescaled per element
+ * (the integrated kernel grows as h^2 on a cubic mesh, the density as h^-3).
+ *   batch   : 1 .. 16 elements.
+ *   sets    : device array of `batch` dks_particle_set.  An element whose
+ *             x, y, z, Ex, Ey or Ez is NULL is treated as having no particles.
+ *   max_np  : host bound on every element's np; sizes the launches.
+ *   scratch : device, >= dks_poisson_batch_scratch_bytes(batch, max_np),
+ *             256-byte aligned, caller-owned; element b uses the b-th of
+ *             `batch` equal parts (rounded down to 256 bytes).
+ * Elements share nothing but the plan's read-only state, so batches on
+ * different streams may run concurrently with distinct scratch buffers. */
+dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t plan, int batch,
+                                               const dks_particle_set* sets, int64_t max_np,
+                                               void* scratch, size_t scratch_bytes,
+                                               dks_stream_t stream);
 
 /* Charge deposit alone (CIC assignment, the "NGP, CIC, TSI" box of the OPAL
  * structure figure), including the mesh fit of a fitted plan.

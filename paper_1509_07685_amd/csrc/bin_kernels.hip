@@ -125,18 +125,18 @@ __device__ __forceinline__ void chunk_of(int64_t n, int blk, int nblk, int64_t* 
 // count
 // ---------------------------------------------------------------------------
 template <typename T, bool LDSHIST>
-__global__ __launch_bounds__(256) void k_bin_count(PtrBatch xs, PtrBatch ys, PtrBatch zs, BatchScalars bs,
-                                                   const Geometry* geo, size_t stride, char* slot_base,
+__global__ __launch_bounds__(256) void k_bin_count(ElemBatch eb, const Geometry* geo, size_t stride, char* slot_base,
                                                    size_t bins_off, MeshDims m, BinGeom bg) {
   extern __shared__ unsigned hist[];
   const int b = blockIdx.y;
-  const T* px = (const T*)xs.p[b];
-  const T* py = (const T*)ys.p[b];
-  const T* pz = (const T*)zs.p[b];
+  const dks_particle_set e = eb.at(b);
+  const T* px = (const T*)e.x;
+  const T* py = (const T*)e.y;
+  const T* pz = (const T*)e.z;
   const Geometry* g = geo_of(geo, stride, b);
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
   int64_t start, end;
-  chunk_of(bs.n(b), blockIdx.x, gridDim.x, &start, &end);
+  chunk_of(eb.n(e), blockIdx.x, gridDim.x, &start, &end);
   if (LDSHIST) {
     for (int k = threadIdx.x; k <= bg.K; k += blockDim.x) hist[k] = 0;
     __syncthreads();
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_bin_count(PtrBatch xs, PtrBatch ys, Ptr
 // of 1024 threads per batch element.  Also publishes the out-of-mesh count.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_bin_scan(const Geometry* geo, size_t stride, char* slot_base,
-                                                   size_t bins_off, BinGeom bg, PtrBatch counters) {
+                                                   size_t bins_off, BinGeom bg, ElemBatch eb) {
   __shared__ unsigned s_cnt[1024];
   __shared__ unsigned s_itm[1024];
   const int b = blockIdx.x;
@@ -200,10 +200,10 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const Geometry* geo, size_t s
     st.item_off[L] = s_itm[1023];
     st.misc[0] = s_itm[1023];
     const unsigned long long outside = st.count[bg.K];
-    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters.p[b]);
+    int64_t* cnt = eb.at(b).n_outside;
     Geometry* gw = const_cast<Geometry*>(geo_of(geo, stride, b));
     gw->n_outside = outside;
-    if (cnt) *cnt = outside;
+    if (cnt) *cnt = (int64_t)outside;
   }
 }
 
@@ -211,8 +211,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const Geometry* geo, size_t s
 // scatter: reserve one range per tile per block, then write packed particles.
 // ---------------------------------------------------------------------------
 template <typename T, bool LDSHIST>
-__global__ __launch_bounds__(256) void k_bin_scatter(PtrBatch xs, PtrBatch ys, PtrBatch zs, BatchScalars bs,
-                                                     const Geometry* geo, size_t stride, char* slot_base,
+__global__ __launch_bounds__(256) void k_bin_scatter(ElemBatch eb, const Geometry* geo, size_t stride, char* slot_base,
                                                      size_t bins_off, char* sorted_base, size_t sorted_stride,
                                                      size_t inv_off, MeshDims m, BinGeom bg) {
   extern __shared__ unsigned lds[];
@@ -220,15 +219,16 @@ __global__ __launch_bounds__(256) void k_bin_scatter(PtrBatch xs, PtrBatch ys, P
   unsigned* lbase = lds + (bg.K + 1);
   using P4 = typename Packed<T>::type;
   const int b = blockIdx.y;
-  const T* px = (const T*)xs.p[b];
-  const T* py = (const T*)ys.p[b];
-  const T* pz = (const T*)zs.p[b];
+  const dks_particle_set e = eb.at(b);
+  const T* px = (const T*)e.x;
+  const T* py = (const T*)e.y;
+  const T* pz = (const T*)e.z;
   const Geometry* g = geo_of(geo, stride, b);
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
   P4* out = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
   unsigned* inv = reinterpret_cast<unsigned*>(sorted_base + (size_t)b * sorted_stride + inv_off);
   int64_t start, end;
-  chunk_of(bs.n(b), blockIdx.x, gridDim.x, &start, &end);
+  chunk_of(eb.n(e), blockIdx.x, gridDim.x, &start, &end);
   if (LDSHIST) {
     for (int k = threadIdx.x; k <= bg.K; k += blockDim.x) lcnt[k] = 0;
     __syncthreads();
@@ -404,16 +404,17 @@ __global__ __launch_bounds__(256) void k_gather_binned(const Geometry* geo, size
 // unsort: E at the particles in their original order.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_unsort(BatchScalars bs, const char* sorted_base, size_t sorted_stride,
-                                                size_t inv_off, PtrBatch exs, PtrBatch eys, PtrBatch ezs) {
+__global__ __launch_bounds__(256) void k_unsort(ElemBatch eb, const char* sorted_base, size_t sorted_stride,
+                                                size_t inv_off) {
   using P4 = typename Packed<T>::type;
   const int b = blockIdx.y;
   const P4* part = reinterpret_cast<const P4*>(sorted_base + (size_t)b * sorted_stride);
   const unsigned* inv = reinterpret_cast<const unsigned*>(sorted_base + (size_t)b * sorted_stride + inv_off);
-  T* qx = (T*)exs.p[b];
-  T* qy = (T*)eys.p[b];
-  T* qz = (T*)ezs.p[b];
-  const int64_t n = bs.n(b);
+  const dks_particle_set s = eb.at(b);
+  T* qx = (T*)s.Ex;
+  T* qy = (T*)s.Ey;
+  T* qz = (T*)s.Ez;
+  const int64_t n = eb.n(s);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const P4 e = part[inv[i]];
     qx[i] = e.x;
@@ -426,38 +427,36 @@ __global__ __launch_bounds__(256) void k_unsort(BatchScalars bs, const char* sor
 // Host launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-hipError_t launch_bin_count(const PtrBatch& xs, const PtrBatch& ys, const PtrBatch& zs, const BatchScalars& bs,
-                            int batch, const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
+hipError_t launch_bin_count(const ElemBatch& eb, int batch, const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                             const MeshDims& m, const BinGeom& bg, int nblk, hipStream_t s) {
   const bool lh = bg.lds_hist != 0;
   const size_t lds = lh ? (size_t)(bg.K + 1) * sizeof(unsigned) : 0;
   if (lh)
-    hipLaunchKernelGGL((k_bin_count<T, true>), dim3(nblk, batch), dim3(256), lds, s, xs, ys, zs, bs, geo, stride,
+    hipLaunchKernelGGL((k_bin_count<T, true>), dim3(nblk, batch), dim3(256), lds, s, eb, geo, stride,
                        slot_base, bins_off, m, bg);
   else
-    hipLaunchKernelGGL((k_bin_count<T, false>), dim3(nblk, batch), dim3(256), 0, s, xs, ys, zs, bs, geo, stride,
+    hipLaunchKernelGGL((k_bin_count<T, false>), dim3(nblk, batch), dim3(256), 0, s, eb, geo, stride,
                        slot_base, bins_off, m, bg);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_scan(const Geometry* geo, size_t stride, char* slot_base, size_t bins_off, const BinGeom& bg,
-                           const PtrBatch& counters, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(k_bin_scan, dim3(batch), dim3(1024), 0, s, geo, stride, slot_base, bins_off, bg, counters);
+                           const ElemBatch& eb, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_bin_scan, dim3(batch), dim3(1024), 0, s, geo, stride, slot_base, bins_off, bg, eb);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_bin_scatter(const PtrBatch& xs, const PtrBatch& ys, const PtrBatch& zs, const BatchScalars& bs,
-                              int batch, const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
+hipError_t launch_bin_scatter(const ElemBatch& eb, int batch, const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                               char* sorted_base, size_t sorted_stride, size_t inv_off, const MeshDims& m,
                               const BinGeom& bg, int nblk, hipStream_t s) {
   const bool lh = bg.lds_hist != 0;
   const size_t lds = lh ? 2 * (size_t)(bg.K + 1) * sizeof(unsigned) : 0;
   if (lh)
-    hipLaunchKernelGGL((k_bin_scatter<T, true>), dim3(nblk, batch), dim3(256), lds, s, xs, ys, zs, bs, geo, stride,
+    hipLaunchKernelGGL((k_bin_scatter<T, true>), dim3(nblk, batch), dim3(256), lds, s, eb, geo, stride,
                        slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
   else
-    hipLaunchKernelGGL((k_bin_scatter<T, false>), dim3(nblk, batch), dim3(256), 0, s, xs, ys, zs, bs, geo, stride,
+    hipLaunchKernelGGL((k_bin_scatter<T, false>), dim3(nblk, batch), dim3(256), 0, s, eb, geo, stride,
                        slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
   return hipGetLastError();
 }
@@ -481,22 +480,19 @@ hipError_t launch_gather_binned(const Geometry* geo, size_t stride, char* slot_b
 }
 
 template <typename T>
-hipError_t launch_unsort(const BatchScalars& bs, int batch, const char* sorted_base, size_t sorted_stride,
-                         size_t inv_off, const PtrBatch& exs, const PtrBatch& eys, const PtrBatch& ezs,
-                         hipStream_t s) {
-  if (bs.max_np == 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>((bs.max_np + 255) / 256, 65535 * 4);
-  hipLaunchKernelGGL(k_unsort<T>, dim3((unsigned)blocks, batch), dim3(256), 0, s, bs, sorted_base, sorted_stride,
-                     inv_off, exs, eys, ezs);
+hipError_t launch_unsort(const ElemBatch& eb, int batch, const char* sorted_base, size_t sorted_stride,
+                         size_t inv_off, hipStream_t s) {
+  if (eb.max_np == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((eb.max_np + 255) / 256, 65535 * 4);
+  hipLaunchKernelGGL(k_unsort<T>, dim3((unsigned)blocks, batch), dim3(256), 0, s, eb, sorted_base, sorted_stride,
+                     inv_off);
   return hipGetLastError();
 }
 
 #define DKS_INSTANTIATE(T)                                                                                         \
-  template hipError_t launch_bin_count<T>(const PtrBatch&, const PtrBatch&, const PtrBatch&, const BatchScalars&,  \
-                                          int, const Geometry*, size_t, char*, size_t, const MeshDims&,            \
+  template hipError_t launch_bin_count<T>(const ElemBatch&, int, const Geometry*, size_t, char*, size_t, const MeshDims&,            \
                                           const BinGeom&, int, hipStream_t);                                       \
-  template hipError_t launch_bin_scatter<T>(const PtrBatch&, const PtrBatch&, const PtrBatch&,                     \
-                                            const BatchScalars&, int, const Geometry*, size_t, char*, size_t,      \
+  template hipError_t launch_bin_scatter<T>(const ElemBatch&, int, const Geometry*, size_t, char*, size_t,      \
                                             char*, size_t, size_t, const MeshDims&, const BinGeom&, int,           \
                                             hipStream_t);                                                          \
   template hipError_t launch_deposit_binned<T>(const Geometry*, size_t, char*, size_t, const char*, size_t, void*, \
@@ -504,8 +500,7 @@ hipError_t launch_unsort(const BatchScalars& bs, int batch, const char* sorted_b
   template hipError_t launch_gather_binned<T>(const Geometry*, size_t, char*, size_t, char*, size_t,               \
                                               const void*, size_t, const MeshDims&, const BinGeom&, int, int,      \
                                               hipStream_t);                                                        \
-  template hipError_t launch_unsort<T>(const BatchScalars&, int, const char*, size_t, size_t, const PtrBatch&,     \
-                                       const PtrBatch&, const PtrBatch&, hipStream_t);
+  template hipError_t launch_unsort<T>(const ElemBatch&, int, const char*, size_t, size_t, hipStream_t);
 DKS_INSTANTIATE(float)
 DKS_INSTANTIATE(double)
 #undef DKS_INSTANTIATE

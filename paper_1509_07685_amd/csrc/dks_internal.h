@@ -84,28 +84,26 @@ struct MeshDims {
   int ncols;          // nx + 1 complex columns
 };
 
-// Up to kMaxBatch per-element caller pointers, passed to kernels by value.
 constexpr int kMaxBatch = 16;
-struct PtrBatch {
-  void* p[kMaxBatch];
-};
+static_assert(sizeof(dks_particle_set) == 80, "dks_particle_set layout is part of the ABI");
 
-// Per-element particle counts and charges of a (batched) particle solve:
-// by value, or (np_dev / q_dev set) read from device memory when the kernels
-// run, so that a captured graph can be replayed with new counts.  max_np
-// bounds every count; it sizes the launches on the host.
-struct BatchScalars {
-  int64_t np[kMaxBatch];
-  double q[kMaxBatch];
-  const int64_t* np_dev;
-  const double* q_dev;
+// Per-element arguments of a particle solve: one element by value (single
+// solves, solve_rho's phi) or a device table of elements read when the
+// kernels run (batched solves).  Accessors return by value so no kernel
+// argument is ever indexed at run time.  Counts are clamped to [0, max_np];
+// an element without positions (or, when need_e, without field outputs) has
+// no particles.
+struct ElemBatch {
+  dks_particle_set local;
+  const dks_particle_set* dev;
   int64_t max_np;
-  __device__ __forceinline__ int64_t n(int b) const {
-    if (!np_dev) return np[b];
-    const int64_t v = np_dev[b];
-    return v < 0 ? 0 : (v > max_np ? max_np : v);
+  int need_e;
+  __device__ __forceinline__ dks_particle_set at(int b) const { return dev ? dev[b] : local; }
+  __device__ __forceinline__ int64_t n(const dks_particle_set& s) const {
+    if (!s.x || !s.y || !s.z) return 0;
+    if (need_e && (!s.Ex || !s.Ey || !s.Ez)) return 0;
+    return s.np < 0 ? 0 : (s.np > max_np ? max_np : s.np);
   }
-  __device__ __forceinline__ double charge(int b) const { return q_dev ? q_dev[b] : q[b]; }
 };
 
 // Arguments of the per-solve geometry kernel.

@@ -408,7 +408,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_inv(const typename
 template <typename T>
 __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_inv(const typename Cplx<T>::type* __restrict__ D,
                                                         size_t in_stride, T* __restrict__ phi_ext,
-                                                        size_t out_stride, PtrBatch phi_user,
+                                                        size_t out_stride, ElemBatch phi_user,
                                                         MeshDims m, const FFTPlan* __restrict__ P,
                                                         const typename Cplx<T>::type* __restrict__ post,
                                                         int nrows, int logTX) {
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_inv(const typename
   C* lds = reinterpret_cast<C*>(smem);
   const C* src = D + blockIdx.y * in_stride;
   T* dst = phi_ext + blockIdx.y * out_stride;
-  T* user = reinterpret_cast<T*>(phi_user.p[blockIdx.y]);
+  T* user = reinterpret_cast<T*>(phi_user.at(blockIdx.y).phi);
   const int row0 = blockIdx.x * P->W;
   const int nvalid = min(P->W, nrows - row0);
   const int nx = m.nx, M = P->N;
@@ -529,7 +529,7 @@ hipError_t launch_fft_y_inv(const void* Cin, void* D, size_t stride, const MeshD
 
 template <typename T>
 hipError_t launch_fft_x_inv(const void* D, size_t in_stride, void* phi_ext, size_t out_stride,
-                            const PtrBatch& phi_user, const MeshDims& m, const PlanRef& P, const void* post,
+                            const ElemBatch& phi_user, const MeshDims& m, const PlanRef& P, const void* post,
                             int batch, hipStream_t s) {
   using C = typename Cplx<T>::type;
   const int nrows = (m.ny + 2) * (m.nz + 2);
@@ -565,7 +565,7 @@ hipError_t launch_store_plans(const FFTPlan* four, FFTPlan* dev, hipStream_t s) 
                                            const MeshDims&, const PlanRef&, const PlanRef&, int, hipStream_t); \
   template hipError_t launch_fft_y_inv<T>(const void*, void*, size_t, const MeshDims&, const PlanRef&, int,    \
                                           hipStream_t);                                                        \
-  template hipError_t launch_fft_x_inv<T>(const void*, size_t, void*, size_t, const PtrBatch&, const MeshDims&, \
+  template hipError_t launch_fft_x_inv<T>(const void*, size_t, void*, size_t, const ElemBatch&, const MeshDims&,\
                                           const PlanRef&, const void*, int, hipStream_t);
 DKS_INSTANTIATE(float)
 DKS_INSTANTIATE(double)

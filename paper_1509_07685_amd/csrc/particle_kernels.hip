@@ -32,11 +32,11 @@ __device__ __forceinline__ const Geometry* geo_at(const Geometry* base, size_t s
 // max z) and writes it to its partial slot.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_bbox(PtrBatch xs, PtrBatch ys, PtrBatch zs, BatchScalars bs,
-                                              double* partial, size_t partial_stride) {
+__global__ __launch_bounds__(256) void k_bbox(ElemBatch eb, double* partial, size_t partial_stride) {
   const int b = blockIdx.y;
-  const T* p[3] = {(const T*)xs.p[b], (const T*)ys.p[b], (const T*)zs.p[b]};
-  const int64_t n = bs.n(b);
+  const dks_particle_set e = eb.at(b);
+  const T* p[3] = {(const T*)e.x, (const T*)e.y, (const T*)e.z};
+  const int64_t n = eb.n(e);
   T lo[3], hi[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -80,9 +80,10 @@ __global__ __launch_bounds__(256) void k_bbox(PtrBatch xs, PtrBatch ys, PtrBatch
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_geometry(const double* partial, size_t partial_stride,
                                                   Geometry* geo, size_t geo_stride, GeoArgs a,
-                                                  BatchScalars bs, PtrBatch counters) {
+                                                  ElemBatch eb) {
 #pragma clang fp contract(off)
   const int b = blockIdx.x;
+  const dks_particle_set e = eb.at(b);
   Geometry* g = reinterpret_cast<Geometry*>(reinterpret_cast<char*>(geo) + (size_t)b * geo_stride);
   if (a.zero_len > 0) {
     unsigned* z = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(g) + a.zero_off);
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(256) void k_geometry(const double* partial, size_t 
   double h[3], origin[3];
   if (a.fitted) {
     double lo[3], hi[3];
-    const bool empty = bs.n(b) <= 0;
+    const bool empty = eb.n(e) <= 0;
     for (int d = 0; d < 3; ++d) {
       lo[d] = empty ? 0.0 : red[d][0];
       hi[d] = empty ? 0.0 : red[3 + d][0];
@@ -143,8 +144,8 @@ __global__ __launch_bounds__(256) void k_geometry(const double* partial, size_t 
   const double coulomb = 1.0 / (4.0 * M_PI * kEps0);
   double scale;
   if (a.mode == 0) scale = coulomb;                                   // rho given in C/m^3
-  else if (a.fitted) scale = coulomb * bs.charge(b) / h[0];                // spectrum built for h = 1 m
-  else scale = coulomb * bs.charge(b) / (h[0] * h[1] * h[2]);             // rho = q W / V
+  else if (a.fitted) scale = coulomb * e.q / h[0];                // spectrum built for h = 1 m
+  else scale = coulomb * e.q / (h[0] * h[1] * h[2]);             // rho = q W / V
   for (int d = 0; d < 3; ++d) {
     g->h[d] = h[d];
     g->origin[d] = origin[d];
@@ -157,8 +158,7 @@ __global__ __launch_bounds__(256) void k_geometry(const double* partial, size_t 
   g->conv_scale = scale;
   g->conv_scale_f = (float)scale;
   g->n_outside = 0;
-  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counters.p[b]);
-  if (cnt) *cnt = 0;
+  if (e.n_outside) *e.n_outside = 0;
 }
 
 // Zero `count` elements of batch element blockIdx.y (vectorised, 16 B per store).
@@ -257,19 +257,17 @@ static inline unsigned grid_for(int64_t n, unsigned cap) {
 }
 
 template <typename T>
-hipError_t launch_bbox(const PtrBatch& xs, const PtrBatch& ys, const PtrBatch& zs, const BatchScalars& bs,
-                       int batch, double* partial, size_t partial_stride, int* nblocks_out, hipStream_t s) {
-  const unsigned nb = grid_for(bs.max_np, kBboxBlocks);
+hipError_t launch_bbox(const ElemBatch& eb, int batch, double* partial, size_t partial_stride, int* nblocks_out,
+                       hipStream_t s) {
+  const unsigned nb = grid_for(eb.max_np, kBboxBlocks);
   *nblocks_out = (int)nb;
-  hipLaunchKernelGGL(k_bbox<T>, dim3(nb, batch), dim3(256), 0, s, xs, ys, zs, bs, partial, partial_stride);
+  hipLaunchKernelGGL(k_bbox<T>, dim3(nb, batch), dim3(256), 0, s, eb, partial, partial_stride);
   return hipGetLastError();
 }
 
 hipError_t launch_geometry(const double* partial, size_t partial_stride, Geometry* geo, size_t geo_stride,
-                           const GeoArgs& a, const BatchScalars& bs, const PtrBatch& counters, int batch,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_geometry, dim3(batch), dim3(256), 0, s, partial, partial_stride, geo, geo_stride, a, bs,
-                     counters);
+                           const GeoArgs& a, const ElemBatch& eb, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_geometry, dim3(batch), dim3(256), 0, s, partial, partial_stride, geo, geo_stride, a, eb);
   return hipGetLastError();
 }
 
@@ -304,8 +302,7 @@ hipError_t launch_gather(const void* E, const void* x, const void* y, const void
 }
 
 #define DKS_INSTANTIATE(T)                                                                                   \
-  template hipError_t launch_bbox<T>(const PtrBatch&, const PtrBatch&, const PtrBatch&, const BatchScalars&, \
-                                     int, double*, size_t, int*, hipStream_t);                               \
+  template hipError_t launch_bbox<T>(const ElemBatch&, int, double*, size_t, int*, hipStream_t);           \
   template hipError_t launch_weights_to_density<T>(const void*, void*, size_t, const Geometry*, double,      \
                                                    hipStream_t);                                             \
   template hipError_t launch_gradient<T>(const void*, void*, const Geometry*, const MeshDims&, hipStream_t); \

@@ -25,26 +25,24 @@ template <typename T> hipError_t launch_fft_z_conv(const void*, void*, size_t, c
                                                    hipStream_t);
 template <typename T> hipError_t launch_fft_y_inv(const void*, void*, size_t, const MeshDims&, const PlanRef&,
                                                   int, hipStream_t);
-template <typename T> hipError_t launch_fft_x_inv(const void*, size_t, void*, size_t, const PtrBatch&,
+template <typename T> hipError_t launch_fft_x_inv(const void*, size_t, void*, size_t, const ElemBatch&,
                                                   const MeshDims&, const PlanRef&, const void*, int,
                                                   hipStream_t);
 hipError_t launch_store_plans(const FFTPlan* four, FFTPlan* dev, hipStream_t s);
-template <typename T> hipError_t launch_bbox(const PtrBatch&, const PtrBatch&, const PtrBatch&,
-                                             const BatchScalars&, int, double*, size_t, int*, hipStream_t);
-hipError_t launch_geometry(const double*, size_t, Geometry*, size_t, const GeoArgs&, const BatchScalars&,
-                           const PtrBatch&, int, hipStream_t);
+template <typename T> hipError_t launch_bbox(const ElemBatch&, int, double*, size_t, int*, hipStream_t);
+hipError_t launch_geometry(const double*, size_t, Geometry*, size_t, const GeoArgs&, const ElemBatch&, int,
+                           hipStream_t);
 hipError_t launch_zero(void*, size_t, size_t, int, hipStream_t);
 template <typename T> hipError_t launch_weights_to_density(const void*, void*, size_t, const Geometry*, double,
                                                            hipStream_t);
 template <typename T> hipError_t launch_gradient(const void*, void*, const Geometry*, const MeshDims&, hipStream_t);
 template <typename T> hipError_t launch_gather(const void*, const void*, const void*, const void*, void*, void*,
                                                void*, int64_t, const Geometry*, const MeshDims&, hipStream_t);
-template <typename T> hipError_t launch_bin_count(const PtrBatch&, const PtrBatch&, const PtrBatch&,
-                                                  const BatchScalars&, int, const Geometry*, size_t, char*, size_t,
+template <typename T> hipError_t launch_bin_count(const ElemBatch&, int, const Geometry*, size_t, char*, size_t,
                                                   const MeshDims&, const BinGeom&, int, hipStream_t);
-hipError_t launch_bin_scan(const Geometry*, size_t, char*, size_t, const BinGeom&, const PtrBatch&, int, hipStream_t);
-template <typename T> hipError_t launch_bin_scatter(const PtrBatch&, const PtrBatch&, const PtrBatch&,
-                                                    const BatchScalars&, int, const Geometry*, size_t, char*,
+hipError_t launch_bin_scan(const Geometry*, size_t, char*, size_t, const BinGeom&, const ElemBatch&, int,
+                           hipStream_t);
+template <typename T> hipError_t launch_bin_scatter(const ElemBatch&, int, const Geometry*, size_t, char*,
                                                     size_t, char*, size_t, size_t, const MeshDims&, const BinGeom&,
                                                     int, hipStream_t);
 template <typename T> hipError_t launch_deposit_binned(const Geometry*, size_t, char*, size_t, const char*, size_t,
@@ -53,8 +51,7 @@ template <typename T> hipError_t launch_deposit_binned(const Geometry*, size_t, 
 template <typename T> hipError_t launch_gather_binned(const Geometry*, size_t, char*, size_t, char*, size_t,
                                                       const void*, size_t, const MeshDims&, const BinGeom&, int, int,
                                                       hipStream_t);
-template <typename T> hipError_t launch_unsort(const BatchScalars&, int, const char*, size_t, size_t,
-                                               const PtrBatch&, const PtrBatch&, const PtrBatch&, hipStream_t);
+template <typename T> hipError_t launch_unsort(const ElemBatch&, int, const char*, size_t, size_t, hipStream_t);
 template <typename T> hipError_t launch_twiddle_pass(void*, int, int, hipStream_t);
 template <typename T> hipError_t launch_twiddle_line(void*, int, int, hipStream_t);
 hipError_t launch_igf_octant(double*, const int*, const double*, const GLBands&, hipStream_t);
@@ -356,7 +353,7 @@ struct Slots {
 // rho (in `src`, element stride in_stride) -> phi_ext in R3 (+ user phi) via the five passes.
 template <typename T>
 dks_status convolve(const dks_poisson_plan_s* p, const void* src, size_t in_stride, int batch, const Slots& sl,
-                    const PtrBatch& phi_user, hipStream_t st) {
+                    const ElemBatch& phi_user, hipStream_t st) {
   const MeshDims& m = p->md;
   const size_t cstride = sl.stride / p->csize;
   const size_t rstride = sl.stride / p->rsize;
@@ -400,8 +397,7 @@ struct PartWork {
   int item_blocks;    // blocks of the deposit and gather kernels (loop over work items)
 };
 
-PartWork part_work(const dks_poisson_plan_s* p, const BatchScalars& bs, int batch) {
-  const int64_t maxn = bs.max_np;
+PartWork part_work(const dks_poisson_plan_s* p, int64_t maxn) {
   PartWork w;
   w.bg = p->bg;
   // Work items bound the fixed-point deposit sums: <= 2^16 particles (FP32), 2^14 (FP64).
@@ -416,22 +412,21 @@ PartWork part_work(const dks_poisson_plan_s* p, const BatchScalars& bs, int batc
 // Mesh fit (fitted plans), geometry, particle binning and the binned deposit:
 // leaves the weights W in R3 and the binned particles in `sorted`.
 template <typename T>
-dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl, const PtrBatch& X,
-                         const PtrBatch& Y, const PtrBatch& Z, const BatchScalars& bs, const PtrBatch& cnt,
+dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl, const ElemBatch& eb,
                          char* sorted, size_t sorted_stride, size_t inv_off, const PartWork& w,
                          hipStream_t st) {
   int nb = 0;
   double* bbox = reinterpret_cast<double*>(sl.base + p->s_bbox);
-  if (p->fitted) DKS_TK("bbox", launch_bbox<T>(X, Y, Z, bs, batch, bbox, sl.stride / sizeof(double), &nb, st));
+  if (p->fitted) DKS_TK("bbox", launch_bbox<T>(eb, batch, bbox, sl.stride / sizeof(double), &nb, st));
   GeoArgs ga = geo_args(p, 1, nb);
   ga.zero_off = p->s_bins;
   ga.zero_len = p->bg.K + 1;
-  DKS_TK("geometry", launch_geometry(bbox, sl.stride / sizeof(double), sl.geo(), sl.stride, ga, bs, cnt, batch, st));
+  DKS_TK("geometry", launch_geometry(bbox, sl.stride / sizeof(double), sl.geo(), sl.stride, ga, eb, batch, st));
   DKS_TK("zero_mesh", launch_zero(sl.base + p->s_r3, sl.stride, p->bytes_W, batch, st));
-  DKS_TK("bin_count", launch_bin_count<T>(X, Y, Z, bs, batch, sl.geo(), sl.stride, sl.base, p->s_bins, p->md, w.bg,
+  DKS_TK("bin_count", launch_bin_count<T>(eb, batch, sl.geo(), sl.stride, sl.base, p->s_bins, p->md, w.bg,
                                           w.count_blocks, st));
-  DKS_TK("bin_scan", launch_bin_scan(sl.geo(), sl.stride, sl.base, p->s_bins, w.bg, cnt, batch, st));
-  DKS_TK("bin_scatter", launch_bin_scatter<T>(X, Y, Z, bs, batch, sl.geo(), sl.stride, sl.base, p->s_bins, sorted,
+  DKS_TK("bin_scan", launch_bin_scan(sl.geo(), sl.stride, sl.base, p->s_bins, w.bg, eb, batch, st));
+  DKS_TK("bin_scatter", launch_bin_scatter<T>(eb, batch, sl.geo(), sl.stride, sl.base, p->s_bins, sorted,
                                               sorted_stride, inv_off, p->md, w.bg, w.count_blocks, st));
   DKS_TK("deposit", launch_deposit_binned<T>(sl.geo(), sl.stride, sl.base, p->s_bins, sorted, sorted_stride,
                                              sl.base + p->s_r3, sl.stride / sizeof(T), p->md, w.bg, w.item_blocks,
@@ -440,21 +435,26 @@ dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl
 }
 
 template <typename T>
-dks_status solve_particles_t(const dks_poisson_plan_s* p, int batch, const Slots& sl, const PtrBatch& X,
-                             const PtrBatch& Y, const PtrBatch& Z, const PtrBatch& EX, const PtrBatch& EY,
-                             const PtrBatch& EZ, const PtrBatch& PHI, const BatchScalars& bs,
-                             const PtrBatch& cnt, char* sorted, size_t sorted_stride, hipStream_t st) {
-  const PartWork w = part_work(p, bs, batch);
-  const size_t inv_off = inv_offset(p, bs.max_np);
-  dks_status r = deposit_stage<T>(p, batch, sl, X, Y, Z, bs, cnt, sorted, sorted_stride, inv_off, w, st);
+dks_status solve_particles_t(const dks_poisson_plan_s* p, int batch, const Slots& sl, const ElemBatch& eb,
+                             char* sorted, size_t sorted_stride, hipStream_t st) {
+  const PartWork w = part_work(p, eb.max_np);
+  const size_t inv_off = inv_offset(p, eb.max_np);
+  dks_status r = deposit_stage<T>(p, batch, sl, eb, sorted, sorted_stride, inv_off, w, st);
   if (r != DKS_OK) return r;
-  r = convolve<T>(p, sl.base + p->s_r3, sl.stride / sizeof(T), batch, sl, PHI, st);
+  r = convolve<T>(p, sl.base + p->s_r3, sl.stride / sizeof(T), batch, sl, eb, st);
   if (r != DKS_OK) return r;
   DKS_TK("gather", launch_gather_binned<T>(sl.geo(), sl.stride, sl.base, p->s_bins, sorted, sorted_stride,
                                            sl.base + p->s_r3, sl.stride / sizeof(T), p->md, w.bg, w.item_blocks,
                                            batch, st));
-  DKS_TK("unsort", launch_unsort<T>(bs, batch, sorted, sorted_stride, inv_off, EX, EY, EZ, st));
+  DKS_TK("unsort", launch_unsort<T>(eb, batch, sorted, sorted_stride, inv_off, st));
   return DKS_OK;
+}
+
+// No particles (mesh-only geometry).
+ElemBatch no_elements() {
+  ElemBatch eb;
+  std::memset(&eb, 0, sizeof(eb));
+  return eb;
 }
 
 template <typename T>
@@ -490,23 +490,32 @@ dks_status prepare_t(dks_poisson_plan_s* p, hipStream_t st) {
   const double inv_ntot = 1.0 / ((double)(2 * p->n[0]) * (double)(2 * p->n[1]) * (double)(2 * p->n[2]));
   DKS_CK(launch_green_pack<T>(g2, p->ws + p->off_green, p->n, p->md.cs, inv_ntot, st));
   if (!p->fitted) {
-    BatchScalars bs;
-    std::memset(&bs, 0, sizeof(bs));
-    PtrBatch cnt;
-    std::memset(&cnt, 0, sizeof(cnt));
     const GeoArgs ga = geo_args(p, 0, 0);
-    DKS_CK(launch_geometry(nullptr, 0, reinterpret_cast<Geometry*>(slot), 0, ga, bs, cnt, 1, st));
+    DKS_CK(launch_geometry(nullptr, 0, reinterpret_cast<Geometry*>(slot), 0, ga, no_elements(), 1, st));
   }
   return DKS_OK;
 }
 
 bool ws_ready(const dks_poisson_plan_s* p) { return p->ws != nullptr && p->ws_bytes >= p->ws_total; }
 
-PtrBatch one(const void* v) {
-  PtrBatch b;
-  std::memset(&b, 0, sizeof(b));
-  b.p[0] = const_cast<void*>(v);
-  return b;
+// One element described by value (single solves).
+ElemBatch single(const void* x, const void* y, const void* z, void* ex, void* ey, void* ez, void* phi,
+                 int64_t* n_outside, int64_t np, double q, bool need_e) {
+  ElemBatch eb;
+  std::memset(&eb, 0, sizeof(eb));
+  eb.local.x = x;
+  eb.local.y = y;
+  eb.local.z = z;
+  eb.local.Ex = ex;
+  eb.local.Ey = ey;
+  eb.local.Ez = ez;
+  eb.local.phi = phi;
+  eb.local.n_outside = n_outside;
+  eb.local.np = np;
+  eb.local.q = q;
+  eb.max_np = np;
+  eb.need_e = need_e ? 1 : 0;
+  return eb;
 }
 
 }  // namespace
@@ -633,22 +642,19 @@ dks_status dks_poisson_solve_rho(dks_poisson_plan_t p, const void* rho, void* ph
   if (!p->prepared) return DKS_ESTATE;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   Slots sl{p->ws + p->off_slot, p->slot_bytes};
-  BatchScalars bs;
-  std::memset(&bs, 0, sizeof(bs));
-  PtrBatch none;
-  std::memset(&none, 0, sizeof(none));
   const GeoArgs ga = geo_args(p, 0, 0);
-  if (launch_geometry(nullptr, 0, sl.geo(), sl.stride, ga, bs, none, 1, st) != hipSuccess) return DKS_EHIP;
+  if (launch_geometry(nullptr, 0, sl.geo(), sl.stride, ga, no_elements(), 1, st) != hipSuccess) return DKS_EHIP;
+  const ElemBatch out = single(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, phi, nullptr, 0, 0.0, false);
   dks_status r;
   if (p->dtype == DKS_F32) {
-    r = convolve<float>(p, rho, 0, 1, sl, one(phi), st);
+    r = convolve<float>(p, rho, 0, 1, sl, out, st);
     if (r == DKS_OK && E_mesh) {
       Timed tm("gradient", st);
       r = hip_status(launch_gradient<float>(sl.base + p->s_r3, E_mesh, sl.geo(), p->md, st));
       tm.done();
     }
   } else {
-    r = convolve<double>(p, rho, 0, 1, sl, one(phi), st);
+    r = convolve<double>(p, rho, 0, 1, sl, out, st);
     if (r == DKS_OK && E_mesh) {
       Timed tm("gradient", st);
       r = hip_status(launch_gradient<double>(sl.base + p->s_r3, E_mesh, sl.geo(), p->md, st));
@@ -669,28 +675,17 @@ dks_status dks_poisson_solve_particles(dks_poisson_plan_t p, const void* x, cons
   if (!p->prepared) return DKS_ESTATE;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   Slots sl{p->ws + p->off_slot, p->slot_bytes};
-  BatchScalars bs;
-  std::memset(&bs, 0, sizeof(bs));
-  bs.np[0] = np;
-  bs.q[0] = q;
-  bs.max_np = np;
-  const dks_status r =
-      p->dtype == DKS_F32
-          ? solve_particles_t<float>(p, 1, sl, one(x), one(y), one(z), one(Ex), one(Ey), one(Ez), one(phi), bs,
-                                     one(n_outside), p->pscratch, 0, st)
-          : solve_particles_t<double>(p, 1, sl, one(x), one(y), one(z), one(Ex), one(Ey), one(Ez), one(phi), bs,
-                                      one(n_outside), p->pscratch, 0, st);
+  const ElemBatch eb = single(x, y, z, Ex, Ey, Ez, phi, n_outside, np, q, true);
+  const dks_status r = p->dtype == DKS_F32 ? solve_particles_t<float>(p, 1, sl, eb, p->pscratch, 0, st)
+                                           : solve_particles_t<double>(p, 1, sl, eb, p->pscratch, 0, st);
   if (r == DKS_OK) p->has_geometry = true;
   return r;
 }
 
-dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, const void* const* x,
-                                               const void* const* y, const void* const* z, const int64_t* np,
-                                               const double* q, int64_t max_np, void* const* Ex, void* const* Ey,
-                                               void* const* Ez, void* const* phi, void* scratch,
-                                               size_t scratch_bytes, int64_t* n_outside, dks_stream_t stream) {
-  if (!p || batch < 1 || batch > kMaxBatch || !x || !y || !z || !np || !q || !Ex || !Ey || !Ez)
-    return DKS_EINVAL;
+dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, const dks_particle_set* sets,
+                                               int64_t max_np, void* scratch, size_t scratch_bytes,
+                                               dks_stream_t stream) {
+  if (!p || batch < 1 || batch > kMaxBatch || !sets) return DKS_EINVAL;
   if (max_np < 0 || max_np > (int64_t)UINT32_MAX) return DKS_EINVAL;
   if (!ws_ready(p)) return DKS_EWORKSPACE;
   if (!p->prepared) return DKS_ESTATE;
@@ -698,31 +693,16 @@ dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, 
   // Element b owns [b * stride, (b + 1) * stride): its slot, then its binned particles.
   const size_t stride = (scratch_bytes / (size_t)batch) & ~(size_t)255;
   if (stride < p->slot_bytes + particle_bytes(p, max_np)) return DKS_EWORKSPACE;
-  PtrBatch X, Y, Z, EX, EY, EZ, PHI, CNT;
-  BatchScalars bs;
-  std::memset(&X, 0, sizeof(X)); std::memset(&Y, 0, sizeof(Y)); std::memset(&Z, 0, sizeof(Z));
-  std::memset(&EX, 0, sizeof(EX)); std::memset(&EY, 0, sizeof(EY)); std::memset(&EZ, 0, sizeof(EZ));
-  std::memset(&PHI, 0, sizeof(PHI)); std::memset(&CNT, 0, sizeof(CNT)); std::memset(&bs, 0, sizeof(bs));
-  for (int b = 0; b < batch; ++b) {
-    if (max_np > 0 && (!x[b] || !y[b] || !z[b] || !Ex[b] || !Ey[b] || !Ez[b])) return DKS_EINVAL;
-    X.p[b] = const_cast<void*>(x[b]);
-    Y.p[b] = const_cast<void*>(y[b]);
-    Z.p[b] = const_cast<void*>(z[b]);
-    EX.p[b] = Ex[b];
-    EY.p[b] = Ey[b];
-    EZ.p[b] = Ez[b];
-    PHI.p[b] = phi ? phi[b] : nullptr;
-    CNT.p[b] = n_outside ? n_outside + b : nullptr;
-  }
-  bs.np_dev = np;
-  bs.q_dev = q;
-  bs.max_np = max_np;
+  ElemBatch eb;
+  std::memset(&eb, 0, sizeof(eb));
+  eb.dev = sets;
+  eb.max_np = max_np;
+  eb.need_e = 1;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   Slots sl{static_cast<char*>(scratch), stride};
   char* sorted = static_cast<char*>(scratch) + p->slot_bytes;
-  return p->dtype == DKS_F32
-             ? solve_particles_t<float>(p, batch, sl, X, Y, Z, EX, EY, EZ, PHI, bs, CNT, sorted, stride, st)
-             : solve_particles_t<double>(p, batch, sl, X, Y, Z, EX, EY, EZ, PHI, bs, CNT, sorted, stride, st);
+  return p->dtype == DKS_F32 ? solve_particles_t<float>(p, batch, sl, eb, sorted, stride, st)
+                             : solve_particles_t<double>(p, batch, sl, eb, sorted, stride, st);
 }
 
 dks_status dks_poisson_deposit(dks_poisson_plan_t p, const void* x, const void* y, const void* z, int64_t np,
@@ -734,21 +714,15 @@ dks_status dks_poisson_deposit(dks_poisson_plan_t p, const void* x, const void* 
   if (!p->prepared) return DKS_ESTATE;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   Slots sl{p->ws + p->off_slot, p->slot_bytes};
-  BatchScalars bs;
-  std::memset(&bs, 0, sizeof(bs));
-  bs.np[0] = np;
-  bs.q[0] = q;
-  bs.max_np = np;
-  const PartWork w = part_work(p, bs, 1);
+  const ElemBatch eb = single(x, y, z, nullptr, nullptr, nullptr, nullptr, n_outside, np, q, false);
+  const PartWork w = part_work(p, np);
   const size_t nmesh = (size_t)p->n[0] * p->n[1] * p->n[2];
   dks_status r;
   if (p->dtype == DKS_F32) {
-    r = deposit_stage<float>(p, 1, sl, one(x), one(y), one(z), bs, one(n_outside), p->pscratch, 0,
-                             inv_offset(p, np), w, st);
+    r = deposit_stage<float>(p, 1, sl, eb, p->pscratch, 0, inv_offset(p, np), w, st);
     if (r == DKS_OK) r = hip_status(launch_weights_to_density<float>(sl.base + p->s_r3, rho, nmesh, sl.geo(), q, st));
   } else {
-    r = deposit_stage<double>(p, 1, sl, one(x), one(y), one(z), bs, one(n_outside), p->pscratch, 0,
-                              inv_offset(p, np), w, st);
+    r = deposit_stage<double>(p, 1, sl, eb, p->pscratch, 0, inv_offset(p, np), w, st);
     if (r == DKS_OK) r = hip_status(launch_weights_to_density<double>(sl.base + p->s_r3, rho, nmesh, sl.geo(), q, st));
   }
   if (r == DKS_OK) p->has_geometry = true;
@@ -764,12 +738,8 @@ dks_status dks_poisson_gather(dks_poisson_plan_t p, const void* E_mesh, const vo
   const hipStream_t st = static_cast<hipStream_t>(stream);
   Slots sl{p->ws + p->off_slot, p->slot_bytes};
   if (!p->fitted) {
-    BatchScalars bs;
-    std::memset(&bs, 0, sizeof(bs));
-    PtrBatch none;
-    std::memset(&none, 0, sizeof(none));
     const GeoArgs ga = geo_args(p, 0, 0);
-    if (launch_geometry(nullptr, 0, sl.geo(), sl.stride, ga, bs, none, 1, st) != hipSuccess) return DKS_EHIP;
+    if (launch_geometry(nullptr, 0, sl.geo(), sl.stride, ga, no_elements(), 1, st) != hipSuccess) return DKS_EHIP;
   } else if (!p->has_geometry) {
     return DKS_ESTATE;
   }

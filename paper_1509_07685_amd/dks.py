@@ -64,8 +64,7 @@ _SIGS = {
     "dks_poisson_prepare": (_i, [_PLAN, _vp]),
     "dks_poisson_solve_rho": (_i, [_PLAN, _vp, _vp, _vp, _vp]),
     "dks_poisson_solve_particles": (_i, [_PLAN, _vp, _vp, _vp, _i64, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
-    "dks_poisson_solve_particles_batched": (_i, [_PLAN, _i, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp,
-                                                 _vp, _vp, _sz, _vp, _vp]),
+    "dks_poisson_solve_particles_batched": (_i, [_PLAN, _i, _vp, _i64, _vp, _sz, _vp]),
     "dks_poisson_deposit": (_i, [_PLAN, _vp, _vp, _vp, _i64, _d, _vp, _vp, _vp]),
     "dks_poisson_gather": (_i, [_PLAN, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
     "dks_poisson_geometry": (_i, [_PLAN, _vp, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
@@ -146,21 +145,30 @@ def dks_poisson_solve_particles(plan, x, y, z, np_, q, Ex, Ey, Ez, phi, n_outsid
            "dks_poisson_solve_particles")
 
 
-def _ptr_array(ptrs):
-    arr = (_vp * len(ptrs))(*[p or None for p in ptrs])
-    return arr
+class dks_particle_set(ctypes.Structure):
+    """One element of a batched solve (device addresses, count, charge)."""
+    _fields_ = [("x", _vp), ("y", _vp), ("z", _vp), ("Ex", _vp), ("Ey", _vp), ("Ez", _vp), ("phi", _vp),
+                ("n_outside", _vp), ("np", _i64), ("q", _d)]
 
 
-def dks_poisson_solve_particles_batched(plan, batch, x, y, z, np_dev, q_dev, max_np, Ex, Ey, Ez, phi,
-                                        scratch, scratch_bytes, n_outside, stream):
-    """x..Ez, phi: sequences of device addresses (ints); np_dev, q_dev: device pointers."""
-    arrs = [_ptr_array(a) for a in (x, y, z, Ex, Ey, Ez)]
-    phi_arr = _ptr_array(phi) if phi is not None else None
-    st = _lib.dks_poisson_solve_particles_batched(
-        plan, batch, *[ctypes.cast(a, _vp) for a in arrs[:3]], np_dev, q_dev, max_np,
-        *[ctypes.cast(a, _vp) for a in arrs[3:]],
-        ctypes.cast(phi_arr, _vp) if phi_arr is not None else None, scratch, scratch_bytes, n_outside,
-        stream)
+PARTICLE_SET_BYTES = ctypes.sizeof(dks_particle_set)
+
+
+def particle_set_table(entries):
+    """Bytes of a dks_particle_set array.  entries: sequence of dicts with keys
+    x, y, z, Ex, Ey, Ez (device addresses), optional phi, n_outside, and np, q."""
+    arr = (dks_particle_set * len(entries))()
+    for a, e in zip(arr, entries):
+        for k in ("x", "y", "z", "Ex", "Ey", "Ez", "phi", "n_outside"):
+            setattr(a, k, e.get(k) or None)
+        a.np = int(e["np"])
+        a.q = float(e["q"])
+    return bytes(arr)
+
+
+def dks_poisson_solve_particles_batched(plan, batch, sets, max_np, scratch, scratch_bytes, stream):
+    """sets: device address of `batch` dks_particle_set records."""
+    st = _lib.dks_poisson_solve_particles_batched(plan, batch, sets, max_np, scratch, scratch_bytes, stream)
     _check(st, "dks_poisson_solve_particles_batched")
 
 
@@ -322,19 +330,16 @@ class PoissonPlan:
         nbytes = dks_poisson_batch_scratch_bytes(self.handle, batch, max_np)
         return torch.empty(nbytes, dtype=torch.uint8, device=self.device), nbytes
 
-    def solve_particles_batched(self, xs, ys, zs, np_dev, q_dev, max_np, outs, scratch, n_outside=None,
-                                phis=None, stream=None):
-        """One batched launch; xs..zs and outs[b] = (Ex, Ey, Ez) are device tensors
-        (fixed addresses if the call is captured), np_dev / q_dev device tensors
-        (int64 / float64) holding each element's count and per-particle charge."""
-        batch = len(xs)
+    def solve_particles_batched(self, table, batch, max_np, scratch, stream=None):
+        """One batched launch.  table: device uint8 tensor holding `batch`
+        dks_particle_set records (see particle_set_table); the library reads it
+        on the device when the kernels run, so a captured launch picks up
+        whatever the table holds at replay."""
         buf, nbytes = scratch
-        dks_poisson_solve_particles_batched(
-            self.handle, batch, [t.data_ptr() for t in xs], [t.data_ptr() for t in ys],
-            [t.data_ptr() for t in zs], _ptr(np_dev), _ptr(q_dev), int(max_np),
-            [o[0].data_ptr() for o in outs], [o[1].data_ptr() for o in outs], [o[2].data_ptr() for o in outs],
-            None if phis is None else [p.data_ptr() if p is not None else 0 for p in phis],
-            _ptr(buf), nbytes, _ptr(n_outside), _stream_handle(stream))
+        if table.numel() < batch * PARTICLE_SET_BYTES:
+            raise ValueError("particle set table too small for the batch")
+        dks_poisson_solve_particles_batched(self.handle, batch, _ptr(table), int(max_np), _ptr(buf), nbytes,
+                                            _stream_handle(stream))
 
     def close(self):
         if self.handle is not None:

@@ -5,9 +5,10 @@ on a clock.  The scheduler:
 
   * keeps one prepared plan per (shape, dtype) resident: twiddles and the
     FP64-built Green's spectrum are computed once and reused by every request
-    of that shape (a fitted cubic mesh scales the cached spectrum by h^2);
-  * admits work by an HBM byte budget: executors (staging buffers, batch
-    scratch, outputs) are created lazily while the budget allows, idle ones
+    of that shape (each request's fitted cubic mesh rescales the cached
+    unit-spacing spectrum);
+  * admits work by an HBM byte budget: executors (batch scratch, descriptor
+    table, captured graphs) are created lazily while the budget allows, idle ones
     are evicted least-recently-used when another shape needs the room, and a
     request whose executor can never fit is refused;
   * forms batches continuously: whenever a stream and an idle executor are
@@ -16,7 +17,9 @@ on a clock.  The scheduler:
     kernel of the step runs once over the batch;
   * replays a HIP graph captured once per (shape, dtype, batch size) for that
     launch, on one of several streams, so batches of different shapes overlap
-    on the device;
+    on the device; the graph reads a device table of per-request descriptors,
+    so a launch costs one small table copy and the replay, with no staging of
+    particle data;
   * records latency = completion observed - scheduled arrival, and reports
     p50/p99 beside throughput.
 
@@ -146,9 +149,35 @@ class Scheduler:
     def _fits_ever(self, key):
         return self.be.plan_bytes(key) + self.be.executor_bytes(key) <= self.budget
 
+    def _accepts(self, job):
+        acc = getattr(self.be, "accepts", None)
+        return acc(job) if acc else True
+
+    def prewarm(self, key, count):
+        """Create up to `count` idle executors of `key` now (within the budget,
+        without evicting), so a later run does not pay for their creation."""
+        made = 0
+        while len(self.idle[key]) < count:
+            if key not in self.plans:
+                need = self.be.plan_bytes(key)
+                if not self._reserve(need):
+                    break
+                self.plans[key] = need
+            if not self._reserve(self.be.executor_bytes(key)):
+                break
+            ex = self.be.create_executor(key)
+            self.created += 1
+            self.idle[key].append(ex)
+            self.lru[id(ex)] = (key, ex)
+            made += 1
+        return made
+
     # -- main loop ----------------------------------------------------------
     def run(self, jobs):
         """Serve `jobs` (sorted by arrival) to completion; returns Stats."""
+        self.created = 0
+        self.evictions = 0
+        self.peak = self.used
         pending = collections.deque(sorted(jobs, key=lambda j: j.arrival_s))
         queues = collections.defaultdict(collections.deque)   # key -> waiting jobs
         free_streams = list(range(self.be.num_streams))
@@ -158,7 +187,7 @@ class Scheduler:
             now = self.clock() - t0
             while pending and pending[0].arrival_s <= now:
                 j = pending.popleft()
-                if not self._fits_ever(j.key):
+                if not self._fits_ever(j.key) or not self._accepts(j):
                     j.status = "refused"
                     finished.append(j)
                     continue
@@ -221,54 +250,72 @@ class Scheduler:
 # --------------------------------------------------------------------------
 
 class Executor:
-    """Fixed device buffers for up to `max_batch` requests of one (shape, dtype)
-    and the HIP graphs captured over them, one per batch size."""
+    """Device state for batches of up to `max_batch` requests of one (shape,
+    dtype): the batch scratch, a device table of per-element descriptors
+    (dks_particle_set) with its pinned host twin, the out-of-mesh counters,
+    and one HIP graph per batch size captured over the table.  A launch
+    rewrites the table (one small host-to-device copy) and replays the graph:
+    the kernels read the requests' own device buffers, so nothing is staged."""
 
     def __init__(self, backend, key):
         torch = backend.torch
+        dks = backend.dks
         self.key = key
-        shape, dt = key
         self.plan = backend.plan(key)
-        self.tdtype = torch.float32 if dt == "f32" else torch.float64
         B, M = backend.max_batch, backend.max_np
         dev = backend.device
-        self.x = [torch.zeros(M, dtype=self.tdtype, device=dev) for _ in range(B)]
-        self.y = [torch.zeros(M, dtype=self.tdtype, device=dev) for _ in range(B)]
-        self.z = [torch.zeros(M, dtype=self.tdtype, device=dev) for _ in range(B)]
-        self.out = [tuple(torch.zeros(M, dtype=self.tdtype, device=dev) for _ in range(3)) for _ in range(B)]
-        self.np_dev = torch.zeros(B, dtype=torch.int64, device=dev)
-        self.q_dev = torch.zeros(B, dtype=torch.float64, device=dev)
-        self.np_host = torch.zeros(B, dtype=torch.int64).pin_memory()
-        self.q_host = torch.zeros(B, dtype=torch.float64).pin_memory()
+        self.max_batch = B
+        self.max_np = M
+        nbytes = B * dks.PARTICLE_SET_BYTES
+        self.table_host = torch.zeros(nbytes, dtype=torch.uint8).pin_memory()
+        self.table_dev = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
         self.cnt = torch.zeros(B, dtype=torch.int64, device=dev)
         self.scratch = self.plan.batch_scratch(B, M)
         self.graphs = {}
         self.use_graphs = backend.use_graphs
-        self.max_np = M
+        self._dks = dks
+        # the plan was prepared on torch's current stream; launches come on others
+        torch.cuda.synchronize()
+        if self.use_graphs:
+            cap = torch.cuda.Stream()
+            for b in range(1, B + 1):
+                with torch.cuda.stream(cap):
+                    self._solve(b)             # eager warm-up: an all-empty table
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=cap):
+                    self._solve(b)
+                self.graphs[b] = g
+            torch.cuda.synchronize()
 
     def _solve(self, b):
-        self.plan.solve_particles_batched(self.x[:b], self.y[:b], self.z[:b], self.np_dev, self.q_dev,
-                                          self.max_np, self.out[:b], self.scratch, n_outside=self.cnt)
+        self.plan.solve_particles_batched(self.table_dev, b, self.max_np, self.scratch)
 
-    def run(self, b, stream, torch):
-        """Solve the first b staged elements on `stream` (graph replay when enabled)."""
-        if not self.use_graphs:
-            with torch.cuda.stream(stream):
-                self._solve(b)
-            return
-        g = self.graphs.get(b)
-        if g is None:
-            cap = torch.cuda.Stream()
-            cap.wait_stream(stream)
-            with torch.cuda.stream(cap):
-                self._solve(b)                     # eager warm-up on the capture stream
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=cap):
-                self._solve(b)
-            stream.wait_stream(cap)
-            self.graphs[b] = g
+    def fill(self, jobs):
+        """Write the descriptors of `jobs` into the pinned host table."""
+        import ctypes
+        base = self.cnt.data_ptr()
+        entries = []
+        for i, j in enumerate(jobs):
+            x, y, z, outs = j.payload
+            entries.append({"x": x.data_ptr(), "y": y.data_ptr(), "z": z.data_ptr(),
+                            "Ex": outs[0].data_ptr(), "Ey": outs[1].data_ptr(), "Ez": outs[2].data_ptr(),
+                            "n_outside": base + 8 * i, "np": j.num_particles, "q": j.charge})
+        raw = self._dks.particle_set_table(entries)
+        ctypes.memmove(self.table_host.data_ptr(), raw, len(raw))
+        return len(raw)
+
+    def run(self, jobs, stream, torch):
+        """Solve `jobs` as one batch on `stream` (graph replay when enabled).
+        The executor is not reused before this launch completes, so the
+        pinned table is free to rewrite by then."""
+        b = len(jobs)
+        nbytes = self.fill(jobs)
         with torch.cuda.stream(stream):
-            g.replay()
+            self.table_dev[:nbytes].copy_(self.table_host[:nbytes], non_blocking=True)
+            if self.use_graphs:
+                self.graphs[b].replay()
+            else:
+                self.plan.solve_particles_batched(self.table_dev, b, self.max_np, self.scratch, stream=stream)
 
 
 class GpuBackend:
@@ -302,12 +349,11 @@ class GpuBackend:
             d = self.dks
             h = d.dks_poisson_plan(*shape, 0.0, 0.0, 0.0, d.DKS_F32 if dt == "f32" else d.DKS_F64)
             try:
-                ws = d.dks_poisson_workspace_bytes(h) + d.dks_poisson_particle_scratch_bytes(h, self.max_np)
+                ws = d.dks_poisson_workspace_bytes(h)
                 scratch = d.dks_poisson_batch_scratch_bytes(h, self.max_batch, self.max_np)
             finally:
                 d.dks_poisson_destroy(h)
-            s = 4 if dt == "f32" else 8
-            self._sizes[key] = (ws, scratch + self.max_batch * self.max_np * s * 6 + 64 * self.max_batch)
+            self._sizes[key] = (ws, scratch + self.max_batch * (d.PARTICLE_SET_BYTES + 8))
         return self._sizes[key]
 
     def plan_bytes(self, key):
@@ -315,6 +361,9 @@ class GpuBackend:
 
     def executor_bytes(self, key):
         return self._size(key)[1]
+
+    def accepts(self, job):
+        return 0 <= job.num_particles <= self.max_np
 
     # lifecycle --------------------------------------------------------------
     def create_executor(self, key):
@@ -327,28 +376,9 @@ class GpuBackend:
     def launch(self, ex, jobs, stream_id):
         torch = self.torch
         s = self.streams[stream_id]
-        b = len(jobs)
-        for i, j in enumerate(jobs):
-            x, y, z, outs = j.payload
-            n = j.num_particles
-            ex.np_host[i] = n
-            ex.q_host[i] = j.charge
-            with torch.cuda.stream(s):
-                ex.x[i][:n].copy_(x, non_blocking=True)
-                ex.y[i][:n].copy_(y, non_blocking=True)
-                ex.z[i][:n].copy_(z, non_blocking=True)
-        with torch.cuda.stream(s):
-            ex.np_dev[:b].copy_(ex.np_host[:b], non_blocking=True)
-            ex.q_dev[:b].copy_(ex.q_host[:b], non_blocking=True)
-        ex.run(b, s, torch)
-        with torch.cuda.stream(s):
-            for i, j in enumerate(jobs):
-                n = j.num_particles
-                outs = j.payload[3]
-                for d in range(3):
-                    outs[d].copy_(ex.out[i][d][:n], non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(s)
+        ex.run(jobs, s, torch)
+        ev = torch.cuda.Event()
+        ev.record(s)
         token = self._next
         self._next += 1
         self._tokens[token] = ev
@@ -412,14 +442,20 @@ def bench_stream(torch, num_requests=2000, rate_hz=500.0, seed=5, budget_bytes=6
     from paper_1509_07685_amd import workloads as wl
     reqs = wl.serving_stream(num_requests, rate_hz, seed)
     backend = GpuBackend(torch)
-    # warm every plan and executor graph shape once, off the clock
+    sched = Scheduler(backend, budget_bytes)
+    # off the clock: resident plans and executors (graphs captured) for every
+    # (shape, dtype) of the stream, then one short warm-up pass
+    keys = sorted({(tuple(r.n), r.dtype) for r in reqs})
+    for per in (1, 2):
+        for k in keys:
+            sched.prewarm(k, per)
     warm = make_jobs(torch, [dataclasses.replace(r, arrival_s=0.0, num_particles=1000)
                              for r in reqs[:60]])
-    Scheduler(backend, budget_bytes).run(warm)
+    sched.run(warm)
     torch.cuda.synchronize()
     jobs = make_jobs(torch, reqs)
     torch.cuda.synchronize()
-    stats = Scheduler(backend, budget_bytes).run(jobs)
+    stats = sched.run(jobs)
     torch.cuda.synchronize()
     del jobs
     torch.cuda.empty_cache()

@@ -1,15 +1,17 @@
-"""Condense rocprofv3 output into the text summaries kept in this folder.
+"""Condense rocprofv3 output (its rocpd SQLite database) into the text
+summaries kept in this folder.
 
-    python profiles/summarize.py stats  <kernel_stats.csv>  "<command that produced it>"
-    python profiles/summarize.py pmc    <counter_collection.csv> <COUNTER> [copy_bytes]
+    python profiles/summarize.py stats <results.db> "<command that produced it>"
+    python profiles/summarize.py pmc   <results.db> <COUNTER> "<command>" [copy_bytes]
 
 `stats` prints per-kernel call count and average/total duration.  `pmc`
-prints the per-kernel average of a byte counter (FETCH_SIZE / WRITE_SIZE are
-reported in KiB per dispatch) and, when the plain copy kernel of copy_bytes
-bytes is in the trace, the factor that maps the counter onto true bytes.
+prints the per-kernel average of a counter per dispatch; for FETCH_SIZE and
+WRITE_SIZE (KiB per dispatch) it also prints the factor that maps the counter
+onto true bytes, taken from the plain device copy of copy_bytes bytes that the
+profiled command ran (the torch elementwise copy kernel).
 """
 
-import csv
+import sqlite3
 import sys
 from collections import defaultdict
 
@@ -18,42 +20,52 @@ def short(name):
     name = name.split("(")[0]
     for pre in ("void ", "dks::"):
         name = name.replace(pre, "")
-    return name[:60]
+    return name[:64]
 
 
-def stats(path, cmd):
-    rows = list(csv.DictReader(open(path)))
-    print(f"# rocprofv3 --kernel-trace --stats\n# command: {cmd}\n")
-    print(f"{'kernel':60s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}")
-    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
-        print(f"{short(r['Name']):60s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
-              f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}")
-
-
-def pmc(path, counter, copy_bytes=None):
+def stats(db, cmd):
+    """Per-kernel durations from the raw dispatch records (end - start, ns)."""
+    c = sqlite3.connect(db)
     acc = defaultdict(list)
-    for r in csv.DictReader(open(path)):
-        if r.get("Counter_Name", counter) != counter:
-            continue
-        acc[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
-    print(f"# rocprofv3 --pmc {counter} (KiB per dispatch, averaged)\n")
+    for name, dur in c.execute("select name, duration from kernels"):
+        acc[short(name)].append(float(dur))
+    total_all = sum(sum(v) for v in acc.values())
+    print("# rocprofv3 --kernel-trace --stats")
+    print(f"# command: {cmd}\n")
+    print(f"{'kernel':64s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}")
+    for k, v in sorted(acc.items(), key=lambda kv: -sum(kv[1])):
+        print(f"{k:64s} {len(v):6d} {sum(v) / len(v) / 1e3:10.2f} {sum(v) / 1e6:10.3f} "
+              f"{100 * sum(v) / total_all:6.2f}")
+
+
+def pmc(db, counter, cmd, copy_bytes=None):
+    c = sqlite3.connect(db)
+    cols = [r[1] for r in c.execute("pragma table_info('counters_collection')")]
+    name_col = "kernel_name" if "kernel_name" in cols else "name"
+    q = (f"select {name_col}, counter_name, value from counters_collection where counter_name = ?")
+    acc = defaultdict(list)
+    for name, _, value in c.execute(q, (counter,)):
+        acc[short(name)].append(float(value))
+    print(f"# rocprofv3 --pmc {counter} (value per dispatch, averaged over dispatches)")
+    print(f"# command: {cmd}\n")
     factor = None
     if copy_bytes:
         for k, v in acc.items():
-            if "copy" in k.lower() or "elementwise" in k.lower():
+            if "elementwise" in k.lower() or "copy" in k.lower():
                 kib = sum(v) / len(v)
                 if kib > 0.5 * copy_bytes / 1024:
                     factor = (copy_bytes / 1024) / kib
-                    print(f"# copy calibration: {k}: {kib:.0f} KiB for {copy_bytes / 1024:.0f} KiB -> factor {factor:.4f}\n")
+                    print(f"# copy calibration: {k}: {kib:.0f} KiB counted for {copy_bytes / 1024:.0f} KiB "
+                          f"moved -> factor {factor:.4f}\n")
                     break
     for k, v in sorted(acc.items(), key=lambda kv: -sum(kv[1]) / len(kv[1])):
-        kib = sum(v) / len(v)
-        scaled = f"{kib * factor / 1024:12.1f} MiB" if factor else ""
-        print(f"{k:60s} {len(v):5d} {kib:14.0f} KiB {scaled}")
+        avg = sum(v) / len(v)
+        scaled = f"{avg * factor / 1024:12.1f} MiB (scaled)" if factor else ""
+        print(f"{k:64s} {len(v):5d} {avg:14.0f} {scaled}")
 
 
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3])
     else:
-        pmc(sys.argv[2], sys.argv[3], float(sys.argv[4]) if len(sys.argv) > 4 else None)
+        pmc(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]) if len(sys.argv) > 5 else None)

@@ -85,10 +85,20 @@ def test_workspace_and_state_checks(dks):
         assert dks.dks_poisson_particle_scratch_bytes(plan, 1000) == 16128 + 4096
         assert dks.dks_poisson_particle_scratch_bytes(plan, 0) == 0
         sz = ctypes.byref(ctypes.c_size_t())
+        fake_s = ctypes.c_void_p(0x300000)
         assert lib.dks_poisson_batch_scratch_bytes(plan, 0, 10, sz) == dks.DKS_EINVAL
         assert lib.dks_poisson_batch_scratch_bytes(plan, 17, 10, sz) == dks.DKS_EINVAL
         assert lib.dks_poisson_batch_scratch_bytes(plan, 2, -1, sz) == dks.DKS_EINVAL
         assert lib.dks_poisson_particle_scratch_bytes(plan, 2 ** 32, sz) == dks.DKS_EINVAL
+        # batched: table and batch checked before anything else
+        assert dks.PARTICLE_SET_BYTES == 80
+        tab = ctypes.c_void_p(0x200000)
+        assert lib.dks_poisson_solve_particles_batched(plan, 2, None, 10, fake_s, 1 << 20, None) == dks.DKS_EINVAL
+        assert lib.dks_poisson_solve_particles_batched(plan, 0, tab, 10, fake_s, 1 << 20, None) == dks.DKS_EINVAL
+        assert lib.dks_poisson_solve_particles_batched(plan, 17, tab, 10, fake_s, 1 << 20, None) == dks.DKS_EINVAL
+        assert lib.dks_poisson_solve_particles_batched(plan, 2, tab, -1, fake_s, 1 << 20, None) == dks.DKS_EINVAL
+        assert lib.dks_poisson_solve_particles_batched(plan, 2, tab, 10, fake_s, 1 << 20,
+                                                       None) == dks.DKS_EWORKSPACE
         # no workspace yet
         fake = ctypes.c_void_p(0x100000)
         assert lib.dks_poisson_solve_rho(plan, fake, fake, None, None) == dks.DKS_EWORKSPACE

@@ -360,11 +360,14 @@ def test_batched_solve_matches_single_solves(dt):
         pad = lambda a: np.concatenate([a, np.full(max_np - c, 7.0, dtype=a.dtype)])   # beyond np: ignored
         xs.append(dev(pad(x), dt)); ys.append(dev(pad(y), dt)); zs.append(dev(pad(z), dt))
         outs.append(tuple(torch.full((max_np,), -1.0, dtype=tdt(dt), device="cuda") for _ in range(3)))
-    np_dev = torch.tensor(counts, dtype=torch.int64, device="cuda")
-    q_dev = torch.tensor(charges, dtype=torch.float64, device="cuda")
     cnt = torch.zeros(len(counts), dtype=torch.int64, device="cuda")
+    table = d.particle_set_table([
+        {"x": xs[b].data_ptr(), "y": ys[b].data_ptr(), "z": zs[b].data_ptr(), "Ex": outs[b][0].data_ptr(),
+         "Ey": outs[b][1].data_ptr(), "Ez": outs[b][2].data_ptr(), "n_outside": cnt.data_ptr() + 8 * b,
+         "np": counts[b], "q": charges[b]} for b in range(len(counts))])
+    table_dev = torch.frombuffer(bytearray(table), dtype=torch.uint8).cuda()
     scratch = plan.batch_scratch(len(counts), max_np)
-    plan.solve_particles_batched(xs, ys, zs, np_dev, q_dev, max_np, outs, scratch, n_outside=cnt)
+    plan.solve_particles_batched(table_dev, len(counts), max_np, scratch)
     cnts = host(cnt)
     for b, ((x, y, z), c, q) in enumerate(zip(parts, counts, charges)):
         got = np.stack([host(t)[:c] for t in outs[b]])
@@ -379,3 +382,33 @@ def test_batched_solve_matches_single_solves(dt):
             assert rel_l2(got, ref["E"]) <= TOL[dt]
         elif c == 1:
             assert np.allclose(got, alone, rtol=0, atol=1e-6 * (np.abs(alone).max() + 1e-30))
+
+
+def test_batched_table_edge_elements():
+    """Descriptor edge cases: an element with a NULL field pointer is empty and
+    untouched; np above max_np is clamped to max_np; a negative np is empty."""
+    d = dks()
+    dt = "f32"
+    n = (16, 16, 16)
+    plan = d.PoissonPlan(n, None, dt)
+    max_np = 3000
+    x, y, z = wl.gaussian_bunch(5000, (1e-3, 1e-3, 1e-3), 71, np.float32)
+    X, Y, Z = dev(x, dt), dev(y, dt), dev(z, dt)
+    outs = [tuple(torch.full((5000,), -1.0, dtype=torch.float32, device="cuda") for _ in range(3))
+            for _ in range(3)]
+    cnt = torch.full((3,), -5, dtype=torch.int64, device="cuda")
+    q = 1e-13
+    ent = lambda b, npart, ez=True: {
+        "x": X.data_ptr(), "y": Y.data_ptr(), "z": Z.data_ptr(), "Ex": outs[b][0].data_ptr(),
+        "Ey": outs[b][1].data_ptr(), "Ez": outs[b][2].data_ptr() if ez else 0,
+        "n_outside": cnt.data_ptr() + 8 * b, "np": npart, "q": q}
+    table = d.particle_set_table([ent(0, 5000), ent(1, 100, ez=False), ent(2, -7)])
+    table_dev = torch.frombuffer(bytearray(table), dtype=torch.uint8).cuda()
+    plan.solve_particles_batched(table_dev, 3, max_np, plan.batch_scratch(3, max_np))
+    got = np.stack([host(t) for t in outs[0]])
+    assert np.all(got[:, max_np:] == -1.0)
+    ref = orc.solve_particles(x[:max_np], y[:max_np], z[:max_np], q, n, dtype=np.float32)
+    assert rel_l2(got[:, :max_np], ref["E"]) <= TOL[dt]
+    for b in (1, 2):
+        assert all(np.all(host(t) == -1.0) for t in outs[b])
+    assert [int(v) for v in host(cnt)] == [0, 0, 0]

@@ -144,3 +144,23 @@ def test_waits_for_memory_instead_of_failing():
 def test_percentile():
     assert serve.percentile([1, 2, 3, 4], 0.5) == 2.5
     assert serve.percentile(list(range(101)), 0.99) == pytest.approx(99.0)
+
+
+def test_prewarm_creates_idle_executors_within_budget():
+    clock = FakeClock()
+    be = FakeBackend(clock, exec_bytes={A: 300 << 20})
+    sched = serve.Scheduler(be, budget_bytes=(1 << 20) + (700 << 20), clock=clock)
+    assert sched.prewarm(A, 4) == 2                  # room for two executors after the plan
+    assert be.created == [A, A] and sched.used <= sched.budget
+    stats = sched.run(jobs_from([(0.0, A), (0.0, A)]))
+    assert stats.completed == 2 and stats.executors_created == 0   # the run reused them
+
+
+def test_backend_can_refuse_a_request():
+    clock = FakeClock()
+    be = FakeBackend(clock)
+    be.accepts = lambda job: job.num_particles <= 500
+    jobs = jobs_from([(0.0, A), (0.0, A)])
+    jobs[1].num_particles = 400
+    stats = serve.Scheduler(be, budget_bytes=1 << 40, clock=clock).run(jobs)
+    assert stats.refused == 1 and stats.completed == 1 and jobs[0].status == "refused"

@@ -28,9 +28,10 @@ def test_graph_replay_matches_eager():
     ex = be.create_executor(key)
     eager_be = serve.GpuBackend(torch, max_batch=4, num_streams=1, max_np=20_000, use_graphs=False)
     ex_eager = eager_be.create_executor(key)
-    reqs = [wl.Request(i, 0.0, (32, 32, 32), 5000 + 3000 * i, (1e-3, 1.2e-3, 0.8e-3), "f32", 77 + i)
-            for i in range(3)]
-    for rep in range(3):
+    for rep in range(4):
+        # fresh request buffers every time: the replayed graph follows the table
+        reqs = [wl.Request(i, 0.0, (32, 32, 32), 5000 + 3000 * i + 17 * rep, (1e-3, 1.2e-3, 0.8e-3), "f32",
+                           77 + i + 10 * rep) for i in range(3 - rep % 2)]
         jobs = serve.make_jobs(torch, reqs)
         ref = serve.make_jobs(torch, reqs)
         t = be.launch(ex, jobs, rep % 2)
@@ -45,7 +46,7 @@ def test_graph_replay_matches_eager():
         for j, r in zip(jobs, ref):
             for d in range(3):
                 assert rel_l2(j.payload[3][d], r.payload[3][d]) <= 1e-6
-    assert sorted(ex.graphs) == [3]
+    assert sorted(ex.graphs) == [1, 2, 3, 4]
 
 
 @pytest.mark.parametrize("use_graphs", [True, False])
@@ -69,6 +70,16 @@ def test_each_result_is_the_same_alone_and_in_the_mix(use_graphs):
         torch.cuda.synchronize()
         for got, alone in zip(outs, (Ex, Ey, Ez)):
             assert rel_l2(got, alone) <= TOL[dt]
+
+
+def test_request_above_max_np_is_refused():
+    reqs = wl.serving_stream(4, rate_hz=1e4, seed=4, min_log10=3.0, max_log10=3.2, shapes=((32, 32, 32),))
+    reqs[2] = dataclasses.replace(reqs[2], num_particles=5000)
+    jobs = serve.make_jobs(torch, reqs)
+    be = serve.GpuBackend(torch, max_batch=2, num_streams=1, max_np=4000)
+    stats = serve.Scheduler(be, budget_bytes=8 << 30).run(jobs)
+    assert stats.refused == 1 and stats.completed == 3
+    assert jobs[2].status == "refused"
 
 
 def test_budget_too_small_refuses_everything_cleanly():
