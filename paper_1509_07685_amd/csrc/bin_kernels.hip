@@ -10,10 +10,12 @@
 //            touched tile per workgroup)
 //   scan     tile offsets, reservation cursors and the work-item list
 //            (a work item is up to kItem particles of one tile)
-//   scatter  each workgroup reserves one contiguous range per tile and writes
-//            its particles there as packed (x, y, z, original index); the
-//            inverse permutation (original index -> binned slot) is written
-//            alongside, in original order
+//   scatter  one workgroup per chunk of 8192 (FP32) / 4096 (FP64) consecutive
+//            particles: ranks within tiles from an LDS histogram, one device
+//            atomic per touched tile to reserve the chunk's range, then the
+//            particles are written there as packed (x, y, z, original index)
+//            and the inverse permutation (original index -> binned slot) is
+//            written in original order
 //   deposit  per work item: accumulate the weights of the tile's particles in
 //            an LDS copy of its 17^3 nodes with integer LDS atomics on a fixed-
 //            point scale (exact and order independent; floating-point LDS
@@ -24,10 +26,11 @@
 //            eight nodes of each particle and interpolate it with the
 //            deposit's weights; the field overwrites the particle's binned
 //            record in place
-//   unsort   in original particle order, read each field through the inverse
-//            permutation and write the three field arrays contiguously
-//            (scattered 4-byte writes to the original indices cost ten times
-//            more than one scattered 16-byte read)
+//   unsort   per scatter chunk, read each field through the inverse
+//            permutation and write the three field arrays contiguously; a
+//            chunk's records lie in one short segment per touched tile, so
+//            its scattered 16-byte reads share cache lines (scattered 4-byte
+//            writes to the original indices would cost far more)
 //
 // Particles outside the mesh fall in an extra tile K: they deposit nothing,
 // get E = 0 and their count is the out-of-mesh count.  The cell decision is
@@ -45,6 +48,8 @@ namespace dks {
 constexpr int kTile = 16;          // cells per tile edge
 constexpr int kTileN = kTile + 1;  // deposit accumulator nodes per edge
 constexpr int kApron = kTile + 3;  // staged phi values per edge (nodes -1 .. 17)
+
+constexpr int kUnroll = 4;         // binned records each lane loads before using any (deposit, gather)
 
 template <typename T> struct Packed;
 template <> struct Packed<float> { using type = float4; };
@@ -114,13 +119,6 @@ __device__ __forceinline__ Cell<T> locate(T x, T y, T z, const Geometry* g, cons
   return c;
 }
 
-// Chunk of batch element b handled by count/scatter block `blk` of `nblk`.
-__device__ __forceinline__ void chunk_of(int64_t n, int blk, int nblk, int64_t* start, int64_t* end) {
-  const int64_t ch = (n + nblk - 1) / nblk;
-  *start = min((int64_t)blk * ch, n);
-  *end = min(*start + ch, n);
-}
-
 // ---------------------------------------------------------------------------
 // count
 // ---------------------------------------------------------------------------
@@ -141,11 +139,11 @@ __global__ __launch_bounds__(256) void k_bin_count(ElemBatch eb, const Geometry*
     for (int k = threadIdx.x; k <= bg.K; k += blockDim.x) hist[k] = 0;
     __syncthreads();
   }
-  for (int64_t i = start + threadIdx.x; i < end; i += blockDim.x) {
-    const int key = locate<T>(px[i], py[i], pz[i], g, m, bg).key;
+  for_each_particle<T>(px, py, pz, start, end, [&](T x, T y, T z, int64_t) {
+    const int key = locate<T>(x, y, z, g, m, bg).key;
     if (LDSHIST) atomicAdd(&hist[key], 1u);
     else atomicAdd(&st.count[key], 1u);
-  }
+  });
   if (LDSHIST) {
     __syncthreads();
     for (int k = threadIdx.x; k <= bg.K; k += blockDim.x)
@@ -208,18 +206,47 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const Geometry* geo, size_t s
 }
 
 // ---------------------------------------------------------------------------
-// scatter: reserve one range per tile per block, then write packed particles.
+// scatter: one workgroup per chunk of kScatterThreads * ScatterCfg<T>::per
+// consecutive particles.  The chunk is read once into registers; an LDS
+// histogram gives every particle its rank within its tile and the chunk's
+// count per tile; one device atomic per touched tile reserves the chunk's
+// range there; then the packed particles and the inverse permutation are
+// written.  A chunk therefore occupies one short contiguous segment per
+// touched tile, which is what lets the unsort pass read a chunk's records
+// back with few cache lines.
 // ---------------------------------------------------------------------------
+constexpr int kScatterThreads = 512;
+template <typename T> struct ScatterCfg;
+template <> struct ScatterCfg<float> { static constexpr int per = 16; };   // 8192 particles per chunk
+template <> struct ScatterCfg<double> { static constexpr int per = 8; };   // 4096 particles per chunk
+
+// Particle of slot j (of `per`) of this thread in the chunk starting at c0:
+// vector layout (each lane owns 16-byte runs) or element layout.
+template <typename T>
+__device__ __forceinline__ int64_t chunk_index(bool vec, int64_t c0, int j) {
+  constexpr int NV = Vec16<T>::n;
+  return vec ? c0 + (int64_t)NV * (threadIdx.x + (j / NV) * kScatterThreads) + (j % NV)
+             : c0 + threadIdx.x + (int64_t)j * kScatterThreads;
+}
+
 template <typename T, bool LDSHIST>
-__global__ __launch_bounds__(256) void k_bin_scatter(ElemBatch eb, const Geometry* geo, size_t stride, char* slot_base,
-                                                     size_t bins_off, char* sorted_base, size_t sorted_stride,
-                                                     size_t inv_off, MeshDims m, BinGeom bg) {
+__global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, const Geometry* geo, size_t stride,
+                                                                 char* slot_base, size_t bins_off,
+                                                                 char* sorted_base, size_t sorted_stride,
+                                                                 size_t inv_off, MeshDims m, BinGeom bg) {
   extern __shared__ unsigned lds[];
-  unsigned* lcnt = lds;
-  unsigned* lbase = lds + (bg.K + 1);
+  constexpr int PER = ScatterCfg<T>::per;
+  constexpr int NV = Vec16<T>::n;
+  constexpr int64_t CH = (int64_t)kScatterThreads * PER;
   using P4 = typename Packed<T>::type;
+  using V = typename Vec16<T>::type;
   const int b = blockIdx.y;
   const dks_particle_set e = eb.at(b);
+  const int64_t n = eb.n(e);
+  const int64_t c0 = (int64_t)blockIdx.x * CH;
+  if (c0 >= n) return;                       // whole workgroup: no barrier is skipped by part of it
+  unsigned* lcnt = lds;
+  unsigned* lbase = lds + (bg.K + 1);
   const T* px = (const T*)e.x;
   const T* py = (const T*)e.y;
   const T* pz = (const T*)e.z;
@@ -227,29 +254,72 @@ __global__ __launch_bounds__(256) void k_bin_scatter(ElemBatch eb, const Geometr
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
   P4* out = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
   unsigned* inv = reinterpret_cast<unsigned*>(sorted_base + (size_t)b * sorted_stride + inv_off);
-  int64_t start, end;
-  chunk_of(eb.n(e), blockIdx.x, gridDim.x, &start, &end);
   if (LDSHIST) {
-    for (int k = threadIdx.x; k <= bg.K; k += blockDim.x) lcnt[k] = 0;
+    for (int k = threadIdx.x; k <= bg.K; k += kScatterThreads) lcnt[k] = 0;
+  }
+  const bool vec = aligned16(px + c0, py + c0, pz + c0);
+  T xs[PER], ys[PER], zs[PER];
+  if (vec) {
+#pragma unroll
+    for (int q = 0; q < PER / NV; ++q) {
+      const int64_t i = chunk_index<T>(true, c0, q * NV);
+      if (i + NV <= n) {
+        const V a = *reinterpret_cast<const V*>(px + i);
+        const V bb = *reinterpret_cast<const V*>(py + i);
+        const V c = *reinterpret_cast<const V*>(pz + i);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+          xs[q * NV + k] = reinterpret_cast<const T*>(&a)[k];
+          ys[q * NV + k] = reinterpret_cast<const T*>(&bb)[k];
+          zs[q * NV + k] = reinterpret_cast<const T*>(&c)[k];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+          const bool ok = i + k < n;
+          xs[q * NV + k] = ok ? px[i + k] : (T)0;
+          ys[q * NV + k] = ok ? py[i + k] : (T)0;
+          zs[q * NV + k] = ok ? pz[i + k] : (T)0;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int64_t i = chunk_index<T>(false, c0, j);
+      const bool ok = i < n;
+      xs[j] = ok ? px[i] : (T)0;
+      ys[j] = ok ? py[i] : (T)0;
+      zs[j] = ok ? pz[i] : (T)0;
+    }
+  }
+  int key[PER];
+  unsigned rank[PER];
+  if (LDSHIST) __syncthreads();              // lcnt cleared
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int64_t i = chunk_index<T>(vec, c0, j);
+    key[j] = i < n ? locate<T>(xs[j], ys[j], zs[j], g, m, bg).key : -1;
+    if (LDSHIST) rank[j] = key[j] >= 0 ? atomicAdd(&lcnt[key[j]], 1u) : 0u;
+    else rank[j] = key[j] >= 0 ? atomicAdd(&st.cursor[key[j]], 1u) : 0u;
+  }
+  if (LDSHIST) {
     __syncthreads();
-    for (int64_t i = start + threadIdx.x; i < end; i += blockDim.x)
-      atomicAdd(&lcnt[locate<T>(px[i], py[i], pz[i], g, m, bg).key], 1u);
-    __syncthreads();
-    for (int k = threadIdx.x; k <= bg.K; k += blockDim.x) {
+    for (int k = threadIdx.x; k <= bg.K; k += kScatterThreads) {
       const unsigned c = lcnt[k];
-      lbase[k] = c ? atomicAdd(&st.cursor[k], c) : 0u;
-      lcnt[k] = 0;
+      if (c) lbase[k] = atomicAdd(&st.cursor[k], c);
     }
     __syncthreads();
   }
-  for (int64_t i = start + threadIdx.x; i < end; i += blockDim.x) {
-    const T x = px[i], y = py[i], z = pz[i];
-    const int key = locate<T>(x, y, z, g, m, bg).key;
-    const unsigned dst = LDSHIST ? lbase[key] + atomicAdd(&lcnt[key], 1u) : atomicAdd(&st.cursor[key], 1u);
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    if (key[j] < 0) continue;
+    const int64_t i = chunk_index<T>(vec, c0, j);
+    const unsigned dst = LDSHIST ? lbase[key[j]] + rank[j] : rank[j];
     P4 v;
-    v.x = x;
-    v.y = y;
-    v.z = z;
+    v.x = xs[j];
+    v.y = ys[j];
+    v.z = zs[j];
     if constexpr (sizeof(T) == 4) v.w = __uint_as_float((unsigned)i);
     else v.w = (double)i;
     out[dst] = v;
@@ -297,20 +367,30 @@ __global__ __launch_bounds__(256) void k_deposit_binned(const Geometry* geo, siz
     const int bx = tx * kTile, by = ty * kTile, bz = tz * kTile;
     for (int e = threadIdx.x; e < NN; e += blockDim.x) acc[e] = 0ull;
     __syncthreads();
-    for (unsigned i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-      const P4 p = part[i];
-      const Cell<T> c = locate<T>(p.x, p.y, p.z, g, m, bg);
-      const T gx = (T)1 - c.fx, gy = (T)1 - c.fy, gz = (T)1 - c.fz;
-      unsigned long long* a = acc + ((c.jz - bz) * kTileN + (c.jy - by)) * kTileN + (c.jx - bx);
-      constexpr int SY = kTileN, SZ = kTileN * kTileN;
-      atomicAdd(a, Fixed<T>::to(gz * gy * gx));
-      atomicAdd(a + 1, Fixed<T>::to(gz * gy * c.fx));
-      atomicAdd(a + SY, Fixed<T>::to(gz * c.fy * gx));
-      atomicAdd(a + SY + 1, Fixed<T>::to(gz * c.fy * c.fx));
-      atomicAdd(a + SZ, Fixed<T>::to(c.fz * gy * gx));
-      atomicAdd(a + SZ + 1, Fixed<T>::to(c.fz * gy * c.fx));
-      atomicAdd(a + SZ + SY, Fixed<T>::to(c.fz * c.fy * gx));
-      atomicAdd(a + SZ + SY + 1, Fixed<T>::to(c.fz * c.fy * c.fx));
+    for (unsigned i0 = s0 + threadIdx.x; i0 < s1; i0 += kUnroll * blockDim.x) {
+      P4 pr[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const unsigned i = i0 + u * blockDim.x;
+        if (i < s1) pr[u] = part[i];
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if (i0 + u * blockDim.x >= s1) break;
+        const P4 p = pr[u];
+        const Cell<T> c = locate<T>(p.x, p.y, p.z, g, m, bg);
+        const T gx = (T)1 - c.fx, gy = (T)1 - c.fy, gz = (T)1 - c.fz;
+        unsigned long long* a = acc + ((c.jz - bz) * kTileN + (c.jy - by)) * kTileN + (c.jx - bx);
+        constexpr int SY = kTileN, SZ = kTileN * kTileN;
+        atomicAdd(a, Fixed<T>::to(gz * gy * gx));
+        atomicAdd(a + 1, Fixed<T>::to(gz * gy * c.fx));
+        atomicAdd(a + SY, Fixed<T>::to(gz * c.fy * gx));
+        atomicAdd(a + SY + 1, Fixed<T>::to(gz * c.fy * c.fx));
+        atomicAdd(a + SZ, Fixed<T>::to(c.fz * gy * gx));
+        atomicAdd(a + SZ + 1, Fixed<T>::to(c.fz * gy * c.fx));
+        atomicAdd(a + SZ + SY, Fixed<T>::to(c.fz * c.fy * gx));
+        atomicAdd(a + SZ + SY + 1, Fixed<T>::to(c.fz * c.fy * c.fx));
+      }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < NN; e += blockDim.x) {
@@ -368,58 +448,146 @@ __global__ __launch_bounds__(256) void k_gather_binned(const Geometry* geo, size
       ph[e] = (x < nx2 && y < ny2 && z < nz2) ? phi[((size_t)z * ny2 + y) * nx2 + x] : (T)0;
     }
     __syncthreads();
-    for (unsigned i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-      const P4 p = part[i];
-      const Cell<T> c = locate<T>(p.x, p.y, p.z, g, m, bg);
-      const T wx[2] = {(T)1 - c.fx, c.fx}, wy[2] = {(T)1 - c.fy, c.fy}, wz[2] = {(T)1 - c.fz, c.fz};
-      // staged index of node (jx, jy, jz): (node - tile base) + 1 per axis
-      const T* o = ph + ((c.jz - bz + 1) * A + (c.jy - by + 1)) * A + (c.jx - bx + 1);
-      T ax = 0, ay = 0, az = 0;
+    for (unsigned i0 = s0 + threadIdx.x; i0 < s1; i0 += kUnroll * blockDim.x) {
+      P4 pr[kUnroll];
 #pragma unroll
-      for (int kz = 0; kz < 2; ++kz)
+      for (int u = 0; u < kUnroll; ++u) {
+        const unsigned i = i0 + u * blockDim.x;
+        if (i < s1) pr[u] = part[i];
+      }
 #pragma unroll
-        for (int ky = 0; ky < 2; ++ky)
+      for (int u = 0; u < kUnroll; ++u) {
+        const unsigned i = i0 + u * blockDim.x;
+        if (i >= s1) break;
+        const P4 p = pr[u];
+        const Cell<T> c = locate<T>(p.x, p.y, p.z, g, m, bg);
+        const T wx[2] = {(T)1 - c.fx, c.fx}, wy[2] = {(T)1 - c.fy, c.fy}, wz[2] = {(T)1 - c.fz, c.fz};
+        // staged index of node (jx, jy, jz): (node - tile base) + 1 per axis
+        const T* o = ph + ((c.jz - bz + 1) * A + (c.jy - by + 1)) * A + (c.jx - bx + 1);
+        // The 32 distinct nodes the eight central differences use: four x
+        // values per (y, z) corner row, and the y and z neighbours beyond the
+        // corner cube.
+        T r[2][2][4], ym[2][2], yp[2][2], zm[2][2], zp[2][2];
+#pragma unroll
+        for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+          for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r[kz][ky][k] = o[(kz * A + ky) * A + k - 1];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
           for (int kx = 0; kx < 2; ++kx) {
-            const T* q = o + (kz * A + ky) * A + kx;
-            const T ex = cx * (q[1] - q[-1]);
-            const T ey = cy * (q[A] - q[-A]);
-            const T ez = cz * (q[A * A] - q[-A * A]);
-            const T wgt = wz[kz] * wy[ky] * wx[kx];
-            ax += wgt * ex;
-            ay += wgt * ey;
-            az += wgt * ez;
+            ym[a][kx] = o[(a * A - 1) * A + kx];         // (x + kx, y - 1, z + a)
+            yp[a][kx] = o[(a * A + 2) * A + kx];         // (x + kx, y + 2, z + a)
+            zm[a][kx] = o[(-A + a) * A + kx];            // (x + kx, y + a, z - 1)
+            zp[a][kx] = o[(2 * A + a) * A + kx];         // (x + kx, y + a, z + 2)
           }
-      P4 e = p;
-      e.x = ax;
-      e.y = ay;
-      e.z = az;
-      part[i] = e;
+        T ax = 0, ay = 0, az = 0;
+#pragma unroll
+        for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+          for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 2; ++kx) {
+              const T ex = cx * (r[kz][ky][kx + 2] - r[kz][ky][kx]);
+              const T yhi = ky ? yp[kz][kx] : r[kz][1][kx + 1];
+              const T ylo = ky ? r[kz][0][kx + 1] : ym[kz][kx];
+              const T zhi = kz ? zp[ky][kx] : r[1][ky][kx + 1];
+              const T zlo = kz ? r[0][ky][kx + 1] : zm[ky][kx];
+              const T ey = cy * (yhi - ylo);
+              const T ez = cz * (zhi - zlo);
+              const T wgt = wz[kz] * wy[ky] * wx[kx];
+              ax += wgt * ex;
+              ay += wgt * ey;
+              az += wgt * ez;
+            }
+        P4 e = p;
+        e.x = ax;
+        e.y = ay;
+        e.z = az;
+        part[i] = e;
+      }
     }
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// unsort: E at the particles in their original order.
+// unsort: E at the particles in their original order.  One workgroup per
+// scatter chunk, every load of the chunk issued before any store: the
+// chunk's records sit in one short segment per touched tile, so the
+// scattered record reads share cache lines within the workgroup.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_unsort(ElemBatch eb, const char* sorted_base, size_t sorted_stride,
-                                                size_t inv_off) {
+__global__ __launch_bounds__(kScatterThreads) void k_unsort(ElemBatch eb, const char* sorted_base,
+                                                            size_t sorted_stride, size_t inv_off) {
+  constexpr int PER = ScatterCfg<T>::per;
+  constexpr int NV = Vec16<T>::n;
+  constexpr int64_t CH = (int64_t)kScatterThreads * PER;
   using P4 = typename Packed<T>::type;
+  using V = typename Vec16<T>::type;
   const int b = blockIdx.y;
+  const dks_particle_set s = eb.at(b);
+  const int64_t n = eb.n(s);
+  const int64_t c0 = (int64_t)blockIdx.x * CH;
+  if (c0 >= n) return;
   const P4* part = reinterpret_cast<const P4*>(sorted_base + (size_t)b * sorted_stride);
   const unsigned* inv = reinterpret_cast<const unsigned*>(sorted_base + (size_t)b * sorted_stride + inv_off);
-  const dks_particle_set s = eb.at(b);
   T* qx = (T*)s.Ex;
   T* qy = (T*)s.Ey;
   T* qz = (T*)s.Ez;
-  const int64_t n = eb.n(s);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const P4 e = part[inv[i]];
-    qx[i] = e.x;
-    qy[i] = e.y;
-    qz[i] = e.z;
+  const bool vec = aligned16(qx + c0, qy + c0, qz + c0);
+  unsigned src[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int64_t i = chunk_index<T>(vec, c0, j);
+    src[j] = i < n ? inv[i] : 0u;
+  }
+  T ex[PER], ey[PER], ez[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const P4 r = part[src[j]];
+    ex[j] = r.x;
+    ey[j] = r.y;
+    ez[j] = r.z;
+  }
+  if (vec) {
+#pragma unroll
+    for (int q = 0; q < PER / NV; ++q) {
+      const int64_t i = chunk_index<T>(true, c0, q * NV);
+      if (i + NV <= n) {
+        V a, bb, c;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+          reinterpret_cast<T*>(&a)[k] = ex[q * NV + k];
+          reinterpret_cast<T*>(&bb)[k] = ey[q * NV + k];
+          reinterpret_cast<T*>(&c)[k] = ez[q * NV + k];
+        }
+        *reinterpret_cast<V*>(qx + i) = a;
+        *reinterpret_cast<V*>(qy + i) = bb;
+        *reinterpret_cast<V*>(qz + i) = c;
+      } else {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+          if (i + k < n) {
+            qx[i + k] = ex[q * NV + k];
+            qy[i + k] = ey[q * NV + k];
+            qz[i + k] = ez[q * NV + k];
+          }
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int64_t i = chunk_index<T>(false, c0, j);
+      if (i < n) {
+        qx[i] = ex[j];
+        qy[i] = ey[j];
+        qz[i] = ez[j];
+      }
+    }
   }
 }
 
@@ -450,14 +618,18 @@ template <typename T>
 hipError_t launch_bin_scatter(const ElemBatch& eb, int batch, const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                               char* sorted_base, size_t sorted_stride, size_t inv_off, const MeshDims& m,
                               const BinGeom& bg, int nblk, hipStream_t s) {
+  (void)nblk;
+  if (eb.max_np == 0) return hipSuccess;
+  const int64_t ch = (int64_t)kScatterThreads * ScatterCfg<T>::per;
+  const unsigned nchunk = (unsigned)((eb.max_np + ch - 1) / ch);
   const bool lh = bg.lds_hist != 0;
   const size_t lds = lh ? 2 * (size_t)(bg.K + 1) * sizeof(unsigned) : 0;
   if (lh)
-    hipLaunchKernelGGL((k_bin_scatter<T, true>), dim3(nblk, batch), dim3(256), lds, s, eb, geo, stride,
-                       slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
+    hipLaunchKernelGGL((k_bin_scatter<T, true>), dim3(nchunk, batch), dim3(kScatterThreads), lds, s, eb, geo,
+                       stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
   else
-    hipLaunchKernelGGL((k_bin_scatter<T, false>), dim3(nblk, batch), dim3(256), 0, s, eb, geo, stride,
-                       slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
+    hipLaunchKernelGGL((k_bin_scatter<T, false>), dim3(nchunk, batch), dim3(kScatterThreads), 0, s, eb, geo,
+                       stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
   return hipGetLastError();
 }
 
@@ -483,9 +655,10 @@ template <typename T>
 hipError_t launch_unsort(const ElemBatch& eb, int batch, const char* sorted_base, size_t sorted_stride,
                          size_t inv_off, hipStream_t s) {
   if (eb.max_np == 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>((eb.max_np + 255) / 256, 65535 * 4);
-  hipLaunchKernelGGL(k_unsort<T>, dim3((unsigned)blocks, batch), dim3(256), 0, s, eb, sorted_base, sorted_stride,
-                     inv_off);
+  const int64_t ch = (int64_t)kScatterThreads * ScatterCfg<T>::per;
+  const unsigned nchunk = (unsigned)((eb.max_np + ch - 1) / ch);
+  hipLaunchKernelGGL(k_unsort<T>, dim3(nchunk, batch), dim3(kScatterThreads), 0, s, eb, sorted_base,
+                     sorted_stride, inv_off);
   return hipGetLastError();
 }
 

@@ -106,6 +106,74 @@ struct ElemBatch {
   }
 };
 
+// 16-byte vector of the dtype (4 floats or 2 doubles).
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+};
+template <> struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+};
+
+__device__ __forceinline__ bool aligned16(const void* a, const void* b, const void* c) {
+  return ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(c)) &
+          15u) == 0;
+}
+
+// Contiguous share [start, end) of n particles for workgroup blk of nblk;
+// shares start on multiples of 64 particles so vector loads stay aligned.
+__device__ __forceinline__ void chunk_of(int64_t n, int blk, int nblk, int64_t* start, int64_t* end) {
+  const int64_t ch = ((n + nblk - 1) / nblk + 63) & ~(int64_t)63;
+  *start = min((int64_t)blk * ch, n);
+  *end = min(*start + ch, n);
+}
+
+// Calls f(x, y, z, i) for every particle i of [start, end), the workgroup's
+// threads sharing the range.  When the three arrays are 16-byte aligned at
+// `start`, each lane reads two 16-byte vectors per array before using any
+// of them (six loads in flight per lane); ragged ends go one element at a time.
+template <typename T, typename F>
+__device__ __forceinline__ void for_each_particle(const T* __restrict__ px, const T* __restrict__ py,
+                                                  const T* __restrict__ pz, int64_t start, int64_t end, F&& f) {
+  using V = typename Vec16<T>::type;
+  constexpr int NV = Vec16<T>::n;
+  int64_t i0 = start;
+  if (end - start >= 2 * NV && aligned16(px + start, py + start, pz + start)) {
+    const V* vx = reinterpret_cast<const V*>(px + start);
+    const V* vy = reinterpret_cast<const V*>(py + start);
+    const V* vz = reinterpret_cast<const V*>(pz + start);
+    const int64_t nv = (end - start) / NV;
+    const int64_t step = 2 * (int64_t)blockDim.x;
+    for (int64_t v = threadIdx.x; v < nv; v += step) {
+      const int64_t v2 = v + blockDim.x;
+      const bool two = v2 < nv;
+      const V x0 = vx[v], y0 = vy[v], z0 = vz[v];
+      V x1 = x0, y1 = y0, z1 = z0;
+      if (two) {
+        x1 = vx[v2];
+        y1 = vy[v2];
+        z1 = vz[v2];
+      }
+      const T* a = reinterpret_cast<const T*>(&x0);
+      const T* b = reinterpret_cast<const T*>(&y0);
+      const T* c = reinterpret_cast<const T*>(&z0);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) f(a[k], b[k], c[k], start + v * NV + k);
+      if (two) {
+        const T* d = reinterpret_cast<const T*>(&x1);
+        const T* e = reinterpret_cast<const T*>(&y1);
+        const T* g = reinterpret_cast<const T*>(&z1);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) f(d[k], e[k], g[k], start + v2 * NV + k);
+      }
+    }
+    i0 = start + nv * NV;
+  }
+  for (int64_t i = i0 + threadIdx.x; i < end; i += blockDim.x) f(px[i], py[i], pz[i], i);
+}
+
 // Arguments of the per-solve geometry kernel.
 struct GeoArgs {
   int n[3];

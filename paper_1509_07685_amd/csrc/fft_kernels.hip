@@ -45,6 +45,11 @@ template <typename T> struct RegCfg {
   static constexpr int ARR = EMAX + 2;     // ceil(EMAX / R) * R <= EMAX + 2 for R in {2,3,4,8}
 };
 
+// Real values per thread of an x-pass tile: a tile holds at most
+// kLdsBytes / sizeof(complex) complex values, i.e. 16 per thread, and the
+// forward x pass stages nx reals per row of nx complex slots.
+constexpr int kTileReals = 16;
+
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
   return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
@@ -127,10 +132,12 @@ template <class F> __device__ __forceinline__ void radix_dispatch(int R, F&& f) 
 // index j) this thread owns takes its R inputs j + r N/R from in(c, idx);
 // after the optional barrier (needed when the pass reads and writes the LDS
 // tile in place) the twiddles w^(r t), t = j mod Ns, and the radix-R DFT are
-// applied and out(R, c, j, base, Ns, vals) receives the R outputs, whose
-// positions are base + r Ns.  The register array is local to this pass.
-template <typename T, bool INV, int R, bool SYNC, class In, class Out>
-__device__ __forceinline__ void fft_pass(const FFTPlan* __restrict__ P, int p, In in, Out out) {
+// applied and out(R, c, j, base, Ns, vals, k) receives the R outputs, whose
+// positions are base + r Ns (k: the thread's butterfly slot).  pre(R, k, c, j)
+// runs right after the inputs are requested, so loads it issues overlap the
+// barrier.  The register array is local to this pass.
+template <typename T, bool INV, int R, bool SYNC, class In, class Out, class Pre>
+__device__ __forceinline__ void fft_pass(const FFTPlan* __restrict__ P, int p, In in, Out out, Pre pre) {
   using C = typename Cplx<T>::type;
   constexpr int TH = RegCfg<T>::THREADS;
   constexpr int K = (RegCfg<T>::EMAX + R - 1) / R;
@@ -146,6 +153,7 @@ __device__ __forceinline__ void fft_pass(const FFTPlan* __restrict__ P, int p, I
       const int c = b & (W - 1), j = b >> logW;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[k * R + r] = in(c, j + r * NR);
+      pre(std::integral_constant<int, R>{}, k, c, j);
       if (Ns > 1) {
         const int q = (int)__umulhi((unsigned)j, magic);
         const C* wt = tw + (j - q * Ns) * (R - 1);
@@ -175,7 +183,7 @@ __device__ __forceinline__ void fft_pass(const FFTPlan* __restrict__ P, int p, I
         base = j * R;
       }
       dft<R, INV>(&v[k * R]);
-      out(std::integral_constant<int, R>{}, c, j, base, Ns, &v[k * R]);
+      out(std::integral_constant<int, R>{}, c, j, base, Ns, &v[k * R], k);
     }
   }
 }
@@ -185,25 +193,30 @@ __device__ __forceinline__ void fft_pass(const FFTPlan* __restrict__ P, int p, I
 // overwriting it); later passes read the tile.  The last pass hands its
 // butterflies to last_out; earlier ones write the tile.  A barrier follows
 // every pass that wrote the tile, except the last.
-template <typename T, bool INV, bool FIRST_LDS, class FirstIn, class LastOut>
+struct NoPre {
+  template <class RC> __device__ __forceinline__ void operator()(RC, int, int, int) const {}
+};
+
+template <typename T, bool INV, bool FIRST_LDS, class FirstIn, class LastOut, class LastPre = NoPre>
 __device__ __forceinline__ void run_fft(typename Cplx<T>::type* lds, const FFTPlan* __restrict__ P, int p0,
-                                        FirstIn first_in, LastOut last_out) {
+                                        FirstIn first_in, LastOut last_out, LastPre last_pre = LastPre{}) {
   using C = typename Cplx<T>::type;
   const int LD = P->LD;
   auto lds_in = [&](int c, int idx) { return lds[idx * LD + c]; };
-  auto lds_out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
+  auto lds_out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
 #pragma unroll
     for (int r = 0; r < RC.value; ++r) lds[(base + r * Ns) * LD + c] = vals[r];
   };
+  const NoPre none;
   const int np = P->npass;
   for (int p = p0; p < np; ++p) {
     const bool first = p == p0, last = p == np - 1;
     radix_dispatch(P->R[p], [&](auto RC) {
       constexpr int R = RC.value;
-      if (first && last) fft_pass<T, INV, R, FIRST_LDS>(P, p, first_in, last_out);
-      else if (first) fft_pass<T, INV, R, FIRST_LDS>(P, p, first_in, lds_out);
-      else if (last) fft_pass<T, INV, R, true>(P, p, lds_in, last_out);
-      else fft_pass<T, INV, R, true>(P, p, lds_in, lds_out);
+      if (first && last) fft_pass<T, INV, R, FIRST_LDS>(P, p, first_in, last_out, last_pre);
+      else if (first) fft_pass<T, INV, R, FIRST_LDS>(P, p, first_in, lds_out, none);
+      else if (last) fft_pass<T, INV, R, true>(P, p, lds_in, last_out, last_pre);
+      else fft_pass<T, INV, R, true>(P, p, lds_in, lds_out, none);
     });
     if (!last) __syncthreads();
   }
@@ -220,7 +233,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __res
                                                         typename Cplx<T>::type* __restrict__ out,
                                                         size_t out_stride, MeshDims m, const FFTPlan* __restrict__ P,
                                                         const typename Cplx<T>::type* __restrict__ post,
-                                                        int nrows, int logTX) {
+                                                        int nrows, int logTX, unsigned magic_nx) {
   using C = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
@@ -231,12 +244,29 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __res
   const int nx = m.nx, M = P->N;
   const int TX = 1 << logTX;
   const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> logTX, TY = RegCfg<T>::THREADS >> logTX;
-  for (int p = ty; p < nvalid; p += TY) {
-    const T* row = src + (size_t)(row0 + p) * nx;
-    for (int x = tx; x < nx; x += TX) {
-      T* slot = reinterpret_cast<T*>(&lds[(x >> 1) * P->LD + p]);
-      slot[x & 1] = row[x];
-      if ((x & 1) == 0 && x == nx - 1) slot[1] = (T)0;
+  {
+    // The tile's rows are contiguous (nvalid * nx reals, at most kTileReals per
+    // thread): every load of the thread is issued before the first LDS store.
+    constexpr int TH = RegCfg<T>::THREADS;
+    constexpr int KL = kTileReals;
+    const T* tsrc = src + (size_t)row0 * nx;
+    const int total = nvalid * nx;
+    T v[KL];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const int e = (int)threadIdx.x + k * TH;
+      v[k] = e < total ? tsrc[e] : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const int e = (int)threadIdx.x + k * TH;
+      if (e < total) {
+        const int p = (int)__umulhi((unsigned)e, magic_nx);
+        const int x = e - p * nx;
+        T* slot = reinterpret_cast<T*>(&lds[(x >> 1) * P->LD + p]);
+        slot[x & 1] = v[k];
+        if ((x & 1) == 0 && x == nx - 1) slot[1] = (T)0;
+      }
     }
   }
   __syncthreads();
@@ -244,7 +274,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __res
     const int nnz = (nx + 1) >> 1;
     const int LD = P->LD;
     auto in = [&](int c, int idx) { return idx < nnz ? lds[idx * LD + c] : C{0, 0}; };
-    auto out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
+    auto out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
 #pragma unroll
       for (int r = 0; r < RC.value; ++r) lds[(base + r * Ns) * LD + c] = vals[r];
     };
@@ -284,7 +314,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_fwd(const typename
   const int ny = m.ny, cs = m.cs;
   const size_t ostep = (size_t)16 * cs;       // next ky row of this plane
   auto in = [&](int c, int idx) { return (idx < ny && c < ncol) ? src[(size_t)idx * cs + c] : C{0, 0}; };
-  auto out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
+  auto out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
     if (c < ncol) {
 #pragma unroll
       for (int r = 0; r < RC.value; ++r) dst[(size_t)(base + r * Ns) * ostep + c] = vals[r];
@@ -334,13 +364,24 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
   const bool inv_single = Pi->npass == 1;
   // Last forward pass: its outputs sit at kz = j + r Ns, exactly the inputs of
   // the first inverse butterfly j (radix R, span 1, no twiddles).
-  auto mid = [&](auto RC, int c, int j, int base, int Ns, C* vals) {
+  // The Green's values of each butterfly are requested with the last forward
+  // pass's inputs (before its barrier); that pass writes kz = j + r * Nz / R.
+  T gpre[RegCfg<T>::ARR];
+  auto gload = [&](auto RC, int k, int c, int j) {
+    constexpr int R = RC.value;
+    const int span = Nz / R;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int kz = j + r * span;
+      const int kzr = min(kz, Nz - kz);
+      gpre[k * R + r] = (c < ncol) ? grow[(size_t)kzr * cs + c] : (T)0;
+    }
+  };
+  auto mid = [&](auto RC, int c, int j, int, int, C* vals, int k) {
     constexpr int R = RC.value;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int kz = base + r * Ns;
-      const int kzr = min(kz, Nz - kz);
-      const T gv = (c < ncol) ? grow[(size_t)kzr * cs + c] * scale : (T)0;
+      const T gv = gpre[k * R + r] * scale;
       vals[r].x *= gv;
       vals[r].y *= gv;
     }
@@ -353,11 +394,11 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
       for (int r = 0; r < R; ++r) lds[(j * R + r) * LD + c] = vals[r];
     }
   };
-  run_fft<T, false, false>(lds, Pf, 0, in, mid);
+  run_fft<T, false, false>(lds, Pf, 0, in, mid, gload);
   if (!inv_single) {
     __syncthreads();
     auto lds_in = [&](int c, int idx) { return lds[idx * LD + c]; };
-    auto out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
+    auto out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
 #pragma unroll
       for (int r = 0; r < RC.value; ++r) store_z(c, base + r * Ns, vals[r]);
     };
@@ -384,7 +425,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_inv(const typename
   const int ny = m.ny, Ny = m.Ny, cs = m.cs;
   const size_t istep = (size_t)16 * cs;       // next ky row of this plane
   auto in = [&](int c, int idx) { return c < ncol ? src[(size_t)idx * istep + c] : C{0, 0}; };
-  auto out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
+  auto out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
 #pragma unroll
     for (int r = 0; r < RC.value; ++r) {
       const int idx = base + r * Ns;
@@ -411,7 +452,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_inv(const typename
                                                         size_t out_stride, ElemBatch phi_user,
                                                         MeshDims m, const FFTPlan* __restrict__ P,
                                                         const typename Cplx<T>::type* __restrict__ post,
-                                                        int nrows, int logTX) {
+                                                        int nrows, int logTX, unsigned magic_m) {
   using C = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
@@ -423,24 +464,49 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_inv(const typename
   const int nx = m.nx, M = P->N;
   const int TX = 1 << logTX;
   const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> logTX, TY = RegCfg<T>::THREADS >> logTX;
-  for (int p = ty; p < nvalid; p += TY) {
-    const C* row = src + (size_t)(row0 + p) * m.cs;
-    for (int k = tx; k < M; k += TX) {
-      const C xk = row[k];
-      C xc = row[M - k];
-      xc.y = -xc.y;
-      const C s = cadd(xk, xc), d = csub(xk, xc);
-      C w = post[k];
-      w.y = -w.y;
-      const C wd = cmul(w, d);
-      lds[k * P->LD + p] = C{s.x - wd.y, s.y + wd.x};
+  {
+    // nvalid * M elements (at most kTileReals per thread), in two halves whose
+    // loads are all issued before they are used.
+    constexpr int TH = RegCfg<T>::THREADS;
+    constexpr int KH = kTileReals / 2;
+    const int total = nvalid * M;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      C xk[KH], xc[KH], w[KH];
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int e = (int)threadIdx.x + (h * KH + k) * TH;
+        if (e < total) {
+          const int p = (int)__umulhi((unsigned)e, magic_m);
+          const int kk = e - p * M;
+          const C* row = src + (size_t)(row0 + p) * m.cs;
+          xk[k] = row[kk];
+          xc[k] = row[M - kk];
+          w[k] = post[kk];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KH; ++k) {
+        const int e = (int)threadIdx.x + (h * KH + k) * TH;
+        if (e < total) {
+          const int p = (int)__umulhi((unsigned)e, magic_m);
+          const int kk = e - p * M;
+          C c = xc[k];
+          c.y = -c.y;
+          const C s = cadd(xk[k], c), d = csub(xk[k], c);
+          C ww = w[k];
+          ww.y = -ww.y;
+          const C wd = cmul(ww, d);
+          lds[kk * P->LD + p] = C{s.x - wd.y, s.y + wd.x};
+        }
+      }
     }
   }
   __syncthreads();
   {
     const int LD = P->LD;
     auto in = [&](int c, int idx) { return lds[idx * LD + c]; };
-    auto out = [&](auto RC, int c, int, int base, int Ns, C* vals) {
+    auto out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
 #pragma unroll
       for (int r = 0; r < RC.value; ++r) lds[(base + r * Ns) * LD + c] = vals[r];
     };
@@ -479,6 +545,11 @@ static inline int log2_floor(int v) {
   return l;
 }
 
+// ceil(2^32 / d): __umulhi(e, magic_of(d)) == e / d whenever e * d < 2^32.
+static inline unsigned magic_of(int d) {
+  return (unsigned)(((1ull << 32) + (unsigned long long)d - 1) / (unsigned long long)d);
+}
+
 template <typename T>
 static size_t lds_bytes(const FFTPlan& P) {
   return (size_t)P.N * P.LD * sizeof(typename Cplx<T>::type);
@@ -490,9 +561,10 @@ hipError_t launch_fft_x_fwd(const void* in, size_t in_stride, void* out, size_t 
   using C = typename Cplx<T>::type;
   const int nrows = m.ny * m.nz;
   const int logTX = log2_floor(std::min(256, std::max(1, m.nx)));
+  if ((size_t)P.host.W * m.nx > (size_t)kTileReals * RegCfg<T>::THREADS) return hipErrorInvalidValue;
   dim3 grid((nrows + P.host.W - 1) / P.host.W, batch);
   hipLaunchKernelGGL(k_fft_x_fwd<T>, grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s, (const T*)in,
-                     in_stride, (C*)out, out_stride, m, P.dev, (const C*)post, nrows, logTX);
+                     in_stride, (C*)out, out_stride, m, P.dev, (const C*)post, nrows, logTX, magic_of(m.nx));
   return hipGetLastError();
 }
 
@@ -534,9 +606,11 @@ hipError_t launch_fft_x_inv(const void* D, size_t in_stride, void* phi_ext, size
   using C = typename Cplx<T>::type;
   const int nrows = (m.ny + 2) * (m.nz + 2);
   const int logTX = log2_floor(std::min(256, std::max(1, m.nx + 2)));
+  if ((size_t)P.host.W * P.host.N > (size_t)kTileReals * RegCfg<T>::THREADS) return hipErrorInvalidValue;
   dim3 grid((nrows + P.host.W - 1) / P.host.W, batch);
   hipLaunchKernelGGL(k_fft_x_inv<T>, grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s, (const C*)D,
-                     in_stride, (T*)phi_ext, out_stride, phi_user, m, P.dev, (const C*)post, nrows, logTX);
+                     in_stride, (T*)phi_ext, out_stride, phi_user, m, P.dev, (const C*)post, nrows, logTX,
+                     magic_of(P.host.N));
   return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ __device__ __forceinline__ const Geometry* geo_at(const Geometry* base, size_t s
 }
 
 // ---------------------------------------------------------------------------
-// Bounding box, stage 1: each block reduces a grid-stride share of the
+// Bounding box, stage 1: each block reduces a contiguous share of the
 // particles of batch element blockIdx.y to (min x, min y, min z, max x, max y,
 // max z) and writes it to its partial slot.
 // ---------------------------------------------------------------------------
@@ -43,15 +43,16 @@ __global__ __launch_bounds__(256) void k_bbox(ElemBatch eb, double* partial, siz
     lo[d] = INFINITY;
     hi[d] = -INFINITY;
   }
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const T v = p[d][i];
-      lo[d] = fmin(lo[d], v);
-      hi[d] = fmax(hi[d], v);
-    }
-  }
+  int64_t start, end;
+  chunk_of(n, blockIdx.x, gridDim.x, &start, &end);
+  for_each_particle<T>(p[0], p[1], p[2], start, end, [&](T x, T y, T z, int64_t) {
+    lo[0] = fmin(lo[0], x);
+    hi[0] = fmax(hi[0], x);
+    lo[1] = fmin(lo[1], y);
+    hi[1] = fmax(hi[1], y);
+    lo[2] = fmin(lo[2], z);
+    hi[2] = fmax(hi[2], z);
+  });
   __shared__ T red[6][256];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {

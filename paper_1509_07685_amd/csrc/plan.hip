@@ -767,7 +767,7 @@ dks_status dks_poisson_geometry(dks_poisson_plan_t p, dks_stream_t stream, doubl
 dks_status dks_timing_enable(int enable) {
   TimingState& t = timing();
   std::lock_guard<std::mutex> lock(t.mu);
-  for (auto& r : t.recs) hipEventSynchronize(r.b);
+  for (auto& r : t.recs) (void)hipEventSynchronize(r.b);
   t.release_all();
   t.on = enable != 0;
   return DKS_OK;

@@ -412,3 +412,50 @@ def test_batched_table_edge_elements():
     for b in (1, 2):
         assert all(np.all(host(t) == -1.0) for t in outs[b])
     assert [int(v) for v in host(cnt)] == [0, 0, 0]
+
+
+def test_deposit_with_global_tile_histogram():
+    """A mesh with more than 8191 tiles of 16^3 cells: the binning keeps its
+    per-tile histograms in device memory instead of LDS (512 x 256 x 256
+    nodes -> 32 x 16 x 16 tiles)."""
+    dt = "f32"
+    n, h = (512, 256, 256), (2e-5, 2e-5, 2e-5)
+    x, y, z = wl.gaussian_bunch(300_000, (2e-3, 1.2e-3, 1.2e-3), 81, np.float32)
+    q = 1e-15
+    plan = dks().PoissonPlan(n, h, dt)
+    rho, cnt = plan.deposit(dev(x, dt), dev(y, dt), dev(z, dt), q)
+    Q, n_out = orc.deposit_cic(x, y, z, q, n, h, orc.centred_origin(n, h), np.float32)
+    assert int(host(cnt)[0]) == n_out
+    assert rel_l2(host(rho), Q / (h[0] * h[1] * h[2])) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_unaligned_particle_arrays_give_identical_results(dt):
+    """Positions and field outputs that are not 16-byte aligned take the
+    element-wise load/store paths.  Work-item sums are exact (fixed point), so
+    the two runs differ only by the order in which the device atomics merge
+    work items into shared mesh nodes: at the last bits."""
+    d = dks()
+    n = (48, 48, 48)
+    num = 50_001
+    x, y, z = wl.gaussian_bunch(num, (1e-3, 0.7e-3, 1.3e-3), 91, NP_DT[dt])
+    q = 2e-14
+    plan = d.PoissonPlan(n, None, dt)
+
+    def run(offset):
+        arrs = []
+        for a in (x, y, z):
+            buf = torch.zeros(num + 1, dtype=tdt(dt), device="cuda")
+            buf[offset:offset + num] = dev(a, dt)
+            arrs.append(buf[offset:offset + num])
+        outs = [torch.zeros(num + 1, dtype=tdt(dt), device="cuda")[offset:offset + num] for _ in range(3)]
+        c = torch.zeros(1, dtype=torch.int64, device="cuda")
+        plan.solve_particles(*arrs, q, out=(outs[0], outs[1], outs[2], c))
+        return np.stack([host(o) for o in outs]), int(host(c)[0])
+
+    e0, c0 = run(0)
+    e1, c1 = run(1)
+    assert c0 == c1 == 0
+    assert rel_l2(e1, e0) <= (1e-14 if dt == "f64" else 1e-6)
+    ref = orc.solve_particles(x, y, z, q, n, dtype=NP_DT[dt])
+    assert rel_l2(e0, ref["E"]) <= TOL[dt]
