@@ -41,8 +41,8 @@ def algorithmic_bytes(n, num_particles, s, kernel):
         "zero_mesh": s * mesh,
         "bin_count": 3 * s * num_particles,
         "bin_scan": 0,
-        "bin_scatter": 3 * s * num_particles + 4 * s * num_particles + 4 * num_particles,
-        "deposit": 4 * s * num_particles + s * mesh,
+        "bin_scatter": 3 * s * num_particles + 3 * s * num_particles + 4 * num_particles,
+        "deposit": 3 * s * num_particles + s * mesh,
         "fft_x_fwd": s * mesh + c * (nx + 1) * ny * nz,
         "fft_y_fwd": c * (nx + 1) * ny * nz + c * (nx + 1) * 2 * ny * nz,
         "fft_z_conv": (c * (nx + 1) * 2 * ny * nz + s * (nx + 1) * (ny + 1) * (nz + 1)
@@ -50,8 +50,8 @@ def algorithmic_bytes(n, num_particles, s, kernel):
         "fft_y_inv": c * (nx + 1) * 2 * ny * (nz + 2) + c * (nx + 1) * (ny + 2) * (nz + 2),
         "fft_x_inv": c * (nx + 1) * (ny + 2) * (nz + 2) + s * (nx + 2) * (ny + 2) * (nz + 2),
         "gradient": s * (nx + 2) * (ny + 2) * (nz + 2) + 3 * s * mesh,
-        "gather": 8 * s * num_particles + s * (nx + 2) * (ny + 2) * (nz + 2),
-        "unsort": 4 * num_particles + 4 * s * num_particles + 3 * s * num_particles,
+        "gather": 6 * s * num_particles + s * (nx + 2) * (ny + 2) * (nz + 2),
+        "unsort": 4 * num_particles + 3 * s * num_particles + 3 * s * num_particles,
     }
     return model[kernel]
 

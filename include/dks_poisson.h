@@ -99,8 +99,8 @@ dks_status dks_poisson_batch_scratch_bytes(dks_poisson_plan_t plan, int batch, i
 /* Particle solves and the deposit group the particles by mesh tile before
  * depositing (so that charge accumulates in on-chip memory rather than by
  * contended device-wide atomics) and need a caller-owned device scratch of
- * dks_poisson_particle_scratch_bytes(np) bytes for np particles (20 bytes per
- * particle in FP32, 36 in FP64: the binned record and the inverse
+ * dks_poisson_particle_scratch_bytes(np) bytes for np particles (16 bytes per
+ * particle in FP32, 28 in FP64: the binned (x, y, z) record and the inverse
  * permutation, each rounded up to 256), attached with
  * dks_poisson_set_particle_scratch (256-byte aligned; NULL with 0 bytes
  * detaches).  A solve of more particles than the attached scratch holds

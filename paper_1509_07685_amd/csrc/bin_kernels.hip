@@ -13,9 +13,9 @@
 //   scatter  one workgroup per chunk of 8192 (FP32) / 4096 (FP64) consecutive
 //            particles: ranks within tiles from an LDS histogram, one device
 //            atomic per touched tile to reserve the chunk's range, then the
-//            particles are written there as packed (x, y, z, original index)
-//            and the inverse permutation (original index -> binned slot) is
-//            written in original order
+//            particles are written there as packed (x, y, z) records and the
+//            inverse permutation (original index -> binned slot) is written
+//            in original order
 //   deposit  per work item: accumulate the weights of the tile's particles in
 //            an LDS copy of its 17^3 nodes with integer LDS atomics on a fixed-
 //            point scale (exact and order independent; floating-point LDS
@@ -49,11 +49,14 @@ constexpr int kTile = 16;          // cells per tile edge
 constexpr int kTileN = kTile + 1;  // deposit accumulator nodes per edge
 constexpr int kApron = kTile + 3;  // staged phi values per edge (nodes -1 .. 17)
 
-constexpr int kUnroll = 4;         // binned records each lane loads before using any (deposit, gather)
+// Binned records each lane loads before using any.
+constexpr int kUnrollDeposit = 4;
+constexpr int kUnrollGather = 1;
 
-template <typename T> struct Packed;
-template <> struct Packed<float> { using type = float4; };
-template <> struct Packed<double> { using type = double4; };
+// A binned particle record: its position, overwritten by the field at it.
+template <typename T> struct Rec {
+  T x, y, z;
+};
 
 // Fixed-point scale of the deposit accumulators: a weight is at most 1 and a
 // work item holds at most 2^16 (FP32) or 2^14 (FP64) particles, so a node sum
@@ -78,12 +81,14 @@ __device__ __forceinline__ const Geometry* geo_of(const Geometry* base, size_t s
 
 __device__ __forceinline__ BinState bin_state(char* slot_base, size_t stride, size_t off, int b, int K) {
   BinState s;
+  const int L = K + 1;
   unsigned* p = reinterpret_cast<unsigned*>(slot_base + (size_t)b * stride + off);
-  s.count = p;
-  s.offset = p + (K + 1);
-  s.cursor = p + 2 * (K + 1) + 1;
-  s.item_off = p + 3 * (K + 1) + 1;
-  s.misc = p + 4 * (K + 1) + 2;
+  s.xcount = p;
+  s.count = p + kXcd * L;
+  s.offset = s.count + L;
+  s.xcursor = s.offset + L + 1;
+  s.item_off = s.xcursor + kXcd * L;
+  s.misc = s.item_off + L + 1;
   return s;
 }
 
@@ -119,41 +124,55 @@ __device__ __forceinline__ Cell<T> locate(T x, T y, T z, const Geometry* g, cons
   return c;
 }
 
+// Scatter chunks: kScatterThreads * ScatterCfg<T>::per consecutive particles.
+constexpr int kScatterThreads = 512;
+template <typename T> struct ScatterCfg;
+template <> struct ScatterCfg<float> { static constexpr int per = 16; };   // 8192 particles per chunk
+template <> struct ScatterCfg<double> { static constexpr int per = 8; };   // 4096 particles per chunk
+template <typename T> constexpr int64_t scatter_chunk() { return (int64_t)kScatterThreads * ScatterCfg<T>::per; }
+
 // ---------------------------------------------------------------------------
-// count
+// count: per XCD group and tile.  Workgroup w walks the scatter chunks
+// c = w, w + G, ... (G = gridDim.x, a multiple of kXcd), which all fall in
+// group (b * nchunk + w) mod kXcd.
 // ---------------------------------------------------------------------------
 template <typename T, bool LDSHIST>
 __global__ __launch_bounds__(256) void k_bin_count(ElemBatch eb, const Geometry* geo, size_t stride, char* slot_base,
-                                                   size_t bins_off, MeshDims m, BinGeom bg) {
+                                                   size_t bins_off, MeshDims m, BinGeom bg, int nchunk) {
   extern __shared__ unsigned hist[];
+  constexpr int64_t CH = scatter_chunk<T>();
   const int b = blockIdx.y;
   const dks_particle_set e = eb.at(b);
   const T* px = (const T*)e.x;
   const T* py = (const T*)e.y;
   const T* pz = (const T*)e.z;
+  const int64_t n = eb.n(e);
   const Geometry* g = geo_of(geo, stride, b);
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
-  int64_t start, end;
-  chunk_of(eb.n(e), blockIdx.x, gridDim.x, &start, &end);
+  unsigned* xc = st.xcount + (int)(((int64_t)b * nchunk + blockIdx.x) % kXcd) * (bg.K + 1);
   if (LDSHIST) {
     for (int k = threadIdx.x; k <= bg.K; k += blockDim.x) hist[k] = 0;
     __syncthreads();
   }
-  for_each_particle<T>(px, py, pz, start, end, [&](T x, T y, T z, int64_t) {
-    const int key = locate<T>(x, y, z, g, m, bg).key;
-    if (LDSHIST) atomicAdd(&hist[key], 1u);
-    else atomicAdd(&st.count[key], 1u);
-  });
+  for (int64_t c = blockIdx.x; c * CH < n; c += gridDim.x) {
+    for_each_particle<T>(px, py, pz, c * CH, min(c * CH + CH, n), [&](T x, T y, T z, int64_t) {
+      const int key = locate<T>(x, y, z, g, m, bg).key;
+      if (LDSHIST) atomicAdd(&hist[key], 1u);
+      else atomicAdd(&xc[key], 1u);
+    });
+  }
   if (LDSHIST) {
     __syncthreads();
     for (int k = threadIdx.x; k <= bg.K; k += blockDim.x)
-      if (hist[k]) atomicAdd(&st.count[k], hist[k]);
+      if (hist[k]) atomicAdd(&xc[k], hist[k]);
   }
 }
 
 // ---------------------------------------------------------------------------
-// scan: offsets (exclusive prefix of counts), cursors, work items.  One block
-// of 1024 threads per batch element.  Also publishes the out-of-mesh count.
+// scan: tile totals, offsets (exclusive prefix over tiles), the per-group
+// reservation cursors inside each tile's range, and the work items.  One
+// block of 1024 threads per batch element.  Also publishes the out-of-mesh
+// count.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_bin_scan(const Geometry* geo, size_t stride, char* slot_base,
                                                    size_t bins_off, BinGeom bg, ElemBatch eb) {
@@ -166,7 +185,10 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const Geometry* geo, size_t s
   const int lo = min((int)threadIdx.x * per, L), hi = min(lo + per, L);
   unsigned sc = 0, si = 0;
   for (int k = lo; k < hi; ++k) {
-    const unsigned c = st.count[k];
+    unsigned c = 0;
+#pragma unroll
+    for (int x = 0; x < kXcd; ++x) c += st.xcount[x * L + k];
+    st.count[k] = c;
     sc += c;
     si += (c + bg.item - 1) / bg.item;
   }
@@ -188,7 +210,12 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const Geometry* geo, size_t s
   for (int k = lo; k < hi; ++k) {
     const unsigned c = st.count[k];
     st.offset[k] = oc;
-    st.cursor[k] = oc;
+    unsigned run = oc;
+#pragma unroll
+    for (int x = 0; x < kXcd; ++x) {
+      st.xcursor[x * L + k] = run;
+      run += st.xcount[x * L + k];
+    }
     st.item_off[k] = oi;
     oc += c;
     oi += (c + bg.item - 1) / bg.item;
@@ -197,6 +224,9 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const Geometry* geo, size_t s
     st.offset[L] = s_cnt[1023];
     st.item_off[L] = s_itm[1023];
     st.misc[0] = s_itm[1023];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
     const unsigned long long outside = st.count[bg.K];
     int64_t* cnt = eb.at(b).n_outside;
     Geometry* gw = const_cast<Geometry*>(geo_of(geo, stride, b));
@@ -210,15 +240,11 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const Geometry* geo, size_t s
 // consecutive particles.  The chunk is read once into registers; an LDS
 // histogram gives every particle its rank within its tile and the chunk's
 // count per tile; one device atomic per touched tile reserves the chunk's
-// range there; then the packed particles and the inverse permutation are
+// range there; then the (x, y, z) records and the inverse permutation are
 // written.  A chunk therefore occupies one short contiguous segment per
 // touched tile, which is what lets the unsort pass read a chunk's records
 // back with few cache lines.
 // ---------------------------------------------------------------------------
-constexpr int kScatterThreads = 512;
-template <typename T> struct ScatterCfg;
-template <> struct ScatterCfg<float> { static constexpr int per = 16; };   // 8192 particles per chunk
-template <> struct ScatterCfg<double> { static constexpr int per = 8; };   // 4096 particles per chunk
 
 // Particle of slot j (of `per`) of this thread in the chunk starting at c0:
 // vector layout (each lane owns 16-byte runs) or element layout.
@@ -238,7 +264,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
   constexpr int PER = ScatterCfg<T>::per;
   constexpr int NV = Vec16<T>::n;
   constexpr int64_t CH = (int64_t)kScatterThreads * PER;
-  using P4 = typename Packed<T>::type;
+  using P4 = Rec<T>;
   using V = typename Vec16<T>::type;
   const int b = blockIdx.y;
   const dks_particle_set e = eb.at(b);
@@ -252,6 +278,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
   const T* pz = (const T*)e.z;
   const Geometry* g = geo_of(geo, stride, b);
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
+  unsigned* cursor = st.xcursor + (int)(((int64_t)b * gridDim.x + blockIdx.x) % kXcd) * (bg.K + 1);
   P4* out = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
   unsigned* inv = reinterpret_cast<unsigned*>(sorted_base + (size_t)b * sorted_stride + inv_off);
   if (LDSHIST) {
@@ -264,14 +291,12 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
     for (int q = 0; q < PER / NV; ++q) {
       const int64_t i = chunk_index<T>(true, c0, q * NV);
       if (i + NV <= n) {
-        const V a = *reinterpret_cast<const V*>(px + i);
-        const V bb = *reinterpret_cast<const V*>(py + i);
-        const V c = *reinterpret_cast<const V*>(pz + i);
+        const V a = ld_stream(px + i), bb = ld_stream(py + i), c = ld_stream(pz + i);
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
-          xs[q * NV + k] = reinterpret_cast<const T*>(&a)[k];
-          ys[q * NV + k] = reinterpret_cast<const T*>(&bb)[k];
-          zs[q * NV + k] = reinterpret_cast<const T*>(&c)[k];
+          xs[q * NV + k] = a[k];
+          ys[q * NV + k] = bb[k];
+          zs[q * NV + k] = c[k];
         }
       } else {
 #pragma unroll
@@ -301,13 +326,13 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
     const int64_t i = chunk_index<T>(vec, c0, j);
     key[j] = i < n ? locate<T>(xs[j], ys[j], zs[j], g, m, bg).key : -1;
     if (LDSHIST) rank[j] = key[j] >= 0 ? atomicAdd(&lcnt[key[j]], 1u) : 0u;
-    else rank[j] = key[j] >= 0 ? atomicAdd(&st.cursor[key[j]], 1u) : 0u;
+    else rank[j] = key[j] >= 0 ? atomicAdd(&cursor[key[j]], 1u) : 0u;
   }
   if (LDSHIST) {
     __syncthreads();
     for (int k = threadIdx.x; k <= bg.K; k += kScatterThreads) {
       const unsigned c = lcnt[k];
-      if (c) lbase[k] = atomicAdd(&st.cursor[k], c);
+      if (c) lbase[k] = atomicAdd(&cursor[k], c);
     }
     __syncthreads();
   }
@@ -316,29 +341,27 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
     if (key[j] < 0) continue;
     const int64_t i = chunk_index<T>(vec, c0, j);
     const unsigned dst = LDSHIST ? lbase[key[j]] + rank[j] : rank[j];
-    P4 v;
-    v.x = xs[j];
-    v.y = ys[j];
-    v.z = zs[j];
-    if constexpr (sizeof(T) == 4) v.w = __uint_as_float((unsigned)i);
-    else v.w = (double)i;
-    out[dst] = v;
+    out[dst] = P4{xs[j], ys[j], zs[j]};
     inv[i] = dst;
   }
 }
 
 // Work item t -> (tile, first particle, one past the last).
-__device__ __forceinline__ void decode_item(const BinState& st, int K, int item, unsigned t, int* tile,
+// The range is clamped to the binned-particle buffer (max_np records).
+__device__ __forceinline__ void decode_item(const BinState& st, const BinGeom& bg, unsigned t, int* tile,
                                             unsigned* start, unsigned* end) {
-  int lo = 0, hi = K + 1;   // item_off[lo] <= t < item_off[hi]
+  int lo = 0, hi = bg.K + 1;   // item_off[lo] <= t < item_off[hi]
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (st.item_off[mid] <= t) lo = mid;
     else hi = mid;
   }
   *tile = lo;
-  *start = st.offset[lo] + (t - st.item_off[lo]) * (unsigned)item;
-  *end = min(*start + (unsigned)item, st.offset[lo + 1]);
+  const unsigned e = min(min(st.offset[lo] + (t - st.item_off[lo]) * (unsigned)bg.item + (unsigned)bg.item,
+                             st.offset[lo + 1]),
+                         bg.max_np);
+  *start = min(st.offset[lo] + (t - st.item_off[lo]) * (unsigned)bg.item, e);
+  *end = e;
 }
 
 // ---------------------------------------------------------------------------
@@ -350,32 +373,32 @@ __global__ __launch_bounds__(256) void k_deposit_binned(const Geometry* geo, siz
                                                         size_t sorted_stride, T* W, size_t w_stride, MeshDims m,
                                                         BinGeom bg) {
   __shared__ unsigned long long acc[kTileN * kTileN * kTileN];
-  using P4 = typename Packed<T>::type;
+  using P4 = Rec<T>;
   const int b = blockIdx.y;
   const Geometry* g = geo_of(geo, stride, b);
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
   const P4* part = reinterpret_cast<const P4*>(sorted_base + (size_t)b * sorted_stride);
   T* w = W + (size_t)b * w_stride;
-  const unsigned nitems = st.misc[0];
+  const unsigned nitems = min(st.misc[0], bg.max_items);
   constexpr int NN = kTileN * kTileN * kTileN;
   for (unsigned t = blockIdx.x; t < nitems; t += gridDim.x) {
     int tile;
     unsigned s0, s1;
-    decode_item(st, bg.K, bg.item, t, &tile, &s0, &s1);
+    decode_item(st, bg, t, &tile, &s0, &s1);
     if (tile == bg.K) continue;                      // outside particles deposit nothing
     const int tx = tile % bg.tx, ty = (tile / bg.tx) % bg.ty, tz = tile / (bg.tx * bg.ty);
     const int bx = tx * kTile, by = ty * kTile, bz = tz * kTile;
     for (int e = threadIdx.x; e < NN; e += blockDim.x) acc[e] = 0ull;
     __syncthreads();
-    for (unsigned i0 = s0 + threadIdx.x; i0 < s1; i0 += kUnroll * blockDim.x) {
-      P4 pr[kUnroll];
+    for (unsigned i0 = s0 + threadIdx.x; i0 < s1; i0 += kUnrollDeposit * blockDim.x) {
+      P4 pr[kUnrollDeposit];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < kUnrollDeposit; ++u) {
         const unsigned i = i0 + u * blockDim.x;
         if (i < s1) pr[u] = part[i];
       }
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < kUnrollDeposit; ++u) {
         if (i0 + u * blockDim.x >= s1) break;
         const P4 p = pr[u];
         const Cell<T> c = locate<T>(p.x, p.y, p.z, g, m, bg);
@@ -415,7 +438,7 @@ __global__ __launch_bounds__(256) void k_gather_binned(const Geometry* geo, size
                                                        const T* __restrict__ phi_ext, size_t phi_stride,
                                                        MeshDims m, BinGeom bg) {
   __shared__ T ph[kApron * kApron * kApron];
-  using P4 = typename Packed<T>::type;
+  using P4 = Rec<T>;
   const int b = blockIdx.y;
   const Geometry* g = geo_of(geo, stride, b);
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
@@ -423,12 +446,12 @@ __global__ __launch_bounds__(256) void k_gather_binned(const Geometry* geo, size
   const T* phi = phi_ext + (size_t)b * phi_stride;
   const T cx = Geo<T>::grad(g, 0), cy = Geo<T>::grad(g, 1), cz = Geo<T>::grad(g, 2);
   const int nx2 = m.nx + 2, ny2 = m.ny + 2, nz2 = m.nz + 2;
-  const unsigned nitems = st.misc[0];
+  const unsigned nitems = min(st.misc[0], bg.max_items);
   constexpr int A = kApron, NA = kApron * kApron * kApron;
   for (unsigned t = blockIdx.x; t < nitems; t += gridDim.x) {
     int tile;
     unsigned s0, s1;
-    decode_item(st, bg.K, bg.item, t, &tile, &s0, &s1);
+    decode_item(st, bg, t, &tile, &s0, &s1);
     if (tile == bg.K) {
       for (unsigned i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
         P4 e = part[i];
@@ -448,15 +471,15 @@ __global__ __launch_bounds__(256) void k_gather_binned(const Geometry* geo, size
       ph[e] = (x < nx2 && y < ny2 && z < nz2) ? phi[((size_t)z * ny2 + y) * nx2 + x] : (T)0;
     }
     __syncthreads();
-    for (unsigned i0 = s0 + threadIdx.x; i0 < s1; i0 += kUnroll * blockDim.x) {
-      P4 pr[kUnroll];
+    for (unsigned i0 = s0 + threadIdx.x; i0 < s1; i0 += kUnrollGather * blockDim.x) {
+      P4 pr[kUnrollGather];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < kUnrollGather; ++u) {
         const unsigned i = i0 + u * blockDim.x;
         if (i < s1) pr[u] = part[i];
       }
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < kUnrollGather; ++u) {
         const unsigned i = i0 + u * blockDim.x;
         if (i >= s1) break;
         const P4 p = pr[u];
@@ -525,7 +548,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_unsort(ElemBatch eb, const 
   constexpr int PER = ScatterCfg<T>::per;
   constexpr int NV = Vec16<T>::n;
   constexpr int64_t CH = (int64_t)kScatterThreads * PER;
-  using P4 = typename Packed<T>::type;
+  using P4 = Rec<T>;
   using V = typename Vec16<T>::type;
   const int b = blockIdx.y;
   const dks_particle_set s = eb.at(b);
@@ -542,7 +565,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_unsort(ElemBatch eb, const 
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int64_t i = chunk_index<T>(vec, c0, j);
-    src[j] = i < n ? inv[i] : 0u;
+    src[j] = i < n ? __builtin_nontemporal_load(inv + i) : 0u;
   }
   T ex[PER], ey[PER], ez[PER];
 #pragma unroll
@@ -560,13 +583,13 @@ __global__ __launch_bounds__(kScatterThreads) void k_unsort(ElemBatch eb, const 
         V a, bb, c;
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
-          reinterpret_cast<T*>(&a)[k] = ex[q * NV + k];
-          reinterpret_cast<T*>(&bb)[k] = ey[q * NV + k];
-          reinterpret_cast<T*>(&c)[k] = ez[q * NV + k];
+          a[k] = ex[q * NV + k];
+          bb[k] = ey[q * NV + k];
+          c[k] = ez[q * NV + k];
         }
-        *reinterpret_cast<V*>(qx + i) = a;
-        *reinterpret_cast<V*>(qy + i) = bb;
-        *reinterpret_cast<V*>(qz + i) = c;
+        st_stream(qx + i, a);
+        st_stream(qy + i, bb);
+        st_stream(qz + i, c);
       } else {
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
@@ -597,14 +620,19 @@ __global__ __launch_bounds__(kScatterThreads) void k_unsort(ElemBatch eb, const 
 template <typename T>
 hipError_t launch_bin_count(const ElemBatch& eb, int batch, const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                             const MeshDims& m, const BinGeom& bg, int nblk, hipStream_t s) {
+  (void)nblk;
+  if (eb.max_np == 0) return hipSuccess;
+  const int64_t nchunk = (eb.max_np + scatter_chunk<T>() - 1) / scatter_chunk<T>();
+  // a multiple of kXcd, so every chunk a workgroup walks is in one XCD group
+  const unsigned grid = (unsigned)std::min<int64_t>(1024, (nchunk + kXcd - 1) / kXcd * kXcd);
   const bool lh = bg.lds_hist != 0;
   const size_t lds = lh ? (size_t)(bg.K + 1) * sizeof(unsigned) : 0;
   if (lh)
-    hipLaunchKernelGGL((k_bin_count<T, true>), dim3(nblk, batch), dim3(256), lds, s, eb, geo, stride,
-                       slot_base, bins_off, m, bg);
+    hipLaunchKernelGGL((k_bin_count<T, true>), dim3(grid, batch), dim3(256), lds, s, eb, geo, stride,
+                       slot_base, bins_off, m, bg, (int)nchunk);
   else
-    hipLaunchKernelGGL((k_bin_count<T, false>), dim3(nblk, batch), dim3(256), 0, s, eb, geo, stride,
-                       slot_base, bins_off, m, bg);
+    hipLaunchKernelGGL((k_bin_count<T, false>), dim3(grid, batch), dim3(256), 0, s, eb, geo, stride,
+                       slot_base, bins_off, m, bg, (int)nchunk);
   return hipGetLastError();
 }
 
@@ -620,7 +648,7 @@ hipError_t launch_bin_scatter(const ElemBatch& eb, int batch, const Geometry* ge
                               const BinGeom& bg, int nblk, hipStream_t s) {
   (void)nblk;
   if (eb.max_np == 0) return hipSuccess;
-  const int64_t ch = (int64_t)kScatterThreads * ScatterCfg<T>::per;
+  const int64_t ch = scatter_chunk<T>();
   const unsigned nchunk = (unsigned)((eb.max_np + ch - 1) / ch);
   const bool lh = bg.lds_hist != 0;
   const size_t lds = lh ? 2 * (size_t)(bg.K + 1) * sizeof(unsigned) : 0;
@@ -655,7 +683,7 @@ template <typename T>
 hipError_t launch_unsort(const ElemBatch& eb, int batch, const char* sorted_base, size_t sorted_stride,
                          size_t inv_off, hipStream_t s) {
   if (eb.max_np == 0) return hipSuccess;
-  const int64_t ch = (int64_t)kScatterThreads * ScatterCfg<T>::per;
+  const int64_t ch = scatter_chunk<T>();
   const unsigned nchunk = (unsigned)((eb.max_np + ch - 1) / ch);
   hipLaunchKernelGGL(k_unsort<T>, dim3(nchunk, batch), dim3(kScatterThreads), 0, s, eb, sorted_base,
                      sorted_stride, inv_off);

@@ -106,16 +106,24 @@ struct ElemBatch {
   }
 };
 
-// 16-byte vector of the dtype (4 floats or 2 doubles).
+// 16-byte native vector of the dtype (4 floats or 2 doubles), and streaming
+// (non-temporal) loads and stores of it: data read or written once bypasses
+// the L2's normal retention so lines that are reused stay resident.
 template <typename T> struct Vec16;
 template <> struct Vec16<float> {
-  using type = float4;
+  typedef float type __attribute__((ext_vector_type(4)));
   static constexpr int n = 4;
 };
 template <> struct Vec16<double> {
-  using type = double2;
+  typedef double type __attribute__((ext_vector_type(2)));
   static constexpr int n = 2;
 };
+template <typename T> __device__ __forceinline__ typename Vec16<T>::type ld_stream(const T* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const typename Vec16<T>::type*>(p));
+}
+template <typename T> __device__ __forceinline__ void st_stream(T* p, typename Vec16<T>::type v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<typename Vec16<T>::type*>(p));
+}
 
 __device__ __forceinline__ bool aligned16(const void* a, const void* b, const void* c) {
   return ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(c)) &
@@ -141,32 +149,24 @@ __device__ __forceinline__ void for_each_particle(const T* __restrict__ px, cons
   constexpr int NV = Vec16<T>::n;
   int64_t i0 = start;
   if (end - start >= 2 * NV && aligned16(px + start, py + start, pz + start)) {
-    const V* vx = reinterpret_cast<const V*>(px + start);
-    const V* vy = reinterpret_cast<const V*>(py + start);
-    const V* vz = reinterpret_cast<const V*>(pz + start);
     const int64_t nv = (end - start) / NV;
     const int64_t step = 2 * (int64_t)blockDim.x;
     for (int64_t v = threadIdx.x; v < nv; v += step) {
       const int64_t v2 = v + blockDim.x;
       const bool two = v2 < nv;
-      const V x0 = vx[v], y0 = vy[v], z0 = vz[v];
+      const V x0 = ld_stream(px + start + v * NV), y0 = ld_stream(py + start + v * NV),
+              z0 = ld_stream(pz + start + v * NV);
       V x1 = x0, y1 = y0, z1 = z0;
       if (two) {
-        x1 = vx[v2];
-        y1 = vy[v2];
-        z1 = vz[v2];
+        x1 = ld_stream(px + start + v2 * NV);
+        y1 = ld_stream(py + start + v2 * NV);
+        z1 = ld_stream(pz + start + v2 * NV);
       }
-      const T* a = reinterpret_cast<const T*>(&x0);
-      const T* b = reinterpret_cast<const T*>(&y0);
-      const T* c = reinterpret_cast<const T*>(&z0);
 #pragma unroll
-      for (int k = 0; k < NV; ++k) f(a[k], b[k], c[k], start + v * NV + k);
+      for (int k = 0; k < NV; ++k) f(x0[k], y0[k], z0[k], start + v * NV + k);
       if (two) {
-        const T* d = reinterpret_cast<const T*>(&x1);
-        const T* e = reinterpret_cast<const T*>(&y1);
-        const T* g = reinterpret_cast<const T*>(&z1);
 #pragma unroll
-        for (int k = 0; k < NV; ++k) f(d[k], e[k], g[k], start + v2 * NV + k);
+        for (int k = 0; k < NV; ++k) f(x1[k], y1[k], z1[k], start + v2 * NV + k);
       }
     }
     i0 = start + nv * NV;
@@ -192,17 +192,33 @@ struct BinGeom {
   int K;               // tx * ty * tz
   int item;            // particles per deposit/gather work item
   int lds_hist;        // 1: per-block tile histograms fit in LDS
+  unsigned max_items;  // bound on the work-item count of one solve
+  unsigned max_np;     // bound on binned particles per element (buffer size)
 };
 
-// Per-slot bin bookkeeping (uint32): count[K+1], offset[K+2], cursor[K+1],
-// item_off[K+2], misc[4] (misc[0] = number of work items).
+// Binning counts and reserves per XCD group: the scatter's chunk c of batch
+// element b belongs to group (b * nchunk + c) mod kXcd, which is the XCD that
+// round-robin dispatch places its workgroup on.  Each tile's range is split
+// into kXcd consecutive sub-ranges, one per group, so the partly written
+// cache lines at the seams between chunks' segments are shared only by
+// workgroups of one XCD and complete in that XCD's L2.  (The grouping is a
+// pure function of the chunk index; results do not depend on the hardware's
+// actual placement.)
+constexpr int kXcd = 8;
+
+// Per-slot bin bookkeeping (uint32), L = K + 1 tiles (tile K: outside):
+// xcount[kXcd][L] (cleared by the geometry kernel), count[L], offset[L+1],
+// xcursor[kXcd][L], item_off[L+1], misc[4] (misc[0] = number of work items).
 struct BinState {
+  unsigned* xcount;
   unsigned* count;
   unsigned* offset;
-  unsigned* cursor;
+  unsigned* xcursor;
   unsigned* item_off;
   unsigned* misc;
 };
+// Total entries of that layout: 2 kXcd L + 3 L + 2 (the two L + 1 arrays) + 4.
+__host__ __device__ constexpr int bins_entries(int K) { return (2 * kXcd + 3) * (K + 1) + 6; }
 
 // Gauss-Legendre product rules of the Green's function bands: band i covers
 // D in [lo[i], lo[i+1]), D = |cell centre| / largest cell side.

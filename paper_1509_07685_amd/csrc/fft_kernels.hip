@@ -327,10 +327,15 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_fwd(const typename
 // z: forward transform of each (kx, ky) pencil over its nz non-zero inputs,
 // multiply by the real Green's spectrum times the solve's scale, inverse
 // transform, keep z in [-1, nz].  Input B[z][ky][kx] (z < nz), output
-// C[z + 1][ky][kx] for z in [-1, nz].  Grid: (column tiles, 2 ny, batch).
-// The inverse plan's radices are the forward's reversed, so the last forward
-// pass and the first inverse pass share a butterfly layout and the multiply
-// happens in registers between them.
+// C[z + 1][ky][kx] for z in [-1, nz].  The inverse plan's radices are the
+// forward's reversed, so the last forward pass and the first inverse pass
+// share a butterfly layout and the multiply happens in registers between them.
+//
+// Rows ky and Ny - ky read the same Green's block (the spectrum is even in
+// ky).  The 1-D grid (per batch element) is ordered so that the two
+// workgroups of a pair are 8 apart: L = 16 A + 8 m + r, pair-tile index
+// 8 A + r, member m.  Round-robin dispatch puts both on one XCD, one round
+// apart, so the second finds the block in that XCD's L2.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
@@ -340,17 +345,24 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
   using C = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
-  const int c0 = blockIdx.x * Pf->W;
-  const int ky = blockIdx.y;
-  const int ncol = min(Pf->W, m.ncols - c0);
+  const int W = Pf->W;
+  const int ntile = (m.ncols + W - 1) / W;
+  const unsigned L = blockIdx.x;
+  const int pt = (int)(((L >> 4) << 3) | (L & 7u));    // pair-tile index
+  const int pair = pt / ntile, tile = pt - pair * ntile;
+  if (pair > m.Ny / 2) return;
+  const bool second = (L >> 3) & 1u;
+  if (second && (pair == 0 || 2 * pair == m.Ny)) return;   // rows 0 and Ny/2 pair with themselves
+  const int ky = second ? m.Ny - pair : pair;
+  const int c0 = tile * W;
+  const int ncol = min(W, m.ncols - c0);
   const size_t zblock = (size_t)m.Ny * 16 * m.cs;   // one block of 16 z rows of B or C
-  const C* src = B + blockIdx.z * stride + (size_t)ky * 16 * m.cs + c0;
-  C* dst = Cout + blockIdx.z * stride + (size_t)ky * 16 * m.cs + c0;
+  const C* src = B + blockIdx.y * stride + (size_t)ky * 16 * m.cs + c0;
+  C* dst = Cout + blockIdx.y * stride + (size_t)ky * 16 * m.cs + c0;
   const Geometry* g = reinterpret_cast<const Geometry*>(reinterpret_cast<const char*>(geo) +
-                                                        blockIdx.z * geo_stride);
+                                                        blockIdx.y * geo_stride);
   const T scale = Geo<T>::scale(g);
-  const int kyr = min(ky, m.Ny - ky);
-  const T* grow = G + (size_t)kyr * (m.nz + 1) * m.cs + c0;
+  const T* gblk = G + ((size_t)pair * (m.cs / W) + tile) * (m.nz + 1) * W;   // [kz][W]
   const int nz = m.nz, Nz = m.Nz, cs = m.cs, LD = Pf->LD;
   auto zoff = [&](int z) { return (size_t)(z >> 4) * zblock + (size_t)(z & 15) * cs; };
   auto in = [&](int c, int idx) { return (idx < nz && c < ncol) ? src[zoff(idx) + c] : C{0, 0}; };
@@ -374,7 +386,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
     for (int r = 0; r < R; ++r) {
       const int kz = j + r * span;
       const int kzr = min(kz, Nz - kz);
-      gpre[k * R + r] = (c < ncol) ? grow[(size_t)kzr * cs + c] : (T)0;
+      gpre[k * R + r] = (c < ncol) ? gblk[kzr * W + c] : (T)0;
     }
   };
   auto mid = [&](auto RC, int c, int j, int, int, C* vals, int k) {
@@ -583,7 +595,9 @@ hipError_t launch_fft_z_conv(const void* B, void* Cout, size_t stride, const voi
                              size_t geo_stride, const MeshDims& m, const PlanRef& Pf, const PlanRef& Pi, int batch,
                              hipStream_t s) {
   using C = typename Cplx<T>::type;
-  dim3 grid((m.ncols + Pf.host.W - 1) / Pf.host.W, m.Ny, batch);
+  const int ntile = (m.ncols + Pf.host.W - 1) / Pf.host.W;
+  const int npt = (m.Ny / 2 + 1) * ntile;                 // pair-tile indices
+  dim3 grid((unsigned)((npt + 7) / 8 * 16), batch);
   hipLaunchKernelGGL(k_fft_z_conv<T>, grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(Pf.host), s, (const C*)B,
                      (C*)Cout, stride, (const T*)G, geo, geo_stride, m, Pf.dev, Pi.dev);
   return hipGetLastError();

@@ -177,11 +177,13 @@ __global__ __launch_bounds__(256) void k_apply_axis(const double* __restrict__ i
   }
 }
 
-// Ghat (dtype) in the layout the z pass reads: [ky][kz][kx], row stride cs,
-// times 1 / (Nx Ny Nz) formed in FP64.
+// Ghat (dtype) in the layout the z pass reads, times 1 / (Nx Ny Nz) formed
+// in FP64: [ky][kx / W][kz][kx % W] for the z pass's tile width W, so the
+// values one z-pass workgroup needs (one ky, W columns, every kz) are one
+// contiguous block.  cs (a multiple of W) columns per ky.
 template <typename T>
 __global__ __launch_bounds__(256) void k_green_pack(const double* __restrict__ G64, T* __restrict__ out, int nx,
-                                                    int ny, int nz, int cs, double inv_ntot) {
+                                                    int ny, int nz, int cs, int W, double inv_ntot) {
   const long long total = (long long)(nx + 1) * (ny + 1) * (nz + 1);
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
@@ -189,7 +191,8 @@ __global__ __launch_bounds__(256) void k_green_pack(const double* __restrict__ G
   const long long rem = e / (nx + 1);
   const int b = (int)(rem % (ny + 1));
   const int c = (int)(rem / (ny + 1));
-  out[((long long)b * (nz + 1) + c) * cs + a] = (T)(G64[e] * inv_ntot);
+  const long long tile = (long long)b * (cs / W) + a / W;
+  out[(tile * (nz + 1) + c) * W + a % W] = (T)(G64[e] * inv_ntot);
 }
 
 // ---------------------------------------------------------------------------
@@ -241,10 +244,12 @@ hipError_t launch_apply_axis(const double* in, double* out, const double* M, con
 }
 
 template <typename T>
-hipError_t launch_green_pack(const double* G64, void* out, const int n[3], int cs, double inv_ntot, hipStream_t s) {
+hipError_t launch_green_pack(const double* G64, void* out, const int n[3], int cs, int W, double inv_ntot,
+                             hipStream_t s) {
+  if (W < 1 || cs % W != 0) return hipErrorInvalidValue;
   const long long total = (long long)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
   hipLaunchKernelGGL(k_green_pack<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, G64, (T*)out, n[0],
-                     n[1], n[2], cs, inv_ntot);
+                     n[1], n[2], cs, W, inv_ntot);
   return hipGetLastError();
 }
 
@@ -252,7 +257,7 @@ template hipError_t launch_twiddle_pass<float>(void*, int, int, hipStream_t);
 template hipError_t launch_twiddle_pass<double>(void*, int, int, hipStream_t);
 template hipError_t launch_twiddle_line<float>(void*, int, int, hipStream_t);
 template hipError_t launch_twiddle_line<double>(void*, int, int, hipStream_t);
-template hipError_t launch_green_pack<float>(const double*, void*, const int*, int, double, hipStream_t);
-template hipError_t launch_green_pack<double>(const double*, void*, const int*, int, double, hipStream_t);
+template hipError_t launch_green_pack<float>(const double*, void*, const int*, int, int, double, hipStream_t);
+template hipError_t launch_green_pack<double>(const double*, void*, const int*, int, int, double, hipStream_t);
 
 }  // namespace dks

@@ -57,7 +57,7 @@ template <typename T> hipError_t launch_twiddle_line(void*, int, int, hipStream_
 hipError_t launch_igf_octant(double*, const int*, const double*, const GLBands&, hipStream_t);
 hipError_t launch_cos_matrix(double*, int, hipStream_t);
 hipError_t launch_apply_axis(const double*, double*, const double*, const int*, int, hipStream_t);
-template <typename T> hipError_t launch_green_pack(const double*, void*, const int*, int, double, hipStream_t);
+template <typename T> hipError_t launch_green_pack(const double*, void*, const int*, int, int, double, hipStream_t);
 
 static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -175,7 +175,7 @@ struct dks_poisson_plan_s {
   size_t bytes_W, bytes_phi_ext;
   BinGeom bg;          // tiles of the binned deposit/gather (item set per solve)
   int bins_len;        // uint32 entries of the bin bookkeeping
-  size_t part_elem;    // bytes per binned particle record (x, y, z, index; later the field)
+  size_t part_elem;    // bytes per binned particle record (x, y, z; later the field)
   size_t ws_total;
   char* ws;
   size_t ws_bytes;
@@ -321,8 +321,8 @@ void layout(dks_poisson_plan_s* p) {
   bg.K = bg.tx * bg.ty * bg.tz;
   bg.item = 65536;
   bg.lds_hist = 2 * (size_t)(bg.K + 1) * sizeof(unsigned) <= 65536 ? 1 : 0;
-  p->bins_len = 4 * (bg.K + 1) + 6;
-  p->part_elem = 4 * s;
+  p->bins_len = bins_entries(bg.K);
+  p->part_elem = 3 * s;
   size_t so = align256(sizeof(Geometry));
   p->s_bbox = so; so = align256(so + (size_t)kBboxBlocks * 6 * sizeof(double));
   p->s_bins = so; so = align256(so + (size_t)p->bins_len * sizeof(unsigned));
@@ -406,6 +406,9 @@ PartWork part_work(const dks_poisson_plan_s* p, int64_t maxn) {
   w.count_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (maxn + 8191) / 8192));
   const int64_t items = (maxn + w.bg.item - 1) / w.bg.item + w.bg.K + 1;
   w.item_blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(1, items));
+  // kernels never trust more items or particles than the buffers were sized for
+  w.bg.max_items = (unsigned)items;
+  w.bg.max_np = (unsigned)maxn;
   return w;
 }
 
@@ -419,8 +422,8 @@ dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl
   double* bbox = reinterpret_cast<double*>(sl.base + p->s_bbox);
   if (p->fitted) DKS_TK("bbox", launch_bbox<T>(eb, batch, bbox, sl.stride / sizeof(double), &nb, st));
   GeoArgs ga = geo_args(p, 1, nb);
-  ga.zero_off = p->s_bins;
-  ga.zero_len = p->bg.K + 1;
+  ga.zero_off = p->s_bins;                  // the per-group tile counts
+  ga.zero_len = kXcd * (p->bg.K + 1);
   DKS_TK("geometry", launch_geometry(bbox, sl.stride / sizeof(double), sl.geo(), sl.stride, ga, eb, batch, st));
   DKS_TK("zero_mesh", launch_zero(sl.base + p->s_r3, sl.stride, p->bytes_W, batch, st));
   DKS_TK("bin_count", launch_bin_count<T>(eb, batch, sl.geo(), sl.stride, sl.base, p->s_bins, p->md, w.bg,
@@ -488,7 +491,7 @@ dks_status prepare_t(dks_poisson_plan_s* p, hipStream_t st) {
   DKS_CK(launch_apply_axis(g2, g1, cos_axis[1], p->n, 1, st));
   DKS_CK(launch_apply_axis(g1, g2, cos_axis[2], p->n, 2, st));
   const double inv_ntot = 1.0 / ((double)(2 * p->n[0]) * (double)(2 * p->n[1]) * (double)(2 * p->n[2]));
-  DKS_CK(launch_green_pack<T>(g2, p->ws + p->off_green, p->n, p->md.cs, inv_ntot, st));
+  DKS_CK(launch_green_pack<T>(g2, p->ws + p->off_green, p->n, p->md.cs, p->pz.dev.W, inv_ntot, st));
   if (!p->fitted) {
     const GeoArgs ga = geo_args(p, 0, 0);
     DKS_CK(launch_geometry(nullptr, 0, reinterpret_cast<Geometry*>(slot), 0, ga, no_elements(), 1, st));

@@ -81,8 +81,8 @@ def test_workspace_and_state_checks(dks):
         per = dks.dks_poisson_batch_scratch_bytes(plan, 1, 0)
         assert dks.dks_poisson_batch_scratch_bytes(plan, 4, 0) == 4 * per
         assert per < nbytes
-        assert dks.dks_poisson_batch_scratch_bytes(plan, 2, 1000) == 2 * (per + 16128 + 4096)
-        assert dks.dks_poisson_particle_scratch_bytes(plan, 1000) == 16128 + 4096
+        assert dks.dks_poisson_batch_scratch_bytes(plan, 2, 1000) == 2 * (per + 12032 + 4096)
+        assert dks.dks_poisson_particle_scratch_bytes(plan, 1000) == 12032 + 4096
         assert dks.dks_poisson_particle_scratch_bytes(plan, 0) == 0
         sz = ctypes.byref(ctypes.c_size_t())
         fake_s = ctypes.c_void_p(0x300000)
@@ -111,7 +111,7 @@ def test_workspace_and_state_checks(dks):
         assert lib.dks_poisson_set_particle_scratch(plan, ctypes.c_void_p(0x100008), 4096) == dks.DKS_EWORKSPACE
         assert lib.dks_poisson_set_particle_scratch(plan, fake, 512) == dks.DKS_OK
         assert lib.dks_poisson_set_workspace(plan, fake, nbytes) == dks.DKS_OK
-        assert lib.dks_poisson_solve_particles(plan, fake, fake, fake, 20, 1e-15, fake, fake, fake,
+        assert lib.dks_poisson_solve_particles(plan, fake, fake, fake, 40, 1e-15, fake, fake, fake,
                                                None, None, None) == dks.DKS_EWORKSPACE
         # attached but not prepared: solves are refused before touching the device
         assert lib.dks_poisson_solve_rho(plan, fake, fake, None, None) == dks.DKS_ESTATE
