@@ -60,15 +60,20 @@ template <typename T> struct Rec {
 
 // Fixed-point scale of the deposit accumulators: a weight is at most 1 and a
 // work item holds at most 2^16 (FP32) or 2^14 (FP64) particles, so a node sum
-// stays below 2^48 resp. 2^63 in 64 bits; the scale keeps 2^-32 resp. 2^-49
-// resolution, finer than the dtype's rounding of the weight products.
+// stays below 2^47 resp. 2^63 in 64 bits; the scale keeps 2^-31 resp. 2^-49
+// resolution, finer than the dtype's rounding of the weight products.  The
+// scale is a power of two, folded exactly into one factor of each product;
+// to() takes the scaled weight (an FP32 one fits 32 bits: one rounding
+// conversion instead of a 64-bit one).
 template <typename T> struct Fixed;
 template <> struct Fixed<float> {
-  static __device__ __forceinline__ unsigned long long to(float w) { return __float2ull_rn(w * 4294967296.0f); }
-  static __device__ __forceinline__ float from(unsigned long long v) { return (float)v * 2.3283064365386963e-10f; }
+  static constexpr float scale = 2147483648.0f;   // 2^31
+  static __device__ __forceinline__ unsigned long long to(float ws) { return (unsigned long long)__float2uint_rn(ws); }
+  static __device__ __forceinline__ float from(unsigned long long v) { return (float)v * 4.656612873077393e-10f; }
 };
 template <> struct Fixed<double> {
-  static __device__ __forceinline__ unsigned long long to(double w) { return __double2ull_rn(w * 562949953421312.0); }
+  static constexpr double scale = 562949953421312.0;   // 2^49
+  static __device__ __forceinline__ unsigned long long to(double ws) { return __double2ull_rn(ws); }
   static __device__ __forceinline__ double from(unsigned long long v) { return (double)v * 1.7763568394002505e-15; }
 };
 
@@ -115,7 +120,8 @@ __device__ __forceinline__ Cell<T> locate(T x, T y, T z, const Geometry* g, cons
     c.fx = sx - (T)c.jx;
     c.fy = sy - (T)c.jy;
     c.fz = sz - (T)c.jz;
-    c.key = ((c.jz / kTile) * bg.ty + (c.jy / kTile)) * bg.tx + (c.jx / kTile);
+    // cell indices are >= 0 here: unsigned division by the tile edge is a shift
+    c.key = (int)((((unsigned)c.jz / kTile) * bg.ty + ((unsigned)c.jy / kTile)) * bg.tx + ((unsigned)c.jx / kTile));
   } else {
     c.key = bg.K;
     c.jx = c.jy = c.jz = 0;
@@ -124,12 +130,14 @@ __device__ __forceinline__ Cell<T> locate(T x, T y, T z, const Geometry* g, cons
   return c;
 }
 
-// Scatter chunks: kScatterThreads * ScatterCfg<T>::per consecutive particles.
-constexpr int kScatterThreads = 512;
-template <typename T> struct ScatterCfg;
-template <> struct ScatterCfg<float> { static constexpr int per = 16; };   // 8192 particles per chunk
-template <> struct ScatterCfg<double> { static constexpr int per = 8; };   // 4096 particles per chunk
-template <typename T> constexpr int64_t scatter_chunk() { return (int64_t)kScatterThreads * ScatterCfg<T>::per; }
+// Scatter chunks: 8192 (FP32) / 4096 (FP64) consecutive particles.  The
+// scatter spreads a chunk over kScatterThreads lanes, the unsort (which
+// processes the same chunks, for cache locality) over kUnsortThreads lanes
+// with more independent loads per lane.
+template <typename T> constexpr int64_t scatter_chunk() { return sizeof(T) == 4 ? 8192 : 4096; }
+constexpr int kScatterThreads = 1024;
+constexpr int kUnsortThreads = 256;
+template <typename T, int THREADS> constexpr int chunk_per() { return (int)(scatter_chunk<T>() / THREADS); }
 
 // ---------------------------------------------------------------------------
 // count: per XCD group and tile.  Workgroup w walks the scatter chunks
@@ -236,23 +244,22 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const Geometry* geo, size_t s
 }
 
 // ---------------------------------------------------------------------------
-// scatter: one workgroup per chunk of kScatterThreads * ScatterCfg<T>::per
-// consecutive particles.  The chunk is read once into registers; an LDS
-// histogram gives every particle its rank within its tile and the chunk's
-// count per tile; one device atomic per touched tile reserves the chunk's
-// range there; then the (x, y, z) records and the inverse permutation are
-// written.  A chunk therefore occupies one short contiguous segment per
-// touched tile, which is what lets the unsort pass read a chunk's records
-// back with few cache lines.
+// scatter: one workgroup per chunk of consecutive particles.  The chunk is
+// read once into registers; an LDS histogram gives every particle its rank
+// within its tile and the chunk's count per tile; one device atomic per
+// touched tile reserves the chunk's range there; then the (x, y, z) records
+// and the inverse permutation are written.  A chunk therefore occupies one
+// short contiguous segment per touched tile, which is what lets the unsort
+// pass read a chunk's records back with few cache lines.
 // ---------------------------------------------------------------------------
 
 // Particle of slot j (of `per`) of this thread in the chunk starting at c0:
 // vector layout (each lane owns 16-byte runs) or element layout.
-template <typename T>
+template <typename T, int THREADS>
 __device__ __forceinline__ int64_t chunk_index(bool vec, int64_t c0, int j) {
   constexpr int NV = Vec16<T>::n;
-  return vec ? c0 + (int64_t)NV * (threadIdx.x + (j / NV) * kScatterThreads) + (j % NV)
-             : c0 + threadIdx.x + (int64_t)j * kScatterThreads;
+  return vec ? c0 + (int64_t)NV * (threadIdx.x + (j / NV) * THREADS) + (j % NV)
+             : c0 + threadIdx.x + (int64_t)j * THREADS;
 }
 
 template <typename T, bool LDSHIST>
@@ -261,9 +268,9 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
                                                                  char* sorted_base, size_t sorted_stride,
                                                                  size_t inv_off, MeshDims m, BinGeom bg) {
   extern __shared__ unsigned lds[];
-  constexpr int PER = ScatterCfg<T>::per;
+  constexpr int PER = chunk_per<T, kScatterThreads>();
   constexpr int NV = Vec16<T>::n;
-  constexpr int64_t CH = (int64_t)kScatterThreads * PER;
+  constexpr int64_t CH = scatter_chunk<T>();
   using P4 = Rec<T>;
   using V = typename Vec16<T>::type;
   const int b = blockIdx.y;
@@ -289,7 +296,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
   if (vec) {
 #pragma unroll
     for (int q = 0; q < PER / NV; ++q) {
-      const int64_t i = chunk_index<T>(true, c0, q * NV);
+      const int64_t i = chunk_index<T, kScatterThreads>(true, c0, q * NV);
       if (i + NV <= n) {
         const V a = ld_stream(px + i), bb = ld_stream(py + i), c = ld_stream(pz + i);
 #pragma unroll
@@ -311,7 +318,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
   } else {
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-      const int64_t i = chunk_index<T>(false, c0, j);
+      const int64_t i = chunk_index<T, kScatterThreads>(false, c0, j);
       const bool ok = i < n;
       xs[j] = ok ? px[i] : (T)0;
       ys[j] = ok ? py[i] : (T)0;
@@ -323,7 +330,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
   if (LDSHIST) __syncthreads();              // lcnt cleared
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int64_t i = chunk_index<T>(vec, c0, j);
+    const int64_t i = chunk_index<T, kScatterThreads>(vec, c0, j);
     key[j] = i < n ? locate<T>(xs[j], ys[j], zs[j], g, m, bg).key : -1;
     if (LDSHIST) rank[j] = key[j] >= 0 ? atomicAdd(&lcnt[key[j]], 1u) : 0u;
     else rank[j] = key[j] >= 0 ? atomicAdd(&cursor[key[j]], 1u) : 0u;
@@ -339,7 +346,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     if (key[j] < 0) continue;
-    const int64_t i = chunk_index<T>(vec, c0, j);
+    const int64_t i = chunk_index<T, kScatterThreads>(vec, c0, j);
     const unsigned dst = LDSHIST ? lbase[key[j]] + rank[j] : rank[j];
     out[dst] = P4{xs[j], ys[j], zs[j]};
     inv[i] = dst;
@@ -402,17 +409,19 @@ __global__ __launch_bounds__(256) void k_deposit_binned(const Geometry* geo, siz
         if (i0 + u * blockDim.x >= s1) break;
         const P4 p = pr[u];
         const Cell<T> c = locate<T>(p.x, p.y, p.z, g, m, bg);
-        const T gx = (T)1 - c.fx, gy = (T)1 - c.fy, gz = (T)1 - c.fz;
+        const T gy = (T)1 - c.fy, gz = (T)1 - c.fz;
+        const T gxs = ((T)1 - c.fx) * Fixed<T>::scale, fxs = c.fx * Fixed<T>::scale;   // exact scaling
+        const T zy00 = gz * gy, zy01 = gz * c.fy, zy10 = c.fz * gy, zy11 = c.fz * c.fy;
         unsigned long long* a = acc + ((c.jz - bz) * kTileN + (c.jy - by)) * kTileN + (c.jx - bx);
         constexpr int SY = kTileN, SZ = kTileN * kTileN;
-        atomicAdd(a, Fixed<T>::to(gz * gy * gx));
-        atomicAdd(a + 1, Fixed<T>::to(gz * gy * c.fx));
-        atomicAdd(a + SY, Fixed<T>::to(gz * c.fy * gx));
-        atomicAdd(a + SY + 1, Fixed<T>::to(gz * c.fy * c.fx));
-        atomicAdd(a + SZ, Fixed<T>::to(c.fz * gy * gx));
-        atomicAdd(a + SZ + 1, Fixed<T>::to(c.fz * gy * c.fx));
-        atomicAdd(a + SZ + SY, Fixed<T>::to(c.fz * c.fy * gx));
-        atomicAdd(a + SZ + SY + 1, Fixed<T>::to(c.fz * c.fy * c.fx));
+        atomicAdd(a, Fixed<T>::to(zy00 * gxs));
+        atomicAdd(a + 1, Fixed<T>::to(zy00 * fxs));
+        atomicAdd(a + SY, Fixed<T>::to(zy01 * gxs));
+        atomicAdd(a + SY + 1, Fixed<T>::to(zy01 * fxs));
+        atomicAdd(a + SZ, Fixed<T>::to(zy10 * gxs));
+        atomicAdd(a + SZ + 1, Fixed<T>::to(zy10 * fxs));
+        atomicAdd(a + SZ + SY, Fixed<T>::to(zy11 * gxs));
+        atomicAdd(a + SZ + SY + 1, Fixed<T>::to(zy11 * fxs));
       }
     }
     __syncthreads();
@@ -506,25 +515,33 @@ __global__ __launch_bounds__(256) void k_gather_binned(const Geometry* geo, size
             zm[a][kx] = o[(-A + a) * A + kx];            // (x + kx, y + a, z - 1)
             zp[a][kx] = o[(2 * A + a) * A + kx];         // (x + kx, y + a, z + 2)
           }
+        // E_d = c_d * sum over the eight corners of weight * (phi(+1) - phi(-1)),
+        // the coefficient applied once at the end.
         T ax = 0, ay = 0, az = 0;
 #pragma unroll
         for (int kz = 0; kz < 2; ++kz)
 #pragma unroll
-          for (int ky = 0; ky < 2; ++ky)
+          for (int ky = 0; ky < 2; ++ky) {
+            const T d0 = r[kz][ky][2] - r[kz][ky][0], d1 = r[kz][ky][3] - r[kz][ky][1];
+            ax += wz[kz] * wy[ky] * (wx[0] * d0 + wx[1] * d1);
+          }
 #pragma unroll
-            for (int kx = 0; kx < 2; ++kx) {
-              const T ex = cx * (r[kz][ky][kx + 2] - r[kz][ky][kx]);
-              const T yhi = ky ? yp[kz][kx] : r[kz][1][kx + 1];
-              const T ylo = ky ? r[kz][0][kx + 1] : ym[kz][kx];
-              const T zhi = kz ? zp[ky][kx] : r[1][ky][kx + 1];
-              const T zlo = kz ? r[0][ky][kx + 1] : zm[ky][kx];
-              const T ey = cy * (yhi - ylo);
-              const T ez = cz * (zhi - zlo);
-              const T wgt = wz[kz] * wy[ky] * wx[kx];
-              ax += wgt * ex;
-              ay += wgt * ey;
-              az += wgt * ez;
-            }
+        for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+          for (int kx = 0; kx < 2; ++kx) {
+            const T d0 = r[kz][1][kx + 1] - ym[kz][kx], d1 = yp[kz][kx] - r[kz][0][kx + 1];
+            ay += wz[kz] * wx[kx] * (wy[0] * d0 + wy[1] * d1);
+          }
+#pragma unroll
+        for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+          for (int kx = 0; kx < 2; ++kx) {
+            const T d0 = r[1][ky][kx + 1] - zm[ky][kx], d1 = zp[ky][kx] - r[0][ky][kx + 1];
+            az += wy[ky] * wx[kx] * (wz[0] * d0 + wz[1] * d1);
+          }
+        ax *= cx;
+        ay *= cy;
+        az *= cz;
         P4 e = p;
         e.x = ax;
         e.y = ay;
@@ -543,11 +560,11 @@ __global__ __launch_bounds__(256) void k_gather_binned(const Geometry* geo, size
 // scattered record reads share cache lines within the workgroup.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kScatterThreads) void k_unsort(ElemBatch eb, const char* sorted_base,
+__global__ __launch_bounds__(kUnsortThreads) void k_unsort(ElemBatch eb, const char* sorted_base,
                                                             size_t sorted_stride, size_t inv_off) {
-  constexpr int PER = ScatterCfg<T>::per;
+  constexpr int PER = chunk_per<T, kUnsortThreads>();
   constexpr int NV = Vec16<T>::n;
-  constexpr int64_t CH = (int64_t)kScatterThreads * PER;
+  constexpr int64_t CH = scatter_chunk<T>();
   using P4 = Rec<T>;
   using V = typename Vec16<T>::type;
   const int b = blockIdx.y;
@@ -564,7 +581,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_unsort(ElemBatch eb, const 
   unsigned src[PER];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int64_t i = chunk_index<T>(vec, c0, j);
+    const int64_t i = chunk_index<T, kUnsortThreads>(vec, c0, j);
     src[j] = i < n ? __builtin_nontemporal_load(inv + i) : 0u;
   }
   T ex[PER], ey[PER], ez[PER];
@@ -578,7 +595,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_unsort(ElemBatch eb, const 
   if (vec) {
 #pragma unroll
     for (int q = 0; q < PER / NV; ++q) {
-      const int64_t i = chunk_index<T>(true, c0, q * NV);
+      const int64_t i = chunk_index<T, kUnsortThreads>(true, c0, q * NV);
       if (i + NV <= n) {
         V a, bb, c;
 #pragma unroll
@@ -604,7 +621,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_unsort(ElemBatch eb, const 
   } else {
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-      const int64_t i = chunk_index<T>(false, c0, j);
+      const int64_t i = chunk_index<T, kUnsortThreads>(false, c0, j);
       if (i < n) {
         qx[i] = ex[j];
         qy[i] = ey[j];
@@ -685,7 +702,7 @@ hipError_t launch_unsort(const ElemBatch& eb, int batch, const char* sorted_base
   if (eb.max_np == 0) return hipSuccess;
   const int64_t ch = scatter_chunk<T>();
   const unsigned nchunk = (unsigned)((eb.max_np + ch - 1) / ch);
-  hipLaunchKernelGGL(k_unsort<T>, dim3(nchunk, batch), dim3(kScatterThreads), 0, s, eb, sorted_base,
+  hipLaunchKernelGGL(k_unsort<T>, dim3(nchunk, batch), dim3(kUnsortThreads), 0, s, eb, sorted_base,
                      sorted_stride, inv_off);
   return hipGetLastError();
 }
