@@ -223,12 +223,152 @@ __device__ __forceinline__ void run_fft(typename Cplx<T>::type* lds, const FFTPl
 }
 
 // ---------------------------------------------------------------------------
+// Compile-time plans.  For the power-of-two lengths of common meshes the
+// kernels are also instantiated with the whole plan known at compile time
+// (length, tile width, LDS stride, radix order), so butterfly indexing,
+// twiddle offsets and guards fold to constants; the runtime plan above
+// serves every other shape.  A launcher uses a compile-time plan only when
+// the host plan matches it exactly.
+// ---------------------------------------------------------------------------
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+struct DynPlan {
+  static constexpr bool is_static = false;
+};
+
+// Power-of-two length N: radix-8 passes, then one radix-4 or radix-2 pass
+// (the host's order); REV reverses the order (the inverse z transform).
+template <int N_, int W_, int LD_, bool REV_>
+struct SPlan {
+  static constexpr bool is_static = true;
+  static constexpr int N = N_, W = W_, LD = LD_, logW = ilog2(W_);
+  static constexpr int n8 = ilog2(N_) / 3, rem = ilog2(N_) % 3;
+  static constexpr int npass = n8 + (rem ? 1 : 0);
+  static constexpr int Rf(int p) { return p < n8 ? 8 : (rem == 2 ? 4 : 2); }
+  static constexpr int R(int p) { return REV_ ? Rf(npass - 1 - p) : Rf(p); }
+  static constexpr int Ns(int p) { return p == 0 ? 1 : Ns(p - 1) * R(p - 1); }
+  static constexpr int tw_off(int p) { return p <= 1 ? 0 : tw_off(p - 1) + Ns(p - 1) * (R(p - 1) - 1); }
+  using Reversed = SPlan<N_, W_, LD_, !REV_>;
+};
+
+// The inverse z plan of a forward plan: radices reversed.
+template <class SP> struct InvPlan { using type = typename SP::Reversed; };
+template <> struct InvPlan<DynPlan> { using type = DynPlan; };
+
+// Plan values a kernel needs, from the compile-time plan or the device copy.
+template <class SP> __device__ __forceinline__ int plan_W(const FFTPlan* P) {
+  if constexpr (SP::is_static) return SP::W;
+  else return P->W;
+}
+template <class SP> __device__ __forceinline__ int plan_LD(const FFTPlan* P) {
+  if constexpr (SP::is_static) return SP::LD;
+  else return P->LD;
+}
+template <class SP> __device__ __forceinline__ int plan_N(const FFTPlan* P) {
+  if constexpr (SP::is_static) return SP::N;
+  else return P->N;
+}
+template <class SP> __device__ __forceinline__ int plan_npass(const FFTPlan* P) {
+  if constexpr (SP::is_static) return SP::npass;
+  else return P->npass;
+}
+
+// fft_pass with every plan value a constant.
+template <typename T, bool INV, class SP, int p, bool SYNC, class In, class Out, class Pre>
+__device__ __forceinline__ void fft_pass_s(const typename Cplx<T>::type* __restrict__ twb, In in, Out out, Pre pre) {
+  using C = typename Cplx<T>::type;
+  constexpr int R = SP::R(p), Ns = SP::Ns(p), NR = SP::N / R, W = SP::W, logW = SP::logW;
+  constexpr int TH = RegCfg<T>::THREADS, nbf = W * NR;
+  constexpr int K = cmin((RegCfg<T>::EMAX + R - 1) / R, (nbf + TH - 1) / TH);
+  constexpr bool guard = K * TH > nbf;
+  const C* tw = twb + SP::tw_off(p);
+  C v[K * R];
+  C w[K * (R - 1)];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int b = (int)threadIdx.x + k * TH;
+    if (!guard || b < nbf) {
+      const int c = b & (W - 1), j = b >> logW;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[k * R + r] = in(c, j + r * NR);
+      pre(std::integral_constant<int, R>{}, k, c, j);
+      if constexpr (Ns > 1) {
+        const C* wt = tw + (j & (Ns - 1)) * (R - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[k * (R - 1) + r - 1] = wt[r - 1];
+      }
+    }
+  }
+  if constexpr (SYNC) __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int b = (int)threadIdx.x + k * TH;
+    if (!guard || b < nbf) {
+      const int c = b & (W - 1), j = b >> logW;
+      int base;
+      if constexpr (Ns > 1) {
+        const int t = j & (Ns - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C wr = w[k * (R - 1) + r - 1];
+          if (INV) wr.y = -wr.y;
+          v[k * R + r] = cmul(v[k * R + r], wr);
+        }
+        base = (j - t) * R + t;
+      } else {
+        base = j * R;
+      }
+      dft<R, INV>(&v[k * R]);
+      out(std::integral_constant<int, R>{}, c, j, base, Ns, &v[k * R], k);
+    }
+  }
+}
+
+template <typename T, bool INV, bool FIRST_LDS, class SP, int p, int p0>
+struct RunStatic {
+  template <class FirstIn, class LastOut, class LastPre>
+  static __device__ __forceinline__ void go(typename Cplx<T>::type* lds, const typename Cplx<T>::type* tw,
+                                            FirstIn& first_in, LastOut& last_out, LastPre& last_pre) {
+    using C = typename Cplx<T>::type;
+    constexpr bool first = p == p0, last = p == SP::npass - 1;
+    auto lds_in = [&](int c, int idx) { return lds[idx * SP::LD + c]; };
+    auto lds_out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
+#pragma unroll
+      for (int r = 0; r < RC.value; ++r) lds[(base + r * Ns) * SP::LD + c] = vals[r];
+    };
+    const NoPre none;
+    if constexpr (first && last) fft_pass_s<T, INV, SP, p, FIRST_LDS>(tw, first_in, last_out, last_pre);
+    else if constexpr (first) fft_pass_s<T, INV, SP, p, FIRST_LDS>(tw, first_in, lds_out, none);
+    else if constexpr (last) fft_pass_s<T, INV, SP, p, true>(tw, lds_in, last_out, last_pre);
+    else fft_pass_s<T, INV, SP, p, true>(tw, lds_in, lds_out, none);
+    if constexpr (!last) {
+      __syncthreads();
+      RunStatic<T, INV, FIRST_LDS, SP, p + 1, p0>::go(lds, tw, first_in, last_out, last_pre);
+    }
+  }
+};
+
+// Passes [P0, npass) with the compile-time plan SP, or with the device plan P.
+template <typename T, bool INV, bool FIRST_LDS, class SP, int P0, class FirstIn, class LastOut,
+          class LastPre = NoPre>
+__device__ __forceinline__ void run_any(typename Cplx<T>::type* lds, const FFTPlan* __restrict__ P,
+                                        FirstIn first_in, LastOut last_out, LastPre last_pre = LastPre{}) {
+  if constexpr (SP::is_static) {
+    RunStatic<T, INV, FIRST_LDS, SP, P0, P0>::go(lds, (const typename Cplx<T>::type*)P->tw, first_in, last_out,
+                                                 last_pre);
+  } else {
+    run_fft<T, INV, FIRST_LDS>(lds, P, P0, first_in, last_out, last_pre);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // x forward: real rows of nx values (zero-padded to 2 nx) -> nx + 1 complex.
 // A length-2nx real transform is done as a length-nx complex transform of
 // z[m] = x[2m] + i x[2m+1], then X[k] = (Z[k] + conj Z[nx-k]) / 2
 // - i w^k (Z[k] - conj Z[nx-k]) / 2 with w = exp(-2 pi i / 2nx).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, class SP>
 __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __restrict__ in, size_t in_stride,
                                                         typename Cplx<T>::type* __restrict__ out,
                                                         size_t out_stride, MeshDims m, const FFTPlan* __restrict__ P,
@@ -239,9 +379,10 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __res
   C* lds = reinterpret_cast<C*>(smem);
   const T* src = in + blockIdx.y * in_stride;
   C* dst = out + blockIdx.y * out_stride;
-  const int row0 = blockIdx.x * P->W;
-  const int nvalid = min(P->W, nrows - row0);
-  const int nx = m.nx, M = P->N;
+  const int Wt = plan_W<SP>(P), LDt = plan_LD<SP>(P);
+  const int row0 = blockIdx.x * Wt;
+  const int nvalid = min(Wt, nrows - row0);
+  const int nx = m.nx, M = plan_N<SP>(P);
   const int TX = 1 << logTX;
   const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> logTX, TY = RegCfg<T>::THREADS >> logTX;
   {
@@ -263,7 +404,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __res
       if (e < total) {
         const int p = (int)__umulhi((unsigned)e, magic_nx);
         const int x = e - p * nx;
-        T* slot = reinterpret_cast<T*>(&lds[(x >> 1) * P->LD + p]);
+        T* slot = reinterpret_cast<T*>(&lds[(x >> 1) * LDt + p]);
         slot[x & 1] = v[k];
         if ((x & 1) == 0 && x == nx - 1) slot[1] = (T)0;
       }
@@ -272,21 +413,21 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __res
   __syncthreads();
   {
     const int nnz = (nx + 1) >> 1;
-    const int LD = P->LD;
+    const int LD = LDt;
     auto in = [&](int c, int idx) { return idx < nnz ? lds[idx * LD + c] : C{0, 0}; };
     auto out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
 #pragma unroll
       for (int r = 0; r < RC.value; ++r) lds[(base + r * Ns) * LD + c] = vals[r];
     };
-    run_fft<T, false, true>(lds, P, 0, in, out);
+    run_any<T, false, true, SP, 0>(lds, P, in, out);
   }
   __syncthreads();
   const int ncols = nx + 1;
   for (int p = ty; p < nvalid; p += TY) {
     C* orow = dst + (size_t)(row0 + p) * m.cs;
     for (int k = tx; k < ncols; k += TX) {
-      const C zk = lds[(k == M ? 0 : k) * P->LD + p];
-      C zc = lds[(k == 0 ? 0 : M - k) * P->LD + p];
+      const C zk = lds[(k == M ? 0 : k) * LDt + p];
+      C zc = lds[(k == 0 ? 0 : M - k) * LDt + p];
       zc.y = -zc.y;
       const C s = cadd(zk, zc), d = csub(zk, zc);
       const C wd = cmul(post[k], d);
@@ -299,15 +440,15 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __res
 // y forward: pencils along y of the x-transformed rows.  Input A[z][y][kx]
 // (y < ny), output B[z][ky][kx] (ky < 2 ny).  Grid: (column tiles, nz, batch).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, class SP>
 __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_fwd(const typename Cplx<T>::type* __restrict__ A,
                                                         typename Cplx<T>::type* __restrict__ B,
                                                         size_t stride, MeshDims m, const FFTPlan* __restrict__ P) {
   using C = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
-  const int c0 = blockIdx.x * P->W;
-  const int ncol = min(P->W, m.ncols - c0);
+  const int c0 = blockIdx.x * plan_W<SP>(P);
+  const int ncol = min(plan_W<SP>(P), m.ncols - c0);
   const int z = blockIdx.y;
   const C* src = A + blockIdx.z * stride + (size_t)z * m.ny * m.cs + c0;
   C* dst = B + blockIdx.z * stride + ((size_t)(z >> 4) * m.Ny * 16 + (z & 15)) * m.cs + c0;
@@ -320,7 +461,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_fwd(const typename
       for (int r = 0; r < RC.value; ++r) dst[(size_t)(base + r * Ns) * ostep + c] = vals[r];
     }
   };
-  run_fft<T, false, false>(lds, P, 0, in, out);
+  run_any<T, false, false, SP, 0>(lds, P, in, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -337,7 +478,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_fwd(const typename
 // 8 A + r, member m.  Round-robin dispatch puts both on one XCD, one round
 // apart, so the second finds the block in that XCD's L2.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, class SP>
 __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
     const typename Cplx<T>::type* __restrict__ B, typename Cplx<T>::type* __restrict__ Cout,
     size_t stride, const T* __restrict__ G, const Geometry* __restrict__ geo, size_t geo_stride,
@@ -345,7 +486,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
   using C = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
-  const int W = Pf->W;
+  const int W = plan_W<SP>(Pf);
   const int ntile = (m.ncols + W - 1) / W;
   const unsigned L = blockIdx.x;
   const int pt = (int)(((L >> 4) << 3) | (L & 7u));    // pair-tile index
@@ -363,7 +504,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
                                                         blockIdx.y * geo_stride);
   const T scale = Geo<T>::scale(g);
   const T* gblk = G + ((size_t)pair * (m.cs / W) + tile) * (m.nz + 1) * W;   // [kz][W]
-  const int nz = m.nz, Nz = m.Nz, cs = m.cs, LD = Pf->LD;
+  const int nz = m.nz, Nz = m.Nz, cs = m.cs, LD = plan_LD<SP>(Pf);
   auto zoff = [&](int z) { return (size_t)(z >> 4) * zblock + (size_t)(z & 15) * cs; };
   auto in = [&](int c, int idx) { return (idx < nz && c < ncol) ? src[zoff(idx) + c] : C{0, 0}; };
   // Final inverse outputs: keep z = -1 (index Nz - 1) and z = 0 .. nz as row z + 1.
@@ -373,7 +514,8 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
     else if (idx == Nz - 1) zo = 0;
     if (zo >= 0 && c < ncol) dst[zoff(zo) + c] = val;
   };
-  const bool inv_single = Pi->npass == 1;
+  using SPi = typename InvPlan<SP>::type;
+  const bool inv_single = plan_npass<SPi>(Pi) == 1;
   // Last forward pass: its outputs sit at kz = j + r Ns, exactly the inputs of
   // the first inverse butterfly j (radix R, span 1, no twiddles).
   // The Green's values of each butterfly are requested with the last forward
@@ -406,7 +548,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
       for (int r = 0; r < R; ++r) lds[(j * R + r) * LD + c] = vals[r];
     }
   };
-  run_fft<T, false, false>(lds, Pf, 0, in, mid, gload);
+  run_any<T, false, false, SP, 0>(lds, Pf, in, mid, gload);
   if (!inv_single) {
     __syncthreads();
     auto lds_in = [&](int c, int idx) { return lds[idx * LD + c]; };
@@ -414,7 +556,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
 #pragma unroll
       for (int r = 0; r < RC.value; ++r) store_z(c, base + r * Ns, vals[r]);
     };
-    run_fft<T, true, true>(lds, Pi, 1, lds_in, out);
+    run_any<T, true, true, SPi, 1>(lds, Pi, lds_in, out);
   }
 }
 
@@ -422,15 +564,15 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
 // y inverse: C[z'][ky][kx] -> D[z'][y + 1][kx] for y in [-1, ny].
 // Grid: (column tiles, nz + 2, batch).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, class SP>
 __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_inv(const typename Cplx<T>::type* __restrict__ Cin,
                                                         typename Cplx<T>::type* __restrict__ D,
                                                         size_t stride, MeshDims m, const FFTPlan* __restrict__ P) {
   using C = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
-  const int c0 = blockIdx.x * P->W;
-  const int ncol = min(P->W, m.ncols - c0);
+  const int c0 = blockIdx.x * plan_W<SP>(P);
+  const int ncol = min(plan_W<SP>(P), m.ncols - c0);
   const int zp = blockIdx.y;
   const C* src = Cin + blockIdx.z * stride + ((size_t)(zp >> 4) * m.Ny * 16 + (zp & 15)) * m.cs + c0;
   C* dst = D + blockIdx.z * stride + (size_t)zp * (m.ny + 2) * m.cs + c0;
@@ -447,7 +589,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_inv(const typename
       if (yo >= 0 && c < ncol) dst[(size_t)yo * cs + c] = vals[r];
     }
   };
-  run_fft<T, true, false>(lds, P, 0, in, out);
+  run_any<T, true, false, SP, 0>(lds, P, in, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -458,7 +600,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_inv(const typename
 // normalisation is folded into the Green's spectrum.  Optionally also writes
 // the physical part of phi to a [nz][ny][nx] array.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, class SP>
 __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_inv(const typename Cplx<T>::type* __restrict__ D,
                                                         size_t in_stride, T* __restrict__ phi_ext,
                                                         size_t out_stride, ElemBatch phi_user,
@@ -471,9 +613,10 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_inv(const typename
   const C* src = D + blockIdx.y * in_stride;
   T* dst = phi_ext + blockIdx.y * out_stride;
   T* user = reinterpret_cast<T*>(phi_user.at(blockIdx.y).phi);
-  const int row0 = blockIdx.x * P->W;
-  const int nvalid = min(P->W, nrows - row0);
-  const int nx = m.nx, M = P->N;
+  const int Wt = plan_W<SP>(P), LDt = plan_LD<SP>(P);
+  const int row0 = blockIdx.x * Wt;
+  const int nvalid = min(Wt, nrows - row0);
+  const int nx = m.nx, M = plan_N<SP>(P);
   const int TX = 1 << logTX;
   const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> logTX, TY = RegCfg<T>::THREADS >> logTX;
   {
@@ -509,20 +652,20 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_inv(const typename
           C ww = w[k];
           ww.y = -ww.y;
           const C wd = cmul(ww, d);
-          lds[kk * P->LD + p] = C{s.x - wd.y, s.y + wd.x};
+          lds[kk * LDt + p] = C{s.x - wd.y, s.y + wd.x};
         }
       }
     }
   }
   __syncthreads();
   {
-    const int LD = P->LD;
+    const int LD = LDt;
     auto in = [&](int c, int idx) { return lds[idx * LD + c]; };
     auto out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
 #pragma unroll
       for (int r = 0; r < RC.value; ++r) lds[(base + r * Ns) * LD + c] = vals[r];
     };
-    run_fft<T, true, true>(lds, P, 0, in, out);
+    run_any<T, true, true, SP, 0>(lds, P, in, out);
   }
   __syncthreads();
   const int nout = nx + 2;
@@ -537,9 +680,9 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_inv(const typename
       const int x = xo - 1;
       T val;
       if (x < 0) {
-        val = lds[(M - 1) * P->LD + p].y;
+        val = lds[(M - 1) * LDt + p].y;
       } else {
-        const C zv = lds[(x >> 1) * P->LD + p];
+        const C zv = lds[(x >> 1) * LDt + p];
         val = (x & 1) ? zv.y : zv.x;
       }
       orow[xo] = val;
@@ -567,6 +710,24 @@ static size_t lds_bytes(const FFTPlan& P) {
   return (size_t)P.N * P.LD * sizeof(typename Cplx<T>::type);
 }
 
+template <class SP> static bool plan_matches(const FFTPlan& h) {
+  if (h.N != SP::N || h.W != SP::W || h.LD != SP::LD || h.npass != SP::npass) return false;
+  for (int p = 0; p < h.npass; ++p)
+    if (h.R[p] != SP::R(p) || h.Ns[p] != SP::Ns(p) || h.tw_off[p] != SP::tw_off(p)) return false;
+  return true;
+}
+
+// Calls f with the compile-time plan equal to host plan h (tile width of 128
+// bytes, LD = W + PAD), or with DynPlan when none is.
+template <typename T, int PAD, class F> static void with_plan(const FFTPlan& h, F&& f) {
+  constexpr int W = 128 / (2 * (int)sizeof(T));
+  if (plan_matches<SPlan<512, W, W + PAD, false>>(h)) f(SPlan<512, W, W + PAD, false>{});
+  else if (plan_matches<SPlan<256, W, W + PAD, false>>(h)) f(SPlan<256, W, W + PAD, false>{});
+  else if (plan_matches<SPlan<128, W, W + PAD, false>>(h)) f(SPlan<128, W, W + PAD, false>{});
+  else if (plan_matches<SPlan<64, W, W + PAD, false>>(h)) f(SPlan<64, W, W + PAD, false>{});
+  else f(DynPlan{});
+}
+
 template <typename T>
 hipError_t launch_fft_x_fwd(const void* in, size_t in_stride, void* out, size_t out_stride, const MeshDims& m,
                             const PlanRef& P, const void* post, int batch, hipStream_t s) {
@@ -575,8 +736,11 @@ hipError_t launch_fft_x_fwd(const void* in, size_t in_stride, void* out, size_t 
   const int logTX = log2_floor(std::min(256, std::max(1, m.nx)));
   if ((size_t)P.host.W * m.nx > (size_t)kTileReals * RegCfg<T>::THREADS) return hipErrorInvalidValue;
   dim3 grid((nrows + P.host.W - 1) / P.host.W, batch);
-  hipLaunchKernelGGL(k_fft_x_fwd<T>, grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s, (const T*)in,
-                     in_stride, (C*)out, out_stride, m, P.dev, (const C*)post, nrows, logTX, magic_of(m.nx));
+  with_plan<T, 1>(P.host, [&](auto sp) {
+    hipLaunchKernelGGL((k_fft_x_fwd<T, decltype(sp)>), grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s,
+                       (const T*)in, in_stride, (C*)out, out_stride, m, P.dev, (const C*)post, nrows, logTX,
+                       magic_of(m.nx));
+  });
   return hipGetLastError();
 }
 
@@ -585,8 +749,10 @@ hipError_t launch_fft_y_fwd(const void* A, void* B, size_t stride, const MeshDim
                             hipStream_t s) {
   using C = typename Cplx<T>::type;
   dim3 grid((m.ncols + P.host.W - 1) / P.host.W, m.nz, batch);
-  hipLaunchKernelGGL(k_fft_y_fwd<T>, grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s, (const C*)A, (C*)B,
-                     stride, m, P.dev);
+  with_plan<T, 0>(P.host, [&](auto sp) {
+    hipLaunchKernelGGL((k_fft_y_fwd<T, decltype(sp)>), grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s,
+                       (const C*)A, (C*)B, stride, m, P.dev);
+  });
   return hipGetLastError();
 }
 
@@ -598,8 +764,19 @@ hipError_t launch_fft_z_conv(const void* B, void* Cout, size_t stride, const voi
   const int ntile = (m.ncols + Pf.host.W - 1) / Pf.host.W;
   const int npt = (m.Ny / 2 + 1) * ntile;                 // pair-tile indices
   dim3 grid((unsigned)((npt + 7) / 8 * 16), batch);
-  hipLaunchKernelGGL(k_fft_z_conv<T>, grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(Pf.host), s, (const C*)B,
-                     (C*)Cout, stride, (const T*)G, geo, geo_stride, m, Pf.dev, Pi.dev);
+  with_plan<T, 0>(Pf.host, [&](auto sp) {
+    using SP = decltype(sp);
+    auto launch = [&](auto spl) {
+      hipLaunchKernelGGL((k_fft_z_conv<T, decltype(spl)>), grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(Pf.host), s,
+                         (const C*)B, (C*)Cout, stride, (const T*)G, geo, geo_stride, m, Pf.dev, Pi.dev);
+    };
+    if constexpr (SP::is_static) {
+      if (plan_matches<typename SP::Reversed>(Pi.host)) launch(SP{});
+      else launch(DynPlan{});
+    } else {
+      launch(DynPlan{});
+    }
+  });
   return hipGetLastError();
 }
 
@@ -608,8 +785,10 @@ hipError_t launch_fft_y_inv(const void* Cin, void* D, size_t stride, const MeshD
                             hipStream_t s) {
   using C = typename Cplx<T>::type;
   dim3 grid((m.ncols + P.host.W - 1) / P.host.W, m.nz + 2, batch);
-  hipLaunchKernelGGL(k_fft_y_inv<T>, grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s, (const C*)Cin, (C*)D,
-                     stride, m, P.dev);
+  with_plan<T, 0>(P.host, [&](auto sp) {
+    hipLaunchKernelGGL((k_fft_y_inv<T, decltype(sp)>), grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s,
+                       (const C*)Cin, (C*)D, stride, m, P.dev);
+  });
   return hipGetLastError();
 }
 
@@ -622,9 +801,11 @@ hipError_t launch_fft_x_inv(const void* D, size_t in_stride, void* phi_ext, size
   const int logTX = log2_floor(std::min(256, std::max(1, m.nx + 2)));
   if ((size_t)P.host.W * P.host.N > (size_t)kTileReals * RegCfg<T>::THREADS) return hipErrorInvalidValue;
   dim3 grid((nrows + P.host.W - 1) / P.host.W, batch);
-  hipLaunchKernelGGL(k_fft_x_inv<T>, grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s, (const C*)D,
-                     in_stride, (T*)phi_ext, out_stride, phi_user, m, P.dev, (const C*)post, nrows, logTX,
-                     magic_of(P.host.N));
+  with_plan<T, 1>(P.host, [&](auto sp) {
+    hipLaunchKernelGGL((k_fft_x_inv<T, decltype(sp)>), grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s,
+                       (const C*)D, in_stride, (T*)phi_ext, out_stride, phi_user, m, P.dev, (const C*)post, nrows,
+                       logTX, magic_of(P.host.N));
+  });
   return hipGetLastError();
 }
 
