@@ -56,6 +56,34 @@ def algorithmic_bytes(n, num_particles, s, kernel):
     return model[kernel]
 
 
+# Library timing names -> kernel symbols as rocprofv3 reports them.
+KERNEL_SYMBOL = {
+    "bbox": "k_bbox", "geometry": "k_geometry", "zero_mesh": "k_zero", "bin_count": "k_bin_count",
+    "bin_scan": "k_bin_scan", "bin_scatter": "k_bin_scatter", "deposit": "k_deposit_binned",
+    "fft_x_fwd": "k_fft_x_fwd", "fft_y_fwd": "k_fft_y_fwd", "fft_z_conv": "k_fft_z_conv",
+    "fft_y_inv": "k_fft_y_inv", "fft_x_inv": "k_fft_x_inv", "gradient": "k_gradient",
+    "gather": "k_gather_binned", "unsort": "k_unsort",
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_halo_gaussian_256cubed_1e8_f32.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when there is none or the kernel sources have
+    changed since it was taken."""
+    import hashlib
+    import json
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    doc = json.load(open(TRAFFIC_FILE))
+    for f, h in doc["sources_sha256"].items():
+        path = os.path.join(ROOT, f)
+        if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != h:
+            return None
+    k = doc["kernels"].get(KERNEL_SYMBOL.get(kernel, ""))
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+
+
 def conv_bytes(n, s):
     return sum(algorithmic_bytes(n, 0, s, k) for k in
                ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv"))
@@ -77,20 +105,22 @@ def time_loop(torch, fn, steps, warmup):
 
 def cpu_baseline():
     """The oracle as it stands on a bounded sample: the full particle step on a
-    128^3 fitted mesh with 1e6 particles of the same halo-Gaussian bunch, twice."""
+    128^3 fitted mesh with 1.25e7 particles of the same halo-Gaussian bunch
+    (the workload scaled by 1/8 in mesh points and particles alike), once."""
     import numpy as np
     from oracle import poisson_oracle as orc
     from paper_1509_07685_amd import workloads as wl
-    x, y, z = wl.halo_gaussian(1_000_000, 1e-3, 0.1, 5e-3, 4, np.float32)
-    reps, n = 2, (128, 128, 128)
+    x, y, z = wl.halo_gaussian(12_500_000, 1e-3, 0.1, 5e-3, 4, np.float32)
+    reps, n = 1, (128, 128, 128)
     t0 = time.perf_counter()
     for _ in range(reps):
         orc.solve_particles(x, y, z, wl.TOTAL_CHARGE / x.size, n, dtype=np.float32)
     dt = (time.perf_counter() - t0) / reps
     return {"value": n[0] * n[1] * n[2] / dt, "unit": "mesh-pts/s", "cores": 1, "kind": "oracle",
             "sample": "FP64 numpy oracle, full particle step (fit, CIC deposit, IGF, doubled-grid FFT "
-                      "convolution, gradient, gather) on a 128^3 fitted mesh with 1e6 particles of the "
-                      "halo-Gaussian bunch, mean of 2 runs; numpy's FFT and bincount are single-threaded",
+                      "convolution, gradient, gather) on a 128^3 fitted mesh with 1.25e7 particles of the "
+                      "halo-Gaussian bunch (the 256^3 / 1e8 workload scaled by 1/8), one run; "
+                      "numpy's FFT and bincount are single-threaded",
             "seconds_per_step": dt}
 
 
@@ -163,7 +193,8 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
     dk = kernels[dom]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dk["GB_s"] / HBM_PEAK_GBS, "traffic": None}
+                "frac": dk["GB_s"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                "alg_bytes": dk["alg_bytes"]}
     conv_names = ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv")
     conv_ms = sum(kernels[k]["avg_ms"] for k in conv_names if k in kernels)
     conv = {"ms": conv_ms, "alg_bytes": conv_bytes(n, 4),

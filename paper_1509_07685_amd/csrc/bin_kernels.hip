@@ -49,6 +49,11 @@ constexpr int kTile = 16;          // cells per tile edge
 constexpr int kTileN = kTile + 1;  // deposit accumulator nodes per edge
 constexpr int kApron = kTile + 3;  // staged phi values per edge (nodes -1 .. 17)
 
+// Lanes per deposit / gather workgroup: the LDS tile bounds the workgroups
+// per CU, so wider workgroups keep more record loads in flight.
+constexpr int kDepositThreads = 1024;
+constexpr int kGatherThreads = 512;
+
 // Binned records each lane loads before using any.
 constexpr int kUnrollDeposit = 4;
 constexpr int kUnrollGather = 1;
@@ -375,7 +380,7 @@ __device__ __forceinline__ void decode_item(const BinState& st, const BinGeom& b
 // deposit: LDS-privatised accumulation per work item, then merge.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_deposit_binned(const Geometry* geo, size_t stride, char* slot_base,
+__global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geometry* geo, size_t stride, char* slot_base,
                                                         size_t bins_off, const char* sorted_base,
                                                         size_t sorted_stride, T* W, size_t w_stride, MeshDims m,
                                                         BinGeom bg) {
@@ -442,7 +447,7 @@ __global__ __launch_bounds__(256) void k_deposit_binned(const Geometry* geo, siz
 // gather with the central-difference field formed on the fly from staged phi.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_gather_binned(const Geometry* geo, size_t stride, char* slot_base,
+__global__ __launch_bounds__(kGatherThreads) void k_gather_binned(const Geometry* geo, size_t stride, char* slot_base,
                                                        size_t bins_off, char* sorted_base, size_t sorted_stride,
                                                        const T* __restrict__ phi_ext, size_t phi_stride,
                                                        MeshDims m, BinGeom bg) {
@@ -682,7 +687,7 @@ template <typename T>
 hipError_t launch_deposit_binned(const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                                  const char* sorted_base, size_t sorted_stride, void* W, size_t w_stride,
                                  const MeshDims& m, const BinGeom& bg, int nblk, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(k_deposit_binned<T>, dim3(nblk, batch), dim3(256), 0, s, geo, stride, slot_base, bins_off,
+  hipLaunchKernelGGL(k_deposit_binned<T>, dim3(nblk, batch), dim3(kDepositThreads), 0, s, geo, stride, slot_base, bins_off,
                      sorted_base, sorted_stride, (T*)W, w_stride, m, bg);
   return hipGetLastError();
 }
@@ -691,7 +696,7 @@ template <typename T>
 hipError_t launch_gather_binned(const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                                 char* sorted_base, size_t sorted_stride, const void* phi_ext, size_t phi_stride,
                                 const MeshDims& m, const BinGeom& bg, int nblk, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_binned<T>, dim3(nblk, batch), dim3(256), 0, s, geo, stride, slot_base, bins_off,
+  hipLaunchKernelGGL(k_gather_binned<T>, dim3(nblk, batch), dim3(kGatherThreads), 0, s, geo, stride, slot_base, bins_off,
                      sorted_base, sorted_stride, (const T*)phi_ext, phi_stride, m, bg);
   return hipGetLastError();
 }

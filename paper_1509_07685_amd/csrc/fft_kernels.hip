@@ -152,7 +152,7 @@ __device__ __forceinline__ void fft_pass(const FFTPlan* __restrict__ P, int p, I
     if (b < nbf) {
       const int c = b & (W - 1), j = b >> logW;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[k * R + r] = in(c, j + r * NR);
+      for (int r = 0; r < R; ++r) v[k * R + r] = in(c, j + r * NR, k * R + r);
       pre(std::integral_constant<int, R>{}, k, c, j);
       if (Ns > 1) {
         const int q = (int)__umulhi((unsigned)j, magic);
@@ -202,7 +202,7 @@ __device__ __forceinline__ void run_fft(typename Cplx<T>::type* lds, const FFTPl
                                         FirstIn first_in, LastOut last_out, LastPre last_pre = LastPre{}) {
   using C = typename Cplx<T>::type;
   const int LD = P->LD;
-  auto lds_in = [&](int c, int idx) { return lds[idx * LD + c]; };
+  auto lds_in = [&](int c, int idx, int) { return lds[idx * LD + c]; };
   auto lds_out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
 #pragma unroll
     for (int r = 0; r < RC.value; ++r) lds[(base + r * Ns) * LD + c] = vals[r];
@@ -256,6 +256,11 @@ struct SPlan {
 template <class SP> struct InvPlan { using type = typename SP::Reversed; };
 template <> struct InvPlan<DynPlan> { using type = DynPlan; };
 
+// Element offsets inside one batch element's intermediate array: 32-bit with
+// a compile-time plan (the launchers use those only when every offset fits),
+// 64-bit otherwise.
+template <class SP> using OffT = typename std::conditional<SP::is_static, unsigned, size_t>::type;
+
 // Plan values a kernel needs, from the compile-time plan or the device copy.
 template <class SP> __device__ __forceinline__ int plan_W(const FFTPlan* P) {
   if constexpr (SP::is_static) return SP::W;
@@ -275,7 +280,9 @@ template <class SP> __device__ __forceinline__ int plan_npass(const FFTPlan* P) 
 }
 
 // fft_pass with every plan value a constant.
-template <typename T, bool INV, class SP, int p, bool SYNC, class In, class Out, class Pre>
+// ZU: the transform's upper half inputs are zero (a zero-padded forward
+// transform): inputs r >= R/2 of the first pass are not read.
+template <typename T, bool INV, class SP, int p, bool SYNC, bool ZU, class In, class Out, class Pre>
 __device__ __forceinline__ void fft_pass_s(const typename Cplx<T>::type* __restrict__ twb, In in, Out out, Pre pre) {
   using C = typename Cplx<T>::type;
   constexpr int R = SP::R(p), Ns = SP::Ns(p), NR = SP::N / R, W = SP::W, logW = SP::logW;
@@ -291,7 +298,7 @@ __device__ __forceinline__ void fft_pass_s(const typename Cplx<T>::type* __restr
     if (!guard || b < nbf) {
       const int c = b & (W - 1), j = b >> logW;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[k * R + r] = in(c, j + r * NR);
+      for (int r = 0; r < R; ++r) v[k * R + r] = (ZU && 2 * r >= R) ? C{0, 0} : in(c, j + r * NR, k * (R / 2) + r);
       pre(std::integral_constant<int, R>{}, k, c, j);
       if constexpr (Ns > 1) {
         const C* wt = tw + (j & (Ns - 1)) * (R - 1);
@@ -325,38 +332,50 @@ __device__ __forceinline__ void fft_pass_s(const typename Cplx<T>::type* __restr
   }
 }
 
-template <typename T, bool INV, bool FIRST_LDS, class SP, int p, int p0>
+template <typename T, bool INV, bool FIRST_LDS, class SP, int p, int p0, bool ZU>
 struct RunStatic {
-  template <class FirstIn, class LastOut, class LastPre>
+  template <class FirstIn, class LastOut, class FirstPre, class LastPre>
   static __device__ __forceinline__ void go(typename Cplx<T>::type* lds, const typename Cplx<T>::type* tw,
-                                            FirstIn& first_in, LastOut& last_out, LastPre& last_pre) {
+                                            FirstIn& first_in, LastOut& last_out, FirstPre& first_pre,
+                                            LastPre& last_pre) {
     using C = typename Cplx<T>::type;
     constexpr bool first = p == p0, last = p == SP::npass - 1;
-    auto lds_in = [&](int c, int idx) { return lds[idx * SP::LD + c]; };
+    auto lds_in = [&](int c, int idx, int) { return lds[idx * SP::LD + c]; };
     auto lds_out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
 #pragma unroll
       for (int r = 0; r < RC.value; ++r) lds[(base + r * Ns) * SP::LD + c] = vals[r];
     };
     const NoPre none;
-    if constexpr (first && last) fft_pass_s<T, INV, SP, p, FIRST_LDS>(tw, first_in, last_out, last_pre);
-    else if constexpr (first) fft_pass_s<T, INV, SP, p, FIRST_LDS>(tw, first_in, lds_out, none);
-    else if constexpr (last) fft_pass_s<T, INV, SP, p, true>(tw, lds_in, last_out, last_pre);
-    else fft_pass_s<T, INV, SP, p, true>(tw, lds_in, lds_out, none);
+    if constexpr (first && last) {
+      auto both = [&](auto RC, int k, int c, int j) {
+        first_pre(RC, k, c, j);
+        last_pre(RC, k, c, j);
+      };
+      fft_pass_s<T, INV, SP, p, FIRST_LDS, ZU>(tw, first_in, last_out, both);
+    } else if constexpr (first) {
+      fft_pass_s<T, INV, SP, p, FIRST_LDS, ZU>(tw, first_in, lds_out, first_pre);
+    } else if constexpr (last) {
+      fft_pass_s<T, INV, SP, p, true, false>(tw, lds_in, last_out, last_pre);
+    } else {
+      fft_pass_s<T, INV, SP, p, true, false>(tw, lds_in, lds_out, none);
+    }
     if constexpr (!last) {
       __syncthreads();
-      RunStatic<T, INV, FIRST_LDS, SP, p + 1, p0>::go(lds, tw, first_in, last_out, last_pre);
+      RunStatic<T, INV, FIRST_LDS, SP, p + 1, p0, ZU>::go(lds, tw, first_in, last_out, first_pre, last_pre);
     }
   }
 };
 
 // Passes [P0, npass) with the compile-time plan SP, or with the device plan P.
-template <typename T, bool INV, bool FIRST_LDS, class SP, int P0, class FirstIn, class LastOut,
+// ZU (compile-time plans only): the first pass's upper-half inputs are zero.
+template <typename T, bool INV, bool FIRST_LDS, class SP, int P0, bool ZU = false, class FirstIn, class LastOut,
           class LastPre = NoPre>
 __device__ __forceinline__ void run_any(typename Cplx<T>::type* lds, const FFTPlan* __restrict__ P,
                                         FirstIn first_in, LastOut last_out, LastPre last_pre = LastPre{}) {
   if constexpr (SP::is_static) {
-    RunStatic<T, INV, FIRST_LDS, SP, P0, P0>::go(lds, (const typename Cplx<T>::type*)P->tw, first_in, last_out,
-                                                 last_pre);
+    NoPre none;
+    RunStatic<T, INV, FIRST_LDS, SP, P0, P0, ZU>::go(lds, (const typename Cplx<T>::type*)P->tw, first_in, last_out,
+                                                     none, last_pre);
   } else {
     run_fft<T, INV, FIRST_LDS>(lds, P, P0, first_in, last_out, last_pre);
   }
@@ -414,12 +433,12 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __res
   {
     const int nnz = (nx + 1) >> 1;
     const int LD = LDt;
-    auto in = [&](int c, int idx) { return idx < nnz ? lds[idx * LD + c] : C{0, 0}; };
+    auto in = [&](int c, int idx, int) { return idx < nnz ? lds[idx * LD + c] : C{0, 0}; };
     auto out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
 #pragma unroll
       for (int r = 0; r < RC.value; ++r) lds[(base + r * Ns) * LD + c] = vals[r];
     };
-    run_any<T, false, true, SP, 0>(lds, P, in, out);
+    run_any<T, false, true, SP, 0, true>(lds, P, in, out);
   }
   __syncthreads();
   const int ncols = nx + 1;
@@ -454,14 +473,15 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_fwd(const typename
   C* dst = B + blockIdx.z * stride + ((size_t)(z >> 4) * m.Ny * 16 + (z & 15)) * m.cs + c0;
   const int ny = m.ny, cs = m.cs;
   const size_t ostep = (size_t)16 * cs;       // next ky row of this plane
-  auto in = [&](int c, int idx) { return (idx < ny && c < ncol) ? src[(size_t)idx * cs + c] : C{0, 0}; };
+  using Off = OffT<SP>;
+  auto in = [&](int c, int idx, int) { return (idx < ny && c < ncol) ? src[(Off)idx * (Off)cs + (Off)c] : C{0, 0}; };
   auto out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
     if (c < ncol) {
 #pragma unroll
-      for (int r = 0; r < RC.value; ++r) dst[(size_t)(base + r * Ns) * ostep + c] = vals[r];
+      for (int r = 0; r < RC.value; ++r) dst[(Off)(base + r * Ns) * (Off)ostep + (Off)c] = vals[r];
     }
   };
-  run_any<T, false, false, SP, 0>(lds, P, in, out);
+  run_any<T, false, false, SP, 0, true>(lds, P, in, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -505,14 +525,15 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
   const T scale = Geo<T>::scale(g);
   const T* gblk = G + ((size_t)pair * (m.cs / W) + tile) * (m.nz + 1) * W;   // [kz][W]
   const int nz = m.nz, Nz = m.Nz, cs = m.cs, LD = plan_LD<SP>(Pf);
-  auto zoff = [&](int z) { return (size_t)(z >> 4) * zblock + (size_t)(z & 15) * cs; };
-  auto in = [&](int c, int idx) { return (idx < nz && c < ncol) ? src[zoff(idx) + c] : C{0, 0}; };
+  using Off = OffT<SP>;
+  auto zoff = [&](int z) { return (Off)(z >> 4) * (Off)zblock + (Off)(z & 15) * (Off)cs; };
+  auto in = [&](int c, int idx, int) { return (idx < nz && c < ncol) ? src[zoff(idx) + (Off)c] : C{0, 0}; };
   // Final inverse outputs: keep z = -1 (index Nz - 1) and z = 0 .. nz as row z + 1.
   auto store_z = [&](int c, int idx, C val) {
     int zo = -1;
     if (idx <= nz) zo = idx + 1;
     else if (idx == Nz - 1) zo = 0;
-    if (zo >= 0 && c < ncol) dst[zoff(zo) + c] = val;
+    if (zo >= 0 && c < ncol) dst[zoff(zo) + (Off)c] = val;
   };
   using SPi = typename InvPlan<SP>::type;
   const bool inv_single = plan_npass<SPi>(Pi) == 1;
@@ -548,10 +569,10 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_z_conv(
       for (int r = 0; r < R; ++r) lds[(j * R + r) * LD + c] = vals[r];
     }
   };
-  run_any<T, false, false, SP, 0>(lds, Pf, in, mid, gload);
+  run_any<T, false, false, SP, 0, true>(lds, Pf, in, mid, gload);
   if (!inv_single) {
     __syncthreads();
-    auto lds_in = [&](int c, int idx) { return lds[idx * LD + c]; };
+    auto lds_in = [&](int c, int idx, int) { return lds[idx * LD + c]; };
     auto out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
 #pragma unroll
       for (int r = 0; r < RC.value; ++r) store_z(c, base + r * Ns, vals[r]);
@@ -578,7 +599,8 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_inv(const typename
   C* dst = D + blockIdx.z * stride + (size_t)zp * (m.ny + 2) * m.cs + c0;
   const int ny = m.ny, Ny = m.Ny, cs = m.cs;
   const size_t istep = (size_t)16 * cs;       // next ky row of this plane
-  auto in = [&](int c, int idx) { return c < ncol ? src[(size_t)idx * istep + c] : C{0, 0}; };
+  using Off = OffT<SP>;
+  auto in = [&](int c, int idx, int) { return c < ncol ? src[(Off)idx * (Off)istep + (Off)c] : C{0, 0}; };
   auto out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
 #pragma unroll
     for (int r = 0; r < RC.value; ++r) {
@@ -586,7 +608,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_inv(const typename
       int yo = -1;
       if (idx <= ny) yo = idx + 1;
       else if (idx == Ny - 1) yo = 0;
-      if (yo >= 0 && c < ncol) dst[(size_t)yo * cs + c] = vals[r];
+      if (yo >= 0 && c < ncol) dst[(Off)yo * (Off)cs + (Off)c] = vals[r];
     }
   };
   run_any<T, true, false, SP, 0>(lds, P, in, out);
@@ -660,7 +682,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_inv(const typename
   __syncthreads();
   {
     const int LD = LDt;
-    auto in = [&](int c, int idx) { return lds[idx * LD + c]; };
+    auto in = [&](int c, int idx, int) { return lds[idx * LD + c]; };
     auto out = [&](auto RC, int c, int, int base, int Ns, C* vals, int) {
 #pragma unroll
       for (int r = 0; r < RC.value; ++r) lds[(base + r * Ns) * LD + c] = vals[r];
@@ -710,6 +732,12 @@ static size_t lds_bytes(const FFTPlan& P) {
   return (size_t)P.N * P.LD * sizeof(typename Cplx<T>::type);
 }
 
+// Every element offset the y and z passes form inside one batch element's
+// intermediate arrays stays below (nz + 16) * Ny * cs.
+static inline bool offsets_fit32(const MeshDims& m) {
+  return (double)(m.nz + 16) * (double)m.Ny * (double)m.cs < 2147483648.0;
+}
+
 template <class SP> static bool plan_matches(const FFTPlan& h) {
   if (h.N != SP::N || h.W != SP::W || h.LD != SP::LD || h.npass != SP::npass) return false;
   for (int p = 0; p < h.npass; ++p)
@@ -718,10 +746,12 @@ template <class SP> static bool plan_matches(const FFTPlan& h) {
 }
 
 // Calls f with the compile-time plan equal to host plan h (tile width of 128
-// bytes, LD = W + PAD), or with DynPlan when none is.
-template <typename T, int PAD, class F> static void with_plan(const FFTPlan& h, F&& f) {
+// bytes, LD = W + PAD), or with DynPlan when none is or when the kernel's
+// element offsets may not fit 32 bits (!off32).
+template <typename T, int PAD, class F> static void with_plan(const FFTPlan& h, F&& f, bool off32 = true) {
   constexpr int W = 128 / (2 * (int)sizeof(T));
-  if (plan_matches<SPlan<512, W, W + PAD, false>>(h)) f(SPlan<512, W, W + PAD, false>{});
+  if (!off32) f(DynPlan{});
+  else if (plan_matches<SPlan<512, W, W + PAD, false>>(h)) f(SPlan<512, W, W + PAD, false>{});
   else if (plan_matches<SPlan<256, W, W + PAD, false>>(h)) f(SPlan<256, W, W + PAD, false>{});
   else if (plan_matches<SPlan<128, W, W + PAD, false>>(h)) f(SPlan<128, W, W + PAD, false>{});
   else if (plan_matches<SPlan<64, W, W + PAD, false>>(h)) f(SPlan<64, W, W + PAD, false>{});
@@ -752,7 +782,7 @@ hipError_t launch_fft_y_fwd(const void* A, void* B, size_t stride, const MeshDim
   with_plan<T, 0>(P.host, [&](auto sp) {
     hipLaunchKernelGGL((k_fft_y_fwd<T, decltype(sp)>), grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s,
                        (const C*)A, (C*)B, stride, m, P.dev);
-  });
+  }, offsets_fit32(m));
   return hipGetLastError();
 }
 
@@ -776,7 +806,7 @@ hipError_t launch_fft_z_conv(const void* B, void* Cout, size_t stride, const voi
     } else {
       launch(DynPlan{});
     }
-  });
+  }, offsets_fit32(m));
   return hipGetLastError();
 }
 
@@ -788,7 +818,7 @@ hipError_t launch_fft_y_inv(const void* Cin, void* D, size_t stride, const MeshD
   with_plan<T, 0>(P.host, [&](auto sp) {
     hipLaunchKernelGGL((k_fft_y_inv<T, decltype(sp)>), grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s,
                        (const C*)Cin, (C*)D, stride, m, P.dev);
-  });
+  }, offsets_fit32(m));
   return hipGetLastError();
 }
 

@@ -154,6 +154,16 @@ class dks_particle_set(ctypes.Structure):
 PARTICLE_SET_BYTES = ctypes.sizeof(dks_particle_set)
 
 
+def _set_dtype():
+    import numpy as np
+    return np.dtype([("x", "<u8"), ("y", "<u8"), ("z", "<u8"), ("Ex", "<u8"), ("Ey", "<u8"), ("Ez", "<u8"),
+                     ("phi", "<u8"), ("n_outside", "<u8"), ("np", "<i8"), ("q", "<f8")])
+
+
+PARTICLE_SET_DTYPE = _set_dtype()   # numpy layout of dks_particle_set
+assert PARTICLE_SET_DTYPE.itemsize == PARTICLE_SET_BYTES
+
+
 def particle_set_table(entries):
     """Bytes of a dks_particle_set array.  entries: sequence of dicts with keys
     x, y, z, Ex, Ey, Ez (device addresses), optional phi, n_outside, and np, q."""

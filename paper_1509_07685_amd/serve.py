@@ -268,6 +268,7 @@ class Executor:
         self.max_np = M
         nbytes = B * dks.PARTICLE_SET_BYTES
         self.table_host = torch.zeros(nbytes, dtype=torch.uint8).pin_memory()
+        self.table_view = self.table_host.numpy().view(dks.PARTICLE_SET_DTYPE)
         self.table_dev = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
         self.cnt = torch.zeros(B, dtype=torch.int64, device=dev)
         self.scratch = self.plan.batch_scratch(B, M)
@@ -277,12 +278,16 @@ class Executor:
         # the plan was prepared on torch's current stream; launches come on others
         torch.cuda.synchronize()
         if self.use_graphs:
+            # each graph starts with the copy of its b table entries from the
+            # pinned host table, so a launch is: write the table, replay
             cap = torch.cuda.Stream()
             for b in range(1, B + 1):
+                nb = b * dks.PARTICLE_SET_BYTES
                 with torch.cuda.stream(cap):
                     self._solve(b)             # eager warm-up: an all-empty table
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g, stream=cap):
+                    self.table_dev[:nb].copy_(self.table_host[:nb], non_blocking=True)
                     self._solve(b)
                 self.graphs[b] = g
             torch.cuda.synchronize()
@@ -291,18 +296,15 @@ class Executor:
         self.plan.solve_particles_batched(self.table_dev, b, self.max_np, self.scratch)
 
     def fill(self, jobs):
-        """Write the descriptors of `jobs` into the pinned host table."""
-        import ctypes
+        """Write the descriptors of `jobs` into the pinned host table (a
+        numpy structured view of it, field by field)."""
+        t = self.table_view
         base = self.cnt.data_ptr()
-        entries = []
         for i, j in enumerate(jobs):
             x, y, z, outs = j.payload
-            entries.append({"x": x.data_ptr(), "y": y.data_ptr(), "z": z.data_ptr(),
-                            "Ex": outs[0].data_ptr(), "Ey": outs[1].data_ptr(), "Ez": outs[2].data_ptr(),
-                            "n_outside": base + 8 * i, "np": j.num_particles, "q": j.charge})
-        raw = self._dks.particle_set_table(entries)
-        ctypes.memmove(self.table_host.data_ptr(), raw, len(raw))
-        return len(raw)
+            t[i] = (x.data_ptr(), y.data_ptr(), z.data_ptr(), outs[0].data_ptr(), outs[1].data_ptr(),
+                    outs[2].data_ptr(), 0, base + 8 * i, j.num_particles, j.charge)
+        return len(jobs) * self._dks.PARTICLE_SET_BYTES
 
     def run(self, jobs, stream, torch):
         """Solve `jobs` as one batch on `stream` (graph replay when enabled).
@@ -311,10 +313,10 @@ class Executor:
         b = len(jobs)
         nbytes = self.fill(jobs)
         with torch.cuda.stream(stream):
-            self.table_dev[:nbytes].copy_(self.table_host[:nbytes], non_blocking=True)
             if self.use_graphs:
                 self.graphs[b].replay()
             else:
+                self.table_dev[:nbytes].copy_(self.table_host[:nbytes], non_blocking=True)
                 self.plan.solve_particles_batched(self.table_dev, b, self.max_np, self.scratch, stream=stream)
 
 
@@ -437,11 +439,11 @@ def serve_sequential(torch, jobs, clock=time.perf_counter, device="cuda"):
             "p99_ms": percentile(lat, 0.99), "mean_ms": sum(lat) / len(lat), "wall_s": clock() - t0}
 
 
-def bench_stream(torch, num_requests=2000, rate_hz=500.0, seed=5, budget_bytes=64 * GiB):
+def bench_stream(torch, num_requests=2000, rate_hz=500.0, seed=5, budget_bytes=64 * GiB, use_graphs=True):
     """The mixed-size request stream: batched server vs the one-at-a-time FP64 path."""
     from paper_1509_07685_amd import workloads as wl
     reqs = wl.serving_stream(num_requests, rate_hz, seed)
-    backend = GpuBackend(torch)
+    backend = GpuBackend(torch, use_graphs=use_graphs)
     sched = Scheduler(backend, budget_bytes)
     # off the clock: resident plans and executors (graphs captured) for every
     # (shape, dtype) of the stream, then one short warm-up pass
