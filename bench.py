@@ -69,18 +69,23 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_halo_gaussian_256cubed_1e
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, or None when there is none or the kernel sources have
-    changed since it was taken."""
+    WRITE_SIZE summary, or None when there is none or the kernel's source file
+    (or the shared internal header) has changed since it was taken."""
     import hashlib
     import json
     if not os.path.exists(TRAFFIC_FILE):
         return None
     doc = json.load(open(TRAFFIC_FILE))
+    sym = KERNEL_SYMBOL.get(kernel, "")
+    src = ("fft_kernels.hip" if sym.startswith("k_fft") else
+           "particle_kernels.hip" if sym in ("k_bbox", "k_geometry", "k_zero", "k_gradient") else "bin_kernels.hip")
     for f, h in doc["sources_sha256"].items():
+        if not (f.endswith(src) or f.endswith("dks_internal.h")):
+            continue
         path = os.path.join(ROOT, f)
         if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != h:
             return None
-    k = doc["kernels"].get(KERNEL_SYMBOL.get(kernel, ""))
+    k = doc["kernels"].get(sym)
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
