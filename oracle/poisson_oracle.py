@@ -8,8 +8,10 @@ HIP library.
 What it computes (paper section "FFT Based Particle-Mesh Solver", subsection
 "FFT-based Convolutions"; the open-boundary doubled grid of the same section):
 
-  1. CIC charge assignment of particles to mesh nodes (the "NGP, CIC, TSI"
-     interpolation box of the OPAL/IPPL structure figure).
+  1. Charge assignment of particles to mesh nodes (the "NGP, CIC, TSI"
+     interpolation box of the OPAL/IPPL structure figure): CIC by default,
+     nearest grid point and the triangular-shaped cloud as variants (read as
+     the second-order, 27-node scheme).
   2. The integrated Green's function (IGF): the free-space kernel 1/r of the
      equation following the convolution solution, integrated over one mesh
      cell.  Near the origin it is the third mixed difference of a closed-form
@@ -24,7 +26,12 @@ What it computes (paper section "FFT Based Particle-Mesh Solver", subsection
                            numpy.fft as a library step (Hadamard-product form).
   4. E = -grad(phi) by second-order central differences (the D-operators box
      of the structure figure).
-  5. CIC interpolation of the mesh field back to the particles.
+  5. Interpolation of the mesh field back to the particles with the same
+     weights as the assignment.
+
+The point kernel of the brute-force equation (G = 1/r times the cell volume,
+with the cell integral standing in at the singular origin) is available as
+a variant of step 2.
 
 Readings of the paper adopted where it is silent (each also listed in the
 design notes of the repository):
@@ -126,6 +133,87 @@ def _corner_weights(frac):
         for cy in (0, 1):
             for cx in (0, 1):
                 out[(cz, cy, cx)] = wz[cz] * wy[cy] * wx[cx]
+    return out
+
+
+# --------------------------------------------------------------------------
+# Assignment schemes of the interpolation box of the OPAL/IPPL structure
+# figure ("NGP, CIC, TSI"): nearest grid point, cloud in cell (linear) and
+# the triangular-shaped cloud (quadratic, 27 nodes).  The same weights assign
+# charge to the mesh and interpolate the field back.
+# --------------------------------------------------------------------------
+
+SCHEMES = ("ngp", "cic", "tsc")
+
+
+def stencil(x, y, z, n, h, origin, dtype, scheme="cic"):
+    """Assignment stencil of each particle.
+
+    Returns (inside, base[3], weights[3]): base[d] is the lowest stencil node
+    on axis d and weights[d] the list of per-offset weights (1, 2 or 3 of
+    them).  A particle is outside when s_d < 0 or s_d > n_d - 1 on any axis,
+    or when its stencil would leave the mesh (TSC needs nearest node in
+    [1, n-2]).  The nearest node is floor(s + 1/2) (halves round up).
+      ngp: weight 1 at the nearest node.
+      cic: lower node min(floor(s), n-2), weights (1-f, f).
+      tsc: d = s - nearest; weights ((1/2 - d)^2 / 2, 3/4 - d^2, (1/2 + d)^2 / 2)
+           at nearest - 1, nearest, nearest + 1.
+    """
+    if scheme not in SCHEMES:
+        raise ValueError(scheme)
+    s = [cell_coordinates(c, o, hd, dtype) for c, o, hd in zip((x, y, z), origin, h)]
+    inside = np.ones(s[0].shape, dtype=bool)
+    for d in range(3):
+        inside &= (s[d] >= 0.0) & (s[d] <= n[d] - 1)
+    near = [np.floor(sd + 0.5) for sd in s]
+    if scheme == "tsc":
+        for d in range(3):
+            inside &= (near[d] >= 1) & (near[d] <= n[d] - 2)
+    base, weights = [], []
+    for d in range(3):
+        sd = np.where(inside, s[d], 0.0)
+        if scheme == "cic":
+            i = np.minimum(np.floor(sd), n[d] - 2)
+            f = sd - i
+            base.append(i.astype(np.int64))
+            weights.append([1.0 - f, f])
+        else:
+            k = np.where(inside, near[d], 0.0)
+            if scheme == "ngp":
+                base.append(k.astype(np.int64))
+                weights.append([np.ones_like(sd)])
+            else:
+                dd = sd - k
+                base.append((k - 1).astype(np.int64))
+                weights.append([0.5 * (0.5 - dd) ** 2, 0.75 - dd * dd, 0.5 * (0.5 + dd) ** 2])
+    return inside, base, weights
+
+
+def deposit(x, y, z, q, n, h, origin, dtype=np.float64, scheme="cic"):
+    """Charge per node Q[nz, ny, nx] (coulomb) with the given scheme; (Q, n_outside)."""
+    nx, ny, nz = n
+    inside, (bx, by, bz), (wx, wy, wz) = stencil(x, y, z, n, h, origin, dtype, scheme)
+    sel = np.nonzero(inside)[0]
+    Q = np.zeros(nx * ny * nz, dtype=np.float64)
+    for cz, wzc in enumerate(wz):
+        for cy, wyc in enumerate(wy):
+            for cx, wxc in enumerate(wx):
+                node = ((bz[sel] + cz) * ny + (by[sel] + cy)) * nx + (bx[sel] + cx)
+                Q += np.bincount(node, weights=q * wzc[sel] * wyc[sel] * wxc[sel], minlength=nx * ny * nz)
+    return Q.reshape(nz, ny, nx), int(inside.size - sel.size)
+
+
+def gather(E, x, y, z, n, h, origin, dtype=np.float64, scheme="cic"):
+    """Field at the particles, sum over the stencil of weight * E(node); 0 outside."""
+    inside, (bx, by, bz), (wx, wy, wz) = stencil(x, y, z, n, h, origin, dtype, scheme)
+    out = np.zeros((3, inside.size), dtype=np.float64)
+    for cz, wzc in enumerate(wz):
+        for cy, wyc in enumerate(wy):
+            for cx, wxc in enumerate(wx):
+                w = wzc * wyc * wxc
+                for d in range(3):
+                    out[d] += w * E[d][bz + cz, by + cy, bx + cx]
+    out[:, ~inside] = 0.0
     return out
 
 
@@ -239,18 +327,42 @@ def igf_octant(n, h):
     return igf_at(a, b, c, h)
 
 
+def point_kernel_octant(n, h):
+    """The point kernel of the brute-force convolution equation, G = 1/r at the
+    node offsets times the cell volume (the equation's h_x h_y h_z factor), on
+    the octant [0, n] per axis; array [c, b, a].  G(0) is singular; the cell
+    integral G_int(0) stands in for V * G(0)."""
+    nx, ny, nz = n
+    c, b, a = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    r = np.sqrt((a * h[0]) ** 2 + (b * h[1]) ** 2 + (c * h[2]) ** 2)
+    V = h[0] * h[1] * h[2]
+    with np.errstate(divide="ignore"):
+        K = V / r
+    K[0, 0, 0] = igf_at(0, 0, 0, h)
+    return K
+
+
+def kernel_octant(n, h, green="integrated"):
+    """The convolution kernel on the octant: 'integrated' (G_int) or 'point'."""
+    if green == "integrated":
+        return igf_octant(n, h)
+    if green == "point":
+        return point_kernel_octant(n, h)
+    raise ValueError(green)
+
+
 # --------------------------------------------------------------------------
 # 3. Discrete free-space convolution on the extended box [-1, n]^3
 # --------------------------------------------------------------------------
 
-def potential_direct(rho, h):
+def potential_direct(rho, h, green="integrated"):
     """Literal double sum: phi_i = K sum_j rho_j G_int(i - j), i in [-1, n]^3.
 
     rho is [nz, ny, nx] in C/m^3; returns phi_ext [nz+2, ny+2, nx+2] in volts,
     phi_ext[k+1, j+1, i+1] = phi at node (i, j, k).  O(M^2): small meshes only.
     """
     nz, ny, nx = rho.shape
-    G = igf_octant((nx + 1, ny + 1, nz + 1), h)  # offsets up to n+1 are needed
+    G = kernel_octant((nx + 1, ny + 1, nz + 1), h, green)  # offsets up to n+1 are needed
     phi = np.zeros((nz + 2, ny + 2, nx + 2), dtype=np.float64)
     ti = np.arange(-1, nx + 1)
     tj = np.arange(-1, ny + 1)
@@ -264,17 +376,17 @@ def potential_direct(rho, h):
     return COULOMB_K * phi
 
 
-def doubled_kernel(n, h):
-    """K on the 2n grid: K[a] = G_int(min(a, 2n - a)) per axis (K[n] = G_int(n))."""
+def doubled_kernel(n, h, green="integrated"):
+    """K on the 2n grid: K[a] = G(min(a, 2n - a)) per axis (K[n] = G(n))."""
     nx, ny, nz = n
-    G = igf_octant(n, h)
+    G = kernel_octant(n, h, green)
     ax = np.minimum(np.arange(2 * nx), 2 * nx - np.arange(2 * nx))
     ay = np.minimum(np.arange(2 * ny), 2 * ny - np.arange(2 * ny))
     az = np.minimum(np.arange(2 * nz), 2 * nz - np.arange(2 * nz))
     return G[az[:, None, None], ay[None, :, None], ax[None, None, :]]
 
 
-def potential_fft(rho, h):
+def potential_fft(rho, h, green="integrated"):
     """Hadamard-product form on the zero-padded 2n grid; phi_ext on [-1, n]^3.
 
     Cyclic convolution of rho (zero-padded to 2n) with K; for target indices
@@ -282,7 +394,7 @@ def potential_fft(rho, h):
     equals the literal sum there.
     """
     nz, ny, nx = rho.shape
-    K = doubled_kernel((nx, ny, nz), h)
+    K = doubled_kernel((nx, ny, nz), h, green)
     shape = (2 * nz, 2 * ny, 2 * nx)
     Rk = np.fft.rfftn(rho, s=shape, axes=(0, 1, 2))
     Kk = np.fft.rfftn(K)
@@ -333,29 +445,31 @@ def gather_cic(E, x, y, z, n, h, origin, dtype=np.float64):
 # Whole path
 # --------------------------------------------------------------------------
 
-def solve_rho(rho, h, method="fft"):
+def solve_rho(rho, h, method="fft", green="integrated"):
     """rho [nz,ny,nx] (C/m^3) -> (phi_ext [nz+2,ny+2,nx+2], E [3,nz,ny,nx])."""
     rho = np.asarray(rho, dtype=np.float64)
-    phi_ext = potential_fft(rho, h) if method == "fft" else potential_direct(rho, h)
+    phi_ext = potential_fft(rho, h, green) if method == "fft" else potential_direct(rho, h, green)
     return phi_ext, gradient(phi_ext, h)
 
 
-def solve_particles(x, y, z, q, n, h=None, origin=None, dtype=np.float64, method="fft"):
+def solve_particles(x, y, z, q, n, h=None, origin=None, dtype=np.float64, method="fft", scheme="cic",
+                    green="integrated"):
     """Particles (SoA) of charge q each -> field at the particles.
 
     h=None selects the particle-fitted cubic mesh; otherwise h is a 3-tuple and
-    origin defaults to the mesh centred at 0.  Returns a dict with Q, rho,
-    phi_ext, E_mesh, E (3 x Np), n_outside, h, origin.
+    origin defaults to the mesh centred at 0.  scheme selects the assignment
+    (ngp, cic, tsc), green the kernel (integrated, point).  Returns a dict with
+    Q, rho, phi_ext, E_mesh, E (3 x Np), n_outside, h, origin.
     """
     if h is None:
         hc, origin = fit_mesh(x, y, z, n)
         h = (hc, hc, hc)
     elif origin is None:
         origin = centred_origin(n, h)
-    Q, n_out = deposit_cic(x, y, z, q, n, h, origin, dtype)
+    Q, n_out = deposit(x, y, z, q, n, h, origin, dtype, scheme)
     rho = Q / (h[0] * h[1] * h[2])
-    phi_ext, E_mesh = solve_rho(rho, h, method)
-    E = gather_cic(E_mesh, x, y, z, n, h, origin, dtype)
+    phi_ext, E_mesh = solve_rho(rho, h, method, green)
+    E = gather(E_mesh, x, y, z, n, h, origin, dtype, scheme)
     return dict(Q=Q, rho=rho, phi_ext=phi_ext, E_mesh=E_mesh, E=E,
                 n_outside=n_out, h=tuple(h), origin=tuple(origin))
 

@@ -436,3 +436,129 @@ def test_small_config_literal_reading_excludes_particles():
     assert out["Q"].sum() == pytest.approx(cfg.charge_per_particle * (cfg.num_particles - out["n_outside"]),
                                           rel=1e-12)
     assert np.all(out["E"][:, (np.abs(x) > 15.5e-4)] == 0.0)
+
+
+# --------------------------------------------------------------------------
+# Assignment schemes (NGP, TSC beside CIC) and the point kernel
+# --------------------------------------------------------------------------
+
+def _unit_mesh_particles(num, n, seed, margin=1.5):
+    g = np.random.default_rng(seed)
+    pts = [g.uniform(margin, n[d] - 1 - margin, num) for d in range(3)]
+    return pts
+
+
+def test_generic_cic_equals_dedicated_cic():
+    n, h = (12, 10, 9), (1.0, 1.0, 1.0)
+    x, y, z = _unit_mesh_particles(500, n, 3, margin=0.0)
+    origin = (0.0, 0.0, 0.0)
+    Q1, o1 = orc.deposit(x, y, z, 1e-12, n, h, origin, scheme="cic")
+    Q2, o2 = orc.deposit_cic(x, y, z, 1e-12, n, h, origin)
+    assert o1 == o2 == 0
+    assert np.allclose(Q1, Q2, rtol=0, atol=1e-27)
+    E = np.random.default_rng(4).standard_normal((3, n[2], n[1], n[0]))
+    assert np.allclose(orc.gather(E, x, y, z, n, h, origin, scheme="cic"),
+                       orc.gather_cic(E, x, y, z, n, h, origin), rtol=0, atol=1e-13)
+
+
+def test_tsc_weights_partition_unity_first_and_second_moment():
+    """TSC weights: sum 1, zero first moment, second moment exactly 1/4 about
+    the particle (a dropped term, a wrong sign or a shifted offset breaks one)."""
+    n, h = (16, 16, 16), (1.0, 1.0, 1.0)
+    x, y, z = _unit_mesh_particles(2000, n, 5)
+    inside, base, weights = orc.stencil(x, y, z, n, h, (0.0, 0.0, 0.0), np.float64, "tsc")
+    assert inside.all()
+    s = (x, y, z)
+    for d in range(3):
+        w = weights[d]
+        assert len(w) == 3
+        assert np.allclose(w[0] + w[1] + w[2], 1.0, atol=1e-15)
+        first = sum(w[k] * (base[d] + k - s[d]) for k in range(3))
+        second = sum(w[k] * (base[d] + k - s[d]) ** 2 for k in range(3))
+        assert np.allclose(first, 0.0, atol=1e-13)
+        assert np.allclose(second, 0.25, atol=1e-13)
+        assert np.all(np.abs(base[d] + 1 - s[d]) <= 0.5)          # centre is the nearest node
+
+
+def test_tsc_particle_on_a_node_and_ngp_nearest_node():
+    n, h = (8, 8, 8), (1.0, 1.0, 1.0)
+    Q, out = orc.deposit([3.0], [4.0], [5.0], 1.0, n, h, (0.0, 0.0, 0.0), scheme="tsc")
+    assert out == 0
+    w1 = np.array([0.125, 0.75, 0.125])
+    expect = np.zeros((8, 8, 8))
+    expect[4:7, 3:6, 2:5] = w1[:, None, None] * w1[None, :, None] * w1[None, None, :]
+    assert np.allclose(Q, expect, atol=1e-16)
+    # NGP by brute force: each particle's whole charge at round-half-up(s)
+    g = np.random.default_rng(8)
+    px, py, pz = (g.uniform(0, 7, 40) for _ in range(3))
+    px[0] = 2.5                                           # a tie goes up
+    Q, out = orc.deposit(px, py, pz, 1.0, n, h, (0.0, 0.0, 0.0), scheme="ngp")
+    ref = np.zeros((8, 8, 8))
+    for a, b, c in zip(px, py, pz):
+        ref[int(math.floor(c + 0.5)), int(math.floor(b + 0.5)), int(math.floor(a + 0.5))] += 1.0
+    assert out == 0 and np.array_equal(Q, ref)
+    assert Q[int(math.floor(pz[0] + 0.5)), int(math.floor(py[0] + 0.5)), 3] >= 1.0
+
+
+def test_tsc_inside_rule_and_charge_conservation():
+    n, h = (10, 10, 10), (1.0, 1.0, 1.0)
+    g = np.random.default_rng(9)
+    x, y, z = (g.uniform(-0.3, 9.3, 3000) for _ in range(3))
+    for scheme in orc.SCHEMES:
+        Q, out = orc.deposit(x, y, z, 2.0, n, h, (0.0, 0.0, 0.0), scheme=scheme)
+        inside, base, w = orc.stencil(x, y, z, n, h, (0.0, 0.0, 0.0), np.float64, scheme)
+        assert out == int((~inside).sum())
+        assert math.isclose(Q.sum(), 2.0 * inside.sum(), rel_tol=1e-13)
+        if scheme == "tsc":
+            near = [np.floor(c + 0.5) for c in (x, y, z)]
+            ok = np.ones(x.size, bool)
+            for d in range(3):
+                ok &= (near[d] >= 1) & (near[d] <= 8) & ((x, y, z)[d] >= 0) & ((x, y, z)[d] <= 9)
+            assert np.array_equal(inside, ok)
+
+
+def test_gather_reproduces_linear_field_cic_tsc_and_constant_ngp():
+    n, h = (12, 11, 10), (1e-3, 2e-3, 1.5e-3)
+    origin = orc.centred_origin(n, h)
+    g = np.random.default_rng(10)
+    x = origin[0] + g.uniform(1.5, n[0] - 2.5, 300) * h[0]
+    y = origin[1] + g.uniform(1.5, n[1] - 2.5, 300) * h[1]
+    z = origin[2] + g.uniform(1.5, n[2] - 2.5, 300) * h[2]
+    kk, jj, ii = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    xn, yn, zn = origin[0] + ii * h[0], origin[1] + jj * h[1], origin[2] + kk * h[2]
+    E = np.stack([3.0 * xn - 2.0 * yn + 1.0, 0.5 * zn + 4.0, -xn + yn + zn])
+    exact = np.stack([3.0 * x - 2.0 * y + 1.0, 0.5 * z + 4.0, -x + y + z])
+    for scheme in ("cic", "tsc"):
+        got = orc.gather(E, x, y, z, n, h, origin, scheme=scheme)
+        assert np.allclose(got, exact, rtol=1e-12, atol=1e-12)
+    const = np.ones((3,) + xn.shape) * np.array([1.0, -2.0, 0.5])[:, None, None, None]
+    got = orc.gather(const, x, y, z, n, h, origin, scheme="ngp")
+    assert np.allclose(got, np.array([1.0, -2.0, 0.5])[:, None], atol=1e-15)
+
+
+@pytest.mark.parametrize("R", [8, 16])
+def test_point_kernel_against_integrated_far_field(R):
+    """V/R differs from the cell integral by the cube's quadrupole-free
+    multipole term: G_int / (V / R) - 1 = -(h^4 / 960)(35 sum x^4 / R^4 - 21) / R^4."""
+    h = (1.0, 1.0, 1.0)
+    Kp = orc.point_kernel_octant((R, 1, 1), h)
+    Gi = orc.igf_octant((R, 1, 1), h)
+    assert Kp[0, 0, 0] == Gi[0, 0, 0]
+    predicted = -(1.0 / 960.0) * (35.0 - 21.0) / R ** 4
+    assert math.isclose(Gi[0, 0, R] / Kp[0, 0, R] - 1.0, predicted, rel_tol=2e-2)
+
+
+def test_point_kernel_convolution_direct_sum_and_point_charge():
+    n, h = (8, 8, 8), (1e-4, 1e-4, 1e-4)
+    rho = np.random.default_rng(11).standard_normal((8, 8, 8))
+    a = orc.potential_direct(rho, h, green="point")
+    b = orc.potential_fft(rho, h, green="point")
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) < 1e-14
+    # one charge exactly on a node: phi = q / (4 pi eps0 r) exactly at every other node
+    q = 1e-12
+    Q, _ = orc.deposit([0.0], [0.0], [0.0], q, n, h, (-3e-4, -4e-4, -2e-4), scheme="ngp")
+    phi = orc.potential_fft(Q / (h[0] * h[1] * h[2]), h, green="point")
+    kk, jj, ii = np.meshgrid(np.arange(-1, 9), np.arange(-1, 9), np.arange(-1, 9), indexing="ij")
+    r = np.sqrt(((ii - 3) * h[0]) ** 2 + ((jj - 4) * h[1]) ** 2 + ((kk - 2) * h[2]) ** 2)
+    mask = r > 0
+    assert np.allclose(phi[mask], orc.COULOMB_K * q / r[mask], rtol=1e-12)
