@@ -62,6 +62,25 @@ typedef enum {
 
 typedef enum { DKS_F32 = 0, DKS_F64 = 1 } dks_dtype;
 
+/* Kernel of the convolution (section "FFT Based Particle-Mesh Solver"):
+ *   DKS_GREEN_INTEGRATED : 1/r integrated over one mesh cell (default);
+ *   DKS_GREEN_POINT      : the brute-force equation's point kernel 1/r at the
+ *                          node offsets times the cell volume, with the cell
+ *                          integral at the singular zero offset. */
+typedef enum { DKS_GREEN_INTEGRATED = 0, DKS_GREEN_POINT = 1 } dks_green;
+
+/* Charge assignment and field interpolation (the NGP / CIC / TSI box of the
+ * OPAL structure figure):
+ *   DKS_ASSIGN_CIC : cloud in cell, 8 nodes, linear weights (default);
+ *   DKS_ASSIGN_NGP : nearest grid point, floor(s + 1/2);
+ *   DKS_ASSIGN_TSC : triangular-shaped cloud, 27 nodes, quadratic weights
+ *                    ((1/2 - d)^2 / 2, 3/4 - d^2, (1/2 + d)^2 / 2) around the
+ *                    nearest node, d = s - nearest.
+ * s = (x - x0) / h in node units.  A particle is outside the mesh when some
+ * s_d is outside [0, n_d - 1] or, for TSC, its nearest node is outside
+ * [1, n_d - 2] (the stencil must lie on the mesh). */
+typedef enum { DKS_ASSIGN_CIC = 0, DKS_ASSIGN_NGP = 1, DKS_ASSIGN_TSC = 2 } dks_assign;
+
 typedef struct dks_poisson_plan_s* dks_poisson_plan_t;
 
 /* A hipStream_t passed as an opaque pointer (NULL = default stream). */
@@ -84,6 +103,12 @@ dks_status dks_poisson_plan(int nx, int ny, int nz, double hx, double hy, double
 /* Move an explicit-h mesh: node (0,0,0) at (x0, y0, z0) metres.  Takes effect
  * from the next solve.  DKS_ESTATE on a fitted plan. */
 dks_status dks_poisson_set_origin(dks_poisson_plan_t plan, double x0, double y0, double z0);
+
+/* Select the convolution kernel and the assignment scheme (defaults:
+ * integrated kernel, CIC).  Host-only.  Changing the kernel invalidates the
+ * cached spectrum: solves return DKS_ESTATE until dks_poisson_prepare runs
+ * again.  DKS_EINVAL for an unknown value. */
+dks_status dks_poisson_set_scheme(dks_poisson_plan_t plan, dks_green green, dks_assign assign);
 
 /* Bytes of device workspace the plan needs: its resident state (Green's
  * spectrum octant, twiddle tables, geometry block) plus the scratch of one

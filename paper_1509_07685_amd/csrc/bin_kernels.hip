@@ -40,14 +40,18 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "dks_internal.h"
 
 namespace dks {
 
 constexpr int kTile = 16;          // cells per tile edge
-constexpr int kTileN = kTile + 1;  // deposit accumulator nodes per edge
-constexpr int kApron = kTile + 3;  // staged phi values per edge (nodes -1 .. 17)
+// Per tile edge: deposit accumulator nodes (the tile's stencil reach) and
+// staged phi values of the gather (one more node on each side for the
+// central differences).  CIC: 17 and 19; NGP: 16 and 18; TSC: 18 and 20.
+template <int SCH> constexpr int acc_edge() { return kTile + Scheme<SCH>::width - 1; }
+template <int SCH> constexpr int apron_edge() { return acc_edge<SCH>() + 2; }
 
 // Lanes per deposit / gather workgroup: the LDS tile bounds the workgroups
 // per CU, so wider workgroups keep more record loads in flight.
@@ -102,37 +106,44 @@ __device__ __forceinline__ BinState bin_state(char* slot_base, size_t stride, si
   return s;
 }
 
-// Cell decision of one particle: returns its tile (K if outside) and the
-// lower CIC node and fractions.
-template <typename T>
+// Cell decision of one particle: its tile (K if outside), the first node of
+// its stencil and the per-axis weights of the assignment scheme.  The tile is
+// that of the node axis_stencil files the particle under.
+template <typename T, int SCH>
 struct Cell {
   int key;
-  int jx, jy, jz;
-  T fx, fy, fz;
+  int bx, by, bz;
+  T wx[Scheme<SCH>::width], wy[Scheme<SCH>::width], wz[Scheme<SCH>::width];
 };
 
-template <typename T>
-__device__ __forceinline__ Cell<T> locate(T x, T y, T z, const Geometry* g, const MeshDims& m, const BinGeom& bg) {
-  Cell<T> c;
+template <typename T, int SCH>
+__device__ __forceinline__ Cell<T, SCH> locate(T x, T y, T z, const Geometry* g, const MeshDims& m,
+                                               const BinGeom& bg) {
+  Cell<T, SCH> c;
   const T sx = cc(x, Geo<T>::origin(g, 0), Geo<T>::inv_h(g, 0));
   const T sy = cc(y, Geo<T>::origin(g, 1), Geo<T>::inv_h(g, 1));
   const T sz = cc(z, Geo<T>::origin(g, 2), Geo<T>::inv_h(g, 2));
-  if (sx >= (T)0 && sx <= (T)(m.nx - 1) && sy >= (T)0 && sy <= (T)(m.ny - 1) && sz >= (T)0 &&
-      sz <= (T)(m.nz - 1)) {
-    c.jx = min((int)floor(sx), m.nx - 2);
-    c.jy = min((int)floor(sy), m.ny - 2);
-    c.jz = min((int)floor(sz), m.nz - 2);
-    c.fx = sx - (T)c.jx;
-    c.fy = sy - (T)c.jy;
-    c.fz = sz - (T)c.jz;
-    // cell indices are >= 0 here: unsigned division by the tile edge is a shift
-    c.key = (int)((((unsigned)c.jz / kTile) * bg.ty + ((unsigned)c.jy / kTile)) * bg.tx + ((unsigned)c.jx / kTile));
+  int kx, ky, kz;
+  const bool in = axis_stencil<T, SCH>(sx, m.nx, kx, c.wx) & axis_stencil<T, SCH>(sy, m.ny, ky, c.wy) &
+                  axis_stencil<T, SCH>(sz, m.nz, kz, c.wz);
+  if (in) {
+    // node indices are >= 0 here: unsigned division by the tile edge is a shift
+    c.key = (int)((((unsigned)kz / kTile) * bg.ty + ((unsigned)ky / kTile)) * bg.tx + ((unsigned)kx / kTile));
+    c.bx = kx + Scheme<SCH>::lo;
+    c.by = ky + Scheme<SCH>::lo;
+    c.bz = kz + Scheme<SCH>::lo;
   } else {
     c.key = bg.K;
-    c.jx = c.jy = c.jz = 0;
-    c.fx = c.fy = c.fz = (T)0;
+    c.bx = c.by = c.bz = 0;
   }
   return c;
+}
+
+// Runs f with the scheme as a compile-time constant.
+template <class F> __device__ __host__ __forceinline__ void with_scheme(int scheme, F&& f) {
+  if (scheme == kSchemeNGP) f(std::integral_constant<int, kSchemeNGP>{});
+  else if (scheme == kSchemeTSC) f(std::integral_constant<int, kSchemeTSC>{});
+  else f(std::integral_constant<int, kSchemeCIC>{});
 }
 
 // Scatter chunks: 8192 (FP32) / 4096 (FP64) consecutive particles.  The
@@ -149,7 +160,7 @@ template <typename T, int THREADS> constexpr int chunk_per() { return (int)(scat
 // c = w, w + G, ... (G = gridDim.x, a multiple of kXcd), which all fall in
 // group (b * nchunk + w) mod kXcd.
 // ---------------------------------------------------------------------------
-template <typename T, bool LDSHIST>
+template <typename T, bool LDSHIST, int SCH>
 __global__ __launch_bounds__(256) void k_bin_count(ElemBatch eb, const Geometry* geo, size_t stride, char* slot_base,
                                                    size_t bins_off, MeshDims m, BinGeom bg, int nchunk) {
   extern __shared__ unsigned hist[];
@@ -169,7 +180,7 @@ __global__ __launch_bounds__(256) void k_bin_count(ElemBatch eb, const Geometry*
   }
   for (int64_t c = blockIdx.x; c * CH < n; c += gridDim.x) {
     for_each_particle<T>(px, py, pz, c * CH, min(c * CH + CH, n), [&](T x, T y, T z, int64_t) {
-      const int key = locate<T>(x, y, z, g, m, bg).key;
+      const int key = locate<T, SCH>(x, y, z, g, m, bg).key;
       if (LDSHIST) atomicAdd(&hist[key], 1u);
       else atomicAdd(&xc[key], 1u);
     });
@@ -267,7 +278,7 @@ __device__ __forceinline__ int64_t chunk_index(bool vec, int64_t c0, int j) {
              : c0 + threadIdx.x + (int64_t)j * THREADS;
 }
 
-template <typename T, bool LDSHIST>
+template <typename T, bool LDSHIST, int SCH>
 __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, const Geometry* geo, size_t stride,
                                                                  char* slot_base, size_t bins_off,
                                                                  char* sorted_base, size_t sorted_stride,
@@ -336,7 +347,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int64_t i = chunk_index<T, kScatterThreads>(vec, c0, j);
-    key[j] = i < n ? locate<T>(xs[j], ys[j], zs[j], g, m, bg).key : -1;
+    key[j] = i < n ? locate<T, SCH>(xs[j], ys[j], zs[j], g, m, bg).key : -1;
     if (LDSHIST) rank[j] = key[j] >= 0 ? atomicAdd(&lcnt[key[j]], 1u) : 0u;
     else rank[j] = key[j] >= 0 ? atomicAdd(&cursor[key[j]], 1u) : 0u;
   }
@@ -379,12 +390,13 @@ __device__ __forceinline__ void decode_item(const BinState& st, const BinGeom& b
 // ---------------------------------------------------------------------------
 // deposit: LDS-privatised accumulation per work item, then merge.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int SCH>
 __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geometry* geo, size_t stride, char* slot_base,
                                                         size_t bins_off, const char* sorted_base,
                                                         size_t sorted_stride, T* W, size_t w_stride, MeshDims m,
                                                         BinGeom bg) {
-  __shared__ unsigned long long acc[kTileN * kTileN * kTileN];
+  constexpr int A = acc_edge<SCH>(), NN = A * A * A, WD = Scheme<SCH>::width;
+  __shared__ unsigned long long acc[NN];
   using P4 = Rec<T>;
   const int b = blockIdx.y;
   const Geometry* g = geo_of(geo, stride, b);
@@ -392,14 +404,14 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geomet
   const P4* part = reinterpret_cast<const P4*>(sorted_base + (size_t)b * sorted_stride);
   T* w = W + (size_t)b * w_stride;
   const unsigned nitems = min(st.misc[0], bg.max_items);
-  constexpr int NN = kTileN * kTileN * kTileN;
   for (unsigned t = blockIdx.x; t < nitems; t += gridDim.x) {
     int tile;
     unsigned s0, s1;
     decode_item(st, bg, t, &tile, &s0, &s1);
     if (tile == bg.K) continue;                      // outside particles deposit nothing
     const int tx = tile % bg.tx, ty = (tile / bg.tx) % bg.ty, tz = tile / (bg.tx * bg.ty);
-    const int bx = tx * kTile, by = ty * kTile, bz = tz * kTile;
+    // first node of the accumulator (the tile's first stencil node)
+    const int bx = tx * kTile + Scheme<SCH>::lo, by = ty * kTile + Scheme<SCH>::lo, bz = tz * kTile + Scheme<SCH>::lo;
     for (int e = threadIdx.x; e < NN; e += blockDim.x) acc[e] = 0ull;
     __syncthreads();
     for (unsigned i0 = s0 + threadIdx.x; i0 < s1; i0 += kUnrollDeposit * blockDim.x) {
@@ -413,20 +425,19 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geomet
       for (int u = 0; u < kUnrollDeposit; ++u) {
         if (i0 + u * blockDim.x >= s1) break;
         const P4 p = pr[u];
-        const Cell<T> c = locate<T>(p.x, p.y, p.z, g, m, bg);
-        const T gy = (T)1 - c.fy, gz = (T)1 - c.fz;
-        const T gxs = ((T)1 - c.fx) * Fixed<T>::scale, fxs = c.fx * Fixed<T>::scale;   // exact scaling
-        const T zy00 = gz * gy, zy01 = gz * c.fy, zy10 = c.fz * gy, zy11 = c.fz * c.fy;
-        unsigned long long* a = acc + ((c.jz - bz) * kTileN + (c.jy - by)) * kTileN + (c.jx - bx);
-        constexpr int SY = kTileN, SZ = kTileN * kTileN;
-        atomicAdd(a, Fixed<T>::to(zy00 * gxs));
-        atomicAdd(a + 1, Fixed<T>::to(zy00 * fxs));
-        atomicAdd(a + SY, Fixed<T>::to(zy01 * gxs));
-        atomicAdd(a + SY + 1, Fixed<T>::to(zy01 * fxs));
-        atomicAdd(a + SZ, Fixed<T>::to(zy10 * gxs));
-        atomicAdd(a + SZ + 1, Fixed<T>::to(zy10 * fxs));
-        atomicAdd(a + SZ + SY, Fixed<T>::to(zy11 * gxs));
-        atomicAdd(a + SZ + SY + 1, Fixed<T>::to(zy11 * fxs));
+        const Cell<T, SCH> c = locate<T, SCH>(p.x, p.y, p.z, g, m, bg);
+        T wxs[WD];
+#pragma unroll
+        for (int k = 0; k < WD; ++k) wxs[k] = c.wx[k] * Fixed<T>::scale;   // exact scaling
+        unsigned long long* a = acc + ((c.bz - bz) * A + (c.by - by)) * A + (c.bx - bx);
+#pragma unroll
+        for (int kz = 0; kz < WD; ++kz)
+#pragma unroll
+          for (int ky = 0; ky < WD; ++ky) {
+            const T zy = c.wz[kz] * c.wy[ky];
+#pragma unroll
+            for (int kx = 0; kx < WD; ++kx) atomicAdd(a + (kz * A + ky) * A + kx, Fixed<T>::to(zy * wxs[kx]));
+          }
       }
     }
     __syncthreads();
@@ -434,9 +445,10 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geomet
       const unsigned long long fv = acc[e];
       if (fv != 0ull) {
         const T v = Fixed<T>::from(fv);
-        const int ex = e % kTileN, ey = (e / kTileN) % kTileN, ez = e / (kTileN * kTileN);
+        const int ex = e % A, ey = (e / A) % A, ez = e / (A * A);
         const int x = bx + ex, y = by + ey, z = bz + ez;
-        if (x < m.nx && y < m.ny && z < m.nz) unsafeAtomicAdd(&w[((size_t)z * m.ny + y) * m.nx + x], v);
+        if (x >= 0 && y >= 0 && z >= 0 && x < m.nx && y < m.ny && z < m.nz)
+          unsafeAtomicAdd(&w[((size_t)z * m.ny + y) * m.nx + x], v);
       }
     }
     __syncthreads();
@@ -446,12 +458,13 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geomet
 // ---------------------------------------------------------------------------
 // gather with the central-difference field formed on the fly from staged phi.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int SCH>
 __global__ __launch_bounds__(kGatherThreads) void k_gather_binned(const Geometry* geo, size_t stride, char* slot_base,
                                                        size_t bins_off, char* sorted_base, size_t sorted_stride,
                                                        const T* __restrict__ phi_ext, size_t phi_stride,
                                                        MeshDims m, BinGeom bg) {
-  __shared__ T ph[kApron * kApron * kApron];
+  constexpr int A = apron_edge<SCH>(), NA = A * A * A, WD = Scheme<SCH>::width;
+  __shared__ T ph[NA];
   using P4 = Rec<T>;
   const int b = blockIdx.y;
   const Geometry* g = geo_of(geo, stride, b);
@@ -461,28 +474,23 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_binned(const Geometry
   const T cx = Geo<T>::grad(g, 0), cy = Geo<T>::grad(g, 1), cz = Geo<T>::grad(g, 2);
   const int nx2 = m.nx + 2, ny2 = m.ny + 2, nz2 = m.nz + 2;
   const unsigned nitems = min(st.misc[0], bg.max_items);
-  constexpr int A = kApron, NA = kApron * kApron * kApron;
   for (unsigned t = blockIdx.x; t < nitems; t += gridDim.x) {
     int tile;
     unsigned s0, s1;
     decode_item(st, bg, t, &tile, &s0, &s1);
     if (tile == bg.K) {
-      for (unsigned i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-        P4 e = part[i];
-        e.x = (T)0;
-        e.y = (T)0;
-        e.z = (T)0;
-        part[i] = e;
-      }
+      for (unsigned i = s0 + threadIdx.x; i < s1; i += blockDim.x) part[i] = P4{(T)0, (T)0, (T)0};
       continue;
     }
     const int tx = tile % bg.tx, ty = (tile / bg.tx) % bg.ty, tz = tile / (bg.tx * bg.ty);
-    const int bx = tx * kTile, by = ty * kTile, bz = tz * kTile;
-    // phi_ext indices bx .. bx + 18 hold nodes bx - 1 .. bx + 17
+    // first stencil node of the tile; staged value e holds node b? - 1 + e,
+    // which is phi_ext index b? + e (phi_ext index = node + 1)
+    const int bx = tx * kTile + Scheme<SCH>::lo, by = ty * kTile + Scheme<SCH>::lo, bz = tz * kTile + Scheme<SCH>::lo;
     for (int e = threadIdx.x; e < NA; e += blockDim.x) {
       const int ex = e % A, ey = (e / A) % A, ez = e / (A * A);
       const int x = bx + ex, y = by + ey, z = bz + ez;
-      ph[e] = (x < nx2 && y < ny2 && z < nz2) ? phi[((size_t)z * ny2 + y) * nx2 + x] : (T)0;
+      ph[e] = (x >= 0 && y >= 0 && z >= 0 && x < nx2 && y < ny2 && z < nz2) ? phi[((size_t)z * ny2 + y) * nx2 + x]
+                                                                           : (T)0;
     }
     __syncthreads();
     for (unsigned i0 = s0 + threadIdx.x; i0 < s1; i0 += kUnrollGather * blockDim.x) {
@@ -497,61 +505,72 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_binned(const Geometry
         const unsigned i = i0 + u * blockDim.x;
         if (i >= s1) break;
         const P4 p = pr[u];
-        const Cell<T> c = locate<T>(p.x, p.y, p.z, g, m, bg);
-        const T wx[2] = {(T)1 - c.fx, c.fx}, wy[2] = {(T)1 - c.fy, c.fy}, wz[2] = {(T)1 - c.fz, c.fz};
-        // staged index of node (jx, jy, jz): (node - tile base) + 1 per axis
-        const T* o = ph + ((c.jz - bz + 1) * A + (c.jy - by + 1)) * A + (c.jx - bx + 1);
-        // The 32 distinct nodes the eight central differences use: four x
-        // values per (y, z) corner row, and the y and z neighbours beyond the
-        // corner cube.
-        T r[2][2][4], ym[2][2], yp[2][2], zm[2][2], zp[2][2];
+        const Cell<T, SCH> c = locate<T, SCH>(p.x, p.y, p.z, g, m, bg);
+        // staged index of the first stencil node: (node - tile's first node) + 1 per axis
+        const T* o = ph + ((c.bz - bz + 1) * A + (c.by - by + 1)) * A + (c.bx - bx + 1);
+        T ax = 0, ay = 0, az = 0;
+        if constexpr (SCH == kSchemeCIC) {
+          const T* wx = c.wx;
+          const T* wy = c.wy;
+          const T* wz = c.wz;
+          // The 32 distinct nodes the eight central differences use: four x
+          // values per (y, z) corner row, and the y and z neighbours beyond the
+          // corner cube.
+          T r[2][2][4], ym[2][2], yp[2][2], zm[2][2], zp[2][2];
 #pragma unroll
-        for (int kz = 0; kz < 2; ++kz)
+          for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+            for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+              for (int k = 0; k < 4; ++k) r[kz][ky][k] = o[(kz * A + ky) * A + k - 1];
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int kx = 0; kx < 2; ++kx) {
+              ym[a][kx] = o[(a * A - 1) * A + kx];         // (x + kx, y - 1, z + a)
+              yp[a][kx] = o[(a * A + 2) * A + kx];         // (x + kx, y + 2, z + a)
+              zm[a][kx] = o[(-A + a) * A + kx];            // (x + kx, y + a, z - 1)
+              zp[a][kx] = o[(2 * A + a) * A + kx];         // (x + kx, y + a, z + 2)
+            }
+          // E_d = c_d * sum over the eight corners of weight * (phi(+1) - phi(-1)),
+          // the coefficient applied once at the end.
+#pragma unroll
+          for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+            for (int ky = 0; ky < 2; ++ky) {
+              const T d0 = r[kz][ky][2] - r[kz][ky][0], d1 = r[kz][ky][3] - r[kz][ky][1];
+              ax += wz[kz] * wy[ky] * (wx[0] * d0 + wx[1] * d1);
+            }
+#pragma unroll
+          for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+            for (int kx = 0; kx < 2; ++kx) {
+              const T d0 = r[kz][1][kx + 1] - ym[kz][kx], d1 = yp[kz][kx] - r[kz][0][kx + 1];
+              ay += wz[kz] * wx[kx] * (wy[0] * d0 + wy[1] * d1);
+            }
 #pragma unroll
           for (int ky = 0; ky < 2; ++ky)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) r[kz][ky][k] = o[(kz * A + ky) * A + k - 1];
+            for (int kx = 0; kx < 2; ++kx) {
+              const T d0 = r[1][ky][kx + 1] - zm[ky][kx], d1 = zp[ky][kx] - r[0][ky][kx + 1];
+              az += wy[ky] * wx[kx] * (wz[0] * d0 + wz[1] * d1);
+            }
+        } else {
+          // every stencil node: weight * (phi(+1) - phi(-1)) per axis
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+          for (int kz = 0; kz < WD; ++kz)
 #pragma unroll
-          for (int kx = 0; kx < 2; ++kx) {
-            ym[a][kx] = o[(a * A - 1) * A + kx];         // (x + kx, y - 1, z + a)
-            yp[a][kx] = o[(a * A + 2) * A + kx];         // (x + kx, y + 2, z + a)
-            zm[a][kx] = o[(-A + a) * A + kx];            // (x + kx, y + a, z - 1)
-            zp[a][kx] = o[(2 * A + a) * A + kx];         // (x + kx, y + a, z + 2)
-          }
-        // E_d = c_d * sum over the eight corners of weight * (phi(+1) - phi(-1)),
-        // the coefficient applied once at the end.
-        T ax = 0, ay = 0, az = 0;
+            for (int ky = 0; ky < WD; ++ky)
 #pragma unroll
-        for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-          for (int ky = 0; ky < 2; ++ky) {
-            const T d0 = r[kz][ky][2] - r[kz][ky][0], d1 = r[kz][ky][3] - r[kz][ky][1];
-            ax += wz[kz] * wy[ky] * (wx[0] * d0 + wx[1] * d1);
-          }
-#pragma unroll
-        for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-          for (int kx = 0; kx < 2; ++kx) {
-            const T d0 = r[kz][1][kx + 1] - ym[kz][kx], d1 = yp[kz][kx] - r[kz][0][kx + 1];
-            ay += wz[kz] * wx[kx] * (wy[0] * d0 + wy[1] * d1);
-          }
-#pragma unroll
-        for (int ky = 0; ky < 2; ++ky)
-#pragma unroll
-          for (int kx = 0; kx < 2; ++kx) {
-            const T d0 = r[1][ky][kx + 1] - zm[ky][kx], d1 = zp[ky][kx] - r[0][ky][kx + 1];
-            az += wy[ky] * wx[kx] * (wz[0] * d0 + wz[1] * d1);
-          }
-        ax *= cx;
-        ay *= cy;
-        az *= cz;
-        P4 e = p;
-        e.x = ax;
-        e.y = ay;
-        e.z = az;
-        part[i] = e;
+              for (int kx = 0; kx < WD; ++kx) {
+                const T* q = o + (kz * A + ky) * A + kx;
+                const T wgt = c.wz[kz] * c.wy[ky] * c.wx[kx];
+                ax += wgt * (q[1] - q[-1]);
+                ay += wgt * (q[A] - q[-A]);
+                az += wgt * (q[A * A] - q[-A * A]);
+              }
+        }
+        part[i] = P4{ax * cx, ay * cy, az * cz};
       }
     }
     __syncthreads();
@@ -649,12 +668,15 @@ hipError_t launch_bin_count(const ElemBatch& eb, int batch, const Geometry* geo,
   const unsigned grid = (unsigned)std::min<int64_t>(1024, (nchunk + kXcd - 1) / kXcd * kXcd);
   const bool lh = bg.lds_hist != 0;
   const size_t lds = lh ? (size_t)(bg.K + 1) * sizeof(unsigned) : 0;
-  if (lh)
-    hipLaunchKernelGGL((k_bin_count<T, true>), dim3(grid, batch), dim3(256), lds, s, eb, geo, stride,
-                       slot_base, bins_off, m, bg, (int)nchunk);
-  else
-    hipLaunchKernelGGL((k_bin_count<T, false>), dim3(grid, batch), dim3(256), 0, s, eb, geo, stride,
-                       slot_base, bins_off, m, bg, (int)nchunk);
+  with_scheme(bg.scheme, [&](auto sc) {
+    constexpr int SCH = decltype(sc)::value;
+    if (lh)
+      hipLaunchKernelGGL((k_bin_count<T, true, SCH>), dim3(grid, batch), dim3(256), lds, s, eb, geo, stride,
+                         slot_base, bins_off, m, bg, (int)nchunk);
+    else
+      hipLaunchKernelGGL((k_bin_count<T, false, SCH>), dim3(grid, batch), dim3(256), 0, s, eb, geo, stride,
+                         slot_base, bins_off, m, bg, (int)nchunk);
+  });
   return hipGetLastError();
 }
 
@@ -674,12 +696,15 @@ hipError_t launch_bin_scatter(const ElemBatch& eb, int batch, const Geometry* ge
   const unsigned nchunk = (unsigned)((eb.max_np + ch - 1) / ch);
   const bool lh = bg.lds_hist != 0;
   const size_t lds = lh ? 2 * (size_t)(bg.K + 1) * sizeof(unsigned) : 0;
-  if (lh)
-    hipLaunchKernelGGL((k_bin_scatter<T, true>), dim3(nchunk, batch), dim3(kScatterThreads), lds, s, eb, geo,
-                       stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
-  else
-    hipLaunchKernelGGL((k_bin_scatter<T, false>), dim3(nchunk, batch), dim3(kScatterThreads), 0, s, eb, geo,
-                       stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
+  with_scheme(bg.scheme, [&](auto sc) {
+    constexpr int SCH = decltype(sc)::value;
+    if (lh)
+      hipLaunchKernelGGL((k_bin_scatter<T, true, SCH>), dim3(nchunk, batch), dim3(kScatterThreads), lds, s, eb, geo,
+                         stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
+    else
+      hipLaunchKernelGGL((k_bin_scatter<T, false, SCH>), dim3(nchunk, batch), dim3(kScatterThreads), 0, s, eb, geo,
+                         stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
+  });
   return hipGetLastError();
 }
 
@@ -687,8 +712,10 @@ template <typename T>
 hipError_t launch_deposit_binned(const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                                  const char* sorted_base, size_t sorted_stride, void* W, size_t w_stride,
                                  const MeshDims& m, const BinGeom& bg, int nblk, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(k_deposit_binned<T>, dim3(nblk, batch), dim3(kDepositThreads), 0, s, geo, stride, slot_base, bins_off,
-                     sorted_base, sorted_stride, (T*)W, w_stride, m, bg);
+  with_scheme(bg.scheme, [&](auto sc) {
+    hipLaunchKernelGGL((k_deposit_binned<T, decltype(sc)::value>), dim3(nblk, batch), dim3(kDepositThreads), 0, s,
+                       geo, stride, slot_base, bins_off, sorted_base, sorted_stride, (T*)W, w_stride, m, bg);
+  });
   return hipGetLastError();
 }
 
@@ -696,8 +723,11 @@ template <typename T>
 hipError_t launch_gather_binned(const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                                 char* sorted_base, size_t sorted_stride, const void* phi_ext, size_t phi_stride,
                                 const MeshDims& m, const BinGeom& bg, int nblk, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_binned<T>, dim3(nblk, batch), dim3(kGatherThreads), 0, s, geo, stride, slot_base, bins_off,
-                     sorted_base, sorted_stride, (const T*)phi_ext, phi_stride, m, bg);
+  with_scheme(bg.scheme, [&](auto sc) {
+    hipLaunchKernelGGL((k_gather_binned<T, decltype(sc)::value>), dim3(nblk, batch), dim3(kGatherThreads), 0, s,
+                       geo, stride, slot_base, bins_off, sorted_base, sorted_stride, (const T*)phi_ext, phi_stride, m,
+                       bg);
+  });
   return hipGetLastError();
 }
 

@@ -174,6 +174,58 @@ __device__ __forceinline__ void for_each_particle(const T* __restrict__ px, cons
   for (int64_t i = i0 + threadIdx.x; i < end; i += blockDim.x) f(px[i], py[i], pz[i], i);
 }
 
+// Assignment schemes: the weights that deposit charge on the mesh and
+// interpolate the field back to the particles (the NGP / CIC / TSI
+// interpolation box of the OPAL structure figure; the third is read as the
+// second-order triangular-shaped cloud).
+enum : int { kSchemeCIC = 0, kSchemeNGP = 1, kSchemeTSC = 2 };
+template <int SCH> struct Scheme;
+// width: stencil nodes per axis; lo: first stencil node relative to the node
+// that files the particle into a tile.
+template <> struct Scheme<kSchemeCIC> { static constexpr int width = 2, lo = 0; };
+template <> struct Scheme<kSchemeNGP> { static constexpr int width = 1, lo = 0; };
+template <> struct Scheme<kSchemeTSC> { static constexpr int width = 3, lo = -1; };
+
+// One axis of a particle's stencil, for its cell coordinate s on n nodes.
+// Returns false when the particle is outside on this axis: s outside
+// [0, n - 1], or (TSC) a nearest node outside [1, n - 2].  node is the lower
+// node of the cell (CIC, min(floor(s), n - 2)) or the nearest node
+// floor(s + 1/2) (NGP, TSC); the stencil covers node + lo ...
+// node + lo + width - 1 with weights w:
+//   CIC  (1 - f, f),                     f = s - node
+//   NGP  (1)
+//   TSC  ((1/2 - d)^2 / 2, 3/4 - d^2, (1/2 + d)^2 / 2),   d = s - node
+// s + 1/2 and s - node are exact in the dtype for the node counts here.
+template <typename T, int SCH>
+__device__ __forceinline__ bool axis_stencil(T s, int n, int& node, T* w) {
+  if (!(s >= (T)0 && s <= (T)(n - 1))) {
+    node = 0;
+#pragma unroll
+    for (int k = 0; k < Scheme<SCH>::width; ++k) w[k] = (T)0;
+    return false;
+  }
+  if constexpr (SCH == kSchemeCIC) {
+    node = min((int)floor(s), n - 2);
+    const T f = s - (T)node;
+    w[0] = (T)1 - f;
+    w[1] = f;
+    return true;
+  } else {
+    node = (int)floor(s + (T)0.5);
+    if constexpr (SCH == kSchemeNGP) {
+      w[0] = (T)1;
+      return true;
+    } else {
+      const T d = s - (T)node;
+      const T a = (T)0.5 - d, c = (T)0.5 + d;
+      w[0] = (T)0.5 * a * a;
+      w[1] = (T)0.75 - d * d;
+      w[2] = (T)0.5 * c * c;
+      return node >= 1 && node <= n - 2;
+    }
+  }
+}
+
 // Arguments of the per-solve geometry kernel.
 struct GeoArgs {
   int n[3];
@@ -194,6 +246,7 @@ struct BinGeom {
   int lds_hist;        // 1: per-block tile histograms fit in LDS
   unsigned max_items;  // bound on the work-item count of one solve
   unsigned max_np;     // bound on binned particles per element (buffer size)
+  int scheme;          // kSchemeCIC / kSchemeNGP / kSchemeTSC
 };
 
 // Binning counts and reserves per XCD group: the scatter's chunk c of batch

@@ -61,7 +61,7 @@ __device__ __forceinline__ double anti(double x, double y, double z) {
 
 // G[c][b][a] for a <= nx, b <= ny, c <= nz (FP64).
 __global__ __launch_bounds__(256) void k_igf_octant(double* G, int nx, int ny, int nz, double hx, double hy,
-                                                    double hz, GLBands gl) {
+                                                    double hz, GLBands gl, int point) {
   const long long total = (long long)(nx + 1) * (ny + 1) * (nz + 1);
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
@@ -71,6 +71,11 @@ __global__ __launch_bounds__(256) void k_igf_octant(double* G, int nx, int ny, i
   const int c = (int)(rem / (ny + 1));
   const double hmax = fmax(hx, fmax(hy, hz));
   const double X = a * hx, Y = b * hy, Z = c * hz;
+  if (point && (a | b | c)) {
+    // point kernel of the brute-force convolution: the cell volume over r
+    G[e] = hx * hy * hz / sqrt(X * X + Y * Y + Z * Z);
+    return;
+  }
   const double D = sqrt(X * X + Y * Y + Z * Z) / hmax;
   double g;
   if (D < gl.lo[0]) {
@@ -212,10 +217,11 @@ hipError_t launch_twiddle_line(void* out, int N, int count, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_igf_octant(double* G, const int n[3], const double h[3], const GLBands& gl, hipStream_t s) {
+hipError_t launch_igf_octant(double* G, const int n[3], const double h[3], const GLBands& gl, int point,
+                             hipStream_t s) {
   const long long total = (long long)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
   hipLaunchKernelGGL(k_igf_octant, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, G, n[0], n[1], n[2],
-                     h[0], h[1], h[2], gl);
+                     h[0], h[1], h[2], gl, point);
   return hipGetLastError();
 }
 

@@ -5,6 +5,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "dks_internal.h"
 
 namespace dks {
@@ -209,34 +211,32 @@ __global__ __launch_bounds__(256) void k_gradient(const T* __restrict__ phi, T* 
 // CIC gather of a [3][nz][ny][nx] mesh field at unsorted particles (the
 // stand-alone gather entry point).  Outside particles receive 0.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int SCH>
 __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ E, const T* __restrict__ px,
                                                 const T* __restrict__ py, const T* __restrict__ pz,
                                                 T* __restrict__ qx, T* __restrict__ qy, T* __restrict__ qz,
                                                 int64_t n, const Geometry* g, MeshDims m) {
+  constexpr int WD = Scheme<SCH>::width;
   const T ox = Geo<T>::origin(g, 0), oy = Geo<T>::origin(g, 1), oz = Geo<T>::origin(g, 2);
   const T ix = Geo<T>::inv_h(g, 0), iy = Geo<T>::inv_h(g, 1), iz = Geo<T>::inv_h(g, 2);
   const int nx = m.nx, ny = m.ny, nz = m.nz;
-  const T ux = (T)(nx - 1), uy = (T)(ny - 1), uz = (T)(nz - 1);
   const size_t total = (size_t)nx * ny * nz;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const T sx = cell_coord(px[i], ox, ix);
-    const T sy = cell_coord(py[i], oy, iy);
-    const T sz = cell_coord(pz[i], oz, iz);
+    T wx[WD], wy[WD], wz[WD];
+    int kx, ky, kz;
+    const bool in = axis_stencil<T, SCH>(cell_coord(px[i], ox, ix), nx, kx, wx) &
+                    axis_stencil<T, SCH>(cell_coord(py[i], oy, iy), ny, ky, wy) &
+                    axis_stencil<T, SCH>(cell_coord(pz[i], oz, iz), nz, kz, wz);
     T ax = 0, ay = 0, az = 0;
-    if (sx >= (T)0 && sx <= ux && sy >= (T)0 && sy <= uy && sz >= (T)0 && sz <= uz) {
-      const int jx = min((int)floor(sx), nx - 2);
-      const int jy = min((int)floor(sy), ny - 2);
-      const int jz = min((int)floor(sz), nz - 2);
-      const T fx = sx - (T)jx, fy = sy - (T)jy, fz = sz - (T)jz;
-      const T wx[2] = {(T)1 - fx, fx}, wy[2] = {(T)1 - fy, fy}, wz[2] = {(T)1 - fz, fz};
+    if (in) {
+      const int bx = kx + Scheme<SCH>::lo, by = ky + Scheme<SCH>::lo, bz = kz + Scheme<SCH>::lo;
 #pragma unroll
-      for (int cz = 0; cz < 2; ++cz)
+      for (int cz = 0; cz < WD; ++cz)
 #pragma unroll
-        for (int cy = 0; cy < 2; ++cy)
+        for (int cy = 0; cy < WD; ++cy)
 #pragma unroll
-          for (int cx = 0; cx < 2; ++cx) {
-            const size_t node = ((size_t)(jz + cz) * ny + (jy + cy)) * nx + (jx + cx);
+          for (int cx = 0; cx < WD; ++cx) {
+            const size_t node = ((size_t)(bz + cz) * ny + (by + cy)) * nx + (bx + cx);
             const T wgt = wz[cz] * wy[cy] * wx[cx];
             ax += wgt * E[node];
             ay += wgt * E[total + node];
@@ -295,10 +295,15 @@ hipError_t launch_gradient(const void* phi, void* out, const Geometry* g, const 
 
 template <typename T>
 hipError_t launch_gather(const void* E, const void* x, const void* y, const void* z, void* ex, void* ey, void* ez,
-                         int64_t n, const Geometry* g, const MeshDims& m, hipStream_t s) {
+                         int64_t n, const Geometry* g, const MeshDims& m, int scheme, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather<T>, dim3(grid_for(n, 65535u * 4)), dim3(256), 0, s, (const T*)E, (const T*)x,
-                     (const T*)y, (const T*)z, (T*)ex, (T*)ey, (T*)ez, n, g, m);
+  auto go = [&](auto sc) {
+    hipLaunchKernelGGL((k_gather<T, decltype(sc)::value>), dim3(grid_for(n, 65535u * 4)), dim3(256), 0, s,
+                       (const T*)E, (const T*)x, (const T*)y, (const T*)z, (T*)ex, (T*)ey, (T*)ez, n, g, m);
+  };
+  if (scheme == kSchemeNGP) go(std::integral_constant<int, kSchemeNGP>{});
+  else if (scheme == kSchemeTSC) go(std::integral_constant<int, kSchemeTSC>{});
+  else go(std::integral_constant<int, kSchemeCIC>{});
   return hipGetLastError();
 }
 
@@ -308,7 +313,7 @@ hipError_t launch_gather(const void* E, const void* x, const void* y, const void
                                                    hipStream_t);                                             \
   template hipError_t launch_gradient<T>(const void*, void*, const Geometry*, const MeshDims&, hipStream_t); \
   template hipError_t launch_gather<T>(const void*, const void*, const void*, const void*, void*, void*,     \
-                                       void*, int64_t, const Geometry*, const MeshDims&, hipStream_t);
+                                       void*, int64_t, const Geometry*, const MeshDims&, int, hipStream_t);
 DKS_INSTANTIATE(float)
 DKS_INSTANTIATE(double)
 #undef DKS_INSTANTIATE

@@ -37,7 +37,7 @@ template <typename T> hipError_t launch_weights_to_density(const void*, void*, s
                                                            hipStream_t);
 template <typename T> hipError_t launch_gradient(const void*, void*, const Geometry*, const MeshDims&, hipStream_t);
 template <typename T> hipError_t launch_gather(const void*, const void*, const void*, const void*, void*, void*,
-                                               void*, int64_t, const Geometry*, const MeshDims&, hipStream_t);
+                                               void*, int64_t, const Geometry*, const MeshDims&, int, hipStream_t);
 template <typename T> hipError_t launch_bin_count(const ElemBatch&, int, const Geometry*, size_t, char*, size_t,
                                                   const MeshDims&, const BinGeom&, int, hipStream_t);
 hipError_t launch_bin_scan(const Geometry*, size_t, char*, size_t, const BinGeom&, const ElemBatch&, int,
@@ -54,7 +54,7 @@ template <typename T> hipError_t launch_gather_binned(const Geometry*, size_t, c
 template <typename T> hipError_t launch_unsort(const ElemBatch&, int, const char*, size_t, size_t, hipStream_t);
 template <typename T> hipError_t launch_twiddle_pass(void*, int, int, hipStream_t);
 template <typename T> hipError_t launch_twiddle_line(void*, int, int, hipStream_t);
-hipError_t launch_igf_octant(double*, const int*, const double*, const GLBands&, hipStream_t);
+hipError_t launch_igf_octant(double*, const int*, const double*, const GLBands&, int, hipStream_t);
 hipError_t launch_cos_matrix(double*, int, hipStream_t);
 hipError_t launch_apply_axis(const double*, double*, const double*, const int*, int, hipStream_t);
 template <typename T> hipError_t launch_green_pack(const double*, void*, const int*, int, int, double, hipStream_t);
@@ -163,6 +163,7 @@ struct dks_poisson_plan_s {
   double origin[3];
   bool fitted;
   dks_dtype dtype;
+  int green;        // dks_green: kernel of the convolution
   size_t rsize;     // sizeof(real)
   size_t csize;     // sizeof(complex)
   MeshDims md;
@@ -315,9 +316,9 @@ void layout(dks_poisson_plan_s* p) {
   const size_t r2 = std::max({B, D, G64});
   const size_t r3 = std::max({p->bytes_W, p->bytes_phi_ext, COS + 256});
   BinGeom& bg = p->bg;
-  bg.tx = (nx - 1 + 15) / 16;    // cells per axis = n - 1, 16 per tile
-  bg.ty = (ny - 1 + 15) / 16;
-  bg.tz = (nz - 1 + 15) / 16;
+  bg.tx = (nx + 15) / 16;        // 16 nodes per tile edge (CIC files by cell, NGP/TSC by node)
+  bg.ty = (ny + 15) / 16;
+  bg.tz = (nz + 15) / 16;
   bg.K = bg.tx * bg.ty * bg.tz;
   bg.item = 65536;
   bg.lds_hist = 2 * (size_t)(bg.K + 1) * sizeof(unsigned) <= 65536 ? 1 : 0;
@@ -485,7 +486,7 @@ dks_status prepare_t(dks_poisson_plan_s* p, hipStream_t st) {
   cos_axis[2] = cos_axis[1] + (size_t)(p->n[1] + 1) * (p->n[1] + 1);
   const double hg[3] = {p->fitted ? 1.0 : p->h[0], p->fitted ? 1.0 : p->h[1], p->fitted ? 1.0 : p->h[2]};
   const GLBands gl = make_bands();
-  DKS_CK(launch_igf_octant(g1, p->n, hg, gl, st));
+  DKS_CK(launch_igf_octant(g1, p->n, hg, gl, p->green == DKS_GREEN_POINT ? 1 : 0, st));
   for (int d = 0; d < 3; ++d) DKS_CK(launch_cos_matrix(cos_axis[d], p->n[d], st));
   DKS_CK(launch_apply_axis(g1, g2, cos_axis[0], p->n, 0, st));
   DKS_CK(launch_apply_axis(g2, g1, cos_axis[1], p->n, 1, st));
@@ -585,6 +586,18 @@ dks_status dks_poisson_set_origin(dks_poisson_plan_t p, double x0, double y0, do
   p->origin[0] = x0;
   p->origin[1] = y0;
   p->origin[2] = z0;
+  return DKS_OK;
+}
+
+dks_status dks_poisson_set_scheme(dks_poisson_plan_t p, dks_green green, dks_assign assign) {
+  if (!p) return DKS_EINVAL;
+  if (green != DKS_GREEN_INTEGRATED && green != DKS_GREEN_POINT) return DKS_EINVAL;
+  if (assign != DKS_ASSIGN_CIC && assign != DKS_ASSIGN_NGP && assign != DKS_ASSIGN_TSC) return DKS_EINVAL;
+  if ((int)green != p->green) {
+    p->green = (int)green;
+    p->prepared = false;           // the spectrum must be rebuilt
+  }
+  p->bg.scheme = assign == DKS_ASSIGN_NGP ? kSchemeNGP : assign == DKS_ASSIGN_TSC ? kSchemeTSC : kSchemeCIC;
   return DKS_OK;
 }
 
@@ -747,8 +760,8 @@ dks_status dks_poisson_gather(dks_poisson_plan_t p, const void* E_mesh, const vo
     return DKS_ESTATE;
   }
   if (p->dtype == DKS_F32)
-    return hip_status(launch_gather<float>(E_mesh, x, y, z, Ex, Ey, Ez, np, sl.geo(), p->md, st));
-  return hip_status(launch_gather<double>(E_mesh, x, y, z, Ex, Ey, Ez, np, sl.geo(), p->md, st));
+    return hip_status(launch_gather<float>(E_mesh, x, y, z, Ex, Ey, Ez, np, sl.geo(), p->md, p->bg.scheme, st));
+  return hip_status(launch_gather<double>(E_mesh, x, y, z, Ex, Ey, Ez, np, sl.geo(), p->md, p->bg.scheme, st));
 }
 
 dks_status dks_poisson_geometry(dks_poisson_plan_t p, dks_stream_t stream, double* h, double* origin) {

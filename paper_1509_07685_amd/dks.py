@@ -21,9 +21,16 @@ DKS_EWORKSPACE = -5
 DKS_ESTATE = -6
 DKS_F32 = 0
 DKS_F64 = 1
+DKS_GREEN_INTEGRATED = 0
+DKS_GREEN_POINT = 1
+DKS_ASSIGN_CIC = 0
+DKS_ASSIGN_NGP = 1
+DKS_ASSIGN_TSC = 2
+GREENS = {"integrated": DKS_GREEN_INTEGRATED, "point": DKS_GREEN_POINT}
+SCHEMES = {"cic": DKS_ASSIGN_CIC, "ngp": DKS_ASSIGN_NGP, "tsc": DKS_ASSIGN_TSC}
 
 EXPORTS = (
-    "dks_poisson_plan", "dks_poisson_set_origin", "dks_poisson_workspace_bytes",
+    "dks_poisson_plan", "dks_poisson_set_origin", "dks_poisson_set_scheme", "dks_poisson_workspace_bytes",
     "dks_poisson_batch_scratch_bytes", "dks_poisson_particle_scratch_bytes",
     "dks_poisson_set_particle_scratch", "dks_poisson_set_workspace", "dks_poisson_prepare",
     "dks_poisson_solve_rho", "dks_poisson_solve_particles", "dks_poisson_solve_particles_batched",
@@ -56,6 +63,7 @@ _PLAN = ctypes.c_void_p
 _SIGS = {
     "dks_poisson_plan": (_i, [_i, _i, _i, _d, _d, _d, _i, ctypes.POINTER(_PLAN)]),
     "dks_poisson_set_origin": (_i, [_PLAN, _d, _d, _d]),
+    "dks_poisson_set_scheme": (_i, [_PLAN, _i, _i]),
     "dks_poisson_workspace_bytes": (_i, [_PLAN, ctypes.POINTER(_sz)]),
     "dks_poisson_batch_scratch_bytes": (_i, [_PLAN, _i, _i64, ctypes.POINTER(_sz)]),
     "dks_poisson_particle_scratch_bytes": (_i, [_PLAN, _i64, ctypes.POINTER(_sz)]),
@@ -102,6 +110,10 @@ def dks_poisson_plan(nx, ny, nz, hx, hy, hz, dtype):
 
 def dks_poisson_set_origin(plan, x0, y0, z0):
     _check(_lib.dks_poisson_set_origin(plan, x0, y0, z0), "dks_poisson_set_origin")
+
+
+def dks_poisson_set_scheme(plan, green, assign):
+    _check(_lib.dks_poisson_set_scheme(plan, green, assign), "dks_poisson_set_scheme")
 
 
 def dks_poisson_workspace_bytes(plan):
@@ -246,10 +258,12 @@ class PoissonPlan:
     """A plan plus its torch-allocated device workspace.
 
     n = (nx, ny, nz) nodes; h = (hx, hy, hz) metres or None for the
-    particle-fitted cubic mesh; dtype "f32"/"f64" (or torch dtype).
+    particle-fitted cubic mesh; dtype "f32"/"f64" (or torch dtype); scheme
+    "cic"/"ngp"/"tsc"; green "integrated"/"point".
     """
 
-    def __init__(self, n, h=None, dtype="f32", device="cuda", stream=None, prepare=True):
+    def __init__(self, n, h=None, dtype="f32", device="cuda", stream=None, prepare=True, scheme="cic",
+                 green="integrated"):
         torch = _torch()
         self.n = tuple(int(v) for v in n)
         self.fitted = h is None
@@ -257,6 +271,7 @@ class PoissonPlan:
         self.code, self.dtype = _dtype_code(dtype)
         self.device = torch.device(device)
         self.handle = dks_poisson_plan(*self.n, *self.h, self.code)
+        dks_poisson_set_scheme(self.handle, GREENS[green], SCHEMES[scheme])
         self.workspace_bytes = dks_poisson_workspace_bytes(self.handle)
         self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
         dks_poisson_set_workspace(self.handle, _ptr(self.workspace), self.workspace_bytes)

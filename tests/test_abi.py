@@ -113,6 +113,12 @@ def test_workspace_and_state_checks(dks):
         assert lib.dks_poisson_set_workspace(plan, fake, nbytes) == dks.DKS_OK
         assert lib.dks_poisson_solve_particles(plan, fake, fake, fake, 40, 1e-15, fake, fake, fake,
                                                None, None, None) == dks.DKS_EWORKSPACE
+        # scheme selection: unknown values refused; a new kernel needs a new prepare
+        assert lib.dks_poisson_set_scheme(plan, 2, 0) == dks.DKS_EINVAL
+        assert lib.dks_poisson_set_scheme(plan, 0, 3) == dks.DKS_EINVAL
+        assert lib.dks_poisson_set_scheme(None, 0, 0) == dks.DKS_EINVAL
+        assert lib.dks_poisson_set_scheme(plan, dks.DKS_GREEN_POINT, dks.DKS_ASSIGN_TSC) == dks.DKS_OK
+        assert lib.dks_poisson_set_scheme(plan, dks.DKS_GREEN_INTEGRATED, dks.DKS_ASSIGN_CIC) == dks.DKS_OK
         # attached but not prepared: solves are refused before touching the device
         assert lib.dks_poisson_solve_rho(plan, fake, fake, None, None) == dks.DKS_ESTATE
         assert lib.dks_poisson_solve_particles(plan, fake, fake, fake, 10, 1e-15, fake, fake, fake,

@@ -459,3 +459,94 @@ def test_unaligned_particle_arrays_give_identical_results(dt):
     assert rel_l2(e1, e0) <= (1e-14 if dt == "f64" else 1e-6)
     ref = orc.solve_particles(x, y, z, q, n, dtype=NP_DT[dt])
     assert rel_l2(e0, ref["E"]) <= TOL[dt]
+
+
+# --------------------------------------------------------------------------
+# Assignment schemes (NGP, TSC) and the point kernel
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme", ["ngp", "tsc"])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_scheme_full_step_explicit_mesh(scheme, dt):
+    """Explicit 32^3 mesh that leaves about a third of the bunch outside: the
+    scheme's inside rule, deposit, solve and gather against the oracle."""
+    cfg = wl.SMALL_GAUSSIAN
+    x, y, z = wl.particles_for(cfg, dtype=dt)
+    q = cfg.charge_per_particle
+    plan = dks().PoissonPlan(cfg.n, cfg.h, dt, scheme=scheme)
+    (Ex, Ey, Ez), phi, cnt = plan.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), q, want_phi=True)
+    ref = orc.solve_particles(x, y, z, q, cfg.n, cfg.h, dtype=NP_DT[dt], scheme=scheme)
+    assert int(host(cnt)[0]) == ref["n_outside"] > 0
+    assert rel_l2(host(phi), ref["phi_ext"][1:-1, 1:-1, 1:-1]) <= TOL[dt]
+    assert rel_l2(np.stack([host(Ex), host(Ey), host(Ez)]), ref["E"]) <= TOL[dt]
+
+
+@pytest.mark.parametrize("scheme", ["ngp", "tsc"])
+def test_scheme_fitted_mesh_tiles_and_deposit(scheme):
+    """Fitted 48^3 mesh (three tiles per axis) with 2e5 particles: deposit and
+    the full step against the oracle in FP64."""
+    dt = "f64"
+    n = (48, 48, 48)
+    x, y, z = wl.gaussian_bunch(200_000, (1e-3, 0.8e-3, 1.3e-3), 61, np.float64)
+    q = 1e-14
+    plan = dks().PoissonPlan(n, None, dt, scheme=scheme)
+    rho, cnt = plan.deposit(dev(x, dt), dev(y, dt), dev(z, dt), q)
+    hc, origin = orc.fit_mesh(x, y, z, n)
+    Q, n_out = orc.deposit(x, y, z, q, n, (hc,) * 3, origin, np.float64, scheme)
+    assert n_out == 0 and int(host(cnt)[0]) == 0
+    assert rel_l2(host(rho), Q / hc ** 3) <= TOL[dt]
+    (Ex, Ey, Ez), _, _ = plan.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), q)
+    ref = orc.solve_particles(x, y, z, q, n, dtype=np.float64, scheme=scheme)
+    assert rel_l2(np.stack([host(Ex), host(Ey), host(Ez)]), ref["E"]) <= TOL[dt]
+
+
+@pytest.mark.parametrize("scheme", ["ngp", "tsc"])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_scheme_standalone_gather(scheme, dt):
+    n, h = (24, 18, 27), (1e-4, 1.2e-4, 0.8e-4)
+    origin = orc.centred_origin(n, h)
+    g = np.random.default_rng(62)
+    E = g.standard_normal((3, n[2], n[1], n[0]))
+    x = (origin[0] + g.uniform(-1, n[0], 4000) * h[0]).astype(NP_DT[dt])
+    y = (origin[1] + g.uniform(-1, n[1], 4000) * h[1]).astype(NP_DT[dt])
+    z = (origin[2] + g.uniform(-1, n[2], 4000) * h[2]).astype(NP_DT[dt])
+    plan = dks().PoissonPlan(n, h, dt, scheme=scheme)
+    got = np.stack([host(t) for t in plan.gather(dev(E, dt), dev(x, dt), dev(y, dt), dev(z, dt))])
+    ref = orc.gather(E, x, y, z, n, h, origin, NP_DT[dt], scheme)
+    assert rel_l2(got, ref) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_point_kernel_solve_rho(dt):
+    n, h = (24, 16, 18), (1e-4, 1.5e-4, 1e-4)
+    rho = np.random.default_rng(63).standard_normal((n[2], n[1], n[0]))
+    plan = dks().PoissonPlan(n, h, dt, green="point")
+    phi, E = plan.solve_rho(dev(rho, dt))
+    ref_phi, ref_E = orc.solve_rho(rho, h, green="point")
+    assert rel_l2(host(phi), ref_phi[1:-1, 1:-1, 1:-1]) <= TOL[dt]
+    assert rel_l2(host(E), ref_E) <= TOL[dt]
+    # and it differs from the integrated kernel (a wrong switch would pass above only by accident)
+    int_phi, _ = orc.solve_rho(rho, h)
+    assert rel_l2(int_phi, ref_phi) > 1e-4
+
+
+def test_point_kernel_fitted_particle_step_and_scheme_switch():
+    """Point kernel on a fitted mesh (unit-spacing spectrum rescaled per
+    solve) with TSC; then switching the same plan back to the integrated
+    kernel requires a new prepare."""
+    dt = "f64"
+    n = (32, 32, 32)
+    x, y, z = wl.gaussian_bunch(50_000, (1e-3, 1e-3, 1e-3), 64, np.float64)
+    q = 2e-14
+    d = dks()
+    plan = d.PoissonPlan(n, None, dt, scheme="tsc", green="point")
+    (Ex, Ey, Ez), _, _ = plan.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), q)
+    ref = orc.solve_particles(x, y, z, q, n, dtype=np.float64, scheme="tsc", green="point")
+    assert rel_l2(np.stack([host(Ex), host(Ey), host(Ez)]), ref["E"]) <= TOL[dt]
+    d.dks_poisson_set_scheme(plan.handle, d.DKS_GREEN_INTEGRATED, d.DKS_ASSIGN_CIC)
+    with pytest.raises(d.DKSError):
+        plan.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), q)
+    plan.prepare()
+    (Ex, Ey, Ez), _, _ = plan.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), q)
+    ref = orc.solve_particles(x, y, z, q, n, dtype=np.float64)
+    assert rel_l2(np.stack([host(Ex), host(Ey), host(Ez)]), ref["E"]) <= TOL[dt]
