@@ -108,6 +108,46 @@ def time_loop(torch, fn, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
+def host_offload(torch, dks, n, dtype="f32", solves=20):
+    """Host-resident solves at mesh n: rho from page-locked host memory, phi
+    (and optionally E) back to host memory, transfer-inclusive.  One at a
+    time (issue, wait: latency p50/p99) and pipelined (all issued back to
+    back: throughput), next to the device-resident solve."""
+    import numpy as np
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    plan = dks.PoissonPlan(n, (1e-5, 1e-5, 1e-5), dtype)
+    shape = plan.mesh_shape()
+    rhos = [torch.rand(shape, dtype=tdt).pin_memory() for _ in range(4)]
+    phis = [torch.empty(shape, dtype=tdt).pin_memory() for _ in range(4)]
+    Es = [torch.empty((3,) + shape, dtype=tdt).pin_memory() for _ in range(4)]
+    out = {"mesh": list(n), "dtype": dtype, "solves": solves,
+           "mesh_bytes": int(np.prod(n)) * (4 if dtype == "f32" else 8)}
+    rho_d = rhos[0].cuda()
+    out["device_resident_ms"] = time_loop(torch, lambda: plan.solve_rho(rho_d, want_E=False), 10, 2)
+    for with_E in (False, True):
+        tag = "phi_E" if with_E else "phi"
+        for i in range(3):   # warm-up
+            plan.host_wait(plan.solve_rho_host(rhos[i % 4], phis[i % 4], Es[i % 4] if with_E else None))
+        lat = []
+        for i in range(solves):
+            t0 = time.perf_counter()
+            plan.host_wait(plan.solve_rho_host(rhos[i % 4], phis[i % 4], Es[i % 4] if with_E else None))
+            lat.append((time.perf_counter() - t0) * 1e3)
+        t0 = time.perf_counter()
+        last = None
+        for i in range(solves):
+            last = plan.solve_rho_host(rhos[i % 4], phis[i % 4], Es[i % 4] if with_E else None)
+        plan.host_wait(last)
+        pipe_ms = (time.perf_counter() - t0) * 1e3 / solves
+        lat = np.array(lat)
+        out[tag] = {"one_at_a_time_p50_ms": float(np.percentile(lat, 50)),
+                    "one_at_a_time_p99_ms": float(np.percentile(lat, 99)),
+                    "pipelined_ms_per_solve": pipe_ms, "pipelined_solves_per_s": 1e3 / pipe_ms,
+                    "pipelined_mesh_pts_per_s": float(np.prod(n)) / (pipe_ms * 1e-3)}
+    plan.close()
+    return out
+
+
 def cpu_baseline():
     """The oracle as it stands on a bounded sample: the full particle step on a
     128^3 fitted mesh with 1.25e7 particles of the same halo-Gaussian bunch
@@ -209,7 +249,22 @@ def main():
 
     extra = {}
     if not args.no_extra:
-        del tx, ty, tz, out, bufs
+        # the same full step with the other assignment schemes and the point kernel
+        variants = {}
+        for green, scheme in (("integrated", "ngp"), ("integrated", "tsc"), ("point", "cic")):
+            dks.dks_poisson_set_scheme(plan.handle, dks.GREENS[green], dks.SCHEMES[scheme])
+            plan.prepare()
+            dks.dks_timing_enable(True)
+            ms = time_loop(torch, step, 10, 2)
+            kk = dks.dks_timing_read()
+            dks.dks_timing_enable(False)
+            variants[f"{scheme}_{green}"] = {
+                "ms_per_step": ms, "mesh_pts_per_s": mesh_pts / (ms * 1e-3),
+                "kernel_ms": {k: kk[k][1] / kk[k][0] for k in ("bin_scatter", "deposit", "gather", "unsort")
+                              if k in kk}}
+        dks.dks_poisson_set_scheme(plan.handle, dks.DKS_GREEN_INTEGRATED, dks.DKS_ASSIGN_CIC)
+        extra["variants"] = variants
+        del tx, ty, tz, out, bufs, plan
         torch.cuda.empty_cache()
         # mesh-only solves (rho -> phi and E) at 256^3 in FP32 and FP64
         for dt_name, tdt in (("f32", torch.float32), ("f64", torch.float64)):
@@ -228,6 +283,8 @@ def main():
                                          "conv_frac": conv_bytes(n, s) / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS}
             del mp, rho, phi
             torch.cuda.empty_cache()
+        extra["host_offload"] = host_offload(torch, dks, n)
+        torch.cuda.empty_cache()
         try:
             from paper_1509_07685_amd import serve
             extra["serving"] = serve.bench_stream(torch)

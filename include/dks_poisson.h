@@ -24,8 +24,9 @@
  *    DKS_F64).  Every host scalar is double.  Units are SI (m, C, V, V/m).
  *  - Streams: every device operation is enqueued asynchronously on the
  *    caller's stream (NULL = the default stream), with no host
- *    synchronisation, so a solve can be captured into a HIP graph.  The only
- *    exception is dks_poisson_geometry, which synchronises the stream.
+ *    synchronisation, so a solve can be captured into a HIP graph.  The
+ *    exceptions are dks_poisson_geometry, which synchronises the stream, and
+ *    the host-resident solves, whose copies run on streams of the plan.
  *  - Mesh: node (i, j, k) sits at origin + (i hx, j hy, k hz).  An
  *    explicit-h plan is centred at 0 unless dks_poisson_set_origin moves it.
  *    A fitted plan (hx = hy = hz = 0) re-fits a cubic mesh to the particles
@@ -252,7 +253,55 @@ dks_status dks_timing_enable(int enable);
  * DKS_EINVAL if capacity is too small (then *count is the number needed). */
 dks_status dks_timing_read(dks_kernel_time* out, int capacity, int* count);
 
-/* Release the plan's host state.  Does not touch the caller's workspace. */
+/* Host-resident offload (the paper's sequence diagram of the FFT Poisson
+ * solver: the density is sent from the host, the potential comes back, and
+ * streams overlap transfers with kernels).  rho comes from host memory and
+ * phi / E go back to host memory.  Two device copies of the input and of the
+ * outputs (the staging area) let solve k+1's upload and solve k-1's download
+ * run on their own copy streams while solve k computes on the caller's
+ * stream.
+ *
+ * Bytes of device staging area a plan needs for host-resident solves: ten
+ * meshes of nx*ny*nz reals, each rounded up to a multiple of 256 bytes (two
+ * slots of rho, phi and the 3-component field).  Alignment required: 256
+ * bytes. */
+dks_status dks_poisson_host_staging_bytes(dks_poisson_plan_t plan, size_t* bytes);
+
+/* Attach the caller-owned device staging area (at least
+ * dks_poisson_host_staging_bytes, 256-byte aligned).  Waits for every
+ * host-resident solve issued on the plan to finish first.  The plan keeps the
+ * pointer; the caller keeps it alive until the plan is destroyed or another
+ * area is attached. */
+dks_status dks_poisson_set_host_staging(dks_poisson_plan_t plan, void* staging, size_t bytes);
+
+/* Enqueue one host-resident solve of an explicit-h plan (DKS_ESTATE on a
+ * fitted plan or before prepare; DKS_EWORKSPACE without a staging area).
+ *   rho_host : host [nz][ny][nx] C/m^3, read by the upload stream.
+ *   phi_host : host [nz][ny][nx] volts, written by the download; may be NULL.
+ *   E_host   : host [3][nz][ny][nx] V/m, written by the download; may be NULL.
+ *   stream   : the compute stream of the solve's kernels.
+ *   ticket   : receives the solve's sequence number (host memory).
+ * At least one of phi_host, E_host must be non-NULL.  Returns without waiting
+ * for any device work.  The host buffers must stay untouched until the
+ * ticket is done (dks_poisson_host_query / dks_poisson_host_wait).  Overlap
+ * requires page-locked host memory (hipHostMalloc); pageable memory gives the
+ * same result with serialised copies.  The library owns two non-blocking copy
+ * streams per plan, created on the first call on the current device; results
+ * land in issue order. */
+dks_status dks_poisson_solve_rho_host(dks_poisson_plan_t plan, const void* rho_host, void* phi_host,
+                                      void* E_host, dks_stream_t stream, uint64_t* ticket);
+
+/* Non-blocking: *done = 1 when the solve `ticket` has written its host
+ * outputs, else 0.  DKS_EINVAL for a ticket not yet issued. */
+dks_status dks_poisson_host_query(dks_poisson_plan_t plan, uint64_t ticket, int* done);
+
+/* Block the calling thread until the solve `ticket` has written its host
+ * outputs.  DKS_EINVAL for a ticket not yet issued. */
+dks_status dks_poisson_host_wait(dks_poisson_plan_t plan, uint64_t ticket);
+
+/* Release the plan's host state.  Waits for outstanding host-resident solves
+ * and releases the plan's copy streams.  Does not touch the caller's
+ * workspace. */
 dks_status dks_poisson_destroy(dks_poisson_plan_t plan);
 
 /* Static, NUL-terminated description of a status code. */

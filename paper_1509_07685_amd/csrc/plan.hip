@@ -157,6 +157,23 @@ static GLBands make_bands() {
 
 using namespace dks;
 
+// State of host-resident solves.  Two staging slots hold a solve's device
+// copy of rho and of its outputs; solve k uses slot k % 2.  Uploads and
+// downloads run on two copy streams of the plan, the kernels on the caller's
+// stream; the events order the three.  Downloads are issued in ticket order
+// on one stream, so they land in ticket order.
+constexpr int kHostRing = 8;
+struct HostPipe {
+  char* stage;
+  size_t stage_bytes;
+  int device;                     // device of the streams; -1 before the first solve
+  hipStream_t up, down;           // copy streams (default priority, non-blocking)
+  hipEvent_t computed[2];         // slot's kernels done: input read, outputs written
+  hipEvent_t uploaded[2];         // slot's input on the device
+  hipEvent_t landed[kHostRing];   // ticket's outputs on the host
+  uint64_t issued;                // tickets handed out so far
+};
+
 struct dks_poisson_plan_s {
   int n[3];
   double h[3];
@@ -184,6 +201,7 @@ struct dks_poisson_plan_s {
   size_t pscratch_bytes;
   bool prepared;
   bool has_geometry;
+  HostPipe hp;         // host-resident solves
 };
 
 namespace {
@@ -522,6 +540,76 @@ ElemBatch single(const void* x, const void* y, const void* z, void* ex, void* ey
   return eb;
 }
 
+// rho (device) -> phi and/or E_mesh (device) on an explicit-h plan.
+dks_status solve_rho_dev(dks_poisson_plan_s* p, const void* rho, void* phi, void* E_mesh, hipStream_t st) {
+  Slots sl{p->ws + p->off_slot, p->slot_bytes};
+  const GeoArgs ga = geo_args(p, 0, 0);
+  if (launch_geometry(nullptr, 0, sl.geo(), sl.stride, ga, no_elements(), 1, st) != hipSuccess) return DKS_EHIP;
+  const ElemBatch out = single(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, phi, nullptr, 0, 0.0, false);
+  dks_status r;
+  if (p->dtype == DKS_F32) {
+    r = convolve<float>(p, rho, 0, 1, sl, out, st);
+    if (r == DKS_OK && E_mesh) {
+      Timed tm("gradient", st);
+      r = hip_status(launch_gradient<float>(sl.base + p->s_r3, E_mesh, sl.geo(), p->md, st));
+      tm.done();
+    }
+  } else {
+    r = convolve<double>(p, rho, 0, 1, sl, out, st);
+    if (r == DKS_OK && E_mesh) {
+      Timed tm("gradient", st);
+      r = hip_status(launch_gradient<double>(sl.base + p->s_r3, E_mesh, sl.geo(), p->md, st));
+      tm.done();
+    }
+  }
+  if (r == DKS_OK) p->has_geometry = true;
+  return r;
+}
+
+// Host staging: per slot rho, phi, E (3 components), each array 256-aligned.
+size_t mesh_unit(const dks_poisson_plan_s* p) {
+  return align256((size_t)p->n[0] * p->n[1] * p->n[2] * p->rsize);
+}
+size_t host_stage_bytes(const dks_poisson_plan_s* p) { return 2 * 5 * mesh_unit(p); }
+
+// Streams and events of the host pipeline, created once on the current device.
+dks_status host_pipe_init(HostPipe& hp) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DKS_EHIP;
+  if (hp.device >= 0) return hp.device == dev ? DKS_OK : DKS_EINVAL;
+  if (hipStreamCreateWithFlags(&hp.up, hipStreamNonBlocking) != hipSuccess) return DKS_EHIP;
+  if (hipStreamCreateWithFlags(&hp.down, hipStreamNonBlocking) != hipSuccess) return DKS_EHIP;
+  for (int b = 0; b < 2; ++b) {
+    if (hipEventCreateWithFlags(&hp.computed[b], hipEventDisableTiming) != hipSuccess) return DKS_EHIP;
+    if (hipEventCreateWithFlags(&hp.uploaded[b], hipEventDisableTiming) != hipSuccess) return DKS_EHIP;
+  }
+  for (int i = 0; i < kHostRing; ++i)
+    if (hipEventCreateWithFlags(&hp.landed[i], hipEventDisableTiming) != hipSuccess) return DKS_EHIP;
+  hp.device = dev;
+  return DKS_OK;
+}
+
+// Wait for every issued host-resident solve, then release streams and events.
+void host_pipe_release(HostPipe& hp) {
+  if (hp.up) (void)hipStreamSynchronize(hp.up);
+  if (hp.down) (void)hipStreamSynchronize(hp.down);
+  for (int b = 0; b < 2; ++b) {
+    if (hp.computed[b]) (void)hipEventDestroy(hp.computed[b]);
+    if (hp.uploaded[b]) (void)hipEventDestroy(hp.uploaded[b]);
+  }
+  for (int i = 0; i < kHostRing; ++i)
+    if (hp.landed[i]) (void)hipEventDestroy(hp.landed[i]);
+  if (hp.up) (void)hipStreamDestroy(hp.up);
+  if (hp.down) (void)hipStreamDestroy(hp.down);
+}
+
+// The event that is complete once `ticket` has landed: its own while it is
+// still in the ring, else the oldest ticket in the ring (in-order landing).
+hipEvent_t landed_event(const HostPipe& hp, uint64_t ticket) {
+  const uint64_t oldest = hp.issued > (uint64_t)kHostRing ? hp.issued - kHostRing : 0;
+  return hp.landed[std::max(ticket, oldest) % kHostRing];
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -567,6 +655,7 @@ dks_status dks_poisson_plan(int nx, int ny, int nz, double hx, double hy, double
   }
   p->fitted = fitted;
   p->dtype = dtype;
+  p->hp.device = -1;
   p->rsize = dtype == DKS_F32 ? sizeof(float) : sizeof(double);
   p->csize = 2 * p->rsize;
   try {
@@ -656,29 +745,81 @@ dks_status dks_poisson_solve_rho(dks_poisson_plan_t p, const void* rho, void* ph
   if (p->fitted) return DKS_ESTATE;
   if (!ws_ready(p)) return DKS_EWORKSPACE;
   if (!p->prepared) return DKS_ESTATE;
+  return solve_rho_dev(p, rho, phi, E_mesh, static_cast<hipStream_t>(stream));
+}
+
+dks_status dks_poisson_host_staging_bytes(dks_poisson_plan_t p, size_t* bytes) {
+  if (!p || !bytes) return DKS_EINVAL;
+  *bytes = host_stage_bytes(p);
+  return DKS_OK;
+}
+
+dks_status dks_poisson_set_host_staging(dks_poisson_plan_t p, void* staging, size_t bytes) {
+  if (!p || !staging) return DKS_EINVAL;
+  if (bytes < host_stage_bytes(p) || (reinterpret_cast<uintptr_t>(staging) & 255) != 0) return DKS_EWORKSPACE;
+  HostPipe& hp = p->hp;
+  if (hp.device >= 0 && (hipStreamSynchronize(hp.up) != hipSuccess || hipStreamSynchronize(hp.down) != hipSuccess))
+    return DKS_EHIP;
+  hp.stage = static_cast<char*>(staging);
+  hp.stage_bytes = bytes;
+  return DKS_OK;
+}
+
+dks_status dks_poisson_solve_rho_host(dks_poisson_plan_t p, const void* rho_host, void* phi_host, void* E_host,
+                                      dks_stream_t stream, uint64_t* ticket) {
+  if (!p || !rho_host || (!phi_host && !E_host) || !ticket) return DKS_EINVAL;
+  if (p->fitted || !p->prepared) return DKS_ESTATE;
+  if (!ws_ready(p) || !p->hp.stage) return DKS_EWORKSPACE;
+  HostPipe& hp = p->hp;
+  const dks_status ri = host_pipe_init(hp);
+  if (ri != DKS_OK) return ri;
   const hipStream_t st = static_cast<hipStream_t>(stream);
-  Slots sl{p->ws + p->off_slot, p->slot_bytes};
-  const GeoArgs ga = geo_args(p, 0, 0);
-  if (launch_geometry(nullptr, 0, sl.geo(), sl.stride, ga, no_elements(), 1, st) != hipSuccess) return DKS_EHIP;
-  const ElemBatch out = single(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, phi, nullptr, 0, 0.0, false);
-  dks_status r;
-  if (p->dtype == DKS_F32) {
-    r = convolve<float>(p, rho, 0, 1, sl, out, st);
-    if (r == DKS_OK && E_mesh) {
-      Timed tm("gradient", st);
-      r = hip_status(launch_gradient<float>(sl.base + p->s_r3, E_mesh, sl.geo(), p->md, st));
-      tm.done();
-    }
-  } else {
-    r = convolve<double>(p, rho, 0, 1, sl, out, st);
-    if (r == DKS_OK && E_mesh) {
-      Timed tm("gradient", st);
-      r = hip_status(launch_gradient<double>(sl.base + p->s_r3, E_mesh, sl.geo(), p->md, st));
-      tm.done();
-    }
+  const uint64_t k = hp.issued;
+  const int b = (int)(k & 1);
+  const size_t u = mesh_unit(p);
+  const size_t mesh = (size_t)p->n[0] * p->n[1] * p->n[2] * p->rsize;
+  char* rho_d = hp.stage + (size_t)b * 5 * u;
+  char* phi_d = rho_d + u;
+  char* E_d = rho_d + 2 * u;
+  // upload into slot b once solve k-2 has finished reading it
+  if (k >= 2 && hipStreamWaitEvent(hp.up, hp.computed[b], 0) != hipSuccess) return DKS_EHIP;
+  if (hipMemcpyAsync(rho_d, rho_host, mesh, hipMemcpyHostToDevice, hp.up) != hipSuccess) return DKS_EHIP;
+  if (hipEventRecord(hp.uploaded[b], hp.up) != hipSuccess) return DKS_EHIP;
+  // compute once the input is there and solve k-2's outputs have left slot b
+  if (hipStreamWaitEvent(st, hp.uploaded[b], 0) != hipSuccess) return DKS_EHIP;
+  if (k >= 2 && hipStreamWaitEvent(st, hp.landed[(k - 2) % kHostRing], 0) != hipSuccess) return DKS_EHIP;
+  const dks_status rc = solve_rho_dev(p, rho_d, phi_host ? phi_d : nullptr, E_host ? E_d : nullptr, st);
+  if (rc != DKS_OK) return rc;
+  if (hipEventRecord(hp.computed[b], st) != hipSuccess) return DKS_EHIP;
+  // download
+  if (hipStreamWaitEvent(hp.down, hp.computed[b], 0) != hipSuccess) return DKS_EHIP;
+  if (phi_host && hipMemcpyAsync(phi_host, phi_d, mesh, hipMemcpyDeviceToHost, hp.down) != hipSuccess)
+    return DKS_EHIP;
+  if (E_host && hipMemcpyAsync(E_host, E_d, 3 * mesh, hipMemcpyDeviceToHost, hp.down) != hipSuccess)
+    return DKS_EHIP;
+  if (hipEventRecord(hp.landed[k % kHostRing], hp.down) != hipSuccess) return DKS_EHIP;
+  hp.issued = k + 1;
+  *ticket = k;
+  return DKS_OK;
+}
+
+dks_status dks_poisson_host_query(dks_poisson_plan_t p, uint64_t ticket, int* done) {
+  if (!p || !done || ticket >= p->hp.issued) return DKS_EINVAL;
+  const hipError_t e = hipEventQuery(landed_event(p->hp, ticket));
+  if (e == hipSuccess) {
+    *done = 1;
+    return DKS_OK;
   }
-  if (r == DKS_OK) p->has_geometry = true;
-  return r;
+  if (e == hipErrorNotReady) {
+    *done = 0;
+    return DKS_OK;
+  }
+  return DKS_EHIP;
+}
+
+dks_status dks_poisson_host_wait(dks_poisson_plan_t p, uint64_t ticket) {
+  if (!p || ticket >= p->hp.issued) return DKS_EINVAL;
+  return hipEventSynchronize(landed_event(p->hp, ticket)) == hipSuccess ? DKS_OK : DKS_EHIP;
 }
 
 dks_status dks_poisson_solve_particles(dks_poisson_plan_t p, const void* x, const void* y, const void* z,
@@ -823,6 +964,7 @@ dks_status dks_timing_read(dks_kernel_time* out, int capacity, int* count) {
 
 dks_status dks_poisson_destroy(dks_poisson_plan_t p) {
   if (!p) return DKS_EINVAL;
+  host_pipe_release(p->hp);
   delete p;
   return DKS_OK;
 }

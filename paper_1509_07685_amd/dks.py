@@ -35,7 +35,9 @@ EXPORTS = (
     "dks_poisson_set_particle_scratch", "dks_poisson_set_workspace", "dks_poisson_prepare",
     "dks_poisson_solve_rho", "dks_poisson_solve_particles", "dks_poisson_solve_particles_batched",
     "dks_poisson_deposit", "dks_poisson_gather", "dks_poisson_geometry", "dks_poisson_destroy",
-    "dks_status_string", "dks_timing_enable", "dks_timing_read",
+    "dks_status_string", "dks_timing_enable", "dks_timing_read", "dks_poisson_host_staging_bytes",
+    "dks_poisson_set_host_staging", "dks_poisson_solve_rho_host", "dks_poisson_host_query",
+    "dks_poisson_host_wait",
 )
 
 
@@ -80,6 +82,11 @@ _SIGS = {
     "dks_status_string": (ctypes.c_char_p, [_i]),
     "dks_timing_enable": (_i, [_i]),
     "dks_timing_read": (_i, [_vp, _i, ctypes.POINTER(_i)]),
+    "dks_poisson_host_staging_bytes": (_i, [_PLAN, ctypes.POINTER(_sz)]),
+    "dks_poisson_set_host_staging": (_i, [_PLAN, _vp, _sz]),
+    "dks_poisson_solve_rho_host": (_i, [_PLAN, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)]),
+    "dks_poisson_host_query": (_i, [_PLAN, ctypes.c_uint64, ctypes.POINTER(_i)]),
+    "dks_poisson_host_wait": (_i, [_PLAN, ctypes.c_uint64]),
 }
 
 
@@ -150,6 +157,33 @@ def dks_poisson_prepare(plan, stream):
 
 def dks_poisson_solve_rho(plan, rho, phi, E_mesh, stream):
     _check(_lib.dks_poisson_solve_rho(plan, rho, phi, E_mesh, stream), "dks_poisson_solve_rho")
+
+
+def dks_poisson_host_staging_bytes(plan):
+    n = _sz()
+    _check(_lib.dks_poisson_host_staging_bytes(plan, ctypes.byref(n)), "dks_poisson_host_staging_bytes")
+    return n.value
+
+
+def dks_poisson_set_host_staging(plan, ptr, nbytes):
+    _check(_lib.dks_poisson_set_host_staging(plan, ptr, nbytes), "dks_poisson_set_host_staging")
+
+
+def dks_poisson_solve_rho_host(plan, rho_host, phi_host, E_host, stream):
+    t = ctypes.c_uint64()
+    _check(_lib.dks_poisson_solve_rho_host(plan, rho_host, phi_host, E_host, stream, ctypes.byref(t)),
+           "dks_poisson_solve_rho_host")
+    return t.value
+
+
+def dks_poisson_host_query(plan, ticket):
+    done = _i()
+    _check(_lib.dks_poisson_host_query(plan, ticket, ctypes.byref(done)), "dks_poisson_host_query")
+    return bool(done.value)
+
+
+def dks_poisson_host_wait(plan, ticket):
+    _check(_lib.dks_poisson_host_wait(plan, ticket), "dks_poisson_host_wait")
 
 
 def dks_poisson_solve_particles(plan, x, y, z, np_, q, Ex, Ey, Ez, phi, n_outside, stream):
@@ -302,6 +336,41 @@ class PoissonPlan:
         E = torch.empty((3,) + self.mesh_shape(), dtype=self.dtype, device=rho.device) if want_E else None
         dks_poisson_solve_rho(self.handle, _ptr(rho), _ptr(phi), _ptr(E), _stream_handle(stream))
         return phi, E
+
+    def host_staging(self):
+        """Attach the device staging area of host-resident solves (once)."""
+        torch = _torch()
+        if getattr(self, "staging", None) is None:
+            nbytes = dks_poisson_host_staging_bytes(self.handle)
+            self.staging = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            dks_poisson_set_host_staging(self.handle, _ptr(self.staging), nbytes)
+        return self.staging
+
+    def _check_host(self, t, shape, name):
+        if t.dtype != self.dtype or not t.is_contiguous() or t.device.type != "cpu":
+            raise ValueError(f"{name} must be a contiguous {self.dtype} host tensor")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+    def solve_rho_host(self, rho_host, phi_host=None, E_host=None, stream=None):
+        """Enqueue a host-resident solve (host tensors, page-locked for
+        overlap); returns its ticket.  The tensors must stay alive and
+        untouched until host_wait(ticket) or host_done(ticket)."""
+        self._check_host(rho_host, self.mesh_shape(), "rho_host")
+        if phi_host is not None:
+            self._check_host(phi_host, self.mesh_shape(), "phi_host")
+        if E_host is not None:
+            self._check_host(E_host, (3,) + self.mesh_shape(), "E_host")
+        self.host_staging()
+        return dks_poisson_solve_rho_host(self.handle, rho_host.data_ptr(),
+                                          None if phi_host is None else phi_host.data_ptr(),
+                                          None if E_host is None else E_host.data_ptr(), _stream_handle(stream))
+
+    def host_done(self, ticket):
+        return dks_poisson_host_query(self.handle, ticket)
+
+    def host_wait(self, ticket):
+        dks_poisson_host_wait(self.handle, ticket)
 
     def reserve_particles(self, npart):
         """Attach (growing if needed) the binned-particle scratch for npart particles."""

@@ -134,6 +134,20 @@ def test_workspace_and_state_checks(dks):
                                                None, None, None) == dks.DKS_EINVAL
         assert lib.dks_poisson_solve_particles(plan, fake, fake, fake, 1, float("inf"), fake, fake, fake,
                                                None, None, None) == dks.DKS_EINVAL
+        # host-resident solves: staging size, attachment and call order, all on the host
+        assert dks.dks_poisson_host_staging_bytes(plan) == 10 * 6912   # 16*12*9 floats = 27 * 256 B
+        assert lib.dks_poisson_set_host_staging(plan, None, 1 << 20) == dks.DKS_EINVAL
+        assert lib.dks_poisson_set_host_staging(plan, ctypes.c_void_p(0x100040), 1 << 20) == dks.DKS_EWORKSPACE
+        assert lib.dks_poisson_set_host_staging(plan, fake, 10 * 6912 - 1) == dks.DKS_EWORKSPACE
+        tk = ctypes.c_uint64()
+        hbuf = (ctypes.c_float * (16 * 12 * 9))()
+        assert lib.dks_poisson_solve_rho_host(plan, hbuf, hbuf, None, None, None) == dks.DKS_EINVAL
+        assert lib.dks_poisson_solve_rho_host(plan, hbuf, None, None, None, ctypes.byref(tk)) == dks.DKS_EINVAL
+        assert lib.dks_poisson_solve_rho_host(plan, None, hbuf, None, None, ctypes.byref(tk)) == dks.DKS_EINVAL
+        assert lib.dks_poisson_solve_rho_host(plan, hbuf, hbuf, None, None, ctypes.byref(tk)) == dks.DKS_ESTATE
+        assert lib.dks_poisson_host_query(plan, 0, ctypes.byref(ctypes.c_int())) == dks.DKS_EINVAL
+        assert lib.dks_poisson_host_wait(plan, 0) == dks.DKS_EINVAL
+        assert lib.dks_poisson_set_host_staging(plan, fake, 10 * 6912) == dks.DKS_OK
         assert lib.dks_poisson_set_origin(plan, 0.0, 1.0, float("nan")) == dks.DKS_EINVAL
         assert lib.dks_poisson_set_origin(plan, 0.0, 1.0, 2.0) == dks.DKS_OK
     finally:
