@@ -148,6 +148,38 @@ def host_offload(torch, dks, n, dtype="f32", solves=20):
     return out
 
 
+def raw_fft(torch, dks, n=(512, 512, 256)):
+    """The raw 3-D FFT entry points at the paper's largest FFT size: C2C
+    forward in place (FP32, FP64) and R2C forward (FP32), against three HBM
+    round trips of the array (the pass structure's compulsory traffic);
+    torch.fft (the platform FFT library) timed beside them for context."""
+    out = {"mesh": list(n)}
+    N = n[0] * n[1] * n[2]
+    for dt, cdt in (("f32", torch.complex64), ("f64", torch.complex128)):
+        plan = dks.FFTPlan(n, 1, "c2c", dt)
+        buf = torch.randn((1, n[2], n[1], n[0]), dtype=cdt, device="cuda")
+        ms = time_loop(torch, lambda: plan.forward(buf, out=buf), 10, 2)
+        c = 8 if dt == "f32" else 16
+        alg = 3 * 2 * c * N
+        lib_ms = time_loop(torch, lambda: torch.fft.fftn(buf, dim=(-3, -2, -1)), 10, 2)
+        out[f"c2c_{dt}"] = {"ms": ms, "alg_bytes": alg, "GB_s": alg / (ms * 1e-3) / 1e9,
+                            "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "torch_fft_ms": lib_ms}
+        del plan, buf
+        torch.cuda.empty_cache()
+    plan = dks.FFTPlan(n, 1, "r2c", "f32")
+    x = torch.randn((1, n[2], n[1], n[0]), dtype=torch.float32, device="cuda")
+    H = torch.empty((1, n[2], n[1], n[0] // 2 + 1), dtype=torch.complex64, device="cuda")
+    ms = time_loop(torch, lambda: plan.forward(x, out=H), 10, 2)
+    nh = n[0] // 2 + 1
+    alg = 4 * N + 8 * nh * n[1] * n[2] + 2 * 2 * 8 * nh * n[1] * n[2]
+    lib_ms = time_loop(torch, lambda: torch.fft.rfftn(x, dim=(-3, -2, -1)), 10, 2)
+    out["r2c_f32"] = {"ms": ms, "alg_bytes": alg, "GB_s": alg / (ms * 1e-3) / 1e9,
+                      "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "torch_fft_ms": lib_ms}
+    del plan, x, H
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline():
     """The oracle as it stands on a bounded sample: the full particle step on a
     128^3 fitted mesh with 1.25e7 particles of the same halo-Gaussian bunch
@@ -284,6 +316,8 @@ def main():
             del mp, rho, phi
             torch.cuda.empty_cache()
         extra["host_offload"] = host_offload(torch, dks, n)
+        torch.cuda.empty_cache()
+        extra["raw_fft"] = raw_fft(torch, dks)
         torch.cuda.empty_cache()
         try:
             from paper_1509_07685_amd import serve

@@ -71,11 +71,11 @@ def irdft3(X, nx):
 def dft3_at(x, k, inverse=False):
     """One output X[kz, ky, kx] of dft3 of a single array x [nz, ny, nx], by
     the sum over all inputs (used to sample outputs of large transforms)."""
-    x = np.asarray(x)
+    x = np.asarray(x, dtype=np.complex128)
     nz, ny, nx = x.shape
     kz, ky, kx = k
     s = 1.0 if inverse else -1.0
     wx = np.exp(s * 2j * np.pi * ((np.arange(nx) * kx) % nx) / nx)
     wy = np.exp(s * 2j * np.pi * ((np.arange(ny) * ky) % ny) / ny)
     wz = np.exp(s * 2j * np.pi * ((np.arange(nz) * kz) % nz) / nz)
-    return complex(((x.astype(np.complex128) @ wx) @ wy) @ wz)
+    return complex(((x @ wx) @ wy) @ wz)

@@ -26,6 +26,8 @@ DKS_GREEN_POINT = 1
 DKS_ASSIGN_CIC = 0
 DKS_ASSIGN_NGP = 1
 DKS_ASSIGN_TSC = 2
+DKS_FFT_C2C = 0
+DKS_FFT_R2C = 1
 GREENS = {"integrated": DKS_GREEN_INTEGRATED, "point": DKS_GREEN_POINT}
 SCHEMES = {"cic": DKS_ASSIGN_CIC, "ngp": DKS_ASSIGN_NGP, "tsc": DKS_ASSIGN_TSC}
 
@@ -37,7 +39,8 @@ EXPORTS = (
     "dks_poisson_deposit", "dks_poisson_gather", "dks_poisson_geometry", "dks_poisson_destroy",
     "dks_status_string", "dks_timing_enable", "dks_timing_read", "dks_poisson_host_staging_bytes",
     "dks_poisson_set_host_staging", "dks_poisson_solve_rho_host", "dks_poisson_host_query",
-    "dks_poisson_host_wait",
+    "dks_poisson_host_wait", "dks_fft_plan", "dks_fft_workspace_bytes", "dks_fft_set_workspace",
+    "dks_fft_prepare", "dks_fft_forward", "dks_fft_inverse", "dks_fft_destroy",
 )
 
 
@@ -87,6 +90,13 @@ _SIGS = {
     "dks_poisson_solve_rho_host": (_i, [_PLAN, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_uint64)]),
     "dks_poisson_host_query": (_i, [_PLAN, ctypes.c_uint64, ctypes.POINTER(_i)]),
     "dks_poisson_host_wait": (_i, [_PLAN, ctypes.c_uint64]),
+    "dks_fft_plan": (_i, [_i, _i, _i, _i, _i, _i, ctypes.POINTER(_PLAN)]),
+    "dks_fft_workspace_bytes": (_i, [_PLAN, ctypes.POINTER(_sz)]),
+    "dks_fft_set_workspace": (_i, [_PLAN, _vp, _sz]),
+    "dks_fft_prepare": (_i, [_PLAN, _vp]),
+    "dks_fft_forward": (_i, [_PLAN, _vp, _vp, _vp]),
+    "dks_fft_inverse": (_i, [_PLAN, _vp, _vp, _vp]),
+    "dks_fft_destroy": (_i, [_PLAN]),
 }
 
 
@@ -184,6 +194,38 @@ def dks_poisson_host_query(plan, ticket):
 
 def dks_poisson_host_wait(plan, ticket):
     _check(_lib.dks_poisson_host_wait(plan, ticket), "dks_poisson_host_wait")
+
+
+def dks_fft_plan(nx, ny, nz, batch, kind, dtype):
+    plan = _PLAN()
+    _check(_lib.dks_fft_plan(nx, ny, nz, batch, kind, dtype, ctypes.byref(plan)), "dks_fft_plan")
+    return plan
+
+
+def dks_fft_workspace_bytes(plan):
+    n = _sz()
+    _check(_lib.dks_fft_workspace_bytes(plan, ctypes.byref(n)), "dks_fft_workspace_bytes")
+    return n.value
+
+
+def dks_fft_set_workspace(plan, ptr, nbytes):
+    _check(_lib.dks_fft_set_workspace(plan, ptr, nbytes), "dks_fft_set_workspace")
+
+
+def dks_fft_prepare(plan, stream):
+    _check(_lib.dks_fft_prepare(plan, stream), "dks_fft_prepare")
+
+
+def dks_fft_forward(plan, inp, out, stream):
+    _check(_lib.dks_fft_forward(plan, inp, out, stream), "dks_fft_forward")
+
+
+def dks_fft_inverse(plan, inp, out, stream):
+    _check(_lib.dks_fft_inverse(plan, inp, out, stream), "dks_fft_inverse")
+
+
+def dks_fft_destroy(plan):
+    _check(_lib.dks_fft_destroy(plan), "dks_fft_destroy")
 
 
 def dks_poisson_solve_particles(plan, x, y, z, np_, q, Ex, Ey, Ez, phi, n_outside, stream):
@@ -438,6 +480,73 @@ class PoissonPlan:
     def close(self):
         if self.handle is not None:
             dks_poisson_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FFTPlan:
+    """A raw 3-D FFT plan plus its torch-allocated workspace.
+
+    n = (nx, ny, nz) (x fastest; extents of 1 give 2-D / 1-D transforms),
+    batch consecutive arrays, kind "c2c" or "r2c", dtype "f32"/"f64".
+    Complex tensors are torch complex64 / complex128 of shape
+    (batch, nz, ny, nx) (or (batch, nz, ny, nx//2+1) for the r2c spectrum).
+    """
+
+    def __init__(self, n, batch=1, kind="c2c", dtype="f32", device="cuda", stream=None):
+        torch = _torch()
+        self.n = tuple(int(v) for v in n)
+        self.batch = int(batch)
+        self.kind = kind
+        self.code, self.dtype = _dtype_code(dtype)
+        self.cdtype = torch.complex64 if self.dtype == torch.float32 else torch.complex128
+        kcode = {"c2c": DKS_FFT_C2C, "r2c": DKS_FFT_R2C}[kind]
+        self.handle = dks_fft_plan(*self.n, self.batch, kcode, self.code)
+        nbytes = dks_fft_workspace_bytes(self.handle)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        dks_fft_set_workspace(self.handle, _ptr(self.workspace), self.workspace.numel())
+        dks_fft_prepare(self.handle, _stream_handle(stream))
+
+    def shape(self, spectrum=False):
+        nx, ny, nz = self.n
+        if spectrum and self.kind == "r2c":
+            nx = nx // 2 + 1
+        return (self.batch, nz, ny, nx)
+
+    def _check(self, t, dtype, shape, name):
+        if t.dtype != dtype or not t.is_contiguous() or t.device.type != "cuda":
+            raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+    def forward(self, x, out=None, stream=None):
+        torch = _torch()
+        in_dt = self.dtype if self.kind == "r2c" else self.cdtype
+        self._check(x, in_dt, self.shape(), "x")
+        if out is None:
+            out = torch.empty(self.shape(spectrum=True), dtype=self.cdtype, device=x.device)
+        self._check(out, self.cdtype, self.shape(spectrum=True), "out")
+        dks_fft_forward(self.handle, _ptr(x), _ptr(out), _stream_handle(stream))
+        return out
+
+    def inverse(self, X, out=None, stream=None):
+        torch = _torch()
+        out_dt = self.dtype if self.kind == "r2c" else self.cdtype
+        self._check(X, self.cdtype, self.shape(spectrum=True), "X")
+        if out is None:
+            out = torch.empty(self.shape(), dtype=out_dt, device=X.device)
+        self._check(out, out_dt, self.shape(), "out")
+        dks_fft_inverse(self.handle, _ptr(X), _ptr(out), _stream_handle(stream))
+        return out
+
+    def close(self):
+        if self.handle is not None:
+            dks_fft_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -9,14 +9,15 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "dks_poisson.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
 LIB = os.path.join(ROOT, "paper_1509_07685_amd", "libdks_poisson.so")
 
 pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libdks_poisson.so not built")
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(dks_\w+)\s*\(", text)))
 
@@ -184,3 +185,35 @@ def test_workspace_grows_with_mesh_and_dtype(dks):
     assert sizes[(64, dks.DKS_F64)] > sizes[(64, dks.DKS_F32)]
     # about 27 sizeof(real) x 8 per node for the doubled-grid intermediates, well under 64x
     assert sizes[(64, dks.DKS_F32)] < 64 * 4 * 64 ** 3 * 8
+
+
+def test_fft_plan_validation(dks):
+    lib = dks._lib
+    plan = ctypes.c_void_p()
+    for args in ((64, 64, 64, 1), (1, 1, 1, 1), (4096, 1, 1, 3), (6, 9, 27, 2), (2, 3, 4096, 1)):
+        for kind in (dks.DKS_FFT_C2C, dks.DKS_FFT_R2C):
+            assert lib.dks_fft_plan(*args, kind, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_OK
+            assert lib.dks_fft_destroy(plan) == dks.DKS_OK
+    assert lib.dks_fft_plan(5, 8, 8, 1, 0, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_EUNSUPPORTED
+    assert lib.dks_fft_plan(8192, 1, 1, 1, 0, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_EUNSUPPORTED
+    assert lib.dks_fft_plan(0, 8, 8, 1, 0, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_EINVAL
+    assert lib.dks_fft_plan(8, 8, 8, 0, 0, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_EINVAL
+    assert lib.dks_fft_plan(8, 8, 8, 1, 2, dks.DKS_F32, ctypes.byref(plan)) == dks.DKS_EINVAL
+    assert lib.dks_fft_plan(8, 8, 8, 1, 0, 5, ctypes.byref(plan)) == dks.DKS_EINVAL
+    assert lib.dks_fft_plan(8, 8, 8, 1, 0, dks.DKS_F32, None) == dks.DKS_EINVAL
+    p = dks.dks_fft_plan(12, 8, 6, 2, dks.DKS_FFT_R2C, dks.DKS_F64)
+    try:
+        nbytes = dks.dks_fft_workspace_bytes(p)
+        # the complex-to-real scratch alone: (12/2 + 1) * 8 * 6 * 2 complex doubles
+        assert nbytes >= 7 * 8 * 6 * 2 * 16
+        fake = ctypes.c_void_p(0x100000)
+        assert lib.dks_fft_forward(p, fake, ctypes.c_void_p(0x200000), None) == dks.DKS_EWORKSPACE
+        assert lib.dks_fft_set_workspace(p, ctypes.c_void_p(0x100010), nbytes) == dks.DKS_EWORKSPACE
+        assert lib.dks_fft_set_workspace(p, fake, nbytes - 1) == dks.DKS_EWORKSPACE
+        assert lib.dks_fft_set_workspace(p, fake, nbytes) == dks.DKS_OK
+        assert lib.dks_fft_forward(p, fake, ctypes.c_void_p(0x200000), None) == dks.DKS_ESTATE
+        assert lib.dks_fft_forward(p, fake, fake, None) == dks.DKS_EINVAL      # R2C is out of place only
+        assert lib.dks_fft_forward(p, None, fake, None) == dks.DKS_EINVAL
+        assert lib.dks_fft_inverse(p, fake, None, None) == dks.DKS_EINVAL
+    finally:
+        dks.dks_fft_destroy(p)
