@@ -152,3 +152,75 @@ def gaussian_bunch_torch(torch, num, sigma, seed, dtype, device="cuda"):
     g.manual_seed(int(seed))
     pts = torch.randn((3, num), generator=g, dtype=torch.float64, device=device)
     return tuple((pts[d] * sigma[d]).to(dtype).contiguous() for d in range(3))
+
+
+# --------------------------------------------------------------------------
+# Muon-spin-rotation positron histograms (the parameter-fitting workload)
+# --------------------------------------------------------------------------
+# Synthesised by simulating decays, not by evaluating the fit model: each
+# muon decays after an exponential time with the muon lifetime, precesses at
+# the Larmor frequency of the field it sees (the applied field plus a normal
+# spread, which is what damps the signal), and its positron is counted by
+# detector j with probability (1 + a_j cos(precession angle + phase_j)) / 2;
+# uncorrelated background events fall uniformly over the bins.
+
+MUON_LIFETIME_US = 2.1969811
+MUON_GAMMA_MHZ_PER_G = 0.01355388094     # gamma_mu / 2 pi
+
+
+@dataclasses.dataclass(frozen=True)
+class MusrConfig:
+    name: str
+    n_det: int
+    n_bins: int
+    dt_us: float          # bin width
+    decays_per_det: int   # simulated muon decays per detector (before acceptance)
+    field_g: float        # applied field B (gauss)
+    sigma_us: float       # field spread expressed as a depolarisation rate (1/us)
+    background: float     # mean background counts per bin
+    seed: int
+
+
+# 16 detectors x 206 250 bins ~ 3.3e6 bins: the largest data set of the
+# parameter-fitting table; 10 us of data.
+MUSR_LARGE = MusrConfig("musr_16x206250", 16, 206_250, 10.0 / 206_250, 3_000_000, 100.0, 0.3, 0.5, 21)
+MUSR_SMALL = MusrConfig("musr_16x4096", 16, 4096, 10.0 / 4096, 200_000, 100.0, 0.3, 0.5, 22)
+
+
+def musr_truth(cfg):
+    """The simulation's own settings per detector: (asymmetry a_j, phase_j)."""
+    j = np.arange(cfg.n_det)
+    return 0.25 + 0.01 * np.cos(j), 2.0 * np.pi * j / cfg.n_det
+
+
+def musr_histograms(cfg, chunk=4_000_000):
+    """Counts [n_det][n_bins] (float64 integers) of the simulated decays."""
+    g = rng(cfg.seed)
+    a, phase = musr_truth(cfg)
+    spread_g = cfg.sigma_us / (2.0 * np.pi * MUON_GAMMA_MHZ_PER_G)
+    out = np.zeros((cfg.n_det, cfg.n_bins), dtype=np.float64)
+    t_end = cfg.n_bins * cfg.dt_us
+    for j in range(cfg.n_det):
+        left = cfg.decays_per_det
+        while left > 0:
+            m = min(chunk, left)
+            left -= m
+            t = g.exponential(MUON_LIFETIME_US, m)
+            field = cfg.field_g + spread_g * g.standard_normal(m)
+            angle = 2.0 * np.pi * MUON_GAMMA_MHZ_PER_G * field * t
+            keep = (t < t_end) & (g.random(m) < 0.5 * (1.0 + a[j] * np.cos(angle + phase[j])))
+            b = np.minimum((t[keep] / cfg.dt_us).astype(np.int64), cfg.n_bins - 1)
+            out[j] += np.bincount(b, minlength=cfg.n_bins)
+        out[j] += g.poisson(cfg.background, cfg.n_bins)
+    return out
+
+
+def musr_start_params(cfg, counts):
+    """A plausible starting parameter vector [sigma, B, (N0, Nbkg, A0, phi) x n_det]
+    from the simulation settings (N0 from the decay count per bin)."""
+    a, phase = musr_truth(cfg)
+    n0 = 0.5 * cfg.decays_per_det * cfg.dt_us / MUON_LIFETIME_US
+    p = [cfg.sigma_us, cfg.field_g]
+    for j in range(cfg.n_det):
+        p += [n0, cfg.background, a[j], phase[j]]
+    return np.array(p, dtype=np.float64)
