@@ -180,6 +180,39 @@ def raw_fft(torch, dks, n=(512, 512, 256)):
     return out
 
 
+def musr_fit(torch, dks):
+    """chi-square and log-likelihood evaluations of 16 positron histograms of
+    206 250 bins (the largest data set of the fitting table), FP64, data
+    resident: device time per evaluation (back to back), the host round trip
+    a minimiser sees per call (parameters in, one number back), and a
+    133-set batch (a central-difference gradient of the 66 parameters)."""
+    import numpy as np
+    from paper_1509_07685_amd import workloads as wl
+    cfg = wl.MUSR_LARGE
+    d = wl.musr_histograms(cfg)
+    p0 = wl.musr_start_params(cfg, d)
+    nsets = 2 * p0.size + 1
+    fit = dks.MusrFit(torch.from_numpy(d).cuda(), cfg.dt_us, max_sets=nsets)
+    P = torch.from_numpy(np.tile(p0, (nsets, 1))).cuda()
+    bins = cfg.n_det * cfg.n_bins
+    out = {"detectors": cfg.n_det, "bins": bins, "dtype": "f64", "bytes_per_eval": 8 * bins}
+    for stat in ("chisq", "mle"):
+        dev_ms = time_loop(torch, lambda: fit.eval_async(stat, p0), 50, 5)
+        lat = []
+        for _ in range(50):
+            t0 = time.perf_counter()
+            fit(stat, p0)
+            lat.append((time.perf_counter() - t0) * 1e3)
+        batch_ms = time_loop(torch, lambda: fit.eval_batch(stat, P), 10, 2)
+        out[stat] = {"device_ms_per_eval": dev_ms, "evals_per_s": 1e3 / dev_ms,
+                     "bins_per_s": bins / (dev_ms * 1e-3),
+                     "host_round_trip_p50_ms": float(np.percentile(lat, 50)),
+                     "batch133_ms_per_eval": batch_ms / nsets,
+                     "batch133_bins_per_s": bins * nsets / (batch_ms * 1e-3)}
+    fit.close()
+    return out
+
+
 def cpu_baseline():
     """The oracle as it stands on a bounded sample: the full particle step on a
     128^3 fitted mesh with 1.25e7 particles of the same halo-Gaussian bunch
@@ -318,6 +351,7 @@ def main():
         extra["host_offload"] = host_offload(torch, dks, n)
         torch.cuda.empty_cache()
         extra["raw_fft"] = raw_fft(torch, dks)
+        extra["musr_fit"] = musr_fit(torch, dks)
         torch.cuda.empty_cache()
         try:
             from paper_1509_07685_amd import serve

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdks_poisson.so")
 SOURCES = ["fft_kernels.hip", "fft_raw.hip", "particle_kernels.hip", "bin_kernels.hip", "greens_kernels.hip",
-           "plan.hip"]
+           "plan.hip", "musr_kernels.hip"]
 ARCH = "gfx950"
 
 COMMON = [

@@ -26,6 +26,9 @@ DKS_GREEN_POINT = 1
 DKS_ASSIGN_CIC = 0
 DKS_ASSIGN_NGP = 1
 DKS_ASSIGN_TSC = 2
+DKS_MUSR_CHISQ = 0
+DKS_MUSR_MLE = 1
+MUSR_STATS = {"chisq": DKS_MUSR_CHISQ, "mle": DKS_MUSR_MLE}
 DKS_FFT_C2C = 0
 DKS_FFT_R2C = 1
 GREENS = {"integrated": DKS_GREEN_INTEGRATED, "point": DKS_GREEN_POINT}
@@ -40,7 +43,9 @@ EXPORTS = (
     "dks_status_string", "dks_timing_enable", "dks_timing_read", "dks_poisson_host_staging_bytes",
     "dks_poisson_set_host_staging", "dks_poisson_solve_rho_host", "dks_poisson_host_query",
     "dks_poisson_host_wait", "dks_fft_plan", "dks_fft_workspace_bytes", "dks_fft_set_workspace",
-    "dks_fft_prepare", "dks_fft_forward", "dks_fft_inverse", "dks_fft_destroy",
+    "dks_fft_prepare", "dks_fft_forward", "dks_fft_inverse", "dks_fft_destroy", "dks_musr_plan",
+    "dks_musr_workspace_bytes", "dks_musr_set_workspace", "dks_musr_prepare", "dks_musr_set_data",
+    "dks_musr_eval", "dks_musr_eval_batch", "dks_musr_destroy",
 )
 
 
@@ -97,6 +102,14 @@ _SIGS = {
     "dks_fft_forward": (_i, [_PLAN, _vp, _vp, _vp]),
     "dks_fft_inverse": (_i, [_PLAN, _vp, _vp, _vp]),
     "dks_fft_destroy": (_i, [_PLAN]),
+    "dks_musr_plan": (_i, [_i, _i64, _d, _i, ctypes.POINTER(_PLAN)]),
+    "dks_musr_workspace_bytes": (_i, [_PLAN, ctypes.POINTER(_sz)]),
+    "dks_musr_set_workspace": (_i, [_PLAN, _vp, _sz]),
+    "dks_musr_prepare": (_i, [_PLAN, _vp]),
+    "dks_musr_set_data": (_i, [_PLAN, _vp]),
+    "dks_musr_eval": (_i, [_PLAN, _i, _vp, _vp, _vp]),
+    "dks_musr_eval_batch": (_i, [_PLAN, _i, _vp, _i, _vp, _vp]),
+    "dks_musr_destroy": (_i, [_PLAN]),
 }
 
 
@@ -226,6 +239,42 @@ def dks_fft_inverse(plan, inp, out, stream):
 
 def dks_fft_destroy(plan):
     _check(_lib.dks_fft_destroy(plan), "dks_fft_destroy")
+
+
+def dks_musr_plan(n_det, n_bins, dt, max_sets):
+    plan = _PLAN()
+    _check(_lib.dks_musr_plan(n_det, n_bins, dt, max_sets, ctypes.byref(plan)), "dks_musr_plan")
+    return plan
+
+
+def dks_musr_workspace_bytes(plan):
+    n = _sz()
+    _check(_lib.dks_musr_workspace_bytes(plan, ctypes.byref(n)), "dks_musr_workspace_bytes")
+    return n.value
+
+
+def dks_musr_set_workspace(plan, ptr, nbytes):
+    _check(_lib.dks_musr_set_workspace(plan, ptr, nbytes), "dks_musr_set_workspace")
+
+
+def dks_musr_prepare(plan, stream):
+    _check(_lib.dks_musr_prepare(plan, stream), "dks_musr_prepare")
+
+
+def dks_musr_set_data(plan, data):
+    _check(_lib.dks_musr_set_data(plan, data), "dks_musr_set_data")
+
+
+def dks_musr_eval(plan, stat, params, result, stream):
+    _check(_lib.dks_musr_eval(plan, stat, params, result, stream), "dks_musr_eval")
+
+
+def dks_musr_eval_batch(plan, stat, params, nsets, results, stream):
+    _check(_lib.dks_musr_eval_batch(plan, stat, params, nsets, results, stream), "dks_musr_eval_batch")
+
+
+def dks_musr_destroy(plan):
+    _check(_lib.dks_musr_destroy(plan), "dks_musr_destroy")
 
 
 def dks_poisson_solve_particles(plan, x, y, z, np_, q, Ex, Ey, Ez, phi, n_outside, stream):
@@ -547,6 +596,63 @@ class FFTPlan:
     def close(self):
         if self.handle is not None:
             dks_fft_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MusrFit:
+    """Resident muSR histograms [n_det][n_bins] (FP64 CUDA tensor) and the
+    device evaluation of the fit statistic for parameter vectors
+    [sigma, B, (N0, Nbkg, A0, phi) per detector]."""
+
+    def __init__(self, data, dt, max_sets=1, stream=None):
+        torch = _torch()
+        if data.dtype != torch.float64 or not data.is_contiguous() or data.device.type != "cuda" or data.dim() != 2:
+            raise ValueError("data must be a contiguous 2-D float64 CUDA tensor [n_det][n_bins]")
+        self.data = data
+        self.n_det, self.n_bins = data.shape
+        self.nparam = 2 + 4 * self.n_det
+        self.handle = dks_musr_plan(self.n_det, self.n_bins, float(dt), int(max_sets))
+        nbytes = dks_musr_workspace_bytes(self.handle)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=data.device)
+        dks_musr_set_workspace(self.handle, _ptr(self.workspace), nbytes)
+        dks_musr_prepare(self.handle, _stream_handle(stream))
+        dks_musr_set_data(self.handle, _ptr(data))
+        self.result = torch.empty(1, dtype=torch.float64, device=data.device)
+
+    def eval_async(self, stat, params, out=None, stream=None):
+        """Enqueue one evaluation; returns the device result tensor (1 element)."""
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+        if p.shape != (self.nparam,):
+            raise ValueError(f"expected {self.nparam} parameters")
+        out = self.result if out is None else out
+        dks_musr_eval(self.handle, MUSR_STATS[stat], p.ctypes.data, _ptr(out), _stream_handle(stream))
+        return out
+
+    def __call__(self, stat, params):
+        return float(self.eval_async(stat, params).item())
+
+    def eval_batch(self, stat, params, out=None, stream=None):
+        """params: float64 CUDA tensor [nsets][nparam]; returns results [nsets]."""
+        torch = _torch()
+        if params.dtype != torch.float64 or not params.is_contiguous() or params.dim() != 2 \
+                or params.shape[1] != self.nparam:
+            raise ValueError(f"params must be a contiguous float64 CUDA tensor [nsets][{self.nparam}]")
+        nsets = params.shape[0]
+        if out is None:
+            out = torch.empty(nsets, dtype=torch.float64, device=params.device)
+        dks_musr_eval_batch(self.handle, MUSR_STATS[stat], _ptr(params), nsets, _ptr(out), _stream_handle(stream))
+        return out
+
+    def close(self):
+        if self.handle is not None:
+            dks_musr_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -217,3 +217,32 @@ def test_fft_plan_validation(dks):
         assert lib.dks_fft_inverse(p, fake, None, None) == dks.DKS_EINVAL
     finally:
         dks.dks_fft_destroy(p)
+
+
+def test_musr_plan_validation(dks):
+    lib = dks._lib
+    plan = ctypes.c_void_p()
+    assert lib.dks_musr_plan(16, 206250, 4.8e-5, 133, ctypes.byref(plan)) == dks.DKS_OK
+    assert lib.dks_musr_destroy(plan) == dks.DKS_OK
+    for args in ((0, 100, 0.1, 1), (33, 100, 0.1, 1), (4, 0, 0.1, 1), (4, 100, 0.0, 1), (4, 100, float("nan"), 1),
+                 (4, 100, 0.1, 0), (4, 100, 0.1, 1025), (4, 2 ** 31, 0.1, 1)):
+        assert lib.dks_musr_plan(*args, ctypes.byref(plan)) == dks.DKS_EINVAL, args
+    p = dks.dks_musr_plan(4, 5000, 0.01, 8)
+    try:
+        nbytes = dks.dks_musr_workspace_bytes(p)
+        assert nbytes >= 8 * 3 * 4 * 8       # partials of 3 workgroups x 4 detectors per set
+        fake = ctypes.c_void_p(0x100000)
+        prm = (ctypes.c_double * 18)()
+        assert lib.dks_musr_eval(p, 0, prm, fake, None) == dks.DKS_EWORKSPACE
+        assert lib.dks_musr_set_workspace(p, ctypes.c_void_p(0x100008), nbytes) == dks.DKS_EWORKSPACE
+        assert lib.dks_musr_set_workspace(p, fake, nbytes - 1) == dks.DKS_EWORKSPACE
+        assert lib.dks_musr_set_workspace(p, fake, nbytes) == dks.DKS_OK
+        assert lib.dks_musr_eval(p, 0, prm, fake, None) == dks.DKS_ESTATE     # not prepared, no data
+        assert lib.dks_musr_eval(p, 2, prm, fake, None) == dks.DKS_EINVAL
+        assert lib.dks_musr_eval(p, 0, None, fake, None) == dks.DKS_EINVAL
+        assert lib.dks_musr_eval(p, 0, prm, None, None) == dks.DKS_EINVAL
+        assert lib.dks_musr_eval_batch(p, 0, fake, 0, fake, None) == dks.DKS_EINVAL
+        assert lib.dks_musr_eval_batch(p, 0, fake, 9, fake, None) == dks.DKS_EINVAL
+        assert lib.dks_musr_set_data(p, None) == dks.DKS_EINVAL
+    finally:
+        dks.dks_musr_destroy(p)
