@@ -79,8 +79,11 @@ def measured_traffic(kernel):
     sym = KERNEL_SYMBOL.get(kernel, "")
     src = ("fft_kernels.hip" if sym.startswith("k_fft") else
            "particle_kernels.hip" if sym in ("k_bbox", "k_geometry", "k_zero", "k_gradient") else "bin_kernels.hip")
+    deps = (src, "dks_internal.h") + (("fft_engine.h",) if src == "fft_kernels.hip" else ())
+    if src == "fft_kernels.hip" and not any(f.endswith("fft_engine.h") for f in doc["sources_sha256"]):
+        return None
     for f, h in doc["sources_sha256"].items():
-        if not (f.endswith(src) or f.endswith("dks_internal.h")):
+        if not f.endswith(deps):
             continue
         path = os.path.join(ROOT, f)
         if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != h:
@@ -221,7 +224,7 @@ def cpu_baseline():
     from oracle import poisson_oracle as orc
     from paper_1509_07685_amd import workloads as wl
     x, y, z = wl.halo_gaussian(12_500_000, 1e-3, 0.1, 5e-3, 4, np.float32)
-    reps, n = 1, (128, 128, 128)
+    reps, n = 3, (128, 128, 128)
     t0 = time.perf_counter()
     for _ in range(reps):
         orc.solve_particles(x, y, z, wl.TOTAL_CHARGE / x.size, n, dtype=np.float32)
@@ -229,9 +232,13 @@ def cpu_baseline():
     return {"value": n[0] * n[1] * n[2] / dt, "unit": "mesh-pts/s", "cores": 1, "kind": "oracle",
             "sample": "FP64 numpy oracle, full particle step (fit, CIC deposit, IGF, doubled-grid FFT "
                       "convolution, gradient, gather) on a 128^3 fitted mesh with 1.25e7 particles of the "
-                      "halo-Gaussian bunch (the 256^3 / 1e8 workload scaled by 1/8), one run; "
+                      "halo-Gaussian bunch (the 256^3 / 1e8 workload scaled by 1/8), mean of three runs; "
                       "numpy's FFT and bincount are single-threaded",
             "seconds_per_step": dt}
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -242,6 +249,8 @@ def main():
     ap.add_argument("--particles", type=int, default=100_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the mesh-only and serving legs")
+    ap.add_argument("--leg", choices=("raw_fft", "musr_fit", "host_offload"),
+                    help="run only this secondary leg and print its JSON (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -260,6 +269,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.leg:
+        legs = {"raw_fft": lambda: raw_fft(torch, dks), "musr_fit": lambda: musr_fit(torch, dks),
+                "host_offload": lambda: host_offload(torch, dks, wl.HALO_GAUSSIAN.n)}
+        print(json.dumps({args.leg: legs[args.leg]()}))
+        return
 
     cfg = wl.HALO_GAUSSIAN
     n = cfg.n
@@ -289,6 +304,7 @@ def main():
     b.record()
     torch.cuda.synchronize()
     ms_per_step = a.elapsed_time(b) / args.steps
+    progress(f"full step {ms_per_step:.3f} ms")
     kt = dks.dks_timing_read()
     dks.dks_timing_enable(False)
     mesh_pts = n[0] * n[1] * n[2]
@@ -329,6 +345,7 @@ def main():
                               if k in kk}}
         dks.dks_poisson_set_scheme(plan.handle, dks.DKS_GREEN_INTEGRATED, dks.DKS_ASSIGN_CIC)
         extra["variants"] = variants
+        progress("scheme variants done")
         del tx, ty, tz, out, bufs, plan
         torch.cuda.empty_cache()
         # mesh-only solves (rho -> phi and E) at 256^3 in FP32 and FP64
@@ -348,18 +365,28 @@ def main():
                                          "conv_frac": conv_bytes(n, s) / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS}
             del mp, rho, phi
             torch.cuda.empty_cache()
+        progress("mesh-only solves done")
         extra["host_offload"] = host_offload(torch, dks, n)
+        progress("host-resident offload done")
         torch.cuda.empty_cache()
         extra["raw_fft"] = raw_fft(torch, dks)
+        progress("raw FFT done")
         extra["musr_fit"] = musr_fit(torch, dks)
+        progress("chi-square / likelihood done")
         torch.cuda.empty_cache()
         try:
             from paper_1509_07685_amd import serve
             extra["serving"] = serve.bench_stream(torch)
+            progress("serving at 500/s done")
+            torch.cuda.empty_cache()
+            # the same stream at 8x the rate: requests queue, batches form
+            extra["serving_4000_per_s"] = serve.bench_stream(torch, rate_hz=4000.0)
         except ImportError:
             extra["serving"] = None
 
     cpu = None if args.no_cpu else cpu_baseline()
+    if cpu:
+        progress("CPU oracle leg done")
     line = {
         "metric": "Poisson solve mesh-pts/s (FP32 vs FP64) + served solves/s at p50/p99 latency",
         "value": value,

@@ -93,9 +93,13 @@ class Scheduler:
       num_streams, max_batch
     """
 
-    def __init__(self, backend, budget_bytes=64 * GiB, clock=time.perf_counter, idle_wait_s=0.0):
+    def __init__(self, backend, budget_bytes=64 * GiB, clock=time.perf_counter, idle_wait_s=0.0, max_per_key=2):
         self.be = backend
         self.budget = budget_bytes
+        # at most this many executors of one (shape, dtype): further requests of
+        # that key wait for one to come back and leave together as a batch
+        self.max_per_key = max_per_key
+        self.count = collections.defaultdict(int)    # key -> executors in existence
         self.clock = clock
         self.idle_wait_s = idle_wait_s
         self.plans = {}                              # key -> bytes (resident plans)
@@ -121,6 +125,7 @@ class Scheduler:
                 continue
             self.lru.pop(exid)
             self.idle[key].remove(ex)
+            self.count[key] -= 1
             self.be.destroy_executor(ex)
             self.used -= self.be.executor_bytes(key)
             self.evictions += 1
@@ -128,11 +133,14 @@ class Scheduler:
         return False
 
     def _executor_for(self, key):
-        """An idle executor of `key`, creating one within the budget; None if not now."""
+        """An idle executor of `key`, creating one within the budget and the
+        per-key limit; None if not now."""
         if self.idle[key]:
             ex = self.idle[key].pop()
             self.lru.pop(id(ex), None)
             return ex
+        if self.count[key] >= self.max_per_key:
+            return None
         if key not in self.plans:
             need = self.be.plan_bytes(key)
             while not self._reserve(need):
@@ -144,6 +152,7 @@ class Scheduler:
             if not self._evict_one(key):
                 return None
         self.created += 1
+        self.count[key] += 1
         return self.be.create_executor(key)
 
     def _fits_ever(self, key):
@@ -167,6 +176,7 @@ class Scheduler:
                 break
             ex = self.be.create_executor(key)
             self.created += 1
+            self.count[key] += 1
             self.idle[key].append(ex)
             self.lru[id(ex)] = (key, ex)
             made += 1

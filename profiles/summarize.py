@@ -66,7 +66,8 @@ def pmc(db, counter, cmd, copy_bytes=None):
 
 
 SOURCES = ("paper_1509_07685_amd/csrc/bin_kernels.hip", "paper_1509_07685_amd/csrc/fft_kernels.hip",
-           "paper_1509_07685_amd/csrc/particle_kernels.hip", "paper_1509_07685_amd/csrc/dks_internal.h")
+           "paper_1509_07685_amd/csrc/fft_engine.h", "paper_1509_07685_amd/csrc/particle_kernels.hip",
+           "paper_1509_07685_amd/csrc/dks_internal.h")
 
 
 def source_hashes(root):

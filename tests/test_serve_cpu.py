@@ -164,3 +164,19 @@ def test_backend_can_refuse_a_request():
     jobs[1].num_particles = 400
     stats = serve.Scheduler(be, budget_bytes=1 << 40, clock=clock).run(jobs)
     assert stats.refused == 1 and stats.completed == 1 and jobs[0].status == "refused"
+
+
+def test_busy_shape_batches_instead_of_growing_executors():
+    """A burst of one shape with every executor of it busy: the waiting
+    requests leave together when one comes back; no third executor is made."""
+    clock = FakeClock()
+    be = FakeBackend(clock, max_batch=8, num_streams=4)
+    sched = serve.Scheduler(be, budget_bytes=8 << 30, clock=clock, max_per_key=2)
+    jobs = jobs_from([(i * 2e-5, A) for i in range(20)])
+    stats = sched.run(jobs)
+    assert stats.completed == 20
+    assert be.created.count(A) == 2
+    assert max(len(r) for _, r, _ in be.launches) > 1
+    # arrival order is kept within the shape
+    order = [rid for _, r, _ in be.launches for rid in r]
+    assert order == sorted(order)
