@@ -255,8 +255,9 @@ def main():
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); nothing in this build "
-              f"spans GPUs.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library has no "
+              f"multi-GPU path; independent solves shard across GPUs by running one process per GPU.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -308,6 +309,29 @@ def main():
     kt = dks.dks_timing_read()
     dks.dks_timing_enable(False)
     mesh_pts = n[0] * n[1] * n[2]
+    # distribution of single steps (events around each step, outside the timed loop above)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for e0, e1 in evs:
+        e0.record()
+        step()
+        e1.record()
+    torch.cuda.synchronize()
+    import numpy as np
+    per = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    step_dist = {"p10": float(np.percentile(per, 10)), "p50": float(np.percentile(per, 50)),
+                 "p90": float(np.percentile(per, 90)), "steps": len(per)}
+    # the Green's spectrum build of a fresh plan (FP64 kernel, cosine transforms, packing)
+    gp = dks.PoissonPlan(n, None, "f32", prepare=False)
+    gp.prepare()
+    torch.cuda.synchronize()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record()
+    gp.prepare()
+    g1.record()
+    torch.cuda.synchronize()
+    green_ms = g0.elapsed_time(g1)
+    gp.close()
+    del gp
     value = mesh_pts / (ms_per_step * 1e-3)
 
     kernels = {}
@@ -406,6 +430,8 @@ def main():
                    "mesh": list(n), "particles": num},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "step_ms": step_dist,
+        "green_build_ms": green_ms,
         "kernels": kernels,
         "convolution": conv,
         **extra,
