@@ -130,7 +130,7 @@ dks_status dks_poisson_batch_scratch_bytes(dks_poisson_plan_t plan, int batch, i
  * permutation, each rounded up to 256), attached with
  * dks_poisson_set_particle_scratch (256-byte aligned; NULL with 0 bytes
  * detaches).  A solve of more particles than the attached scratch holds
- * returns DKS_EWORKSPACE.  np must be < 2^32. */
+ * returns DKS_EWORKSPACE.  np must be at most 2^32 - 2^20. */
 dks_status dks_poisson_particle_scratch_bytes(dks_poisson_plan_t plan, int64_t np, size_t* bytes);
 dks_status dks_poisson_set_particle_scratch(dks_poisson_plan_t plan, void* scratch, size_t bytes);
 
@@ -164,7 +164,7 @@ dks_status dks_poisson_solve_rho(dks_poisson_plan_t plan, const void* rho, void*
 /* One full particle step: (fit the mesh,) CIC deposit, free-space potential,
  * central-difference field, CIC gather back to the particles.
  *   x, y, z    : device [np] particle positions in metres, read only.
- *   np         : number of particles, >= 0.
+ *   np         : number of particles, 0 <= np <= 2^32 - 2^20.
  *   q          : charge of each particle in coulombs.
  *   Ex, Ey, Ez : device [np] field at the particles, V/m, written (np > 0).
  *   phi        : device [nz][ny][nx] mesh potential, volts; may be NULL.
@@ -201,7 +201,7 @@ typedef struct {
  *   batch   : 1 .. 16 elements.
  *   sets    : device array of `batch` dks_particle_set.  An element whose
  *             x, y, z, Ex, Ey or Ez is NULL is treated as having no particles.
- *   max_np  : host bound on every element's np; sizes the launches.
+ *   max_np  : host bound on every element's np (at most 2^32 - 2^20); sizes the launches.
  *   scratch : device, >= dks_poisson_batch_scratch_bytes(batch, max_np),
  *             256-byte aligned, caller-owned; element b uses the b-th of
  *             `batch` equal parts (rounded down to 256 bytes).

@@ -61,6 +61,10 @@ template <typename T> hipError_t launch_green_pack(const double*, void*, const i
 
 static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Particles per solve: binned positions are 32-bit, and a lane's loop index
+// may run up to 2^20 past the end of its range before the bound check.
+constexpr int64_t kMaxParticles = (int64_t(1) << 32) - (int64_t(1) << 20);
+
 static bool factor23(int N) {
   if (N < 1) return false;
   while (N % 2 == 0) N /= 2;
@@ -697,7 +701,7 @@ dks_status dks_poisson_workspace_bytes(dks_poisson_plan_t p, size_t* bytes) {
 }
 
 dks_status dks_poisson_particle_scratch_bytes(dks_poisson_plan_t p, int64_t np, size_t* bytes) {
-  if (!p || !bytes || np < 0 || np > (int64_t)UINT32_MAX) return DKS_EINVAL;
+  if (!p || !bytes || np < 0 || np > kMaxParticles) return DKS_EINVAL;
   *bytes = particle_bytes(p, np);
   return DKS_OK;
 }
@@ -711,7 +715,7 @@ dks_status dks_poisson_set_particle_scratch(dks_poisson_plan_t p, void* scratch,
 }
 
 dks_status dks_poisson_batch_scratch_bytes(dks_poisson_plan_t p, int batch, int64_t max_np, size_t* bytes) {
-  if (!p || !bytes || batch < 1 || batch > kMaxBatch || max_np < 0 || max_np > (int64_t)UINT32_MAX)
+  if (!p || !bytes || batch < 1 || batch > kMaxBatch || max_np < 0 || max_np > kMaxParticles)
     return DKS_EINVAL;
   *bytes = (size_t)batch * (p->slot_bytes + particle_bytes(p, max_np));
   return DKS_OK;
@@ -825,7 +829,7 @@ dks_status dks_poisson_host_wait(dks_poisson_plan_t p, uint64_t ticket) {
 dks_status dks_poisson_solve_particles(dks_poisson_plan_t p, const void* x, const void* y, const void* z,
                                        int64_t np, double q, void* Ex, void* Ey, void* Ez, void* phi,
                                        int64_t* n_outside, dks_stream_t stream) {
-  if (!p || np < 0 || np > (int64_t)UINT32_MAX || !std::isfinite(q)) return DKS_EINVAL;
+  if (!p || np < 0 || np > kMaxParticles || !std::isfinite(q)) return DKS_EINVAL;
   if (np > 0 && (!x || !y || !z || !Ex || !Ey || !Ez)) return DKS_EINVAL;
   if (!ws_ready(p)) return DKS_EWORKSPACE;
   if (particle_bytes(p, np) > p->pscratch_bytes) return DKS_EWORKSPACE;
@@ -843,7 +847,7 @@ dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, 
                                                int64_t max_np, void* scratch, size_t scratch_bytes,
                                                dks_stream_t stream) {
   if (!p || batch < 1 || batch > kMaxBatch || !sets) return DKS_EINVAL;
-  if (max_np < 0 || max_np > (int64_t)UINT32_MAX) return DKS_EINVAL;
+  if (max_np < 0 || max_np > kMaxParticles) return DKS_EINVAL;
   if (!ws_ready(p)) return DKS_EWORKSPACE;
   if (!p->prepared) return DKS_ESTATE;
   if (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255u)) return DKS_EWORKSPACE;
@@ -864,7 +868,7 @@ dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, 
 
 dks_status dks_poisson_deposit(dks_poisson_plan_t p, const void* x, const void* y, const void* z, int64_t np,
                                double q, void* rho, int64_t* n_outside, dks_stream_t stream) {
-  if (!p || !rho || np < 0 || np > (int64_t)UINT32_MAX || !std::isfinite(q)) return DKS_EINVAL;
+  if (!p || !rho || np < 0 || np > kMaxParticles || !std::isfinite(q)) return DKS_EINVAL;
   if (np > 0 && (!x || !y || !z)) return DKS_EINVAL;
   if (!ws_ready(p)) return DKS_EWORKSPACE;
   if (particle_bytes(p, np) > p->pscratch_bytes) return DKS_EWORKSPACE;

@@ -91,6 +91,9 @@ def test_workspace_and_state_checks(dks):
         assert lib.dks_poisson_batch_scratch_bytes(plan, 17, 10, sz) == dks.DKS_EINVAL
         assert lib.dks_poisson_batch_scratch_bytes(plan, 2, -1, sz) == dks.DKS_EINVAL
         assert lib.dks_poisson_particle_scratch_bytes(plan, 2 ** 32, sz) == dks.DKS_EINVAL
+        assert lib.dks_poisson_particle_scratch_bytes(plan, 2 ** 32 - 2 ** 20 + 1, sz) == dks.DKS_EINVAL
+        assert lib.dks_poisson_particle_scratch_bytes(plan, 2 ** 32 - 2 ** 20, sz) == dks.DKS_OK
+        assert lib.dks_poisson_batch_scratch_bytes(plan, 1, 2 ** 32 - 2 ** 20 + 1, sz) == dks.DKS_EINVAL
         # batched: table and batch checked before anything else
         assert dks.PARTICLE_SET_BYTES == 80
         tab = ctypes.c_void_p(0x200000)
