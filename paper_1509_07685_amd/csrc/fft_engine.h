@@ -366,12 +366,6 @@ __device__ __forceinline__ void run_any(typename Cplx<T>::type* lds, const FFTPl
 // ---------------------------------------------------------------------------
 // Host helpers of the launchers
 // ---------------------------------------------------------------------------
-static inline int log2_floor(int v) {
-  int l = 0;
-  while ((1 << (l + 1)) <= v) ++l;
-  return l;
-}
-
 // ceil(2^32 / d): __umulhi(e, magic_of(d)) == e / d whenever e * d < 2^32.
 static inline unsigned magic_of(int d) {
   return (unsigned)(((1ull << 32) + (unsigned long long)d - 1) / (unsigned long long)d);

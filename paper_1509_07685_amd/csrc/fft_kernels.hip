@@ -40,7 +40,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __res
                                                         typename Cplx<T>::type* __restrict__ out,
                                                         size_t out_stride, MeshDims m, const FFTPlan* __restrict__ P,
                                                         const typename Cplx<T>::type* __restrict__ post,
-                                                        int nrows, int logTX, unsigned magic_nx) {
+                                                        int nrows, unsigned magic_out, unsigned magic_nx) {
   using C = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
@@ -50,8 +50,6 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __res
   const int row0 = blockIdx.x * Wt;
   const int nvalid = min(Wt, nrows - row0);
   const int nx = m.nx, M = plan_N<SP>(P);
-  const int TX = 1 << logTX;
-  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> logTX, TY = RegCfg<T>::THREADS >> logTX;
   {
     // The tile's rows are contiguous (nvalid * nx reals, at most kTileReals per
     // thread): every load of the thread is issued before the first LDS store.
@@ -89,17 +87,19 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __res
     run_any<T, false, true, SP, 0, true>(lds, P, in, out);
   }
   __syncthreads();
+  // outputs flattened over (row, column) so every lane has work: a row holds
+  // nx + 1 values, which a row-per-lane-group split would leave ragged
   const int ncols = nx + 1;
-  for (int p = ty; p < nvalid; p += TY) {
-    C* orow = dst + (size_t)(row0 + p) * m.cs;
-    for (int k = tx; k < ncols; k += TX) {
-      const C zk = lds[(k == M ? 0 : k) * LDt + p];
-      C zc = lds[(k == 0 ? 0 : M - k) * LDt + p];
-      zc.y = -zc.y;
-      const C s = cadd(zk, zc), d = csub(zk, zc);
-      const C wd = cmul(post[k], d);
-      orow[k] = C{(T)0.5 * (s.x + wd.y), (T)0.5 * (s.y - wd.x)};
-    }
+  const int total = nvalid * ncols;
+  for (int e = (int)threadIdx.x; e < total; e += RegCfg<T>::THREADS) {
+    const int p = (int)__umulhi((unsigned)e, magic_out);
+    const int k = e - p * ncols;
+    const C zk = lds[(k == M ? 0 : k) * LDt + p];
+    C zc = lds[(k == 0 ? 0 : M - k) * LDt + p];
+    zc.y = -zc.y;
+    const C s = cadd(zk, zc), d = csub(zk, zc);
+    const C wd = cmul(post[k], d);
+    dst[(size_t)(row0 + p) * m.cs + k] = C{(T)0.5 * (s.x + wd.y), (T)0.5 * (s.y - wd.x)};
   }
 }
 
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_inv(const typename
                                                         size_t out_stride, ElemBatch phi_user,
                                                         MeshDims m, const FFTPlan* __restrict__ P,
                                                         const typename Cplx<T>::type* __restrict__ post,
-                                                        int nrows, int logTX, unsigned magic_m) {
+                                                        int nrows, unsigned magic_out, unsigned magic_m) {
   using C = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
@@ -287,8 +287,6 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_inv(const typename
   const int row0 = blockIdx.x * Wt;
   const int nvalid = min(Wt, nrows - row0);
   const int nx = m.nx, M = plan_N<SP>(P);
-  const int TX = 1 << logTX;
-  const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x >> logTX, TY = RegCfg<T>::THREADS >> logTX;
   {
     // nvalid * M elements (at most kTileReals per thread), in two halves whose
     // loads are all issued before they are used.
@@ -338,25 +336,27 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_inv(const typename
     run_any<T, true, true, SP, 0>(lds, P, in, out);
   }
   __syncthreads();
+  // outputs flattened over (row, column) so every lane has work (rows of
+  // nx + 2 values)
   const int nout = nx + 2;
   const int ny2 = m.ny + 2;
-  for (int p = ty; p < nvalid; p += TY) {
+  const int total = nvalid * nout;
+  for (int e = (int)threadIdx.x; e < total; e += RegCfg<T>::THREADS) {
+    const int p = (int)__umulhi((unsigned)e, magic_out);
+    const int xo = e - p * nout;
     const int r = row0 + p;          // row index z' * (ny + 2) + y'
-    T* orow = dst + (size_t)r * nout;
-    const int zp = r / ny2, yp = r - zp * ny2;
-    const bool phys = user && zp >= 1 && zp <= m.nz && yp >= 1 && yp <= m.ny;
-    const size_t ubase = phys ? ((size_t)(zp - 1) * m.ny + (yp - 1)) * nx : 0;
-    for (int xo = tx; xo < nout; xo += TX) {
-      const int x = xo - 1;
-      T val;
-      if (x < 0) {
-        val = lds[(M - 1) * LDt + p].y;
-      } else {
-        const C zv = lds[(x >> 1) * LDt + p];
-        val = (x & 1) ? zv.y : zv.x;
-      }
-      orow[xo] = val;
-      if (phys && xo >= 1 && xo <= nx) user[ubase + xo - 1] = val;
+    const int x = xo - 1;
+    T val;
+    if (x < 0) {
+      val = lds[(M - 1) * LDt + p].y;
+    } else {
+      const C zv = lds[(x >> 1) * LDt + p];
+      val = (x & 1) ? zv.y : zv.x;
+    }
+    dst[(size_t)r * nout + xo] = val;
+    if (user && xo >= 1 && xo <= nx) {
+      const int zp = r / ny2, yp = r - zp * ny2;
+      if (zp >= 1 && zp <= m.nz && yp >= 1 && yp <= m.ny) user[((size_t)(zp - 1) * m.ny + (yp - 1)) * nx + xo - 1] = val;
     }
   }
 }
@@ -388,12 +388,11 @@ hipError_t launch_fft_x_fwd(const void* in, size_t in_stride, void* out, size_t 
                             const PlanRef& P, const void* post, int batch, hipStream_t s) {
   using C = typename Cplx<T>::type;
   const int nrows = m.ny * m.nz;
-  const int logTX = log2_floor(std::min(256, std::max(1, m.nx)));
   if ((size_t)P.host.W * m.nx > (size_t)kTileReals * RegCfg<T>::THREADS) return hipErrorInvalidValue;
   dim3 grid((nrows + P.host.W - 1) / P.host.W, batch);
   with_plan<T, 1>(P.host, [&](auto sp) {
     hipLaunchKernelGGL((k_fft_x_fwd<T, decltype(sp)>), grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s,
-                       (const T*)in, in_stride, (C*)out, out_stride, m, P.dev, (const C*)post, nrows, logTX,
+                       (const T*)in, in_stride, (C*)out, out_stride, m, P.dev, (const C*)post, nrows, magic_of(m.nx + 1),
                        magic_of(m.nx));
   });
   return hipGetLastError();
@@ -453,13 +452,12 @@ hipError_t launch_fft_x_inv(const void* D, size_t in_stride, void* phi_ext, size
                             int batch, hipStream_t s) {
   using C = typename Cplx<T>::type;
   const int nrows = (m.ny + 2) * (m.nz + 2);
-  const int logTX = log2_floor(std::min(256, std::max(1, m.nx + 2)));
   if ((size_t)P.host.W * P.host.N > (size_t)kTileReals * RegCfg<T>::THREADS) return hipErrorInvalidValue;
   dim3 grid((nrows + P.host.W - 1) / P.host.W, batch);
   with_plan<T, 1>(P.host, [&](auto sp) {
     hipLaunchKernelGGL((k_fft_x_inv<T, decltype(sp)>), grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s,
                        (const C*)D, in_stride, (T*)phi_ext, out_stride, phi_user, m, P.dev, (const C*)post, nrows,
-                       logTX, magic_of(P.host.N));
+                       magic_of(m.nx + 2), magic_of(P.host.N));
   });
   return hipGetLastError();
 }
