@@ -356,8 +356,8 @@ dks_status dks_fft_plan(int nx, int ny, int nz, int batch, dks_fft_kind kind, dk
   const int ns[3] = {nx, ny, nz};
   for (int n : ns)
     if (n > kMaxLength || !is_23(n)) return DKS_EUNSUPPORTED;
-  const double total = (double)nx * ny * nz * batch;
-  if (total * 16.0 > 1.0e15) return DKS_EINVAL;
+  // every pass's workgroup count must fit a 1-D grid (checked again at launch)
+  if ((double)ny * nz * batch > 2147483647.0) return DKS_EINVAL;
   dks_fft_plan_s* p = new (std::nothrow) dks_fft_plan_s;
   if (!p) return DKS_ENOMEM;
   std::memset(p, 0, sizeof(*p));

@@ -576,23 +576,6 @@ size_t mesh_unit(const dks_poisson_plan_s* p) {
 }
 size_t host_stage_bytes(const dks_poisson_plan_s* p) { return 2 * 5 * mesh_unit(p); }
 
-// Streams and events of the host pipeline, created once on the current device.
-dks_status host_pipe_init(HostPipe& hp) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return DKS_EHIP;
-  if (hp.device >= 0) return hp.device == dev ? DKS_OK : DKS_EINVAL;
-  if (hipStreamCreateWithFlags(&hp.up, hipStreamNonBlocking) != hipSuccess) return DKS_EHIP;
-  if (hipStreamCreateWithFlags(&hp.down, hipStreamNonBlocking) != hipSuccess) return DKS_EHIP;
-  for (int b = 0; b < 2; ++b) {
-    if (hipEventCreateWithFlags(&hp.computed[b], hipEventDisableTiming) != hipSuccess) return DKS_EHIP;
-    if (hipEventCreateWithFlags(&hp.uploaded[b], hipEventDisableTiming) != hipSuccess) return DKS_EHIP;
-  }
-  for (int i = 0; i < kHostRing; ++i)
-    if (hipEventCreateWithFlags(&hp.landed[i], hipEventDisableTiming) != hipSuccess) return DKS_EHIP;
-  hp.device = dev;
-  return DKS_OK;
-}
-
 // Wait for every issued host-resident solve, then release streams and events.
 void host_pipe_release(HostPipe& hp) {
   if (hp.up) (void)hipStreamSynchronize(hp.up);
@@ -600,11 +583,36 @@ void host_pipe_release(HostPipe& hp) {
   for (int b = 0; b < 2; ++b) {
     if (hp.computed[b]) (void)hipEventDestroy(hp.computed[b]);
     if (hp.uploaded[b]) (void)hipEventDestroy(hp.uploaded[b]);
+    hp.computed[b] = hp.uploaded[b] = nullptr;
   }
-  for (int i = 0; i < kHostRing; ++i)
+  for (int i = 0; i < kHostRing; ++i) {
     if (hp.landed[i]) (void)hipEventDestroy(hp.landed[i]);
+    hp.landed[i] = nullptr;
+  }
   if (hp.up) (void)hipStreamDestroy(hp.up);
   if (hp.down) (void)hipStreamDestroy(hp.down);
+  hp.up = hp.down = nullptr;
+}
+
+// Streams and events of the host pipeline, created once on the current device
+// (all or nothing: a failure releases what was made).
+dks_status host_pipe_init(HostPipe& hp) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DKS_EHIP;
+  if (hp.device >= 0) return hp.device == dev ? DKS_OK : DKS_EINVAL;
+  bool ok = hipStreamCreateWithFlags(&hp.up, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&hp.down, hipStreamNonBlocking) == hipSuccess;
+  for (int b = 0; ok && b < 2; ++b)
+    ok = hipEventCreateWithFlags(&hp.computed[b], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&hp.uploaded[b], hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; ok && i < kHostRing; ++i)
+    ok = hipEventCreateWithFlags(&hp.landed[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    host_pipe_release(hp);
+    return DKS_EHIP;
+  }
+  hp.device = dev;
+  return DKS_OK;
 }
 
 // The event that is complete once `ticket` has landed: its own while it is
