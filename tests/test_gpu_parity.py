@@ -377,12 +377,14 @@ def test_repeated_solves_reuse_state():
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_batched_solve_matches_single_solves(dt):
+@pytest.mark.parametrize("scheme,green", [("cic", "integrated"), ("tsc", "integrated"), ("ngp", "point")])
+def test_batched_solve_matches_single_solves(dt, scheme, green):
     """One batched launch over elements with different particle counts and
-    charges equals the elements solved one by one (and the oracle)."""
+    charges equals the elements solved one by one (and the oracle), for each
+    assignment scheme and kernel."""
     d = dks()
     n = (32, 24, 36)
-    plan = d.PoissonPlan(n, None, dt)
+    plan = d.PoissonPlan(n, None, dt, scheme=scheme, green=green)
     counts = [5000, 0, 12345, 1, 30000]
     charges = [1e-13, 2e-13, 5e-14, 1e-12, 3e-14]
     sig = [(1e-3, 1e-3, 1e-3), (1e-3, 1e-3, 1e-3), (0.5e-3, 1.5e-3, 1e-3), (1e-3, 1e-3, 1e-3), (2e-3, 1e-3, 1e-3)]
@@ -405,13 +407,13 @@ def test_batched_solve_matches_single_solves(dt):
     for b, ((x, y, z), c, q) in enumerate(zip(parts, counts, charges)):
         got = np.stack([host(t)[:c] for t in outs[b]])
         assert np.all(host(outs[b][0])[c:] == -1.0)     # nothing written past np
-        single = d.PoissonPlan(n, None, dt)
+        single = d.PoissonPlan(n, None, dt, scheme=scheme, green=green)
         (Ex, Ey, Ez), _, sc = single.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), q)
         alone = np.stack([host(Ex), host(Ey), host(Ez)])
         assert int(cnts[b]) == int(host(sc)[0]) == 0
         if c > 1:
             assert rel_l2(got, alone) <= TOL[dt]
-            ref = orc.solve_particles(x, y, z, q, n, dtype=NP_DT[dt])
+            ref = orc.solve_particles(x, y, z, q, n, dtype=NP_DT[dt], scheme=scheme, green=green)
             assert rel_l2(got, ref["E"]) <= TOL[dt]
         elif c == 1:
             assert np.allclose(got, alone, rtol=0, atol=1e-6 * (np.abs(alone).max() + 1e-30))
