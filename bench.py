@@ -343,15 +343,23 @@ def main():
                          "alg_bytes": alg, "GB_s": alg / (avg * 1e-3) / 1e9 if alg else None}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
     dk = kernels[dom]
+    # a plain 1 GiB device-to-device copy on this GPU: the achievable streaming rate
+    csrc = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    cdst = torch.empty_like(csrc)
+    copy_ms = time_loop(torch, lambda: cdst.copy_(csrc), 10, 2)
+    copy_gbs = 2 * csrc.numel() * 4 / (copy_ms * 1e-3) / 1e9
+    del csrc, cdst
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": dk["GB_s"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
-                "alg_bytes": dk["alg_bytes"]}
+                "alg_bytes": dk["alg_bytes"], "device_copy_GB_s": copy_gbs,
+                "frac_of_device_copy": dk["GB_s"] / copy_gbs}
     conv_names = ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv")
     conv_ms = sum(kernels[k]["avg_ms"] for k in conv_names if k in kernels)
     conv = {"ms": conv_ms, "alg_bytes": conv_bytes(n, 4),
             "GB_s": conv_bytes(n, 4) / (conv_ms * 1e-3) / 1e9,
             "mesh_pts_per_s": mesh_pts / (conv_ms * 1e-3)}
     conv["frac"] = conv["GB_s"] / HBM_PEAK_GBS
+    conv["frac_of_device_copy"] = conv["GB_s"] / copy_gbs
 
     extra = {}
     if not args.no_extra:
