@@ -1,0 +1,44 @@
+/* A plain C client of the three headers: plans, workspace sizes and the
+ * host-side argument checks, with no device work (runs without a GPU).
+ * Prints "ok" and exits 0 when every check holds. */
+#include <stdio.h>
+#include <stdlib.h>
+
+#include "dks_fft.h"
+#include "dks_musr.h"
+#include "dks_poisson.h"
+
+#define CHECK(cond)                                               \
+  do {                                                            \
+    if (!(cond)) {                                                \
+      fprintf(stderr, "check failed at line %d: %s\n", __LINE__, #cond); \
+      return 1;                                                   \
+    }                                                             \
+  } while (0)
+
+int main(void) {
+  dks_poisson_plan_t p = NULL;
+  size_t bytes = 0;
+  CHECK(dks_poisson_plan(64, 64, 64, 1e-4, 1e-4, 1e-4, DKS_F32, &p) == DKS_OK && p != NULL);
+  CHECK(dks_poisson_workspace_bytes(p, &bytes) == DKS_OK && bytes > 0);
+  CHECK(dks_poisson_set_scheme(p, DKS_GREEN_POINT, DKS_ASSIGN_TSC) == DKS_OK);
+  CHECK(dks_poisson_solve_rho(p, NULL, NULL, NULL, NULL) == DKS_EINVAL);
+  CHECK(dks_poisson_host_staging_bytes(p, &bytes) == DKS_OK && bytes >= 10u * 64 * 64 * 64 * 4);
+  CHECK(dks_poisson_destroy(p) == DKS_OK);
+  CHECK(dks_poisson_plan(5, 8, 8, 1.0, 1.0, 1.0, DKS_F64, &p) == DKS_EUNSUPPORTED);
+
+  dks_fft_plan_t f = NULL;
+  CHECK(dks_fft_plan(512, 512, 256, 1, DKS_FFT_C2C, DKS_F32, &f) == DKS_OK);
+  CHECK(dks_fft_workspace_bytes(f, &bytes) == DKS_OK && bytes > 0);
+  CHECK(dks_fft_forward(f, NULL, NULL, NULL) == DKS_EINVAL);
+  CHECK(dks_fft_destroy(f) == DKS_OK);
+
+  dks_musr_plan_t m = NULL;
+  CHECK(dks_musr_plan(16, 206250, 10.0 / 206250, 133, &m) == DKS_OK);
+  CHECK(dks_musr_workspace_bytes(m, &bytes) == DKS_OK && bytes > 0);
+  CHECK(dks_musr_eval(m, DKS_MUSR_CHISQ, NULL, NULL, NULL) == DKS_EINVAL);
+  CHECK(dks_musr_destroy(m) == DKS_OK);
+
+  printf("ok %s\n", dks_status_string(DKS_EWORKSPACE));
+  return 0;
+}

@@ -249,3 +249,22 @@ def test_musr_plan_validation(dks):
         assert lib.dks_musr_set_data(p, None) == dks.DKS_EINVAL
     finally:
         dks.dks_musr_destroy(p)
+
+
+def test_plain_c_client(tmp_path):
+    """The headers compile as C99 with gcc and a C program linked against the
+    library runs its host-side calls."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    exe = tmp_path / "abi_client"
+    libdir = os.path.dirname(LIB)
+    src = os.path.join(ROOT, "tests", "c", "abi_client.c")
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"), src,
+                        "-o", str(exe), "-L", libdir, "-ldks_poisson", f"-Wl,-rpath,{libdir}"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.startswith("ok ")
