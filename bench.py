@@ -37,8 +37,7 @@ def algorithmic_bytes(n, num_particles, s, kernel):
     mesh = nx * ny * nz
     model = {
         "bbox": 3 * s * num_particles,
-        "geometry": 0,
-        "zero_mesh": s * mesh,
+        "geometry": s * mesh,          # the fit and the zero fill of the deposit mesh
         "bin_count": 3 * s * num_particles,
         "bin_scan": 0,
         "bin_scatter": 3 * s * num_particles + 3 * s * num_particles + 4 * num_particles,
@@ -58,7 +57,7 @@ def algorithmic_bytes(n, num_particles, s, kernel):
 
 # Library timing names -> kernel symbols as rocprofv3 reports them.
 KERNEL_SYMBOL = {
-    "bbox": "k_bbox", "geometry": "k_geometry", "zero_mesh": "k_zero", "bin_count": "k_bin_count",
+    "bbox": "k_bbox", "geometry": "k_geometry_zero", "bin_count": "k_bin_count",
     "bin_scan": "k_bin_scan", "bin_scatter": "k_bin_scatter", "deposit": "k_deposit_binned",
     "fft_x_fwd": "k_fft_x_fwd", "fft_y_fwd": "k_fft_y_fwd", "fft_z_conv": "k_fft_z_conv",
     "fft_y_inv": "k_fft_y_inv", "fft_x_inv": "k_fft_x_inv", "gradient": "k_gradient",
@@ -78,7 +77,7 @@ def measured_traffic(kernel):
     doc = json.load(open(TRAFFIC_FILE))
     sym = KERNEL_SYMBOL.get(kernel, "")
     src = ("fft_kernels.hip" if sym.startswith("k_fft") else
-           "particle_kernels.hip" if sym in ("k_bbox", "k_geometry", "k_zero", "k_gradient") else "bin_kernels.hip")
+           "particle_kernels.hip" if sym in ("k_bbox", "k_geometry_zero", "k_gradient") else "bin_kernels.hip")
     deps = (src, "dks_internal.h") + (("fft_engine.h",) if src == "fft_kernels.hip" else ())
     if src == "fft_kernels.hip" and not any(f.endswith("fft_engine.h") for f in doc["sources_sha256"]):
         return None

@@ -81,11 +81,9 @@ __global__ __launch_bounds__(256) void k_bbox(ElemBatch eb, double* partial, siz
 // partials, fit h and the origin, and derive every FP64 factor of the solve.
 // Thread 0 also clears the out-of-mesh counter.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_geometry(const double* partial, size_t partial_stride,
-                                                  Geometry* geo, size_t geo_stride, GeoArgs a,
-                                                  ElemBatch eb) {
+__device__ __forceinline__ void geometry_of(int b, const double* partial, size_t partial_stride, Geometry* geo,
+                                            size_t geo_stride, const GeoArgs& a, const ElemBatch& eb) {
 #pragma clang fp contract(off)
-  const int b = blockIdx.x;
   const dks_particle_set e = eb.at(b);
   Geometry* g = reinterpret_cast<Geometry*>(reinterpret_cast<char*>(geo) + (size_t)b * geo_stride);
   if (a.zero_len > 0) {
@@ -164,14 +162,25 @@ __global__ __launch_bounds__(256) void k_geometry(const double* partial, size_t 
   if (e.n_outside) *e.n_outside = 0;
 }
 
-// Zero `count` elements of batch element blockIdx.y (vectorised, 16 B per store).
-__global__ __launch_bounds__(256) void k_zero(void* base, size_t stride_bytes, size_t bytes) {
-  char* p = reinterpret_cast<char*>(base) + (size_t)blockIdx.y * stride_bytes;
-  const size_t n16 = bytes / 16;
+__global__ __launch_bounds__(256) void k_geometry(const double* partial, size_t partial_stride,
+                                                  Geometry* geo, size_t geo_stride, GeoArgs a,
+                                                  ElemBatch eb) {
+  geometry_of(blockIdx.x, partial, partial_stride, geo, geo_stride, a, eb);
+}
+
+// The geometry of element blockIdx.y (by workgroup 0 of the row) and the
+// zero fill of that element's deposit mesh (by every workgroup of the row):
+// one launch for two steps that do not depend on each other.
+__global__ __launch_bounds__(256) void k_geometry_zero(const double* partial, size_t partial_stride,
+                                                       Geometry* geo, size_t geo_stride, GeoArgs a,
+                                                       ElemBatch eb, void* zbase, size_t zstride, size_t zbytes) {
+  if (blockIdx.x == 0) geometry_of(blockIdx.y, partial, partial_stride, geo, geo_stride, a, eb);
+  char* p = reinterpret_cast<char*>(zbase) + (size_t)blockIdx.y * zstride;
+  const size_t n16 = zbytes / 16;
   uint4* q = reinterpret_cast<uint4*>(p);
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
     q[i] = make_uint4(0, 0, 0, 0);
-  const size_t tail = bytes - n16 * 16;
+  const size_t tail = zbytes - n16 * 16;
   if (blockIdx.x == 0 && threadIdx.x < tail) p[n16 * 16 + threadIdx.x] = 0;
 }
 
@@ -272,9 +281,12 @@ hipError_t launch_geometry(const double* partial, size_t partial_stride, Geometr
   return hipGetLastError();
 }
 
-hipError_t launch_zero(void* base, size_t stride_bytes, size_t bytes, int batch, hipStream_t s) {
-  const unsigned nb = grid_for((int64_t)(bytes / 16 + 1), 8192);
-  hipLaunchKernelGGL(k_zero, dim3(nb, batch), dim3(256), 0, s, base, stride_bytes, bytes);
+hipError_t launch_geometry_zero(const double* partial, size_t partial_stride, Geometry* geo, size_t geo_stride,
+                                const GeoArgs& a, const ElemBatch& eb, int batch, void* zbase, size_t zstride,
+                                size_t zbytes, hipStream_t s) {
+  const unsigned nb = grid_for((int64_t)(zbytes / 16 + 1), 8192);
+  hipLaunchKernelGGL(k_geometry_zero, dim3(nb, batch), dim3(256), 0, s, partial, partial_stride, geo, geo_stride, a,
+                     eb, zbase, zstride, zbytes);
   return hipGetLastError();
 }
 

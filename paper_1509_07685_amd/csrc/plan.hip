@@ -32,7 +32,8 @@ hipError_t launch_store_plans(const FFTPlan* four, FFTPlan* dev, hipStream_t s);
 template <typename T> hipError_t launch_bbox(const ElemBatch&, int, double*, size_t, int*, hipStream_t);
 hipError_t launch_geometry(const double*, size_t, Geometry*, size_t, const GeoArgs&, const ElemBatch&, int,
                            hipStream_t);
-hipError_t launch_zero(void*, size_t, size_t, int, hipStream_t);
+hipError_t launch_geometry_zero(const double*, size_t, Geometry*, size_t, const GeoArgs&, const ElemBatch&, int,
+                                void*, size_t, size_t, hipStream_t);
 template <typename T> hipError_t launch_weights_to_density(const void*, void*, size_t, const Geometry*, double,
                                                            hipStream_t);
 template <typename T> hipError_t launch_gradient(const void*, void*, const Geometry*, const MeshDims&, hipStream_t);
@@ -447,8 +448,8 @@ dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl
   GeoArgs ga = geo_args(p, 1, nb);
   ga.zero_off = p->s_bins;                  // the per-group tile counts
   ga.zero_len = kXcd * (p->bg.K + 1);
-  DKS_TK("geometry", launch_geometry(bbox, sl.stride / sizeof(double), sl.geo(), sl.stride, ga, eb, batch, st));
-  DKS_TK("zero_mesh", launch_zero(sl.base + p->s_r3, sl.stride, p->bytes_W, batch, st));
+  DKS_TK("geometry", launch_geometry_zero(bbox, sl.stride / sizeof(double), sl.geo(), sl.stride, ga, eb, batch,
+                                          sl.base + p->s_r3, sl.stride, p->bytes_W, st));
   DKS_TK("bin_count", launch_bin_count<T>(eb, batch, sl.geo(), sl.stride, sl.base, p->s_bins, p->md, w.bg,
                                           w.count_blocks, st));
   DKS_TK("bin_scan", launch_bin_scan(sl.geo(), sl.stride, sl.base, p->s_bins, w.bg, eb, batch, st));
