@@ -320,6 +320,19 @@ def main():
     per = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
     step_dist = {"p10": float(np.percentile(per, 10)), "p50": float(np.percentile(per, 50)),
                  "p90": float(np.percentile(per, 90)), "steps": len(per)}
+    # the same step captured once as a HIP graph and replayed (one launch per step from the host)
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        step()
+    torch.cuda.current_stream().wait_stream(cap)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=cap):
+        step()
+    torch.cuda.synchronize()
+    graph_ms = time_loop(torch, graph.replay, args.steps, 2)
+    del graph
     # the Green's spectrum build of a fresh plan (FP64 kernel, cosine transforms, packing)
     gp = dks.PoissonPlan(n, None, "f32", prepare=False)
     gp.prepare()
@@ -439,6 +452,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "step_ms": step_dist,
+        "graph_ms_per_step": graph_ms,
         "green_build_ms": green_ms,
         "kernels": kernels,
         "convolution": conv,

@@ -585,3 +585,36 @@ def test_point_kernel_fitted_particle_step_and_scheme_switch():
     (Ex, Ey, Ez), _, _ = plan.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), q)
     ref = orc.solve_particles(x, y, z, q, n, dtype=np.float64)
     assert rel_l2(np.stack([host(Ex), host(Ey), host(Ez)]), ref["E"]) <= TOL[dt]
+
+
+def test_particle_step_replays_from_a_captured_graph():
+    """A full particle step captured into a HIP graph and replayed several
+    times, with eager work between the replays, gives the eager result every
+    time (to rounding: the deposit's merge uses float atomics)."""
+    cfg = wl.UNIFORM_SPHERE
+    x, y, z = wl.particles_for(cfg, dtype="f32", num=200_000)
+    q = wl.TOTAL_CHARGE / x.size
+    plan = dks().PoissonPlan(cfg.n, None, "f32")
+    tx, ty, tz = dev(x, "f32"), dev(y, "f32"), dev(z, "f32")
+    out = tuple(torch.empty(x.size, dtype=torch.float32, device="cuda") for _ in range(3))
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    plan.solve_particles(tx, ty, tz, q, out=out + (cnt,))
+    ref = np.stack([host(t) for t in out])
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        plan.solve_particles(tx, ty, tz, q, out=out + (cnt,))
+    torch.cuda.current_stream().wait_stream(cap)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=cap):
+        plan.solve_particles(tx, ty, tz, q, out=out + (cnt,))
+    for rep in range(4):
+        for t in out:
+            t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = np.stack([host(t) for t in out])
+        assert rel_l2(got, ref) <= 1e-6, rep
+        torch.randn(1 << 20, device="cuda").sum().item()    # unrelated eager work between replays
