@@ -198,56 +198,120 @@ __global__ __launch_bounds__(256) void k_bin_count(ElemBatch eb, const Geometry*
 // block of 1024 threads per batch element.  Also publishes the out-of-mesh
 // count.
 // ---------------------------------------------------------------------------
+// Exclusive prefix sums of (a, b) over the 1024 lanes of the workgroup in
+// lane order: inclusive scans within each wavefront by shuffles, then the
+// wavefront totals; returns the exclusive sums, totals in *ta, *tb.
+__device__ __forceinline__ void scan1024(unsigned a, unsigned b, unsigned* wa, unsigned* wb, unsigned* ea,
+                                         unsigned* eb_, unsigned* ta, unsigned* tb) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned x = a, y = b;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned xo = __shfl_up(x, o, 64), yo = __shfl_up(y, o, 64);
+    if (lane >= o) {
+      x += xo;
+      y += yo;
+    }
+  }
+  if (lane == 63) {
+    wa[w] = x;
+    wb[w] = y;
+  }
+  __syncthreads();
+  unsigned pa = 0, pb = 0, sa = 0, sb = 0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (i < w) {
+      pa += wa[i];
+      pb += wb[i];
+    }
+    sa += wa[i];
+    sb += wb[i];
+  }
+  *ea = pa + x - a;
+  *eb_ = pb + y - b;
+  *ta = sa;
+  *tb = sb;
+}
+
+// Tile counts of one element: per-XCD-group counts summed, exclusive offsets,
+// per-group reservation cursors, and the work-item list.  Each lane owns a
+// contiguous run of tiles; when the run is at most kScanRun tiles (up to
+// 8192 tiles, e.g. a 320^3 mesh) its counts stay in registers and all its
+// loads are issued together.
+constexpr int kScanRun = 8;
 __global__ __launch_bounds__(1024) void k_bin_scan(const Geometry* geo, size_t stride, char* slot_base,
                                                    size_t bins_off, BinGeom bg, ElemBatch eb) {
-  __shared__ unsigned s_cnt[1024];
-  __shared__ unsigned s_itm[1024];
+  __shared__ unsigned wa[16], wb[16];
   const int b = blockIdx.x;
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
   const int L = bg.K + 1;
   const int per = (L + 1023) / 1024;
   const int lo = min((int)threadIdx.x * per, L), hi = min(lo + per, L);
-  unsigned sc = 0, si = 0;
-  for (int k = lo; k < hi; ++k) {
-    unsigned c = 0;
+  unsigned sc = 0, si = 0, oc, oi, tc, ti;
+  if (per <= kScanRun) {
+    unsigned c[kScanRun];
 #pragma unroll
-    for (int x = 0; x < kXcd; ++x) c += st.xcount[x * L + k];
-    st.count[k] = c;
-    sc += c;
-    si += (c + bg.item - 1) / bg.item;
-  }
-  s_cnt[threadIdx.x] = sc;
-  s_itm[threadIdx.x] = si;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    unsigned a = 0, c = 0;
-    if ((int)threadIdx.x >= d) {
-      a = s_cnt[threadIdx.x - d];
-      c = s_itm[threadIdx.x - d];
-    }
-    __syncthreads();
-    s_cnt[threadIdx.x] += a;
-    s_itm[threadIdx.x] += c;
-    __syncthreads();
-  }
-  unsigned oc = s_cnt[threadIdx.x] - sc, oi = s_itm[threadIdx.x] - si;
-  for (int k = lo; k < hi; ++k) {
-    const unsigned c = st.count[k];
-    st.offset[k] = oc;
-    unsigned run = oc;
+    for (int j = 0; j < kScanRun; ++j) {
+      c[j] = 0;
+      if (lo + j < hi) {
 #pragma unroll
-    for (int x = 0; x < kXcd; ++x) {
-      st.xcursor[x * L + k] = run;
-      run += st.xcount[x * L + k];
+        for (int x = 0; x < kXcd; ++x) c[j] += st.xcount[x * L + lo + j];
+      }
     }
-    st.item_off[k] = oi;
-    oc += c;
-    oi += (c + bg.item - 1) / bg.item;
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+      if (lo + j < hi) {
+        st.count[lo + j] = c[j];
+        sc += c[j];
+        si += (c[j] + bg.item - 1) / bg.item;
+      }
+    }
+    scan1024(sc, si, wa, wb, &oc, &oi, &tc, &ti);
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+      const int k = lo + j;
+      if (k < hi) {
+        st.offset[k] = oc;
+        unsigned run = oc;
+#pragma unroll
+        for (int x = 0; x < kXcd; ++x) {
+          st.xcursor[x * L + k] = run;
+          run += st.xcount[x * L + k];
+        }
+        st.item_off[k] = oi;
+        oc += c[j];
+        oi += (c[j] + bg.item - 1) / bg.item;
+      }
+    }
+  } else {
+    for (int k = lo; k < hi; ++k) {
+      unsigned c = 0;
+#pragma unroll
+      for (int x = 0; x < kXcd; ++x) c += st.xcount[x * L + k];
+      st.count[k] = c;
+      sc += c;
+      si += (c + bg.item - 1) / bg.item;
+    }
+    scan1024(sc, si, wa, wb, &oc, &oi, &tc, &ti);
+    for (int k = lo; k < hi; ++k) {
+      const unsigned c = st.count[k];
+      st.offset[k] = oc;
+      unsigned run = oc;
+#pragma unroll
+      for (int x = 0; x < kXcd; ++x) {
+        st.xcursor[x * L + k] = run;
+        run += st.xcount[x * L + k];
+      }
+      st.item_off[k] = oi;
+      oc += c;
+      oi += (c + bg.item - 1) / bg.item;
+    }
   }
   if (threadIdx.x == 1023) {
-    st.offset[L] = s_cnt[1023];
-    st.item_off[L] = s_itm[1023];
-    st.misc[0] = s_itm[1023];
+    st.offset[L] = tc;
+    st.item_off[L] = ti;
+    st.misc[0] = ti;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
