@@ -426,6 +426,10 @@ def main():
             torch.cuda.empty_cache()
             # the same stream at 8x the rate: requests queue, batches form
             extra["serving_4000_per_s"] = serve.bench_stream(torch, rate_hz=4000.0)
+            torch.cuda.empty_cache()
+            # transfer-inclusive: requests start and end in page-locked host memory
+            extra["serving_host_io"] = serve.bench_stream(torch, num_requests=500, host_io=True)
+            progress("serving with transfers done")
         except ImportError:
             extra["serving"] = None
 

@@ -265,7 +265,11 @@ class Executor:
     (dks_particle_set) with its pinned host twin, the out-of-mesh counters,
     and one HIP graph per batch size captured over the table.  A launch
     rewrites the table (one small host-to-device copy) and replays the graph:
-    the kernels read the requests' own device buffers, so nothing is staged."""
+    the kernels read the requests' own device buffers, so nothing is staged.
+    With host-resident requests (backend.host_io) the executor also owns a
+    device slot per batch element; a launch uploads each request's positions
+    into its slot, replays the graph over the slots and downloads the fields,
+    all on the launch's stream."""
 
     def __init__(self, backend, key):
         torch = backend.torch
@@ -282,6 +286,10 @@ class Executor:
         self.table_dev = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
         self.cnt = torch.zeros(B, dtype=torch.int64, device=dev)
         self.scratch = self.plan.batch_scratch(B, M)
+        self.host_io = backend.host_io
+        if self.host_io:
+            tdt = torch.float32 if key[1] == "f32" else torch.float64
+            self.slots = torch.empty((B, 6, M), dtype=tdt, device=dev)   # x, y, z, Ex, Ey, Ez
         self.graphs = {}
         self.use_graphs = backend.use_graphs
         self._dks = dks
@@ -311,9 +319,13 @@ class Executor:
         t = self.table_view
         base = self.cnt.data_ptr()
         for i, j in enumerate(jobs):
-            x, y, z, outs = j.payload
-            t[i] = (x.data_ptr(), y.data_ptr(), z.data_ptr(), outs[0].data_ptr(), outs[1].data_ptr(),
-                    outs[2].data_ptr(), 0, base + 8 * i, j.num_particles, j.charge)
+            if self.host_io:
+                v = [self.slots[i, c].data_ptr() for c in range(6)]
+            else:
+                x, y, z, outs = j.payload
+                v = [x.data_ptr(), y.data_ptr(), z.data_ptr(), outs[0].data_ptr(), outs[1].data_ptr(),
+                     outs[2].data_ptr()]
+            t[i] = (*v, 0, base + 8 * i, j.num_particles, j.charge)
         return len(jobs) * self._dks.PARTICLE_SET_BYTES
 
     def run(self, jobs, stream, torch):
@@ -323,17 +335,29 @@ class Executor:
         b = len(jobs)
         nbytes = self.fill(jobs)
         with torch.cuda.stream(stream):
+            if self.host_io:
+                for i, j in enumerate(jobs):
+                    n = j.num_particles
+                    for c in range(3):
+                        self.slots[i, c, :n].copy_(j.payload[c], non_blocking=True)
             if self.use_graphs:
                 self.graphs[b].replay()
             else:
                 self.table_dev[:nbytes].copy_(self.table_host[:nbytes], non_blocking=True)
                 self.plan.solve_particles_batched(self.table_dev, b, self.max_np, self.scratch, stream=stream)
+            if self.host_io:
+                for i, j in enumerate(jobs):
+                    n = j.num_particles
+                    for c in range(3):
+                        j.payload[3][c].copy_(self.slots[i, 3 + c, :n], non_blocking=True)
 
 
 class GpuBackend:
-    def __init__(self, torch, max_batch=8, num_streams=4, max_np=1_000_000, use_graphs=True, device="cuda"):
+    def __init__(self, torch, max_batch=8, num_streams=4, max_np=1_000_000, use_graphs=True, device="cuda",
+                 host_io=False):
         from paper_1509_07685_amd import dks
         self.torch = torch
+        self.host_io = host_io          # requests' particles and fields live in page-locked host memory
         self.dks = dks
         self.max_batch = max_batch
         self.num_streams = num_streams
@@ -365,7 +389,8 @@ class GpuBackend:
                 scratch = d.dks_poisson_batch_scratch_bytes(h, self.max_batch, self.max_np)
             finally:
                 d.dks_poisson_destroy(h)
-            self._sizes[key] = (ws, scratch + self.max_batch * (d.PARTICLE_SET_BYTES + 8))
+            slots = 6 * self.max_batch * self.max_np * (4 if dt == "f32" else 8) if self.host_io else 0
+            self._sizes[key] = (ws, scratch + self.max_batch * (d.PARTICLE_SET_BYTES + 8) + slots)
         return self._sizes[key]
 
     def plan_bytes(self, key):
@@ -407,25 +432,32 @@ class GpuBackend:
         return None
 
 
-def make_jobs(torch, requests, device="cuda", dtype_override=None):
-    """Device-resident inputs and outputs for each request (staged before the clock)."""
+def make_jobs(torch, requests, device="cuda", dtype_override=None, host=False):
+    """Inputs and outputs of each request, made before the clock starts: in
+    device memory, or (host=True) in page-locked host memory."""
     from paper_1509_07685_amd import workloads as wl
     jobs = []
     for r in requests:
         dt = dtype_override or r.dtype
         tdt = torch.float32 if dt == "f32" else torch.float64
         x, y, z = wl.gaussian_bunch_torch(torch, r.num_particles, r.sigma, r.seed, tdt, device)
-        outs = tuple(torch.empty(r.num_particles, dtype=tdt, device=device) for _ in range(3))
+        if host:
+            x, y, z = (t.cpu().pin_memory() for t in (x, y, z))
+            outs = tuple(torch.empty(r.num_particles, dtype=tdt).pin_memory() for _ in range(3))
+        else:
+            outs = tuple(torch.empty(r.num_particles, dtype=tdt, device=device) for _ in range(3))
         jobs.append(Job(r.rid, r.arrival_s, (tuple(r.n), dt), r.num_particles, r.charge_per_particle,
                         payload=(x, y, z, outs)))
     return jobs
 
 
-def serve_sequential(torch, jobs, clock=time.perf_counter, device="cuda"):
+def serve_sequential(torch, jobs, clock=time.perf_counter, device="cuda", host_io=False):
     """Baseline: one solve at a time in arrival order, one stream, no batching
-    or graphs (plans are still cached per shape)."""
+    or graphs (plans are still cached per shape).  host_io: the requests live
+    in host memory; each is uploaded, solved and downloaded before the next."""
     from paper_1509_07685_amd import dks
     plans = {}
+    bufs = {}
     cnt = torch.zeros(1, dtype=torch.int64, device=device)
     t0 = clock()
     s = torch.cuda.current_stream()
@@ -438,7 +470,20 @@ def serve_sequential(torch, jobs, clock=time.perf_counter, device="cuda"):
             p.reserve_particles(1_000_000)
         x, y, z, outs = j.payload
         j.start_s = clock() - t0
-        p.solve_particles(x, y, z, j.charge, out=(outs[0], outs[1], outs[2], cnt), stream=s)
+        if host_io:
+            buf = bufs.get(j.key[1])
+            if buf is None:
+                tdt = torch.float32 if j.key[1] == "f32" else torch.float64
+                buf = bufs[j.key[1]] = torch.empty((6, 1_000_000), dtype=tdt, device=device)
+            n = j.num_particles
+            for c, t in enumerate((x, y, z)):
+                buf[c, :n].copy_(t, non_blocking=True)
+            p.solve_particles(buf[0, :n], buf[1, :n], buf[2, :n], j.charge,
+                              out=(buf[3, :n], buf[4, :n], buf[5, :n], cnt), stream=s)
+            for c in range(3):
+                outs[c].copy_(buf[3 + c, :n], non_blocking=True)
+        else:
+            p.solve_particles(x, y, z, j.charge, out=(outs[0], outs[1], outs[2], cnt), stream=s)
         s.synchronize()
         j.done_s = clock() - t0
         j.status = "done"
@@ -449,11 +494,14 @@ def serve_sequential(torch, jobs, clock=time.perf_counter, device="cuda"):
             "p99_ms": percentile(lat, 0.99), "mean_ms": sum(lat) / len(lat), "wall_s": clock() - t0}
 
 
-def bench_stream(torch, num_requests=2000, rate_hz=500.0, seed=5, budget_bytes=64 * GiB, use_graphs=True):
-    """The mixed-size request stream: batched server vs the one-at-a-time FP64 path."""
+def bench_stream(torch, num_requests=2000, rate_hz=500.0, seed=5, budget_bytes=64 * GiB, use_graphs=True,
+                 host_io=False):
+    """The mixed-size request stream: batched server vs the one-at-a-time FP64
+    path.  host_io: requests start and end in page-locked host memory, and
+    both latencies include the uploads and downloads."""
     from paper_1509_07685_amd import workloads as wl
     reqs = wl.serving_stream(num_requests, rate_hz, seed)
-    backend = GpuBackend(torch, use_graphs=use_graphs)
+    backend = GpuBackend(torch, use_graphs=use_graphs, host_io=host_io)
     sched = Scheduler(backend, budget_bytes)
     # off the clock: resident plans and executors (graphs captured) for every
     # (shape, dtype) of the stream, then one short warm-up pass
@@ -462,23 +510,29 @@ def bench_stream(torch, num_requests=2000, rate_hz=500.0, seed=5, budget_bytes=6
         for k in keys:
             sched.prewarm(k, per)
     warm = make_jobs(torch, [dataclasses.replace(r, arrival_s=0.0, num_particles=1000)
-                             for r in reqs[:60]])
+                             for r in reqs[:60]], host=host_io)
     sched.run(warm)
     torch.cuda.synchronize()
-    jobs = make_jobs(torch, reqs)
+    jobs = make_jobs(torch, reqs, host=host_io)
     torch.cuda.synchronize()
     stats = sched.run(jobs)
     torch.cuda.synchronize()
     del jobs
+    for ex_list in sched.idle.values():
+        for ex in ex_list:
+            backend.destroy_executor(ex)
+    sched.idle.clear()
+    sched.lru.clear()
     torch.cuda.empty_cache()
-    base_jobs = make_jobs(torch, reqs, dtype_override="f64")
+    base_jobs = make_jobs(torch, reqs, dtype_override="f64", host=host_io)
     torch.cuda.synchronize()
     serve_sequential(torch, make_jobs(torch, [dataclasses.replace(r, arrival_s=0.0, num_particles=1000)
-                                                 for r in reqs[:20]], dtype_override="f64"))
-    base = serve_sequential(torch, base_jobs)
+                                              for r in reqs[:20]], dtype_override="f64", host=host_io),
+                     host_io=host_io)
+    base = serve_sequential(torch, base_jobs, host_io=host_io)
     del base_jobs
     torch.cuda.empty_cache()
     out = stats.as_dict()
     out.update({"requests": num_requests, "rate_hz": rate_hz, "budget_GiB": budget_bytes / GiB,
-                "baseline_fp64_one_at_a_time": base})
+                "transfers_included": host_io, "baseline_fp64_one_at_a_time": base})
     return out

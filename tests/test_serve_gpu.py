@@ -89,3 +89,28 @@ def test_budget_too_small_refuses_everything_cleanly():
     be = serve.GpuBackend(torch, max_batch=2, num_streams=1, max_np=10_000)
     stats = serve.Scheduler(be, budget_bytes=1 << 20).run(jobs)
     assert stats.refused == 5 and stats.completed == 0
+
+
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_host_resident_requests_match_device_solves(use_graphs):
+    """Requests whose particles and fields live in page-locked host memory:
+    uploaded into the executor's slots, solved in batches, downloaded; each
+    result equals the request solved alone on the device."""
+    from paper_1509_07685_amd import dks
+    reqs = wl.serving_stream(16, rate_hz=20000.0, seed=12, min_log10=3.0, max_log10=4.3,
+                             shapes=((32, 32, 32), (48, 48, 48)))
+    jobs = serve.make_jobs(torch, reqs, host=True)
+    be = serve.GpuBackend(torch, max_batch=4, num_streams=2, max_np=30_000, use_graphs=use_graphs, host_io=True)
+    stats = serve.Scheduler(be, budget_bytes=8 << 30).run(jobs)
+    torch.cuda.synchronize()
+    assert stats.completed == len(reqs) and max(stats.batch_hist) > 1
+    plans = {}
+    for j in jobs:
+        shape, dt = j.key
+        p = plans.get(j.key) or plans.setdefault(j.key, dks.PoissonPlan(shape, None, dt))
+        x, y, z, outs = j.payload
+        assert outs[0].device.type == "cpu"
+        (Ex, Ey, Ez), _, _ = p.solve_particles(x.cuda(), y.cuda(), z.cuda(), j.charge)
+        torch.cuda.synchronize()
+        for got, alone in zip(outs, (Ex, Ey, Ez)):
+            assert rel_l2(got, alone) <= TOL[dt]
