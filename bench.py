@@ -228,7 +228,14 @@ def cpu_baseline():
     for _ in range(reps):
         orc.solve_particles(x, y, z, wl.TOTAL_CHARGE / x.size, n, dtype=np.float32)
     dt = (time.perf_counter() - t0) / reps
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n[0] * n[1] * n[2] / dt, "unit": "mesh-pts/s", "cores": 1, "kind": "oracle",
+            "host_cpu": model, "host_threads": len(os.sched_getaffinity(0)),
             "sample": "FP64 numpy oracle, full particle step (fit, CIC deposit, IGF, doubled-grid FFT "
                       "convolution, gradient, gather) on a 128^3 fitted mesh with 1.25e7 particles of the "
                       "halo-Gaussian bunch (the 256^3 / 1e8 workload scaled by 1/8), mean of three runs; "
