@@ -58,6 +58,17 @@ template <int SCH> constexpr int apron_edge() { return acc_edge<SCH>() + 2; }
 constexpr int kDepositThreads = 1024;
 constexpr int kGatherThreads = 512;
 
+// FP32 CIC gather: phi staged as (phi(x), phi(x + 1)) pairs, so that the 32
+// node values of a particle come in 16 eight-byte LDS reads instead of 32
+// four-byte ones (the gather is bound by the bank conflicts of these reads).
+constexpr bool kPairPhi = true;
+template <typename T, int SCH> constexpr bool pair_phi() {
+  return kPairPhi && SCH == kSchemeCIC && sizeof(T) == 4;
+}
+// The paired tile takes 54 KB of LDS, which leaves room for two workgroups
+// per CU: 1024 lanes each keep the CU's wave slots filled.
+template <typename T, int SCH> constexpr int gather_threads() { return pair_phi<T, SCH>() ? 1024 : kGatherThreads; }
+
 // Binned records each lane loads before using any.
 constexpr int kUnrollDeposit = 4;
 constexpr int kUnrollGather = 1;
@@ -331,6 +342,12 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const Geometry* geo, size_t s
 // and the inverse permutation are written.  A chunk therefore occupies one
 // short contiguous segment per touched tile, which is what lets the unsort
 // pass read a chunk's records back with few cache lines.
+//
+// STAGE (the histogram and the whole chunk fit in LDS): the records are first
+// placed in LDS in the chunk's own tile order (exclusive scan of the chunk's
+// tile counts), then lane p stores record p, so each wavefront's stores cover
+// contiguous runs of the destination segments instead of 64 unrelated
+// addresses.
 // ---------------------------------------------------------------------------
 
 // Particle of slot j (of `per`) of this thread in the chunk starting at c0:
@@ -342,15 +359,26 @@ __device__ __forceinline__ int64_t chunk_index(bool vec, int64_t c0, int j) {
              : c0 + threadIdx.x + (int64_t)j * THREADS;
 }
 
-template <typename T, bool LDSHIST, int SCH>
+// LDS bytes of the staged scatter: tile counts/offsets and bases, then the
+// chunk's records and their tile keys.
+template <typename T> constexpr size_t scatter_stage_lds(int K) {
+  return 2 * (size_t)(K + 1) * sizeof(unsigned) + (size_t)scatter_chunk<T>() * (sizeof(Rec<T>) + sizeof(unsigned short));
+}
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;   // gfx950
+// Tiles per lane in the staged scan: the staged path needs K + 1 <= 8 * 1024.
+constexpr int kStageRun = 8;
+
+template <typename T, bool LDSHIST, bool STAGE, int SCH>
 __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, const Geometry* geo, size_t stride,
                                                                  char* slot_base, size_t bins_off,
                                                                  char* sorted_base, size_t sorted_stride,
                                                                  size_t inv_off, MeshDims m, BinGeom bg) {
   extern __shared__ unsigned lds[];
+  __shared__ unsigned wa[16], wb[16];
   constexpr int PER = chunk_per<T, kScatterThreads>();
   constexpr int NV = Vec16<T>::n;
   constexpr int64_t CH = scatter_chunk<T>();
+  static_assert(!STAGE || LDSHIST, "staging needs the LDS histogram");
   using P4 = Rec<T>;
   using V = typename Vec16<T>::type;
   const int b = blockIdx.y;
@@ -360,10 +388,17 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
   if (c0 >= n) return;                       // whole workgroup: no barrier is skipped by part of it
   unsigned* lcnt = lds;
   unsigned* lbase = lds + (bg.K + 1);
+  // 2 (K + 1) words precede the records: 8-byte aligned for FP64 records
+  P4* srec = reinterpret_cast<P4*>(lds + 2 * (bg.K + 1));
+  unsigned short* skey = reinterpret_cast<unsigned short*>(srec + CH);
   const T* px = (const T*)e.x;
   const T* py = (const T*)e.y;
   const T* pz = (const T*)e.z;
-  const Geometry* g = geo_of(geo, stride, b);
+  // A private copy of the geometry: the LDS atomics between the particles'
+  // cell decisions would otherwise make the compiler reload its fields (and
+  // wait for them) once per particle.
+  const Geometry gcopy = *geo_of(geo, stride, b);
+  const Geometry* g = &gcopy;
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
   unsigned* cursor = st.xcursor + (int)(((int64_t)b * gridDim.x + blockIdx.x) % kXcd) * (bg.K + 1);
   P4* out = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
@@ -414,6 +449,97 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
     key[j] = i < n ? locate<T, SCH>(xs[j], ys[j], zs[j], g, m, bg).key : -1;
     if (LDSHIST) rank[j] = key[j] >= 0 ? atomicAdd(&lcnt[key[j]], 1u) : 0u;
     else rank[j] = key[j] >= 0 ? atomicAdd(&cursor[key[j]], 1u) : 0u;
+  }
+  if constexpr (STAGE) {
+    // Each lane owns a contiguous run of at most kStageRun tiles: chunk-local
+    // exclusive offsets replace the counts in lcnt, and lbase holds (reserved
+    // global start - local offset), so that a record's destination is its
+    // local position plus lbase of its tile.  The lane's reservations are all
+    // issued before the scan and their results used after it.
+    __syncthreads();
+    const int L = bg.K + 1;
+    const int per = (L + kScatterThreads - 1) / kScatterThreads;
+    const int lo = min((int)threadIdx.x * per, L), hi = min(lo + per, L);
+    unsigned cv[kStageRun], rv[kStageRun];
+    unsigned sum = 0;
+#pragma unroll
+    for (int q = 0; q < kStageRun; ++q) {
+      cv[q] = lo + q < hi ? lcnt[lo + q] : 0u;
+      sum += cv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kStageRun; ++q) rv[q] = cv[q] ? atomicAdd(&cursor[lo + q], cv[q]) : 0u;
+    unsigned off, unused0, unused1, unused2;
+    scan1024(sum, 0u, wa, wb, &off, &unused0, &unused1, &unused2);
+#pragma unroll
+    for (int q = 0; q < kStageRun; ++q) {
+      if (lo + q < hi) {
+        lcnt[lo + q] = off;
+        lbase[lo + q] = rv[q] - off;
+        off += cv[q];
+      }
+    }
+    __syncthreads();
+    // Records and keys into LDS at their local positions; every destination
+    // is formed before the inverse permutation is stored (vector stores of
+    // a lane's consecutive particles in the vector layout).
+    unsigned dv[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      dv[j] = 0u;
+      if (key[j] >= 0) {
+        const unsigned lp = lcnt[key[j]] + rank[j];
+        srec[lp] = P4{xs[j], ys[j], zs[j]};
+        skey[lp] = (unsigned short)key[j];
+        dv[j] = lp + lbase[key[j]];
+      }
+    }
+    if (vec) {
+      struct alignas(NV * sizeof(unsigned)) U { unsigned v[NV]; };
+#pragma unroll
+      for (int q = 0; q < PER / NV; ++q) {
+        const int64_t i = chunk_index<T, kScatterThreads>(true, c0, q * NV);
+        if (i + NV <= n) {
+          U u;
+#pragma unroll
+          for (int k = 0; k < NV; ++k) u.v[k] = dv[q * NV + k];
+          *reinterpret_cast<U*>(inv + i) = u;
+        } else {
+#pragma unroll
+          for (int k = 0; k < NV; ++k)
+            if (i + k < n) inv[i + k] = dv[q * NV + k];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int64_t i = chunk_index<T, kScatterThreads>(false, c0, j);
+        if (i < n) inv[i] = dv[j];
+      }
+    }
+    __syncthreads();
+    // The chunk's valid particles fill local positions 0 .. nv - 1; a lane
+    // reads all of its records before storing any.
+    const unsigned nv = (unsigned)min(CH, n - c0);   // >= 1
+    T rx[PER], ry[PER], rz[PER];
+    unsigned dd[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      // lanes past the end re-read the last record and store nothing
+      const unsigned p = min(threadIdx.x + (unsigned)j * kScatterThreads, nv - 1);
+      const P4 r = srec[p];
+      rx[j] = r.x;
+      ry[j] = r.y;
+      rz[j] = r.z;
+      dd[j] = p + lbase[skey[p]];
+    }
+    // Keep the reads above the stores: a store's registers cannot be reused
+    // before it completes, so interleaving would serialise the stores.
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+      if (threadIdx.x + (unsigned)j * kScatterThreads < nv) out[dd[j]] = P4{rx[j], ry[j], rz[j]};
+    return;
   }
   if (LDSHIST) {
     __syncthreads();
@@ -523,12 +649,14 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geomet
 // gather with the central-difference field formed on the fly from staged phi.
 // ---------------------------------------------------------------------------
 template <typename T, int SCH>
-__global__ __launch_bounds__(kGatherThreads) void k_gather_binned(const Geometry* geo, size_t stride, char* slot_base,
+__global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(const Geometry* geo, size_t stride, char* slot_base,
                                                        size_t bins_off, char* sorted_base, size_t sorted_stride,
                                                        const T* __restrict__ phi_ext, size_t phi_stride,
                                                        MeshDims m, BinGeom bg) {
   constexpr int A = apron_edge<SCH>(), NA = A * A * A, WD = Scheme<SCH>::width;
-  __shared__ T ph[NA];
+  constexpr bool PAIR = pair_phi<T, SCH>();
+  // Staged phi: one value per node, or (node, node + 1 in x) pairs.
+  __shared__ typename std::conditional<PAIR, float2, T>::type ph[NA];
   using P4 = Rec<T>;
   const int b = blockIdx.y;
   const Geometry* g = geo_of(geo, stride, b);
@@ -553,8 +681,16 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_binned(const Geometry
     for (int e = threadIdx.x; e < NA; e += blockDim.x) {
       const int ex = e % A, ey = (e / A) % A, ez = e / (A * A);
       const int x = bx + ex, y = by + ey, z = bz + ez;
-      ph[e] = (x >= 0 && y >= 0 && z >= 0 && x < nx2 && y < ny2 && z < nz2) ? phi[((size_t)z * ny2 + y) * nx2 + x]
-                                                                           : (T)0;
+      const bool in_yz = y >= 0 && z >= 0 && y < ny2 && z < nz2;
+      const T* row = phi + ((size_t)z * ny2 + y) * nx2;
+      const T v0 = (in_yz && x >= 0 && x < nx2) ? row[x] : (T)0;
+      if constexpr (PAIR) {
+        // the second value of the last pair of a row is never read
+        const T v1 = (in_yz && ex + 1 < A && x + 1 >= 0 && x + 1 < nx2) ? row[x + 1] : (T)0;
+        ph[e] = make_float2(v0, v1);
+      } else {
+        ph[e] = v0;
+      }
     }
     __syncthreads();
     for (unsigned i0 = s0 + threadIdx.x; i0 < s1; i0 += kUnrollGather * blockDim.x) {
@@ -571,9 +707,61 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_binned(const Geometry
         const P4 p = pr[u];
         const Cell<T, SCH> c = locate<T, SCH>(p.x, p.y, p.z, g, m, bg);
         // staged index of the first stencil node: (node - tile's first node) + 1 per axis
-        const T* o = ph + ((c.bz - bz + 1) * A + (c.by - by + 1)) * A + (c.bx - bx + 1);
+        const int o_idx = ((c.bz - bz + 1) * A + (c.by - by + 1)) * A + (c.bx - bx + 1);
         T ax = 0, ay = 0, az = 0;
-        if constexpr (SCH == kSchemeCIC) {
+        if constexpr (PAIR) {
+          const float2* o = ph + o_idx;
+          const float* wx = c.wx;
+          const float* wy = c.wy;
+          const float* wz = c.wz;
+          // the same 32 values as the scalar CIC path below, two per read
+          float r[2][2][4], ym[2][2], yp[2][2], zm[2][2], zp[2][2];
+#pragma unroll
+          for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+            for (int ky = 0; ky < 2; ++ky) {
+              const float2 lo = o[(kz * A + ky) * A - 1], hi = o[(kz * A + ky) * A + 1];
+              r[kz][ky][0] = lo.x;
+              r[kz][ky][1] = lo.y;
+              r[kz][ky][2] = hi.x;
+              r[kz][ky][3] = hi.y;
+            }
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const float2 qym = o[(a * A - 1) * A], qyp = o[(a * A + 2) * A];
+            const float2 qzm = o[(-A + a) * A], qzp = o[(2 * A + a) * A];
+            ym[a][0] = qym.x;
+            ym[a][1] = qym.y;
+            yp[a][0] = qyp.x;
+            yp[a][1] = qyp.y;
+            zm[a][0] = qzm.x;
+            zm[a][1] = qzm.y;
+            zp[a][0] = qzp.x;
+            zp[a][1] = qzp.y;
+          }
+#pragma unroll
+          for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+            for (int ky = 0; ky < 2; ++ky) {
+              const float d0 = r[kz][ky][2] - r[kz][ky][0], d1 = r[kz][ky][3] - r[kz][ky][1];
+              ax += wz[kz] * wy[ky] * (wx[0] * d0 + wx[1] * d1);
+            }
+#pragma unroll
+          for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+            for (int kx = 0; kx < 2; ++kx) {
+              const float d0 = r[kz][1][kx + 1] - ym[kz][kx], d1 = yp[kz][kx] - r[kz][0][kx + 1];
+              ay += wz[kz] * wx[kx] * (wy[0] * d0 + wy[1] * d1);
+            }
+#pragma unroll
+          for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 2; ++kx) {
+              const float d0 = r[1][ky][kx + 1] - zm[ky][kx], d1 = zp[ky][kx] - r[0][ky][kx + 1];
+              az += wy[ky] * wx[kx] * (wz[0] * d0 + wz[1] * d1);
+            }
+        } else if constexpr (SCH == kSchemeCIC) {
+          const T* o = ph + o_idx;
           const T* wx = c.wx;
           const T* wy = c.wy;
           const T* wz = c.wz;
@@ -620,6 +808,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_binned(const Geometry
               az += wy[ky] * wx[kx] * (wz[0] * d0 + wz[1] * d1);
             }
         } else {
+          const T* o = ph + o_idx;
           // every stencil node: weight * (phi(+1) - phi(-1)) per axis
 #pragma unroll
           for (int kz = 0; kz < WD; ++kz)
@@ -759,15 +948,21 @@ hipError_t launch_bin_scatter(const ElemBatch& eb, int batch, const Geometry* ge
   const int64_t ch = scatter_chunk<T>();
   const unsigned nchunk = (unsigned)((eb.max_np + ch - 1) / ch);
   const bool lh = bg.lds_hist != 0;
-  const size_t lds = lh ? 2 * (size_t)(bg.K + 1) * sizeof(unsigned) : 0;
+  // 256 bytes left for the static scan scratch
+  const bool stage = lh && scatter_stage_lds<T>(bg.K) + 256 <= kLdsPerWorkgroup &&
+                     bg.K + 1 <= kStageRun * kScatterThreads;
+  const size_t lds = stage ? scatter_stage_lds<T>(bg.K) : lh ? 2 * (size_t)(bg.K + 1) * sizeof(unsigned) : 0;
   with_scheme(bg.scheme, [&](auto sc) {
     constexpr int SCH = decltype(sc)::value;
-    if (lh)
-      hipLaunchKernelGGL((k_bin_scatter<T, true, SCH>), dim3(nchunk, batch), dim3(kScatterThreads), lds, s, eb, geo,
-                         stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
+    if (stage)
+      hipLaunchKernelGGL((k_bin_scatter<T, true, true, SCH>), dim3(nchunk, batch), dim3(kScatterThreads), lds, s, eb,
+                         geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
+    else if (lh)
+      hipLaunchKernelGGL((k_bin_scatter<T, true, false, SCH>), dim3(nchunk, batch), dim3(kScatterThreads), lds, s,
+                         eb, geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
     else
-      hipLaunchKernelGGL((k_bin_scatter<T, false, SCH>), dim3(nchunk, batch), dim3(kScatterThreads), 0, s, eb, geo,
-                         stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
+      hipLaunchKernelGGL((k_bin_scatter<T, false, false, SCH>), dim3(nchunk, batch), dim3(kScatterThreads), 0, s,
+                         eb, geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
   });
   return hipGetLastError();
 }
@@ -788,7 +983,8 @@ hipError_t launch_gather_binned(const Geometry* geo, size_t stride, char* slot_b
                                 char* sorted_base, size_t sorted_stride, const void* phi_ext, size_t phi_stride,
                                 const MeshDims& m, const BinGeom& bg, int nblk, int batch, hipStream_t s) {
   with_scheme(bg.scheme, [&](auto sc) {
-    hipLaunchKernelGGL((k_gather_binned<T, decltype(sc)::value>), dim3(nblk, batch), dim3(kGatherThreads), 0, s,
+    constexpr int SCH = decltype(sc)::value;
+    hipLaunchKernelGGL((k_gather_binned<T, SCH>), dim3(nblk, batch), dim3(gather_threads<T, SCH>()), 0, s,
                        geo, stride, slot_base, bins_off, sorted_base, sorted_stride, (const T*)phi_ext, phi_stride, m,
                        bg);
   });

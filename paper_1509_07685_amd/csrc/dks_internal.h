@@ -118,11 +118,16 @@ template <> struct Vec16<double> {
   typedef double type __attribute__((ext_vector_type(2)));
   static constexpr int n = 2;
 };
+// The particle arrays come in through generic pointers; addressing them as
+// global memory gives global (not flat) loads and stores, which do not share
+// the LDS wait counter.
 template <typename T> __device__ __forceinline__ typename Vec16<T>::type ld_stream(const T* p) {
-  return __builtin_nontemporal_load(reinterpret_cast<const typename Vec16<T>::type*>(p));
+  using V = typename Vec16<T>::type;
+  return __builtin_nontemporal_load((const __attribute__((address_space(1))) V*)p);
 }
 template <typename T> __device__ __forceinline__ void st_stream(T* p, typename Vec16<T>::type v) {
-  __builtin_nontemporal_store(v, reinterpret_cast<typename Vec16<T>::type*>(p));
+  using V = typename Vec16<T>::type;
+  __builtin_nontemporal_store(v, (__attribute__((address_space(1))) V*)p);
 }
 
 __device__ __forceinline__ bool aligned16(const void* a, const void* b, const void* c) {

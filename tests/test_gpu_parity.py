@@ -464,6 +464,21 @@ def test_deposit_with_global_tile_histogram():
     assert rel_l2(host(rho), Q / (h[0] * h[1] * h[2])) <= TOL[dt]
 
 
+def test_deposit_with_lds_histogram_without_staging():
+    """6144 tiles (384 x 256 x 256 nodes): the FP32 tile histogram still fits
+    in LDS, the chunk's records beside it do not, so the scatter stores each
+    record straight from its lane instead of staging the chunk in LDS."""
+    dt = "f32"
+    n, h = (384, 256, 256), (2e-5, 2e-5, 2e-5)
+    x, y, z = wl.gaussian_bunch(300_000, (1.6e-3, 1.2e-3, 1.2e-3), 83, np.float32)
+    q = 1e-15
+    plan = dks().PoissonPlan(n, h, dt)
+    rho, cnt = plan.deposit(dev(x, dt), dev(y, dt), dev(z, dt), q)
+    Q, n_out = orc.deposit_cic(x, y, z, q, n, h, orc.centred_origin(n, h), np.float32)
+    assert int(host(cnt)[0]) == n_out
+    assert rel_l2(host(rho), Q / (h[0] * h[1] * h[2])) <= TOL[dt]
+
+
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_unaligned_particle_arrays_give_identical_results(dt):
     """Positions and field outputs that are not 16-byte aligned take the
