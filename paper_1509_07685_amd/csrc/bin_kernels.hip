@@ -71,7 +71,7 @@ template <typename T, int SCH> constexpr int gather_threads() { return pair_phi<
 
 // Binned records each lane loads before using any.
 constexpr int kUnrollDeposit = 4;
-constexpr int kUnrollGather = 1;
+constexpr int kUnrollGather = 2;
 
 // A binned particle record: its position, overwritten by the field at it.
 template <typename T> struct Rec {
@@ -589,7 +589,8 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geomet
   __shared__ unsigned long long acc[NN];
   using P4 = Rec<T>;
   const int b = blockIdx.y;
-  const Geometry* g = geo_of(geo, stride, b);
+  const Geometry gcopy = *geo_of(geo, stride, b);   // private copy: not reloaded after each store
+  const Geometry* g = &gcopy;
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
   const P4* part = reinterpret_cast<const P4*>(sorted_base + (size_t)b * sorted_stride);
   T* w = W + (size_t)b * w_stride;
@@ -659,7 +660,8 @@ __global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(co
   __shared__ typename std::conditional<PAIR, float2, T>::type ph[NA];
   using P4 = Rec<T>;
   const int b = blockIdx.y;
-  const Geometry* g = geo_of(geo, stride, b);
+  const Geometry gcopy = *geo_of(geo, stride, b);   // private copy: not reloaded after each store
+  const Geometry* g = &gcopy;
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
   P4* part = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
   const T* phi = phi_ext + (size_t)b * phi_stride;
@@ -855,6 +857,36 @@ __global__ __launch_bounds__(kUnsortThreads) void k_unsort(ElemBatch eb, const c
   T* qy = (T*)s.Ey;
   T* qz = (T*)s.Ez;
   const bool vec = aligned16(qx + c0, qy + c0, qz + c0);
+  if (vec && c0 + CH <= n) {
+    // A whole chunk in the vector layout: straight-line code, so that every
+    // load is issued before the first wait and the stores go out back to
+    // back (a branch between them would make each wait for the last).
+    typedef unsigned UV __attribute__((ext_vector_type(NV)));
+    unsigned src[PER];
+#pragma unroll
+    for (int q = 0; q < PER / NV; ++q) {
+      const int64_t i = chunk_index<T, kUnsortThreads>(true, c0, q * NV);
+      const UV v = __builtin_nontemporal_load((const __attribute__((address_space(1))) UV*)(inv + i));
+#pragma unroll
+      for (int k = 0; k < NV; ++k) src[q * NV + k] = v[k];
+    }
+    V ax[PER / NV], ay[PER / NV], az[PER / NV];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const P4 r = part[src[j]];
+      ax[j / NV][j % NV] = r.x;
+      ay[j / NV][j % NV] = r.y;
+      az[j / NV][j % NV] = r.z;
+    }
+#pragma unroll
+    for (int q = 0; q < PER / NV; ++q) {
+      const int64_t i = chunk_index<T, kUnsortThreads>(true, c0, q * NV);
+      st_stream(qx + i, ax[q]);
+      st_stream(qy + i, ay[q]);
+      st_stream(qz + i, az[q]);
+    }
+    return;
+  }
   unsigned src[PER];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
