@@ -75,6 +75,11 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __res
       }
     }
   }
+  // The nx + 1 post-twiddles go to LDS after the tile, so that the output
+  // loop below has no global loads: a load there would make every iteration
+  // wait for the previous iteration's store.
+  C* lpost = lds + (size_t)M * LDt;
+  for (int k = (int)threadIdx.x; k <= nx; k += RegCfg<T>::THREADS) lpost[k] = post[k];
   __syncthreads();
   {
     const int nnz = (nx + 1) >> 1;
@@ -98,7 +103,7 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_x_fwd(const T* __res
     C zc = lds[(k == 0 ? 0 : M - k) * LDt + p];
     zc.y = -zc.y;
     const C s = cadd(zk, zc), d = csub(zk, zc);
-    const C wd = cmul(post[k], d);
+    const C wd = cmul(lpost[k], d);
     dst[(size_t)(row0 + p) * m.cs + k] = C{(T)0.5 * (s.x + wd.y), (T)0.5 * (s.y - wd.x)};
   }
 }
@@ -391,7 +396,8 @@ hipError_t launch_fft_x_fwd(const void* in, size_t in_stride, void* out, size_t 
   if ((size_t)P.host.W * m.nx > (size_t)kTileReals * RegCfg<T>::THREADS) return hipErrorInvalidValue;
   dim3 grid((nrows + P.host.W - 1) / P.host.W, batch);
   with_plan<T, 1>(P.host, [&](auto sp) {
-    hipLaunchKernelGGL((k_fft_x_fwd<T, decltype(sp)>), grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s,
+    hipLaunchKernelGGL((k_fft_x_fwd<T, decltype(sp)>), grid, dim3(RegCfg<T>::THREADS),
+                       lds_bytes<T>(P.host) + (size_t)(m.nx + 1) * sizeof(C), s,
                        (const T*)in, in_stride, (C*)out, out_stride, m, P.dev, (const C*)post, nrows, magic_of(m.nx + 1),
                        magic_of(m.nx));
   });
