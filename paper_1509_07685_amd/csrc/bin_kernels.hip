@@ -368,11 +368,129 @@ constexpr size_t kLdsPerWorkgroup = 160 * 1024;   // gfx950
 // Tiles per lane in the staged scan: the staged path needs K + 1 <= 8 * 1024.
 constexpr int kStageRun = 8;
 
+// The staged scatter of one chunk, once its keys and ranks are in registers
+// and lcnt holds its tile counts (all lanes, after the ranking atomics):
+// chunk-local offsets and reservations, records and keys into LDS, the
+// inverse permutation, then the records in local order.  Each lane owns a
+// contiguous run of at most kStageRun tiles: the chunk-local exclusive
+// offsets replace the counts in lcnt, and lbase holds (reserved global start
+// - local offset), so that a record's destination is its local position plus
+// lbase of its tile.  The lane's reservations are all issued before the scan
+// and their results used after it.  FULL: a whole chunk in the vector layout
+// (no per-particle checks, vector stores of the inverse permutation); lcnt
+// is cleared for the next chunk while the records are stored.  mid() runs
+// once the reservations have returned (the pipelined kernel issues the next
+// chunk's loads there: issued earlier, waiting for the reservations would
+// wait for them too).
+struct NoMid {
+  __device__ void operator()() const {}
+};
+template <typename T, bool FULL, class Mid = NoMid, int PER = chunk_per<T, kScatterThreads>()>
+__device__ __forceinline__ void scatter_stage_chunk(unsigned* lcnt, unsigned* lbase, Rec<T>* srec,
+                                                    unsigned short* skey, unsigned* wa, unsigned* wb,
+                                                    unsigned* cursor, const BinGeom& bg, const int (&key)[PER],
+                                                    const unsigned (&rank)[PER], const T (&xs)[PER],
+                                                    const T (&ys)[PER], const T (&zs)[PER], int64_t c0, int64_t n,
+                                                    bool vec, Rec<T>* out, unsigned* inv, Mid mid = Mid{}) {
+  using P4 = Rec<T>;
+  constexpr int NV = Vec16<T>::n;
+  constexpr int64_t CH = scatter_chunk<T>();
+  __syncthreads();
+  const int L = bg.K + 1;
+  const int per = (L + kScatterThreads - 1) / kScatterThreads;
+  const int lo = min((int)threadIdx.x * per, L), hi = min(lo + per, L);
+  unsigned cv[kStageRun], rv[kStageRun];
+  unsigned sum = 0;
+#pragma unroll
+  for (int q = 0; q < kStageRun; ++q) {
+    cv[q] = lo + q < hi ? lcnt[lo + q] : 0u;
+    sum += cv[q];
+  }
+#pragma unroll
+  for (int q = 0; q < kStageRun; ++q) rv[q] = cv[q] ? atomicAdd(&cursor[lo + q], cv[q]) : 0u;
+  unsigned off, unused0, unused1, unused2;
+  scan1024(sum, 0u, wa, wb, &off, &unused0, &unused1, &unused2);
+#pragma unroll
+  for (int q = 0; q < kStageRun; ++q) {
+    if (lo + q < hi) {
+      lcnt[lo + q] = off;
+      lbase[lo + q] = rv[q] - off;
+      off += cv[q];
+    }
+  }
+  mid();
+  __syncthreads();
+  // Records and keys into LDS at their local positions; every destination
+  // is formed before the inverse permutation is stored (vector stores of a
+  // lane's consecutive particles in the vector layout).
+  unsigned dv[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    dv[j] = 0u;
+    if (FULL || key[j] >= 0) {
+      const unsigned lp = lcnt[key[j]] + rank[j];
+      srec[lp] = P4{xs[j], ys[j], zs[j]};
+      skey[lp] = (unsigned short)key[j];
+      dv[j] = lp + lbase[key[j]];
+    }
+  }
+  if (FULL || vec) {
+    struct alignas(NV * sizeof(unsigned)) U { unsigned v[NV]; };
+#pragma unroll
+    for (int q = 0; q < PER / NV; ++q) {
+      const int64_t i = chunk_index<T, kScatterThreads>(true, c0, q * NV);
+      if (FULL || i + NV <= n) {
+        U u;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) u.v[k] = dv[q * NV + k];
+        *reinterpret_cast<U*>(inv + i) = u;
+      } else {
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+          if (i + k < n) inv[i + k] = dv[q * NV + k];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int64_t i = chunk_index<T, kScatterThreads>(false, c0, j);
+      if (i < n) inv[i] = dv[j];
+    }
+  }
+  __syncthreads();
+  if (FULL) {
+    for (int k = threadIdx.x; k < L; k += kScatterThreads) lcnt[k] = 0;
+  }
+  // The chunk's valid particles fill local positions 0 .. nv - 1; a lane
+  // reads all of its records before storing any.
+  const unsigned nv = FULL ? (unsigned)CH : (unsigned)min(CH, n - c0);   // >= 1
+  T rx[PER], ry[PER], rz[PER];
+  unsigned dd[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    // lanes past the end re-read the last record and store nothing
+    const unsigned p = FULL ? threadIdx.x + (unsigned)j * kScatterThreads
+                            : min(threadIdx.x + (unsigned)j * kScatterThreads, nv - 1);
+    const P4 r = srec[p];
+    rx[j] = r.x;
+    ry[j] = r.y;
+    rz[j] = r.z;
+    dd[j] = p + lbase[skey[p]];
+  }
+  // Keep the reads above the stores: a store's registers cannot be reused
+  // before it completes, so interleaving would serialise the stores.
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int j = 0; j < PER; ++j)
+    if (FULL || threadIdx.x + (unsigned)j * kScatterThreads < nv) out[dd[j]] = P4{rx[j], ry[j], rz[j]};
+}
+
 template <typename T, bool LDSHIST, bool STAGE, int SCH>
 __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, const Geometry* geo, size_t stride,
                                                                  char* slot_base, size_t bins_off,
                                                                  char* sorted_base, size_t sorted_stride,
-                                                                 size_t inv_off, MeshDims m, BinGeom bg) {
+                                                                 size_t inv_off, MeshDims m, BinGeom bg,
+                                                                 int chunk0, int nchunk) {
   extern __shared__ unsigned lds[];
   __shared__ unsigned wa[16], wb[16];
   constexpr int PER = chunk_per<T, kScatterThreads>();
@@ -384,7 +502,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
   const int b = blockIdx.y;
   const dks_particle_set e = eb.at(b);
   const int64_t n = eb.n(e);
-  const int64_t c0 = (int64_t)blockIdx.x * CH;
+  const int chunk = chunk0 + (int)blockIdx.x;
+  const int64_t c0 = (int64_t)chunk * CH;
   if (c0 >= n) return;                       // whole workgroup: no barrier is skipped by part of it
   unsigned* lcnt = lds;
   unsigned* lbase = lds + (bg.K + 1);
@@ -400,7 +519,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
   const Geometry gcopy = *geo_of(geo, stride, b);
   const Geometry* g = &gcopy;
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
-  unsigned* cursor = st.xcursor + (int)(((int64_t)b * gridDim.x + blockIdx.x) % kXcd) * (bg.K + 1);
+  // the chunk's XCD group, as the count kernel assigned it
+  unsigned* cursor = st.xcursor + (int)(((int64_t)b * nchunk + chunk) % kXcd) * (bg.K + 1);
   P4* out = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
   unsigned* inv = reinterpret_cast<unsigned*>(sorted_base + (size_t)b * sorted_stride + inv_off);
   if (LDSHIST) {
@@ -451,94 +571,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
     else rank[j] = key[j] >= 0 ? atomicAdd(&cursor[key[j]], 1u) : 0u;
   }
   if constexpr (STAGE) {
-    // Each lane owns a contiguous run of at most kStageRun tiles: chunk-local
-    // exclusive offsets replace the counts in lcnt, and lbase holds (reserved
-    // global start - local offset), so that a record's destination is its
-    // local position plus lbase of its tile.  The lane's reservations are all
-    // issued before the scan and their results used after it.
-    __syncthreads();
-    const int L = bg.K + 1;
-    const int per = (L + kScatterThreads - 1) / kScatterThreads;
-    const int lo = min((int)threadIdx.x * per, L), hi = min(lo + per, L);
-    unsigned cv[kStageRun], rv[kStageRun];
-    unsigned sum = 0;
-#pragma unroll
-    for (int q = 0; q < kStageRun; ++q) {
-      cv[q] = lo + q < hi ? lcnt[lo + q] : 0u;
-      sum += cv[q];
-    }
-#pragma unroll
-    for (int q = 0; q < kStageRun; ++q) rv[q] = cv[q] ? atomicAdd(&cursor[lo + q], cv[q]) : 0u;
-    unsigned off, unused0, unused1, unused2;
-    scan1024(sum, 0u, wa, wb, &off, &unused0, &unused1, &unused2);
-#pragma unroll
-    for (int q = 0; q < kStageRun; ++q) {
-      if (lo + q < hi) {
-        lcnt[lo + q] = off;
-        lbase[lo + q] = rv[q] - off;
-        off += cv[q];
-      }
-    }
-    __syncthreads();
-    // Records and keys into LDS at their local positions; every destination
-    // is formed before the inverse permutation is stored (vector stores of
-    // a lane's consecutive particles in the vector layout).
-    unsigned dv[PER];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      dv[j] = 0u;
-      if (key[j] >= 0) {
-        const unsigned lp = lcnt[key[j]] + rank[j];
-        srec[lp] = P4{xs[j], ys[j], zs[j]};
-        skey[lp] = (unsigned short)key[j];
-        dv[j] = lp + lbase[key[j]];
-      }
-    }
-    if (vec) {
-      struct alignas(NV * sizeof(unsigned)) U { unsigned v[NV]; };
-#pragma unroll
-      for (int q = 0; q < PER / NV; ++q) {
-        const int64_t i = chunk_index<T, kScatterThreads>(true, c0, q * NV);
-        if (i + NV <= n) {
-          U u;
-#pragma unroll
-          for (int k = 0; k < NV; ++k) u.v[k] = dv[q * NV + k];
-          *reinterpret_cast<U*>(inv + i) = u;
-        } else {
-#pragma unroll
-          for (int k = 0; k < NV; ++k)
-            if (i + k < n) inv[i + k] = dv[q * NV + k];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < PER; ++j) {
-        const int64_t i = chunk_index<T, kScatterThreads>(false, c0, j);
-        if (i < n) inv[i] = dv[j];
-      }
-    }
-    __syncthreads();
-    // The chunk's valid particles fill local positions 0 .. nv - 1; a lane
-    // reads all of its records before storing any.
-    const unsigned nv = (unsigned)min(CH, n - c0);   // >= 1
-    T rx[PER], ry[PER], rz[PER];
-    unsigned dd[PER];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      // lanes past the end re-read the last record and store nothing
-      const unsigned p = min(threadIdx.x + (unsigned)j * kScatterThreads, nv - 1);
-      const P4 r = srec[p];
-      rx[j] = r.x;
-      ry[j] = r.y;
-      rz[j] = r.z;
-      dd[j] = p + lbase[skey[p]];
-    }
-    // Keep the reads above the stores: a store's registers cannot be reused
-    // before it completes, so interleaving would serialise the stores.
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int j = 0; j < PER; ++j)
-      if (threadIdx.x + (unsigned)j * kScatterThreads < nv) out[dd[j]] = P4{rx[j], ry[j], rz[j]};
+    scatter_stage_chunk<T, false>(lcnt, lbase, srec, skey, wa, wb, cursor, bg, key, rank, xs, ys, zs, c0, n, vec, out,
+                                  inv);
     return;
   }
   if (LDSHIST) {
@@ -584,6 +618,86 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
     const int64_t i = chunk_index<T, kScatterThreads>(vec, c0, j);
     out[dv[j]] = P4{xs[j], ys[j], zs[j]};
     inv[i] = dv[j];
+  }
+}
+
+// Staged scatter of whole chunks with the next chunk's positions in flight:
+// workgroup w takes chunks w, w + G, ... (G = gridDim.x, a multiple of kXcd,
+// one workgroup per CU), and loads chunk c + G while chunk c is ranked,
+// staged and stored.  One element whose positions are 16-byte aligned; the
+// chunks are the first nfull (whole) ones.
+template <typename T, int SCH>
+__global__ __launch_bounds__(kScatterThreads) void k_bin_scatter_pipe(ElemBatch eb, const Geometry* geo, size_t stride,
+                                                                      char* slot_base, size_t bins_off,
+                                                                      char* sorted_base, size_t sorted_stride,
+                                                                      size_t inv_off, MeshDims m, BinGeom bg,
+                                                                      int nchunk, int nfull) {
+  extern __shared__ unsigned lds[];
+  __shared__ unsigned wa[16], wb[16];
+  constexpr int PER = chunk_per<T, kScatterThreads>();
+  constexpr int NV = Vec16<T>::n;
+  constexpr int64_t CH = scatter_chunk<T>();
+  using P4 = Rec<T>;
+  using V = typename Vec16<T>::type;
+  const int b = blockIdx.y;
+  const dks_particle_set e = eb.at(b);
+  const int64_t n = eb.n(e);
+  int c = blockIdx.x;
+  if (c >= nfull) return;                    // whole workgroup
+  unsigned* lcnt = lds;
+  unsigned* lbase = lds + (bg.K + 1);
+  P4* srec = reinterpret_cast<P4*>(lds + 2 * (bg.K + 1));
+  unsigned short* skey = reinterpret_cast<unsigned short*>(srec + CH);
+  const T* px = (const T*)e.x;
+  const T* py = (const T*)e.y;
+  const T* pz = (const T*)e.z;
+  const Geometry gcopy = *geo_of(geo, stride, b);
+  const Geometry* g = &gcopy;
+  BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
+  P4* out = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
+  unsigned* inv = reinterpret_cast<unsigned*>(sorted_base + (size_t)b * sorted_stride + inv_off);
+  auto load = [&](int ch, T (&x)[PER], T (&y)[PER], T (&z)[PER]) {
+#pragma unroll
+    for (int q = 0; q < PER / NV; ++q) {
+      const int64_t i = chunk_index<T, kScatterThreads>(true, (int64_t)ch * CH, q * NV);
+      const V a = ld_stream(px + i), bb = ld_stream(py + i), cc = ld_stream(pz + i);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        x[q * NV + k] = a[k];
+        y[q * NV + k] = bb[k];
+        z[q * NV + k] = cc[k];
+      }
+    }
+  };
+  for (int k = threadIdx.x; k <= bg.K; k += kScatterThreads) lcnt[k] = 0;
+  T xs[PER], ys[PER], zs[PER];
+  load(c, xs, ys, zs);
+  for (;;) {
+    unsigned* cursor = st.xcursor + (int)(((int64_t)b * nchunk + c) % kXcd) * (bg.K + 1);
+    __syncthreads();                         // lcnt cleared, the previous chunk's records read
+    int key[PER];
+    unsigned rank[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      key[j] = locate<T, SCH>(xs[j], ys[j], zs[j], g, m, bg).key;
+      rank[j] = atomicAdd(&lcnt[key[j]], 1u);
+    }
+    // the next chunk, loaded once the reservations are back (the last chunk
+    // re-reads itself, so no load is conditional)
+    const int cn = c + (int)gridDim.x;
+    const bool more = cn < nfull;
+    T nxs[PER], nys[PER], nzs[PER];
+    scatter_stage_chunk<T, true>(lcnt, lbase, srec, skey, wa, wb, cursor, bg, key, rank, xs, ys, zs,
+                                 (int64_t)c * CH, n, true, out, inv,
+                                 [&]() { load(more ? cn : c, nxs, nys, nzs); });
+    if (!more) break;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      xs[j] = nxs[j];
+      ys[j] = nys[j];
+      zs[j] = nzs[j];
+    }
+    c = cn;
   }
 }
 
@@ -1008,6 +1122,19 @@ hipError_t launch_bin_scan(const Geometry* geo, size_t stride, char* slot_base, 
   return hipGetLastError();
 }
 
+// Compute units of the current device (cached per device).
+static int compute_units() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cache[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    cache[dev] = v;
+  }
+  return cache[dev];
+}
+
 template <typename T>
 hipError_t launch_bin_scatter(const ElemBatch& eb, int batch, const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                               char* sorted_base, size_t sorted_stride, size_t inv_off, const MeshDims& m,
@@ -1021,17 +1148,43 @@ hipError_t launch_bin_scatter(const ElemBatch& eb, int batch, const Geometry* ge
   const bool stage = lh && scatter_stage_lds<T>(bg.K) + 256 <= kLdsPerWorkgroup &&
                      bg.K + 1 <= kStageRun * kScatterThreads;
   const size_t lds = stage ? scatter_stage_lds<T>(bg.K) : lh ? 2 * (size_t)(bg.K + 1) * sizeof(unsigned) : 0;
+  // One element with aligned positions and at least one chunk per CU: the
+  // whole chunks go through the pipelined kernel, the partial last chunk (if
+  // any) through the one-chunk kernel.
+  int nfull = 0, G = 0;
+  if (stage && batch == 1 && eb.dev == nullptr) {
+    const dks_particle_set& e = eb.local;
+    const bool have = e.x && e.y && e.z && (!eb.need_e || (e.Ex && e.Ey && e.Ez));
+    const int64_t n = have ? std::min<int64_t>(std::max<int64_t>(e.np, 0), eb.max_np) : 0;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(e.x) | reinterpret_cast<uintptr_t>(e.y) |
+                           reinterpret_cast<uintptr_t>(e.z)) & 15u) == 0;
+    const int cus = compute_units();
+    if (aligned && cus > 0 && n / ch >= 2 * cus) {
+      nfull = (int)(n / ch);
+      G = std::max(kXcd, cus / kXcd * kXcd);
+    }
+  }
   with_scheme(bg.scheme, [&](auto sc) {
     constexpr int SCH = decltype(sc)::value;
-    if (stage)
+    if (nfull > 0) {
+      hipLaunchKernelGGL((k_bin_scatter_pipe<T, SCH>), dim3(G, 1), dim3(kScatterThreads), lds, s, eb, geo, stride,
+                         slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg, (int)nchunk, nfull);
+      if ((unsigned)nfull < nchunk)
+        hipLaunchKernelGGL((k_bin_scatter<T, true, true, SCH>), dim3(nchunk - nfull, 1), dim3(kScatterThreads), lds,
+                           s, eb, geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg,
+                           nfull, (int)nchunk);
+    } else if (stage) {
       hipLaunchKernelGGL((k_bin_scatter<T, true, true, SCH>), dim3(nchunk, batch), dim3(kScatterThreads), lds, s, eb,
-                         geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
-    else if (lh)
+                         geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg, 0, (int)nchunk);
+    } else if (lh) {
       hipLaunchKernelGGL((k_bin_scatter<T, true, false, SCH>), dim3(nchunk, batch), dim3(kScatterThreads), lds, s,
-                         eb, geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
-    else
+                         eb, geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg, 0,
+                         (int)nchunk);
+    } else {
       hipLaunchKernelGGL((k_bin_scatter<T, false, false, SCH>), dim3(nchunk, batch), dim3(kScatterThreads), 0, s,
-                         eb, geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg);
+                         eb, geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg, 0,
+                         (int)nchunk);
+    }
   });
   return hipGetLastError();
 }

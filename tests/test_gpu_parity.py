@@ -464,6 +464,24 @@ def test_deposit_with_global_tile_histogram():
     assert rel_l2(host(rho), Q / (h[0] * h[1] * h[2])) <= TOL[dt]
 
 
+@pytest.mark.parametrize("dt,num,tail", [("f32", 5 * 8192 * 256, 0), ("f32", 5 * 8192 * 256 + 4099, 4099),
+                                         ("f64", 5 * 4096 * 256 + 17, 17)])
+def test_pipelined_scatter_full_step(dt, num, tail):
+    """Enough particles for the pipelined scatter (at least two whole chunks
+    per CU: each workgroup loads its next chunk while storing the current
+    one), with and without a partial last chunk, element by element against
+    the oracle on a fitted 64^3 mesh."""
+    x, y, z = wl.halo_gaussian(num, 1e-3, 0.1, 5e-3, 97, NP_DT[dt])
+    q = 1e-16
+    n = (64, 64, 64)
+    plan = dks().PoissonPlan(n, None, dt)
+    (Ex, Ey, Ez), phi, cnt = plan.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), q, want_phi=True)
+    ref = orc.solve_particles(x, y, z, q, n, dtype=NP_DT[dt])
+    assert int(host(cnt)[0]) == ref["n_outside"] == 0
+    assert rel_l2(host(phi), ref["phi_ext"][1:-1, 1:-1, 1:-1]) <= TOL[dt]
+    assert rel_l2(np.stack([host(Ex), host(Ey), host(Ez)]), ref["E"]) <= TOL[dt]
+
+
 def test_deposit_with_lds_histogram_without_staging():
     """6144 tiles (384 x 256 x 256 nodes): the FP32 tile histogram still fits
     in LDS, the chunk's records beside it do not, so the scatter stores each
