@@ -58,7 +58,7 @@ def algorithmic_bytes(n, num_particles, s, kernel):
 # Library timing names -> kernel symbols as rocprofv3 reports them.
 KERNEL_SYMBOL = {
     "bbox": "k_bbox", "geometry": "k_geometry_zero", "bin_count": "k_bin_count",
-    "bin_scan": "k_bin_scan", "bin_scatter": "k_bin_scatter", "deposit": "k_deposit_binned",
+    "bin_scan": "k_bin_scan", "bin_scatter": "k_bin_scatter_pipe", "deposit": "k_deposit_binned",
     "fft_x_fwd": "k_fft_x_fwd", "fft_y_fwd": "k_fft_y_fwd", "fft_z_conv": "k_fft_z_conv",
     "fft_y_inv": "k_fft_y_inv", "fft_x_inv": "k_fft_x_inv", "gradient": "k_gradient",
     "gather": "k_gather_binned", "unsort": "k_unsort",
@@ -88,7 +88,15 @@ def measured_traffic(kernel):
         if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != h:
             return None
     k = doc["kernels"].get(sym)
-    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+    if k is None:
+        return None
+    total = k["fetch_bytes"] + k["write_bytes"]
+    # the scatter's whole chunks go through the pipelined kernel, a partial
+    # last chunk through the one-chunk kernel launched after it
+    if sym == "k_bin_scatter_pipe" and "k_bin_scatter" in doc["kernels"]:
+        t = doc["kernels"]["k_bin_scatter"]
+        total += t["fetch_bytes"] + t["write_bytes"]
+    return total
 
 
 def conv_bytes(n, s):
