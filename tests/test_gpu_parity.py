@@ -482,6 +482,24 @@ def test_pipelined_scatter_full_step(dt, num, tail):
     assert rel_l2(np.stack([host(Ex), host(Ey), host(Ez)]), ref["E"]) <= TOL[dt]
 
 
+@pytest.mark.parametrize("scheme", ["ngp", "tsc"])
+def test_pipelined_scatter_schemes(scheme):
+    """The pipelined scatter with the other assignment schemes (their tile of
+    a particle is that of its lowest stencil node), at the smallest particle
+    count that uses it plus a partial last chunk."""
+    dt = "f32"
+    num = 2 * 8192 * 256 + 5
+    x, y, z = wl.halo_gaussian(num, 1e-3, 0.1, 5e-3, 98, NP_DT[dt])
+    q = 1e-16
+    n = (48, 48, 48)
+    plan = dks().PoissonPlan(n, None, dt, scheme=scheme)
+    (Ex, Ey, Ez), phi, cnt = plan.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), q, want_phi=True)
+    ref = orc.solve_particles(x, y, z, q, n, dtype=NP_DT[dt], scheme=scheme)
+    assert int(host(cnt)[0]) == ref["n_outside"]
+    assert rel_l2(host(phi), ref["phi_ext"][1:-1, 1:-1, 1:-1]) <= TOL[dt]
+    assert rel_l2(np.stack([host(Ex), host(Ey), host(Ez)]), ref["E"]) <= TOL[dt]
+
+
 def test_deposit_with_lds_histogram_without_staging():
     """6144 tiles (384 x 256 x 256 nodes): the FP32 tile histogram still fits
     in LDS, the chunk's records beside it do not, so the scatter stores each
