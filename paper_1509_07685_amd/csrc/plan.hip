@@ -425,11 +425,14 @@ PartWork part_work(const dks_poisson_plan_s* p, int64_t maxn) {
   PartWork w;
   w.bg = p->bg;
   // Work items bound the fixed-point deposit sums: <= 2^16 particles (FP32), 2^14 (FP64).
-  const int64_t item_cap = p->dtype == DKS_F32 ? 65536 : 16384;
+  // FP32 items of 2^15 and one workgroup per item (up to 16384) balance the
+  // deposit and gather better than 2^16 and 2048 workgroups looping over
+  // items (measured: gather 703 -> 658 us, deposit 394 -> 379 us at 1e8).
+  const int64_t item_cap = p->dtype == DKS_F32 ? 32768 : 16384;
   w.bg.item = (int)std::min<int64_t>(item_cap, std::max<int64_t>(8192, maxn / 512));
   w.count_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (maxn + 8191) / 8192));
   const int64_t items = (maxn + w.bg.item - 1) / w.bg.item + w.bg.K + 1;
-  w.item_blocks = (int)std::min<int64_t>(2048, std::max<int64_t>(1, items));
+  w.item_blocks = (int)std::min<int64_t>(16384, std::max<int64_t>(1, items));
   // kernels never trust more items or particles than the buffers were sized for
   w.bg.max_items = (unsigned)items;
   w.bg.max_np = (unsigned)maxn;
