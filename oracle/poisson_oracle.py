@@ -14,10 +14,10 @@ What it computes (paper section "FFT Based Particle-Mesh Solver", subsection
      the second-order, 27-node scheme).
   2. The integrated Green's function (IGF): the free-space kernel 1/r of the
      equation following the convolution solution, integrated over one mesh
-     cell.  Near the origin it is the third mixed difference of a closed-form
-     antiderivative over the cell corners; farther out, where that difference
-     cancels catastrophically in FP64, the Gauss-Legendre product rule over the
-     cell (the integrand is analytic there) with enough points to reach FP64
+     cell.  At every offset it is the alternating sum of a closed-form
+     antiderivative over the cell corners, evaluated in 113-bit arithmetic
+     (oracle/igf_quad.c, built with gcc) so that the sum's cancellation, which
+     would cost FP64 up to 9 digits at 256 cells, leaves it exact to FP64
      rounding.
   3. The discrete free-space convolution of the brute-force equation
      (phi_ijk = sum rho G_{i-i',j-j',k-k'}), done two ways:
@@ -41,10 +41,13 @@ design notes of the repository):
   * phi is returned on the extended box [-1, n] per axis (a one-node ghost
     layer), which the doubled grid gives exactly when the kernel value at
     offset n is the true G_int(n).
-  * The in/out-of-mesh and cell-index decision of a particle is taken on
+  * Where floating point decides an integer -- a particle's in/out-of-mesh
+    status and its stencil node -- the decision is taken on
     s = (x - x0) * (1/h) evaluated in the run's dtype with two correctly
-    rounded operations (difference, then product), because floating point
-    decides an integer there; everything after that decision is FP64.
+    rounded operations (difference, then product), as the run does.  The
+    weights then come from the FP64 cell coordinate (x - x0) / h of the same
+    input positions, so the oracle's result carries none of the dtype's
+    position rounding.
   * eps0 = 8.8541878128e-12 F/m (CODATA 2018).
 """
 
@@ -93,12 +96,28 @@ def fit_mesh(x, y, z, n):
 
 
 def cell_coordinates(pos, origin, h, dtype):
-    """s = (pos - origin) * (1/h) in `dtype`, two rounded operations, as FP64."""
+    """Cell coordinate of each position, for decisions and for weights.
+
+    Returns (s_dec, s_exact) as FP64 arrays:
+      s_dec   -- (pos - x0) * (1/h) in `dtype`: x0 and 1/h rounded from FP64 to
+                 the dtype, then two correctly rounded dtype operations.  It
+                 decides the in/out status and the stencil node.
+      s_exact -- (pos - origin) / h in FP64 from the same input positions
+                 (FP32 inputs widened exactly).  It gives the weights.
+    """
     dt = np.dtype(dtype)
     x0 = dt.type(origin)
     inv = dt.type(1.0 / h)
-    s = (np.asarray(pos).astype(dt) - x0) * inv
-    return s.astype(np.float64)
+    p = np.asarray(pos).astype(dt)
+    s_dec = (p - x0) * inv
+    s_exact = (p.astype(np.float64) - float(origin)) / float(h)
+    return s_dec.astype(np.float64), s_exact
+
+
+def _nearest_node(s_dec, dtype):
+    """floor(s + 1/2) with the addition rounded in the dtype (halves go up)."""
+    dt = np.dtype(dtype)
+    return np.floor((s_dec.astype(dt) + dt.type(0.5)).astype(np.float64))
 
 
 def cic_stencil(x, y, z, n, h, origin, dtype):
@@ -107,18 +126,20 @@ def cic_stencil(x, y, z, n, h, origin, dtype):
     Returns (inside mask, i[3] int64 lower node index, f[3] float64 fraction).
     A particle is outside when s_d < 0 or s_d > n_d - 1 on any axis.  The
     lower node is min(floor(s), n-2), so a particle exactly on the last node
-    goes entirely to it with f = 1.
+    goes entirely to it with f = 1.  Inside test and node use the dtype's
+    s; the fraction f = s_exact - i is FP64.
     """
-    s = [cell_coordinates(c, o, hd, dtype) for c, o, hd in zip((x, y, z), origin, h)]
-    inside = np.ones(s[0].shape, dtype=bool)
+    cs = [cell_coordinates(c, o, hd, dtype) for c, o, hd in zip((x, y, z), origin, h)]
+    inside = np.ones(cs[0][0].shape, dtype=bool)
     for d in range(3):
-        inside &= (s[d] >= 0.0) & (s[d] <= n[d] - 1)
+        inside &= (cs[d][0] >= 0.0) & (cs[d][0] <= n[d] - 1)
     idx, frac = [], []
     for d in range(3):
-        sd = np.where(inside, s[d], 0.0)
+        sd = np.where(inside, cs[d][0], 0.0)
+        se = np.where(inside, cs[d][1], 0.0)
         i = np.minimum(np.floor(sd), n[d] - 2).astype(np.int64)
         idx.append(i)
-        frac.append(sd - i)
+        frac.append(se - i)
     return inside, idx, frac
 
 
@@ -158,23 +179,26 @@ def stencil(x, y, z, n, h, origin, dtype, scheme="cic"):
       cic: lower node min(floor(s), n-2), weights (1-f, f).
       tsc: d = s - nearest; weights ((1/2 - d)^2 / 2, 3/4 - d^2, (1/2 + d)^2 / 2)
            at nearest - 1, nearest, nearest + 1.
+    The inside test and the nodes use the dtype's s (s_dec of
+    cell_coordinates); f and d use the FP64 s_exact.
     """
     if scheme not in SCHEMES:
         raise ValueError(scheme)
-    s = [cell_coordinates(c, o, hd, dtype) for c, o, hd in zip((x, y, z), origin, h)]
-    inside = np.ones(s[0].shape, dtype=bool)
+    cs = [cell_coordinates(c, o, hd, dtype) for c, o, hd in zip((x, y, z), origin, h)]
+    inside = np.ones(cs[0][0].shape, dtype=bool)
     for d in range(3):
-        inside &= (s[d] >= 0.0) & (s[d] <= n[d] - 1)
-    near = [np.floor(sd + 0.5) for sd in s]
+        inside &= (cs[d][0] >= 0.0) & (cs[d][0] <= n[d] - 1)
+    near = [_nearest_node(c[0], dtype) for c in cs]
     if scheme == "tsc":
         for d in range(3):
             inside &= (near[d] >= 1) & (near[d] <= n[d] - 2)
     base, weights = [], []
     for d in range(3):
-        sd = np.where(inside, s[d], 0.0)
+        sd = np.where(inside, cs[d][0], 0.0)
+        se = np.where(inside, cs[d][1], 0.0)
         if scheme == "cic":
             i = np.minimum(np.floor(sd), n[d] - 2)
-            f = sd - i
+            f = se - i
             base.append(i.astype(np.int64))
             weights.append([1.0 - f, f])
         else:
@@ -183,14 +207,34 @@ def stencil(x, y, z, n, h, origin, dtype, scheme="cic"):
                 base.append(k.astype(np.int64))
                 weights.append([np.ones_like(sd)])
             else:
-                dd = sd - k
+                dd = se - k
                 base.append((k - 1).astype(np.int64))
                 weights.append([0.5 * (0.5 - dd) ** 2, 0.75 - dd * dd, 0.5 * (0.5 + dd) ** 2])
     return inside, base, weights
 
 
+# Particles are taken in chunks of this many, which bounds the memory of the
+# per-particle temporaries at large counts; every sum stays FP64.
+_CHUNK = 1 << 22
+
+
+def _chunks(num):
+    return [(lo, min(lo + _CHUNK, num)) for lo in range(0, num, _CHUNK)] or [(0, 0)]
+
+
 def deposit(x, y, z, q, n, h, origin, dtype=np.float64, scheme="cic"):
     """Charge per node Q[nz, ny, nx] (coulomb) with the given scheme; (Q, n_outside)."""
+    nx, ny, nz = n
+    Q = np.zeros((nz, ny, nx), dtype=np.float64)
+    n_out = 0
+    for lo, hi in _chunks(np.asarray(x).size):
+        Qc, oc = _deposit_part(x[lo:hi], y[lo:hi], z[lo:hi], q, n, h, origin, dtype, scheme)
+        Q += Qc
+        n_out += oc
+    return Q, n_out
+
+
+def _deposit_part(x, y, z, q, n, h, origin, dtype, scheme):
     nx, ny, nz = n
     inside, (bx, by, bz), (wx, wy, wz) = stencil(x, y, z, n, h, origin, dtype, scheme)
     sel = np.nonzero(inside)[0]
@@ -205,6 +249,13 @@ def deposit(x, y, z, q, n, h, origin, dtype=np.float64, scheme="cic"):
 
 def gather(E, x, y, z, n, h, origin, dtype=np.float64, scheme="cic"):
     """Field at the particles, sum over the stencil of weight * E(node); 0 outside."""
+    out = np.zeros((3, np.asarray(x).size), dtype=np.float64)
+    for lo, hi in _chunks(out.shape[1]):
+        out[:, lo:hi] = _gather_part(E, x[lo:hi], y[lo:hi], z[lo:hi], n, h, origin, dtype, scheme)
+    return out
+
+
+def _gather_part(E, x, y, z, n, h, origin, dtype, scheme):
     inside, (bx, by, bz), (wx, wy, wz) = stencil(x, y, z, n, h, origin, dtype, scheme)
     out = np.zeros((3, inside.size), dtype=np.float64)
     for cz, wzc in enumerate(wz):
@@ -228,6 +279,17 @@ def deposit_cic(x, y, z, q, n, h, origin, dtype=np.float64):
     Returns (Q, n_outside).  rho = Q / (h_x h_y h_z).
     """
     nx, ny, nz = n
+    Q = np.zeros((nz, ny, nx), dtype=np.float64)
+    n_out = 0
+    for lo, hi in _chunks(np.asarray(x).size):
+        Qc, oc = _deposit_cic_part(x[lo:hi], y[lo:hi], z[lo:hi], q, n, h, origin, dtype)
+        Q += Qc
+        n_out += oc
+    return Q, n_out
+
+
+def _deposit_cic_part(x, y, z, q, n, h, origin, dtype):
+    nx, ny, nz = n
     inside, (ix, iy, iz), frac = cic_stencil(x, y, z, n, h, origin, dtype)
     Q = np.zeros(nx * ny * nz, dtype=np.float64)
     sel = np.nonzero(inside)[0]
@@ -243,88 +305,70 @@ def deposit_cic(x, y, z, q, n, h, origin, dtype=np.float64):
 # 2. Integrated Green's function
 # --------------------------------------------------------------------------
 
-def _antiderivative(x, y, z):
-    """F with d^3F/dxdydz = 1/sqrt(x^2+y^2+z^2), valid where no coordinate is 0."""
-    r = np.sqrt(x * x + y * y + z * z)
-    return (y * z * np.log(x + r) + x * z * np.log(y + r) + x * y * np.log(z + r)
-            - 0.5 * x * x * np.arctan(y * z / (x * r))
-            - 0.5 * y * y * np.arctan(x * z / (y * r))
-            - 0.5 * z * z * np.arctan(x * y / (z * r)))
+def _igf_lib():
+    """The oracle's C library (igf_quad.c), built with gcc on first use."""
+    global _LIB
+    if _LIB is None:
+        import ctypes
+        from oracle import build as _build
+        lib = ctypes.CDLL(_build.ensure_built())
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int64)
+        lib.oracle_igf_octant.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double] * 3 + [dp]
+        lib.oracle_igf_octant.restype = ctypes.c_int
+        lib.oracle_igf_at.argtypes = [ctypes.c_int64, ip, ip, ip] + [ctypes.c_double] * 3 + [dp]
+        lib.oracle_igf_at.restype = ctypes.c_int
+        _LIB = lib
+    return _LIB
 
 
-# Gauss-Legendre bands: (lower bound of D, points per axis).  D is the
-# distance of the cell centre from the origin in units of the largest cell
-# side.  Below D = 2 the closed form is used.
-_GL_BANDS = ((2.0, 10), (4.0, 8), (8.0, 6), (16.0, 5), (32.0, 4))
+_LIB = None
 
 
-def igf_closed_form(a, b, c, h):
-    """G_int at integer offsets (arrays broadcast) from the antiderivative.
-
-    G_int(a,b,c) = third mixed difference of F over the corners
-    ((a -+ 1/2) hx, (b -+ 1/2) hy, (c -+ 1/2) hz).  Exact in exact arithmetic,
-    but in FP64 it loses digits to cancellation as the offset grows
-    (about 1e-10 relative at 64 cells, 1e-7 at 256).
-    """
-    hx, hy, hz = h
-    a = np.abs(np.asarray(a, dtype=np.float64))
-    b = np.abs(np.asarray(b, dtype=np.float64))
-    c = np.abs(np.asarray(c, dtype=np.float64))
-    total = 0.0
-    for dz in (0, 1):
-        for dy in (0, 1):
-            for dx in (0, 1):
-                sign = (-1.0) ** (3 - dx - dy - dz)
-                total = total + sign * _antiderivative((a - 0.5 + dx) * hx,
-                                                       (b - 0.5 + dy) * hy,
-                                                       (c - 0.5 + dz) * hz)
-    return total
-
-
-def igf_gauss_legendre(a, b, c, h, m):
-    """G_int by the m x m x m Gauss-Legendre product rule over the cell."""
-    hx, hy, hz = h
-    a = np.abs(np.asarray(a, dtype=np.float64))
-    b = np.abs(np.asarray(b, dtype=np.float64))
-    c = np.abs(np.asarray(c, dtype=np.float64))
-    t, w = np.polynomial.legendre.leggauss(m)
-    total = np.zeros(np.broadcast(a, b, c).shape)
-    for i in range(m):
-        xi = (a + 0.5 * t[i]) * hx
-        for j in range(m):
-            yj = (b + 0.5 * t[j]) * hy
-            for k in range(m):
-                zk = (c + 0.5 * t[k]) * hz
-                total += (w[i] * w[j] * w[k]) / np.sqrt(xi * xi + yj * yj + zk * zk)
-    return total * (hx * hy * hz / 8.0)
+def _ptr(a, ctype):
+    import ctypes
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
 def igf_at(a, b, c, h):
     """G_int(a, b, c): the integral of 1/r over the cell centred at (a hx, b hy, c hz).
 
-    Closed form where the cell centre is within 2 largest-cell-sides of the
-    origin; elsewhere the integrand is analytic on the cell and the
-    Gauss-Legendre product rule of the band reaches FP64 rounding.
+    The alternating sum of the closed-form antiderivative
+      F = yz ln(x+r) + xz ln(y+r) + xy ln(z+r)
+          - x^2/2 atan(yz/(xr)) - y^2/2 atan(xz/(yr)) - z^2/2 atan(xy/(zr))
+    over the eight cell corners, evaluated in 113-bit arithmetic so the
+    cancellation of the sum (about 3 log10(offset) digits) leaves the FP64
+    result exact to rounding at every offset.  Arrays broadcast; integer
+    offsets (negative ones give the value at |offset|).
     """
-    a, b, c = np.broadcast_arrays(*(np.abs(np.asarray(v, dtype=np.float64)) for v in (a, b, c)))
-    hmax = max(h)
-    D = np.sqrt((a * h[0]) ** 2 + (b * h[1]) ** 2 + (c * h[2]) ** 2) / hmax
-    out = np.empty(a.shape, dtype=np.float64)
-    near = D < _GL_BANDS[0][0]
-    out[near] = igf_closed_form(a[near], b[near], c[near], h)
-    for idx, (lo, m) in enumerate(_GL_BANDS):
-        hi = _GL_BANDS[idx + 1][0] if idx + 1 < len(_GL_BANDS) else np.inf
-        sel = (D >= lo) & (D < hi)
-        if np.any(sel):
-            out[sel] = igf_gauss_legendre(a[sel], b[sel], c[sel], h, m)
-    return out
+    import ctypes
+    a, b, c = np.broadcast_arrays(*(np.asarray(v) for v in (a, b, c)))
+    shape = a.shape
+    ai, bi, ci = (np.ascontiguousarray(np.rint(v).astype(np.int64).ravel()) for v in (a, b, c))
+    out = np.empty(ai.size, dtype=np.float64)
+    rc = _igf_lib().oracle_igf_at(ai.size, _ptr(ai, ctypes.c_int64), _ptr(bi, ctypes.c_int64),
+                                  _ptr(ci, ctypes.c_int64), float(h[0]), float(h[1]), float(h[2]),
+                                  _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise ValueError("igf_at: bad arguments")
+    out = out.reshape(shape)
+    return out if shape else float(out)
 
 
 def igf_octant(n, h):
-    """G_int(a, b, c) for a in [0, nx], b in [0, ny], c in [0, nz]; array [c, b, a]."""
-    nx, ny, nz = n
-    c, b, a = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
-    return igf_at(a, b, c, h)
+    """G_int(a, b, c) for a in [0, nx], b in [0, ny], c in [0, nz]; array [c, b, a].
+
+    Same closed form as igf_at, with F evaluated once per corner of the
+    half-integer lattice (a - 1/2) h and differenced along each axis.
+    """
+    import ctypes
+    nx, ny, nz = (int(v) for v in n)
+    out = np.empty((nz + 1, ny + 1, nx + 1), dtype=np.float64)
+    rc = _igf_lib().oracle_igf_octant(nx, ny, nz, float(h[0]), float(h[1]), float(h[2]),
+                                      _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise ValueError("igf_octant: bad arguments")
+    return out
 
 
 def point_kernel_octant(n, h):
@@ -427,7 +471,13 @@ def gradient(phi_ext, h):
 
 def gather_cic(E, x, y, z, n, h, origin, dtype=np.float64):
     """E at the particles: sum over the 8 nodes of w * E(node); 0 outside."""
-    nx, ny, nz = n
+    out = np.zeros((3, np.asarray(x).size), dtype=np.float64)
+    for lo, hi in _chunks(out.shape[1]):
+        out[:, lo:hi] = _gather_cic_part(E, x[lo:hi], y[lo:hi], z[lo:hi], n, h, origin, dtype)
+    return out
+
+
+def _gather_cic_part(E, x, y, z, n, h, origin, dtype):
     inside, (ix, iy, iz), frac = cic_stencil(x, y, z, n, h, origin, dtype)
     w = _corner_weights(frac)
     out = np.zeros((3, inside.size), dtype=np.float64)

@@ -101,20 +101,28 @@ def _mp_closed_form(a, b, c, h):
     return t
 
 
-@pytest.mark.parametrize("h,tol", [((1.0, 1.0, 1.0), 3e-15),
-                                   ((5e-5, 5e-5, 2e-4), 3e-13),
-                                   ((1.3e-4, 0.7e-4, 2.1e-4), 1e-13)])
-def test_igf_reaches_fp64_accuracy_at_all_offsets(h, tol):
+@pytest.mark.parametrize("h", [(1.0, 1.0, 1.0), (5e-5, 5e-5, 2e-4), (1.3e-4, 0.7e-4, 2.1e-4), (2.0, 0.5, 0.5)])
+def test_igf_reaches_fp64_accuracy_at_all_offsets(h):
     """The closed form evaluated in 40-digit arithmetic is the exact integral
     (it agrees with independent quadrature above); the oracle's FP64 value must
-    match it to rounding level from the centre cell out to 256 cells."""
+    be that number correctly rounded (within one unit in the last place) from
+    the centre cell out to 256 cells and beyond, for cubic and 4:1 cells."""
     offsets = [(0, 0, 0), (1, 0, 0), (1, 1, 1), (2, 1, 0), (4, 0, 0), (8, 3, 1), (16, 16, 16),
                (32, 5, 9), (64, 64, 64), (128, 0, 0), (128, 128, 256), (256, 256, 256),
-               (3, 40, 7), (200, 1, 90)]
+               (3, 40, 7), (200, 1, 90), (0, 256, 1), (512, 511, 3), (1000, 0, 0)]
     for off in offsets:
         exact = float(_mp_closed_form(*off, h))
         got = float(orc.igf_at(*off, h))
-        assert abs(got - exact) <= tol * abs(exact), off
+        assert abs(got - exact) <= 2.3e-16 * abs(exact), off
+
+
+def test_igf_octant_equals_pointwise_values():
+    """The lattice form of the octant and the per-offset form take the same
+    corner sums: identical values, anisotropic cells, offsets up to n."""
+    n, h = (20, 13, 9), (1.3e-4, 0.7e-4, 2.1e-4)
+    g = orc.igf_octant(n, h)
+    c, b, a = np.meshgrid(np.arange(n[2] + 1), np.arange(n[1] + 1), np.arange(n[0] + 1), indexing="ij")
+    np.testing.assert_array_equal(g, orc.igf_at(a, b, c, h))
 
 
 @pytest.mark.parametrize("R", [8, 16])
@@ -257,15 +265,17 @@ def test_deposit_conserves_charge_and_dipole(dtype):
     Q, n_out = orc.deposit_cic(x, y, z, q, n, h, origin, dtype)
     assert n_out == 0
     assert Q.sum() == pytest.approx(q * 5000, rel=1e-13)
-    # CIC reproduces the first moment exactly (its weights interpolate linearly)
+    # CIC reproduces the first moment exactly (its weights interpolate
+    # linearly), and the weights come from the FP64 cell coordinate of the
+    # input positions, so the deposited dipole is that of the positions as
+    # given (FP32 inputs included: no FP32 rounding of s enters the weights)
     nodes = [origin[d] + np.arange(n[d]) * h[d] for d in range(3)]
-    s = [orc.cell_coordinates(c, o, hd, dtype) for c, o, hd in zip((x, y, z), origin, h)]
-    for d, axis in ((0, 2), (1, 1), (2, 0)):
+    for d, axis, pos in ((0, 2, x), (1, 1, y), (2, 0, z)):
         shape = [1, 1, 1]
         shape[axis] = n[d]
         moment = float((Q * nodes[d].reshape(shape)).sum())
-        want = q * float(np.sum(origin[d] + s[d] * h[d]))
-        assert moment == pytest.approx(want, rel=1e-11, abs=1e-12 * q * 5000 * h[d])
+        want = q * float(np.sum(pos.astype(np.float64)))
+        assert moment == pytest.approx(want, rel=1e-12, abs=1e-13 * q * 5000 * h[d])
 
 
 def test_deposit_node_and_edges():
@@ -313,17 +323,71 @@ def test_deposit_pure_python_loop_small():
     np.testing.assert_allclose(Q, ref, rtol=1e-13, atol=1e-15)
 
 
+def _round_f32(v):
+    """Nearest binary32 value of the rational v (ties to even), by exact
+    rational arithmetic (no floating point on the way)."""
+    from fractions import Fraction
+    v = Fraction(v)
+    if v == 0:
+        return Fraction(0)
+    sign = -1 if v < 0 else 1
+    a = abs(v)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    while Fraction(2) ** e > a:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= a:
+        e += 1
+    scale = Fraction(2) ** (e - 23)           # 24-bit significand (normal range)
+    m = a / scale
+    lo = m.numerator // m.denominator
+    rem = m - lo
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and lo % 2 == 1):
+        lo += 1
+    return sign * lo * scale
+
+
 def test_float32_cell_decision_uses_float32_arithmetic():
-    # a particle whose FP64 coordinate is just below the mesh end but whose
-    # FP32 cell coordinate rounds onto it stays inside in the FP32 run
-    n = (4, 4, 4)
-    h = (0.1, 0.1, 0.1)
-    origin = (0.0, 0.0, 0.0)
-    x32 = np.array([np.float32(0.3)], dtype=np.float32)
-    s32 = (x32 - np.float32(0.0)) * np.float32(1.0 / 0.1)
-    assert s32.dtype == np.float32
-    s = orc.cell_coordinates(x32, 0.0, 0.1, np.float32)
-    assert s[0] == float(s32[0])
+    """The in/out decision and the cell of an FP32 particle come from
+    s = (x - x0) * (1/h) with two correctly rounded binary32 operations
+    (x0 and 1/h rounded to binary32 from FP64), emulated here by exact
+    rational arithmetic.  FP32 positions next to the mesh end and to interior
+    nodes are scanned; some of them are decided differently by exact
+    arithmetic, and the oracle must follow the binary32 result for all."""
+    from fractions import Fraction
+    n, h, origin = (4, 4, 4), (0.1, 0.1, 0.1), (0.0, 0.0, 0.0)
+    inv32 = _round_f32(Fraction(1.0 / 0.1))
+    cands = []
+    for centre in (np.float32(0.3), np.float32(0.2), np.float32(0.1)):
+        v = centre
+        for _ in range(8):
+            v = np.nextafter(v, np.float32(-1))
+        for _ in range(17):
+            cands.append(v)
+            v = np.nextafter(v, np.float32(1))
+    x = np.array(cands, dtype=np.float32)
+    yz = np.full(x.size, 0.15, dtype=np.float32)
+    s_dec, s_exact = orc.cell_coordinates(x, origin[0], h[0], np.float32)
+    differs = 0
+    for k, xv in enumerate(x):
+        s32 = _round_f32(_round_f32(Fraction(float(xv)) - 0) * inv32)
+        assert Fraction(float(s_dec[k])) == s32
+        ex = Fraction(float(xv)) / Fraction(0.1)
+        inside32, inside_ex = 0 <= s32 <= 3, 0 <= ex <= 3
+        cell32 = min(int(s32), 2) if inside32 else None
+        cell_ex = min(int(ex), 2) if inside_ex else None
+        differs += (inside32 != inside_ex) or (cell32 != cell_ex)
+        assert s_exact[k] == pytest.approx(float(ex), rel=2e-16)
+    assert differs > 0
+    inside, idx, frac = orc.cic_stencil(x, yz, yz, n, h, origin, np.float32)
+    for k in range(x.size):
+        s32 = Fraction(float(s_dec[k]))
+        assert bool(inside[k]) == (0 <= s32 <= 3)
+        if inside[k]:
+            assert idx[0][k] == min(int(s32), 2)
+            assert frac[0][k] == pytest.approx(float(s_exact[k]) - idx[0][k], abs=1e-15)
+    Q, n_out = orc.deposit_cic(x, yz, yz, 1.0, n, h, origin, np.float32)
+    assert n_out == int((~inside).sum())
+    assert Q.sum() == pytest.approx(float(inside.sum()), rel=1e-14)
 
 
 def test_gradient_exact_for_quadratic():
