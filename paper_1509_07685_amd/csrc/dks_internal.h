@@ -13,6 +13,7 @@ namespace dks {
 constexpr int kMaxPass = 12;        // radix passes per transform (N <= 4096)
 constexpr int kMaxLength = 4096;    // longest transform length
 constexpr int kLdsBytes = 65536;    // LDS budget per FFT workgroup
+constexpr size_t kLdsHardware = 163840;   // LDS per workgroup on gfx950 (160 KiB)
 constexpr int kBboxBlocks = 1024;   // first-stage blocks of the bounding-box reduction
 constexpr double kEps0 = 8.8541878128e-12;  // F/m (CODATA 2018)
 

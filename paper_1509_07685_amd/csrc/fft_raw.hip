@@ -23,6 +23,7 @@
 
 #include "dks_fft.h"
 #include "fft_engine.h"
+#include "fft_plan_check.h"
 
 namespace dks {
 
@@ -385,6 +386,22 @@ dks_status dks_fft_plan(int nx, int ny, int nz, int batch, dks_fft_kind kind, dk
   for (int a = 0; a < 3; ++a) {
     p->off_tw[a] = off;
     off = al256(off + (size_t)p->pl[a].tw_count * p->csize + 16);
+  }
+  // the pass kernels' invariants: rows staged through EMAX registers per
+  // thread (N values per row at most), columns read straight from memory
+  {
+    EngineLimits L;
+    L.threads = dtype == DKS_F32 ? RegCfg<float>::THREADS : RegCfg<double>::THREADS;
+    L.emax = dtype == DKS_F32 ? RegCfg<float>::EMAX : RegCfg<double>::EMAX;
+    L.max_length = kMaxLength;
+    L.max_pass = kMaxPass;
+    L.lds_hw = kLdsHardware;
+    int v = fft_plan_violation(p->pl[0].dev, L, p->csize, nx, L.emax, 0);
+    for (int a = 1; a < 3 && v == kPlanOk; ++a) v = fft_plan_violation(p->pl[a].dev, L, p->csize, 0, 0, 0);
+    if (v != kPlanOk) {
+      delete p;
+      return DKS_EUNSUPPORTED;
+    }
   }
   p->off_tmp = off;
   p->tmp_bytes = kind == DKS_FFT_R2C ? al256((size_t)(nx / 2 + 1) * ny * nz * batch * p->csize) : 0;

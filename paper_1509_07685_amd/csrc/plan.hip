@@ -12,6 +12,8 @@
 #include <vector>
 
 #include "dks_internal.h"
+#include "fft_engine.h"
+#include "fft_plan_check.h"
 
 namespace dks {
 
@@ -294,6 +296,34 @@ class Timed {
     if (e_ != hipSuccess) return DKS_EHIP;        \
     tm_.done();                                   \
   } while (0)
+
+// The pass kernels' limits for the dtype (what fft_engine.h is built with).
+template <typename T> EngineLimits engine_limits() {
+  EngineLimits L;
+  L.threads = RegCfg<T>::THREADS;
+  L.emax = RegCfg<T>::EMAX;
+  L.max_length = kMaxLength;
+  L.max_pass = kMaxPass;
+  L.lds_hw = kLdsHardware;
+  return L;
+}
+
+// Checks the four plans against the invariants of the pass kernels that use
+// them: x forward (rows of nx reals staged through kTileReals registers per
+// thread, nx + 1 post-twiddles in LDS beside the tile), x inverse (rows of N
+// complex values staged the same way), y, z forward and z inverse (pencils
+// read straight from memory).  Returns the first violation, or kPlanOk.
+int check_plans(const dks_poisson_plan_s* p) {
+  const EngineLimits L = p->dtype == DKS_F32 ? engine_limits<float>() : engine_limits<double>();
+  const size_t c = p->csize;
+  const int nx = p->md.nx;
+  int v = fft_plan_violation(p->px.dev, L, c, nx, kTileReals, (size_t)(nx + 1) * c);
+  if (v == kPlanOk) v = fft_plan_violation(p->px.dev, L, c, p->px.dev.N, kTileReals, 0);
+  if (v == kPlanOk) v = fft_plan_violation(p->py.dev, L, c, 0, 0, 0);
+  if (v == kPlanOk) v = fft_plan_violation(p->pz.dev, L, c, 0, 0, 0);
+  if (v == kPlanOk) v = fft_plan_violation(p->pzi.dev, L, c, 0, 0, 0);
+  return v;
+}
 
 void layout(dks_poisson_plan_s* p) {
   const int nx = p->n[0], ny = p->n[1], nz = p->n[2];
@@ -679,6 +709,10 @@ dks_status dks_poisson_plan(int nx, int ny, int nz, double hx, double hy, double
   } catch (...) {
     delete p;
     return DKS_ENOMEM;
+  }
+  if (check_plans(p) != kPlanOk) {
+    delete p;
+    return DKS_EUNSUPPORTED;
   }
   *out = p;
   return DKS_OK;
