@@ -21,7 +21,13 @@ on a clock.  The scheduler:
     so a launch costs one small table copy and the replay, with no staging of
     particle data;
   * records latency = completion observed - scheduled arrival, and reports
-    p50/p99 beside throughput.
+    p50/p99 beside throughput;
+  * fails requests one batch at a time: a launch that raises, or a batch whose
+    completion reports an error, fails that batch's requests (the executor is
+    discarded, its memory returned to the budget) while every other request
+    proceeds; with a deadline, a request still waiting or running that long
+    after its arrival fails as timed out (a running batch keeps its executor
+    and stream until the device finishes it, and is not reported twice).
 
 The scheduler is plain Python and talks to a backend; `GpuBackend` drives
 the HIP library through its C ABI (all solve work runs in the library's
@@ -48,7 +54,8 @@ class Job:
     start_s: float = None
     done_s: float = None
     batch_size: int = None
-    status: str = "waiting"      # waiting | running | done | refused | failed
+    status: str = "waiting"      # waiting | running | done | refused | failed | timeout
+    error: str = None            # why a failed request failed
 
 
 @dataclasses.dataclass
@@ -56,6 +63,7 @@ class Stats:
     completed: int
     refused: int
     failed: int
+    timed_out: int
     wall_s: float
     throughput: float
     p50_ms: float
@@ -88,13 +96,19 @@ class Scheduler:
       create_executor(key) -> ex          allocate (and prepare) an executor
       destroy_executor(ex)
       launch(ex, jobs, stream) -> token   enqueue one batched solve, non-blocking
-      done(token) -> bool                 has the launch completed
-      error(token) -> str or None
+                                          (may raise: the batch fails)
+      done(token) -> bool                 has the launch completed (or failed)
+      error(token) -> str or None         why a completed launch failed
       num_streams, max_batch
+
+    timeout_s: deadline of a request, counted from its scheduled arrival
+    (None: no deadline).
     """
 
-    def __init__(self, backend, budget_bytes=64 * GiB, clock=time.perf_counter, idle_wait_s=0.0, max_per_key=2):
+    def __init__(self, backend, budget_bytes=64 * GiB, clock=time.perf_counter, idle_wait_s=0.0, max_per_key=2,
+                 timeout_s=None):
         self.be = backend
+        self.timeout_s = timeout_s
         self.budget = budget_bytes
         # at most this many executors of one (shape, dtype): further requests of
         # that key wait for one to come back and leave together as a batch
@@ -105,6 +119,7 @@ class Scheduler:
         self.plans = {}                              # key -> bytes (resident plans)
         self.idle = collections.defaultdict(list)    # key -> [executor]
         self.busy = {}                               # token -> (executor, jobs, stream)
+        self.abandoned = set()                       # tokens whose requests already timed out
         self.lru = collections.OrderedDict()         # executor id -> (key, executor) of idle executors
         self.used = 0
         self.peak = 0
@@ -131,6 +146,15 @@ class Scheduler:
             self.evictions += 1
             return True
         return False
+
+    def _discard(self, ex):
+        """Drop an executor whose launch failed; its bytes return to the budget."""
+        self.count[ex.key] -= 1
+        self.used -= self.be.executor_bytes(ex.key)
+        try:
+            self.be.destroy_executor(ex)
+        except Exception:       # the executor is gone either way
+            pass
 
     def _executor_for(self, key):
         """An idle executor of `key`, creating one within the budget and the
@@ -208,14 +232,36 @@ class Scheduler:
                     ex, batch, stream = self.busy.pop(token)
                     t_done = self.clock() - t0
                     err = self.be.error(token)
-                    for j in batch:
-                        j.done_s = t_done
-                        j.status = "failed" if err else "done"
-                        finished.append(j)
-                    self.idle[ex.key].append(ex)
-                    self.lru[id(ex)] = (ex.key, ex)
+                    if token in self.abandoned:
+                        self.abandoned.discard(token)
+                    else:
+                        for j in batch:
+                            j.done_s = t_done
+                            j.status = "failed" if err else "done"
+                            j.error = err
+                            finished.append(j)
+                    if err:
+                        self._discard(ex)
+                    else:
+                        self.idle[ex.key].append(ex)
+                        self.lru[id(ex)] = (ex.key, ex)
                     free_streams.append(stream)
                     progressed = True
+            if self.timeout_s is not None:
+                now = self.clock() - t0
+                for q in queues.values():
+                    while q and now - q[0].arrival_s > self.timeout_s:
+                        j = q.popleft()
+                        j.status, j.done_s, j.error = "timeout", now, "deadline passed while waiting"
+                        finished.append(j)
+                for token, (ex, batch, stream) in self.busy.items():
+                    if token in self.abandoned:
+                        continue
+                    if now - min(j.arrival_s for j in batch) > self.timeout_s:
+                        self.abandoned.add(token)
+                        for j in batch:
+                            j.status, j.done_s, j.error = "timeout", now, "deadline passed while running"
+                            finished.append(j)
             while free_streams:
                 ready = [(q[0].arrival_s, q[0].rid, k) for k, q in queues.items() if q]
                 if not ready:
@@ -233,7 +279,17 @@ class Scheduler:
                         j.start_s = t_start
                         j.batch_size = len(batch)
                         j.status = "running"
-                    token = self.be.launch(ex, batch, stream)
+                    try:
+                        token = self.be.launch(ex, batch, stream)
+                    except Exception as e:      # this batch fails; the loop goes on
+                        t_fail = self.clock() - t0
+                        for j in batch:
+                            j.done_s, j.status, j.error = t_fail, "failed", repr(e)
+                            finished.append(j)
+                        self._discard(ex)
+                        free_streams.append(stream)
+                        launched = progressed = True
+                        break
                     self.busy[token] = (ex, batch, stream)
                     launched = progressed = True
                     break
@@ -247,7 +303,8 @@ class Scheduler:
         hist = collections.Counter(j.batch_size for j in done)
         span = max((j.done_s for j in done), default=0.0) - min((j.arrival_s for j in jobs), default=0.0)
         return Stats(completed=len(done), refused=sum(j.status == "refused" for j in finished),
-                     failed=sum(j.status == "failed" for j in finished), wall_s=wall,
+                     failed=sum(j.status == "failed" for j in finished),
+                     timed_out=sum(j.status == "timeout" for j in finished), wall_s=wall,
                      throughput=len(done) / span if span > 0 else float("nan"),
                      p50_ms=percentile(lat, 0.5), p99_ms=percentile(lat, 0.99),
                      mean_ms=sum(lat) / len(lat) if lat else float("nan"),
@@ -367,6 +424,7 @@ class GpuBackend:
         self.streams = [torch.cuda.Stream() for _ in range(num_streams)]
         self._plans = {}
         self._tokens = {}
+        self._errors = {}
         self._next = 0
         self._sizes = {}
 
@@ -411,25 +469,38 @@ class GpuBackend:
         del ex
 
     def launch(self, ex, jobs, stream_id):
+        """Enqueue the batch; a failure to enqueue it (a library status, a
+        HIP error raised by the runtime) is kept as the token's error and the
+        token reads as done, so only this batch fails."""
         torch = self.torch
-        s = self.streams[stream_id]
-        ex.run(jobs, s, torch)
-        ev = torch.cuda.Event()
-        ev.record(s)
         token = self._next
         self._next += 1
+        s = self.streams[stream_id]
+        try:
+            ex.run(jobs, s, torch)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        except Exception as e:
+            self._errors[token] = repr(e)
+            return token
         self._tokens[token] = ev
         return token
 
     def done(self, token):
-        ev = self._tokens[token]
-        if ev.query():
-            del self._tokens[token]
+        if token in self._errors:
             return True
-        return False
+        ev = self._tokens[token]
+        try:
+            ok = ev.query()
+        except Exception as e:          # an error raised by the device work
+            self._errors[token] = repr(e)
+            ok = True
+        if ok:
+            del self._tokens[token]
+        return ok
 
     def error(self, token):
-        return None
+        return self._errors.pop(token, None)
 
 
 def make_jobs(torch, requests, device="cuda", dtype_override=None, host=False):
@@ -498,9 +569,14 @@ def bench_stream(torch, num_requests=2000, rate_hz=500.0, seed=5, budget_bytes=6
                  host_io=False):
     """The mixed-size request stream: batched server vs the one-at-a-time FP64
     path.  host_io: requests start and end in page-locked host memory, and
-    both latencies include the uploads and downloads."""
+    both latencies include the uploads and downloads.  rate_hz=None: the
+    same requests (those of the 500/s stream) all arrive at once, which
+    measures the capacity of each path."""
     from paper_1509_07685_amd import workloads as wl
-    reqs = wl.serving_stream(num_requests, rate_hz, seed)
+    if rate_hz is None:
+        reqs = [dataclasses.replace(r, arrival_s=0.0) for r in wl.serving_stream(num_requests, 500.0, seed)]
+    else:
+        reqs = wl.serving_stream(num_requests, rate_hz, seed)
     backend = GpuBackend(torch, use_graphs=use_graphs, host_io=host_io)
     sched = Scheduler(backend, budget_bytes)
     # off the clock: resident plans and executors (graphs captured) for every

@@ -180,3 +180,87 @@ def test_busy_shape_batches_instead_of_growing_executors():
     # arrival order is kept within the shape
     order = [rid for _, r, _ in be.launches for rid in r]
     assert order == sorted(order)
+
+
+class FaultyBackend(FakeBackend):
+    """FakeBackend with injected failures: a launch that raises for one
+    request, a completion that reports an error for another, and a launch
+    whose completion stalls for `stall_s`."""
+
+    def __init__(self, clock, raise_rid=None, error_rid=None, stall_rid=None, stall_s=0.0, **kw):
+        super().__init__(clock, **kw)
+        self.raise_rid, self.error_rid, self.stall_rid, self.stall_s = raise_rid, error_rid, stall_rid, stall_s
+        self.errors = {}
+
+    def launch(self, ex, jobs, stream):
+        rids = [j.rid for j in jobs]
+        if self.raise_rid in rids:
+            raise RuntimeError("injected: launch failed")
+        token = super().launch(ex, jobs, stream)
+        if self.error_rid in rids:
+            self.errors[token] = "injected: device error"
+        if self.stall_rid in rids:
+            self.inflight[token] += self.stall_s
+        return token
+
+    def error(self, token):
+        return self.errors.pop(token, None)
+
+
+def test_a_launch_that_raises_fails_only_its_batch():
+    clock = FakeClock()
+    be = FaultyBackend(clock, raise_rid=7, max_batch=1, num_streams=2)
+    jobs = jobs_from([(0.0002 * i, A if i % 2 else B) for i in range(40)])
+    sched = serve.Scheduler(be, budget_bytes=1 << 40, clock=clock)
+    stats = sched.run(jobs)
+    assert stats.failed == 1 and stats.completed == 39
+    assert jobs[7].status == "failed" and "injected" in jobs[7].error
+    assert all(j.status == "done" for j in jobs if j.rid != 7)
+    # the failed executor was discarded and its bytes returned
+    assert sched.used == sum(sched.plans.values()) + sum(
+        len(v) * be.executor_bytes(k) for k, v in sched.idle.items())
+
+
+def test_a_completion_with_an_error_fails_its_batch_and_discards_the_executor():
+    clock = FakeClock()
+    be = FaultyBackend(clock, error_rid=3, max_batch=4, num_streams=2)
+    jobs = jobs_from([(0.0, A)] * 2 + [(0.001, A)] * 6)
+    stats = serve.Scheduler(be, budget_bytes=1 << 40, clock=clock).run(jobs)
+    bad = [j for j in jobs if j.status == "failed"]
+    assert 3 in [j.rid for j in bad] and all(j.error == "injected: device error" for j in bad)
+    assert stats.failed == len(bad) and stats.completed == 8 - len(bad)
+    assert len(bad) <= be.max_batch
+    assert A in be.destroyed
+
+
+def test_a_stalled_batch_times_out_and_the_rest_proceeds():
+    """One batch's completion stalls for 50 ms; with a 5 ms deadline its
+    requests fail as timed out, requests of the same shape behind it use the
+    other executor and stream, and the stalled executor is reused once the
+    device finishes (its requests are not reported twice)."""
+    clock = FakeClock()
+    be = FaultyBackend(clock, stall_rid=2, stall_s=0.05, max_batch=1, num_streams=2)
+    jobs = jobs_from([(0.0005 * i, A) for i in range(30)])
+    sched = serve.Scheduler(be, budget_bytes=1 << 40, clock=clock, timeout_s=0.005)
+    stats = sched.run(jobs)
+    assert jobs[2].status == "timeout" and "running" in jobs[2].error
+    assert stats.timed_out >= 1 and stats.completed + stats.timed_out == 30
+    assert stats.failed == 0
+    assert sum(1 for j in jobs if j.status == "done") == stats.completed
+    assert be.created.count(A) <= 2 and not sched.busy and not sched.abandoned
+    # the stalled batch's executor went back to the idle pool at the end
+    assert len(sched.idle[A]) == be.created.count(A)
+
+
+def test_requests_waiting_past_their_deadline_time_out():
+    """One stream, slow solves and a burst: requests that cannot start before
+    their deadline time out while waiting; those that do start complete."""
+    clock = FakeClock()
+    be = FakeBackend(clock, max_batch=1, num_streams=1)
+    jobs = jobs_from([(0.0, C)] * 10)
+    stats = serve.Scheduler(be, budget_bytes=1 << 40, clock=clock, timeout_s=0.006).run(jobs)
+    late = [j for j in jobs if j.status == "timeout"]
+    assert any("waiting" in j.error for j in late)
+    assert all(("waiting" in j.error) or ("running" in j.error) for j in late)
+    assert stats.completed + stats.timed_out == 10 and stats.completed >= 1
+    assert all(j.done_s - j.arrival_s <= 0.006 + 0.005 for j in jobs if j.status == "done")
