@@ -101,8 +101,11 @@ typedef void* dks_stream_t;
 dks_status dks_poisson_plan(int nx, int ny, int nz, double hx, double hy, double hz,
                             dks_dtype dtype, dks_poisson_plan_t* out);
 
-/* Move an explicit-h mesh: node (0,0,0) at (x0, y0, z0) metres.  Takes effect
- * from the next solve.  DKS_ESTATE on a fitted plan. */
+/* Move an explicit-h mesh: node (0,0,0) at (x0, y0, z0) metres (the mesh
+ * the solver section places over the bunch; here its position is the
+ * caller's choice instead of a fit).  Takes effect from the next solve.
+ * Host-only.  DKS_EINVAL for a non-finite value, DKS_ESTATE on a fitted
+ * plan. */
 dks_status dks_poisson_set_origin(dks_poisson_plan_t plan, double x0, double y0, double z0);
 
 /* Select the convolution kernel and the assignment scheme (defaults:
@@ -113,18 +116,24 @@ dks_status dks_poisson_set_scheme(dks_poisson_plan_t plan, dks_green green, dks_
 
 /* Bytes of device workspace the plan needs: its resident state (Green's
  * spectrum octant, twiddle tables, geometry block) plus the scratch of one
- * solve.  Alignment required: 256 bytes. */
+ * solve.  The caller allocates it (section "DKS": memory management is left
+ * to the user, as in its allocate / write / call / read / free example).
+ * Alignment required: 256 bytes.  Host-only; DKS_EINVAL for NULL. */
 dks_status dks_poisson_workspace_bytes(dks_poisson_plan_t plan, size_t* bytes);
 
 /* Bytes of per-element scratch a batched solve needs for `batch` elements
  * of at most max_np particles each, on top of the plan workspace: each
- * element's mesh intermediates and its binned particle records. */
+ * element's mesh intermediates and its binned particle records.  Caller-
+ * allocated like every buffer (section "DKS": memory management is the
+ * user's).  Host-only; DKS_EINVAL for batch outside 1..16, a negative or too
+ * large max_np, or NULL. */
 dks_status dks_poisson_batch_scratch_bytes(dks_poisson_plan_t plan, int batch, int64_t max_np,
                                            size_t* bytes);
 
 /* Particle solves and the deposit group the particles by mesh tile before
- * depositing (so that charge accumulates in on-chip memory rather than by
- * contended device-wide atomics) and need a caller-owned device scratch of
+ * depositing (so that the CIC charge assignment of the OPAL structure figure
+ * accumulates in on-chip memory rather than by contended device-wide
+ * atomics) and need a caller-owned device scratch of
  * dks_poisson_particle_scratch_bytes(np) bytes for np particles (16 bytes per
  * particle in FP32, 28 in FP64: the binned (x, y, z) record and the inverse
  * permutation, each rounded up to 256), attached with
@@ -161,8 +170,13 @@ dks_status dks_poisson_prepare(dks_poisson_plan_t plan, dks_stream_t stream);
 dks_status dks_poisson_solve_rho(dks_poisson_plan_t plan, const void* rho, void* phi,
                                  void* E_mesh, dks_stream_t stream);
 
-/* One full particle step: (fit the mesh,) CIC deposit, free-space potential,
- * central-difference field, CIC gather back to the particles.
+/* One full particle step (section "FFT Based Particle-Mesh Solver" and the
+ * OPAL structure figure): (fit the mesh to the bunch,) CIC deposit of the
+ * charge, free-space potential by the doubled-grid FFT convolution with the
+ * Green's function, central-difference field, CIC gather back to the
+ * particles.  Needs the attached particle scratch (DKS_EWORKSPACE without
+ * room for np particles), the workspace and a prepared spectrum
+ * (DKS_ESTATE otherwise).
  *   x, y, z    : device [np] particle positions in metres, read only.
  *   np         : number of particles, 0 <= np <= 2^32 - 2^20.
  *   q          : charge of each particle in coulombs.
@@ -194,8 +208,10 @@ typedef struct {
 } dks_particle_set;
 
 /* The particle step for `batch` independent particle sets of the plan's
- * shape and dtype, each kernel launched once over the whole batch (the batch
- * index is part of the grid).  On a fitted plan every element gets its own
+ * shape and dtype (the many solver clients the paper's DKS implementation of
+ * the Poisson solver lets share one GPU, section "The DKS Implementation of
+ * the Poisson Solver"), each kernel launched once over the whole batch (the
+ * batch index is part of the grid).  On a fitted plan every element gets its own
  * mesh fit, and the cached unit-spacing spectrum is rescaled per element
  * (the integrated kernel grows as h^2 on a cubic mesh, the density as h^-3).
  *   batch   : 1 .. 16 elements.
@@ -299,12 +315,16 @@ dks_status dks_poisson_host_query(dks_poisson_plan_t plan, uint64_t ticket, int*
  * outputs.  DKS_EINVAL for a ticket not yet issued. */
 dks_status dks_poisson_host_wait(dks_poisson_plan_t plan, uint64_t ticket);
 
-/* Release the plan's host state.  Waits for outstanding host-resident solves
- * and releases the plan's copy streams.  Does not touch the caller's
- * workspace. */
+/* Release the plan's host state (the free step of section "DKS"'s usage
+ * example, for the library's own part: the caller frees the buffers it
+ * allocated).  Waits for outstanding host-resident solves and releases the
+ * plan's copy streams.  Does not touch the caller's workspace.  NULL is
+ * DKS_EINVAL; the handle is invalid afterwards. */
 dks_status dks_poisson_destroy(dks_poisson_plan_t plan);
 
-/* Static, NUL-terminated description of a status code. */
+/* Static, NUL-terminated description of a status code (the error side of
+ * the status-returning calls of section "DKS"'s usage example); never NULL,
+ * "unknown status" for a value outside dks_status. */
 const char* dks_status_string(dks_status status);
 
 #ifdef __cplusplus
