@@ -31,7 +31,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 
 
 def algorithmic_bytes(n, num_particles, s, kernel):
-    """Bytes a kernel must move per launch (compulsory traffic of the design)."""
+    """Bytes a kernel must move per launch in this design (its compulsory
+    traffic: every array it reads and writes, once)."""
     nx, ny, nz = n
     c = 2 * s
     mesh = nx * ny * nz
@@ -53,6 +54,31 @@ def algorithmic_bytes(n, num_particles, s, kernel):
         "unsort": 4 * num_particles + 3 * s * num_particles + 3 * s * num_particles,
     }
     return model[kernel]
+
+
+def method_bytes(n, num_particles, s, kernel):
+    """Bytes the method itself must move per launch, by the per-step byte model
+    of the path (mesh fit: positions read once; deposit: positions read, mesh
+    written, plus one read and one write of the positions for binning; the
+    five convolution passes; gather: positions read, field at the particles
+    written in the caller's order, mesh read).  What a kernel moves beyond
+    this (the count pass's second read of the positions, the permutation,
+    the gather's sorted copy of the field and the unsort's re-read of it) is
+    overhead of this design."""
+    nx, ny, nz = n
+    mesh = nx * ny * nz
+    part = 3 * s * num_particles
+    if kernel in ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv", "geometry", "bin_scan",
+                  "gradient"):
+        return algorithmic_bytes(n, num_particles, s, kernel)
+    return {
+        "bbox": part,
+        "bin_count": 0,
+        "bin_scatter": 2 * part,
+        "deposit": part + s * mesh,
+        "gather": part + s * (nx + 2) * (ny + 2) * (nz + 2),
+        "unsort": part,
+    }[kernel]
 
 
 # Library timing names -> kernel symbols as rocprofv3 reports them.
@@ -224,31 +250,60 @@ def musr_fit(torch, dks):
 
 
 def cpu_baseline():
-    """The oracle as it stands on a bounded sample: the full particle step on a
-    128^3 fitted mesh with 1.25e7 particles of the same halo-Gaussian bunch
-    (the workload scaled by 1/8 in mesh points and particles alike), once."""
+    """The oracle as it stands, timed on this host's cores.
+
+    All threads (the oracle's chunk pool, FFT workers and Green's-function
+    loops): one full particle step on the benchmark's own 256^3 fitted mesh
+    with a 1e7-particle sample of the same halo-Gaussian bunch; the mesh part
+    (Green's function, convolution, gradient) is timed alone and the per-step
+    time for the 1e8 particles is the mesh part plus ten times the sample's
+    particle part (deposit and gather are linear in the particle count).
+    One thread: the same step on the workload scaled by 1/8 (128^3 mesh,
+    1.25e7 particles), whose rate is reported as measured."""
     import numpy as np
     from oracle import poisson_oracle as orc
     from paper_1509_07685_amd import workloads as wl
-    x, y, z = wl.halo_gaussian(12_500_000, 1e-3, 0.1, 5e-3, 4, np.float32)
-    reps, n = 3, (128, 128, 128)
+    threads_all = len(os.sched_getaffinity(0))
+    full = wl.HALO_GAUSSIAN
+    n = full.n
+    sample = 10_000_000
+    x, y, z = wl.halo_gaussian(sample, 1e-3, 0.1, 5e-3, full.seed, np.float32)
+    q = wl.TOTAL_CHARGE / sample
+    orc.set_threads(threads_all)
     t0 = time.perf_counter()
-    for _ in range(reps):
-        orc.solve_particles(x, y, z, wl.TOTAL_CHARGE / x.size, n, dtype=np.float32)
-    dt = (time.perf_counter() - t0) / reps
+    ref = orc.solve_particles(x, y, z, q, n, dtype=np.float32)
+    t_step = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    orc.solve_rho(ref["rho"], ref["h"])
+    t_mesh = time.perf_counter() - t0
+    del ref
+    t_part = max(t_step - t_mesh, 0.0)
+    t_full = t_mesh + t_part * full.num_particles / sample
+    # one thread, the workload scaled by 1/8
+    n8 = (128, 128, 128)
+    x8, y8, z8 = wl.halo_gaussian(12_500_000, 1e-3, 0.1, 5e-3, full.seed, np.float32)
+    orc.set_threads(1)
+    t0 = time.perf_counter()
+    orc.solve_particles(x8, y8, z8, wl.TOTAL_CHARGE / x8.size, n8, dtype=np.float32)
+    t_one = time.perf_counter() - t0
+    orc.set_threads(threads_all)
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": n[0] * n[1] * n[2] / dt, "unit": "mesh-pts/s", "cores": 1, "kind": "oracle",
-            "host_cpu": model, "host_threads": len(os.sched_getaffinity(0)),
-            "sample": "FP64 numpy oracle, full particle step (fit, CIC deposit, IGF, doubled-grid FFT "
-                      "convolution, gradient, gather) on a 128^3 fitted mesh with 1.25e7 particles of the "
-                      "halo-Gaussian bunch (the 256^3 / 1e8 workload scaled by 1/8), mean of three runs; "
-                      "numpy's FFT and bincount are single-threaded",
-            "seconds_per_step": dt}
+    mesh_pts = n[0] * n[1] * n[2]
+    return {"value": mesh_pts / t_full, "unit": "mesh-pts/s", "cores": threads_all, "kind": "oracle",
+            "host_cpu": model, "host_threads": threads_all,
+            "sample": f"FP64 oracle (numpy, scipy.fft, the Green's function in 113-bit C), {threads_all} threads: "
+                      f"one full particle step on the 256^3 fitted mesh with a 1e7-particle sample of the "
+                      f"halo-Gaussian bunch; seconds per 1e8-particle step = mesh part + 10 x particle part",
+            "seconds_per_step": t_full, "mesh_part_s": t_mesh, "particle_part_s_per_1e7": t_part,
+            "single_thread": {"value": n8[0] * n8[1] * n8[2] / t_one, "unit": "mesh-pts/s", "cores": 1,
+                              "sample": "one full particle step on a 128^3 fitted mesh with 1.25e7 particles "
+                                        "(the workload scaled by 1/8), measured",
+                              "seconds_per_step": t_one}}
 
 
 def progress(msg):
@@ -366,27 +421,43 @@ def main():
     for name, (launches, total, mn, mx) in kt.items():
         avg = total / launches
         alg = algorithmic_bytes(n, num, 4, name)
+        mb = method_bytes(n, num, 4, name)
         kernels[name] = {"launches": launches, "avg_ms": avg, "min_ms": mn, "max_ms": mx,
-                         "alg_bytes": alg, "GB_s": alg / (avg * 1e-3) / 1e9 if alg else None}
-    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
-    dk = kernels[dom]
+                         "alg_bytes": alg, "GB_s": alg / (avg * 1e-3) / 1e9 if alg else None,
+                         "method_bytes": mb, "method_GB_s": mb / (avg * 1e-3) / 1e9 if mb else None}
     # a plain 1 GiB device-to-device copy on this GPU: the achievable streaming rate
     csrc = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
     cdst = torch.empty_like(csrc)
     copy_ms = time_loop(torch, lambda: cdst.copy_(csrc), 10, 2)
     copy_gbs = 2 * csrc.numel() * 4 / (copy_ms * 1e-3) / 1e9
     del csrc, cdst
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dk["GB_s"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
-                "alg_bytes": dk["alg_bytes"], "device_copy_GB_s": copy_gbs,
-                "frac_of_device_copy": dk["GB_s"] / copy_gbs}
+    # the roofline of the path's target: the five passes of the 256^3 FFT
+    # convolution (512^3 doubled grid), their summed average launch durations
+    # against the byte model of the pruned passes
     conv_names = ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv")
     conv_ms = sum(kernels[k]["avg_ms"] for k in conv_names if k in kernels)
-    conv = {"ms": conv_ms, "alg_bytes": conv_bytes(n, 4),
-            "GB_s": conv_bytes(n, 4) / (conv_ms * 1e-3) / 1e9,
-            "mesh_pts_per_s": mesh_pts / (conv_ms * 1e-3)}
-    conv["frac"] = conv["GB_s"] / HBM_PEAK_GBS
-    conv["frac_of_device_copy"] = conv["GB_s"] / copy_gbs
+    conv_alg = conv_bytes(n, 4)
+    conv_traffic = [measured_traffic(k) for k in conv_names]
+    conv_gbs = conv_alg / (conv_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "convolution: " + " + ".join(KERNEL_SYMBOL[k] for k in conv_names),
+                "achieved": conv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": conv_gbs / HBM_PEAK_GBS,
+                "traffic": None if None in conv_traffic else sum(conv_traffic),
+                "alg_bytes": conv_alg, "avg_ms": conv_ms,
+                "per_kernel_ms": {KERNEL_SYMBOL[k]: kernels[k]["avg_ms"] for k in conv_names if k in kernels},
+                "device_copy_GB_s": copy_gbs, "frac_of_device_copy": conv_gbs / copy_gbs}
+    conv = {"ms": conv_ms, "alg_bytes": conv_alg, "GB_s": conv_gbs, "mesh_pts_per_s": mesh_pts / (conv_ms * 1e-3),
+            "frac": conv_gbs / HBM_PEAK_GBS, "frac_of_device_copy": conv_gbs / copy_gbs}
+    # the longest kernel of the step, by the method's bytes and by this design's
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
+    dk = kernels[dom]
+    slowest = {"kernel": KERNEL_SYMBOL.get(dom, dom), "avg_ms": dk["avg_ms"], "method_bytes": dk["method_bytes"],
+               "method_frac": (dk["method_GB_s"] or 0.0) / HBM_PEAK_GBS, "design_bytes": dk["alg_bytes"],
+               "design_frac": (dk["GB_s"] or 0.0) / HBM_PEAK_GBS, "traffic": measured_traffic(dom)}
+    step_method = sum(k["method_bytes"] for k in kernels.values())
+    step_design = sum(k["alg_bytes"] for k in kernels.values())
+    step_bytes = {"method_bytes": step_method, "design_bytes": step_design,
+                  "method_frac": step_method / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                  "design_frac": step_design / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     extra = {}
     if not args.no_extra:
@@ -420,7 +491,7 @@ def main():
             dks.dks_timing_enable(False)
             s = 4 if dt_name == "f32" else 8
             cms = sum(kk[k][1] / kk[k][0] for k in conv_names if k in kk)
-            extra[f"solve_{dt_name}"] = {"ms": ms, "mesh_pts_per_s": mesh_pts / (ms * 1e-3),
+            extra[f"solve_{dt_name}"] = {"ms": ms, "mesh_pts_per_s": mesh_pts / (ms * 1e-3), "conv_ms": cms,
                                          "conv_GB_s": conv_bytes(n, s) / (cms * 1e-3) / 1e9,
                                          "conv_frac": conv_bytes(n, s) / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS}
             del mp, rho, phi
@@ -475,6 +546,8 @@ def main():
         "green_build_ms": green_ms,
         "kernels": kernels,
         "convolution": conv,
+        "slowest_kernel": slowest,
+        "step_bytes": step_bytes,
         **extra,
     }
     print(json.dumps(line))

@@ -35,6 +35,7 @@
  * special case.
  */
 #include <math.h>
+#include <omp.h>
 #include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -63,6 +64,11 @@ static q_t cell_integral(int64_t a, int64_t b, int64_t c, q_t hx, q_t hy, q_t hz
         else total -= f;
       }
   return total;
+}
+
+/* Number of OpenMP threads the loops below use. */
+void oracle_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
 }
 
 /*

@@ -229,9 +229,12 @@ _THREADS = max(1, min(os.cpu_count() or 1, 16))
 
 
 def set_threads(num):
-    """Number of host threads the oracle uses (chunk pool and FFT workers)."""
+    """Number of host threads the oracle uses (chunk pool, FFT workers and the
+    Green's function loops of the C part)."""
     global _THREADS
     _THREADS = max(1, int(num))
+    if _LIB is not None:
+        _LIB.oracle_set_threads(_THREADS)
 
 
 def threads():
@@ -352,6 +355,9 @@ def _igf_lib():
         lib.oracle_igf_octant.restype = ctypes.c_int
         lib.oracle_igf_at.argtypes = [ctypes.c_int64, ip, ip, ip] + [ctypes.c_double] * 3 + [dp]
         lib.oracle_igf_at.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
+        lib.oracle_set_threads(_THREADS)
         _LIB = lib
     return _LIB
 

@@ -34,3 +34,22 @@ def test_particle_kernel_bytes():
     assert set(bench.KERNEL_SYMBOL) <= set(["bbox", "geometry", "bin_count", "bin_scan", "bin_scatter", "deposit",
                                             "fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv",
                                             "gradient", "gather", "unsort"])
+
+
+def test_method_bytes_of_the_step():
+    """The method's bytes per step: the path's byte model (mesh fit, deposit
+    with one binning read and write, five convolution passes, gather), with
+    no share for this design's permutation, count pass or unsort re-reads."""
+    n, npart, s = (256, 256, 256), 100_000_000, 4
+    mb = lambda k: bench.method_bytes(n, npart, s, k)
+    part = 3 * s * npart
+    assert mb("bin_count") == 0
+    assert mb("bin_scatter") == 2 * part
+    assert mb("gather") + mb("unsort") == 2 * part + s * 258 ** 3
+    names = ("bbox", "geometry", "bin_count", "bin_scan", "bin_scatter", "deposit", "fft_x_fwd", "fft_y_fwd",
+             "fft_z_conv", "fft_y_inv", "fft_x_inv", "gather", "unsort")
+    total = sum(mb(k) for k in names)
+    model = part + s * 256 ** 3 + (part + s * 256 ** 3 + 2 * part) + bench.conv_bytes(n, s) + \
+        (2 * part + s * 258 ** 3)
+    assert total == model
+    assert all(mb(k) <= bench.algorithmic_bytes(n, npart, s, k) for k in names)
