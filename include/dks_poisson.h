@@ -228,6 +228,32 @@ dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t plan, int batc
                                                void* scratch, size_t scratch_bytes,
                                                dks_stream_t stream);
 
+/* Bytes of the library's own binned-particle scratch used by
+ * dks_poisson_solve_particles_noalloc (64 MiB per GPU). */
+#define DKS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* dks_poisson_solve_particles for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, hosts that forbid
+ * allocation after start-up): the same step, arguments, results and errors,
+ * but the binned-particle scratch is not the plan's attached one.  It is a
+ * static device array of DKS_NOALLOC_SCRATCH_BYTES inside the library, one per
+ * GPU, held from the first such call on that GPU until the process ends.
+ * The call allocates nothing; the plan's workspace (set beforehand) is used as
+ * by dks_poisson_solve_particles.
+ *   np : at most the count whose dks_poisson_particle_scratch_bytes is
+ *        <= DKS_NOALLOC_SCRATCH_BYTES (about 4.1 million FP32 particles, 2.3
+ *        million FP64); larger counts return DKS_EWORKSPACE before any
+ *        device work.
+ * Every call on one GPU shares that GPU's array, through all plans: calls
+ * whose device work overlaps (concurrent streams, or host threads) race and
+ * give wrong results; calls ordered on one stream, or separated by a
+ * synchronisation, are safe.  Nothing in the array needs clearing between
+ * calls (each call writes what it reads). */
+dks_status dks_poisson_solve_particles_noalloc(dks_poisson_plan_t plan, const void* x, const void* y,
+                                               const void* z, int64_t np, double q, void* Ex,
+                                               void* Ey, void* Ez, void* phi, int64_t* n_outside,
+                                               dks_stream_t stream);
+
 /* Charge deposit alone (CIC assignment, the "NGP, CIC, TSI" box of the OPAL
  * structure figure), including the mesh fit of a fitted plan.
  *   rho       : device [nz][ny][nx], written with the charge density, C/m^3.

@@ -658,6 +658,32 @@ hipEvent_t landed_event(const HostPipe& hp, uint64_t ticket) {
 
 }  // namespace
 
+// Binned-particle scratch of the allocation-free particle solve: a file-scope
+// device array (each GPU the library runs on holds its own copy until the
+// process ends).  Host code never uses the array's name as an address: its
+// device address is looked up once per device with hipGetSymbolAddress.
+constexpr size_t kNoallocScratchBytes = (size_t)DKS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up on the first call on it.
+static dks_status noalloc_scratch(char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return DKS_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return DKS_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return DKS_EHIP;
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return DKS_OK;
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -752,11 +778,11 @@ dks_status dks_poisson_particle_scratch_bytes(dks_poisson_plan_t p, int64_t np, 
   return DKS_OK;
 }
 
-dks_status dks_poisson_set_particle_scratch(dks_poisson_plan_t p, void* scratch, size_t bytes) {
+dks_status dks_poisson_set_particle_scratch(dks_poisson_plan_t p, void* buf, size_t bytes) {
   if (!p) return DKS_EINVAL;
-  if (bytes > 0 && (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255u))) return DKS_EWORKSPACE;
-  p->pscratch = static_cast<char*>(scratch);
-  p->pscratch_bytes = scratch ? bytes : 0;
+  if (bytes > 0 && (!buf || (reinterpret_cast<uintptr_t>(buf) & 255u))) return DKS_EWORKSPACE;
+  p->pscratch = static_cast<char*>(buf);
+  p->pscratch_bytes = buf ? bytes : 0;
   return DKS_OK;
 }
 
@@ -889,16 +915,36 @@ dks_status dks_poisson_solve_particles(dks_poisson_plan_t p, const void* x, cons
   return r;
 }
 
+dks_status dks_poisson_solve_particles_noalloc(dks_poisson_plan_t p, const void* x, const void* y, const void* z,
+                                               int64_t np, double q, void* Ex, void* Ey, void* Ez, void* phi,
+                                               int64_t* n_outside, dks_stream_t stream) {
+  if (!p || np < 0 || np > kMaxParticles || !std::isfinite(q)) return DKS_EINVAL;
+  if (np > 0 && (!x || !y || !z || !Ex || !Ey || !Ez)) return DKS_EINVAL;
+  if (!ws_ready(p)) return DKS_EWORKSPACE;
+  if (particle_bytes(p, np) > kNoallocScratchBytes) return DKS_EWORKSPACE;
+  if (!p->prepared) return DKS_ESTATE;
+  char* buf = nullptr;
+  const dks_status rs = noalloc_scratch(&buf);
+  if (rs != DKS_OK) return rs;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  Slots sl{p->ws + p->off_slot, p->slot_bytes};
+  const ElemBatch eb = single(x, y, z, Ex, Ey, Ez, phi, n_outside, np, q, true);
+  const dks_status r = p->dtype == DKS_F32 ? solve_particles_t<float>(p, 1, sl, eb, buf, 0, st)
+                                           : solve_particles_t<double>(p, 1, sl, eb, buf, 0, st);
+  if (r == DKS_OK) p->has_geometry = true;
+  return r;
+}
+
 dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, const dks_particle_set* sets,
-                                               int64_t max_np, void* scratch, size_t scratch_bytes,
+                                               int64_t max_np, void* buf, size_t buf_bytes,
                                                dks_stream_t stream) {
   if (!p || batch < 1 || batch > kMaxBatch || !sets) return DKS_EINVAL;
   if (max_np < 0 || max_np > kMaxParticles) return DKS_EINVAL;
   if (!ws_ready(p)) return DKS_EWORKSPACE;
   if (!p->prepared) return DKS_ESTATE;
-  if (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255u)) return DKS_EWORKSPACE;
+  if (!buf || (reinterpret_cast<uintptr_t>(buf) & 255u)) return DKS_EWORKSPACE;
   // Element b owns [b * stride, (b + 1) * stride): its slot, then its binned particles.
-  const size_t stride = (scratch_bytes / (size_t)batch) & ~(size_t)255;
+  const size_t stride = (buf_bytes / (size_t)batch) & ~(size_t)255;
   if (stride < p->slot_bytes + particle_bytes(p, max_np)) return DKS_EWORKSPACE;
   ElemBatch eb;
   std::memset(&eb, 0, sizeof(eb));
@@ -906,8 +952,8 @@ dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, 
   eb.max_np = max_np;
   eb.need_e = 1;
   const hipStream_t st = static_cast<hipStream_t>(stream);
-  Slots sl{static_cast<char*>(scratch), stride};
-  char* sorted = static_cast<char*>(scratch) + p->slot_bytes;
+  Slots sl{static_cast<char*>(buf), stride};
+  char* sorted = static_cast<char*>(buf) + p->slot_bytes;
   return p->dtype == DKS_F32 ? solve_particles_t<float>(p, batch, sl, eb, sorted, stride, st)
                              : solve_particles_t<double>(p, batch, sl, eb, sorted, stride, st);
 }

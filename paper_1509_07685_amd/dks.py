@@ -45,7 +45,7 @@ EXPORTS = (
     "dks_poisson_host_wait", "dks_fft_plan", "dks_fft_workspace_bytes", "dks_fft_set_workspace",
     "dks_fft_prepare", "dks_fft_forward", "dks_fft_inverse", "dks_fft_destroy", "dks_musr_plan",
     "dks_musr_workspace_bytes", "dks_musr_set_workspace", "dks_musr_prepare", "dks_musr_set_data",
-    "dks_musr_eval", "dks_musr_eval_batch", "dks_musr_destroy",
+    "dks_musr_eval", "dks_musr_eval_batch", "dks_musr_destroy", "dks_poisson_solve_particles_noalloc",
 )
 
 
@@ -83,6 +83,7 @@ _SIGS = {
     "dks_poisson_solve_rho": (_i, [_PLAN, _vp, _vp, _vp, _vp]),
     "dks_poisson_solve_particles": (_i, [_PLAN, _vp, _vp, _vp, _i64, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
     "dks_poisson_solve_particles_batched": (_i, [_PLAN, _i, _vp, _i64, _vp, _sz, _vp]),
+    "dks_poisson_solve_particles_noalloc": (_i, [_PLAN, _vp, _vp, _vp, _i64, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
     "dks_poisson_deposit": (_i, [_PLAN, _vp, _vp, _vp, _i64, _d, _vp, _vp, _vp]),
     "dks_poisson_gather": (_i, [_PLAN, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
     "dks_poisson_geometry": (_i, [_PLAN, _vp, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
@@ -280,6 +281,14 @@ def dks_musr_destroy(plan):
 def dks_poisson_solve_particles(plan, x, y, z, np_, q, Ex, Ey, Ez, phi, n_outside, stream):
     _check(_lib.dks_poisson_solve_particles(plan, x, y, z, np_, q, Ex, Ey, Ez, phi, n_outside, stream),
            "dks_poisson_solve_particles")
+
+
+def dks_poisson_solve_particles_noalloc(plan, x, y, z, np_, q, Ex, Ey, Ez, phi, n_outside, stream):
+    _check(_lib.dks_poisson_solve_particles_noalloc(plan, x, y, z, np_, q, Ex, Ey, Ez, phi, n_outside, stream),
+           "dks_poisson_solve_particles_noalloc")
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20     # DKS_NOALLOC_SCRATCH_BYTES
 
 
 class dks_particle_set(ctypes.Structure):
