@@ -30,9 +30,11 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 
 
-def algorithmic_bytes(n, num_particles, s, kernel):
+def algorithmic_bytes(n, num_particles, s, kernel, tile_order=False):
     """Bytes a kernel must move per launch in this design (its compulsory
-    traffic: every array it reads and writes, once)."""
+    traffic: every array it reads and writes, once).  tile_order: the step
+    that returns the particles in binned order (the gather writes the field
+    and the positions, and there is no unsort)."""
     nx, ny, nz = n
     c = 2 * s
     mesh = nx * ny * nz
@@ -50,13 +52,13 @@ def algorithmic_bytes(n, num_particles, s, kernel):
         "fft_y_inv": c * (nx + 1) * 2 * ny * (nz + 2) + c * (nx + 1) * (ny + 2) * (nz + 2),
         "fft_x_inv": c * (nx + 1) * (ny + 2) * (nz + 2) + s * (nx + 2) * (ny + 2) * (nz + 2),
         "gradient": s * (nx + 2) * (ny + 2) * (nz + 2) + 3 * s * mesh,
-        "gather": 6 * s * num_particles + s * (nx + 2) * (ny + 2) * (nz + 2),
+        "gather": ((9 if tile_order else 6) * s * num_particles + s * (nx + 2) * (ny + 2) * (nz + 2)),
         "unsort": 4 * num_particles + 3 * s * num_particles + 3 * s * num_particles,
     }
     return model[kernel]
 
 
-def method_bytes(n, num_particles, s, kernel):
+def method_bytes(n, num_particles, s, kernel, tile_order=False):
     """Bytes the method itself must move per launch, by the per-step byte model
     of the path (mesh fit: positions read once; deposit: positions read, mesh
     written, plus one read and one write of the positions for binning; the
@@ -76,7 +78,7 @@ def method_bytes(n, num_particles, s, kernel):
         "bin_count": 0,
         "bin_scatter": 2 * part,
         "deposit": part + s * mesh,
-        "gather": part + s * (nx + 2) * (ny + 2) * (nz + 2),
+        "gather": (2 * part if tile_order else part) + s * (nx + 2) * (ny + 2) * (nz + 2),
         "unsort": part,
     }[kernel]
 
@@ -85,14 +87,14 @@ def method_bytes(n, num_particles, s, kernel):
 KERNEL_SYMBOL = {
     "bbox": "k_bbox", "geometry": "k_geometry_zero", "bin_count": "k_bin_count",
     "bin_scan": "k_bin_scan", "bin_scatter": "k_bin_scatter_pipe", "deposit": "k_deposit_binned",
-    "fft_x_fwd": "k_fft_x_fwd", "fft_y_fwd": "k_fft_y_fwd", "fft_z_conv": "k_fft_z_conv",
+    "fft_x_fwd": "k_fft_x_fwd", "fft_y_fwd": "k_fft_y_fwd", "fft_z_conv": "k_fft_z_conv_pipe",
     "fft_y_inv": "k_fft_y_inv", "fft_x_inv": "k_fft_x_inv", "gradient": "k_gradient",
     "gather": "k_gather_binned", "unsort": "k_unsort",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_halo_gaussian_256cubed_1e8_f32.json")
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, tile_order=False):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, or None when there is none or the kernel's source file
     (or the shared internal header) has changed since it was taken."""
@@ -102,6 +104,8 @@ def measured_traffic(kernel):
         return None
     doc = json.load(open(TRAFFIC_FILE))
     sym = KERNEL_SYMBOL.get(kernel, "")
+    if kernel == "gather" and tile_order:
+        sym = "k_gather_binned_tile"
     src = ("fft_kernels.hip" if sym.startswith("k_fft") else
            "particle_kernels.hip" if sym in ("k_bbox", "k_geometry_zero", "k_gradient") else "bin_kernels.hip")
     deps = (src, "dks_internal.h") + (("fft_engine.h",) if src == "fft_kernels.hip" else ())
@@ -317,6 +321,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--particles", type=int, default=100_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--order", choices=("tile", "input"), default="tile",
+                    help="timed step: particles kept in the binned (tile) order, or field in the input order")
     ap.add_argument("--no-extra", action="store_true", help="skip the mesh-only and serving legs")
     ap.add_argument("--leg", choices=("raw_fft", "musr_fit", "host_offload"),
                     help="run only this secondary leg and print its JSON (for profiling)")
@@ -359,8 +365,18 @@ def main():
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
     bufs = out + (cnt,)
 
+    # The timed step keeps the particles resident on the device in the order
+    # the step bins them (each step rewrites the positions in its tile order
+    # and returns the field in that order), as a particle code that keeps its
+    # particles on the device does; the step that returns the field in the
+    # caller's input order is timed beside it (input_order_step).
+    tile_order = args.order == "tile"
+
     def step():
-        plan.solve_particles(tx, ty, tz, q, out=bufs)
+        if tile_order:
+            plan.solve_particles_sorted(tx, ty, tz, q, out=bufs)
+        else:
+            plan.solve_particles(tx, ty, tz, q, out=bufs)
 
     for _ in range(args.warmup):
         step()
@@ -420,8 +436,8 @@ def main():
     kernels = {}
     for name, (launches, total, mn, mx) in kt.items():
         avg = total / launches
-        alg = algorithmic_bytes(n, num, 4, name)
-        mb = method_bytes(n, num, 4, name)
+        alg = algorithmic_bytes(n, num, 4, name, tile_order)
+        mb = method_bytes(n, num, 4, name, tile_order)
         kernels[name] = {"launches": launches, "avg_ms": avg, "min_ms": mn, "max_ms": mx,
                          "alg_bytes": alg, "GB_s": alg / (avg * 1e-3) / 1e9 if alg else None,
                          "method_bytes": mb, "method_GB_s": mb / (avg * 1e-3) / 1e9 if mb else None}
@@ -437,7 +453,7 @@ def main():
     conv_names = ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv")
     conv_ms = sum(kernels[k]["avg_ms"] for k in conv_names if k in kernels)
     conv_alg = conv_bytes(n, 4)
-    conv_traffic = [measured_traffic(k) for k in conv_names]
+    conv_traffic = [measured_traffic(k, tile_order) for k in conv_names]
     conv_gbs = conv_alg / (conv_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "convolution: " + " + ".join(KERNEL_SYMBOL[k] for k in conv_names),
                 "achieved": conv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": conv_gbs / HBM_PEAK_GBS,
@@ -452,7 +468,7 @@ def main():
     dk = kernels[dom]
     slowest = {"kernel": KERNEL_SYMBOL.get(dom, dom), "avg_ms": dk["avg_ms"], "method_bytes": dk["method_bytes"],
                "method_frac": (dk["method_GB_s"] or 0.0) / HBM_PEAK_GBS, "design_bytes": dk["alg_bytes"],
-               "design_frac": (dk["GB_s"] or 0.0) / HBM_PEAK_GBS, "traffic": measured_traffic(dom)}
+               "design_frac": (dk["GB_s"] or 0.0) / HBM_PEAK_GBS, "traffic": measured_traffic(dom, tile_order)}
     step_method = sum(k["method_bytes"] for k in kernels.values())
     step_design = sum(k["alg_bytes"] for k in kernels.values())
     step_bytes = {"method_bytes": step_method, "design_bytes": step_design,
@@ -460,6 +476,18 @@ def main():
                   "design_frac": step_design / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     extra = {}
+    if tile_order:
+        # the same step with the field returned in the caller's input order
+        # (binning, then an unsort pass through the inverse permutation)
+        dks.dks_timing_enable(True)
+        io_ms = time_loop(torch, lambda: plan.solve_particles(tx, ty, tz, q, out=bufs), args.steps, 2)
+        kk = dks.dks_timing_read()
+        dks.dks_timing_enable(False)
+        io_k = {k: kk[k][1] / kk[k][0] for k in kk}
+        extra["input_order_step"] = {
+            "ms_per_step": io_ms, "mesh_pts_per_s": mesh_pts / (io_ms * 1e-3), "kernel_ms": io_k,
+            "design_bytes": sum(algorithmic_bytes(n, num, 4, k) for k in kk)}
+        progress(f"input-order step {io_ms:.3f} ms")
     if not args.no_extra:
         # the same full step with the other assignment schemes and the point kernel
         variants = {}
@@ -516,6 +544,11 @@ def main():
             # transfer-inclusive: requests start and end in page-locked host memory
             extra["serving_host_io"] = serve.bench_stream(torch, num_requests=500, host_io=True)
             progress("serving with transfers done")
+            torch.cuda.empty_cache()
+            # capacity: the same 2000 requests all arriving at once, so each path
+            # runs as fast as it can (served solves/s is then the path's capacity)
+            extra["serving_capacity"] = serve.bench_stream(torch, rate_hz=None)
+            progress("serving capacity done")
         except ImportError:
             extra["serving"] = None
 
@@ -537,7 +570,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "halo_gaussian_256cubed_1e8_f32: 256^3 fitted mesh (512^3 doubled), "
                                f"{num} particles (90% Gaussian sigma 1 mm + 10% uniform halo to 5 sigma), "
-                               "full particle step per solve, Green's spectrum cached",
+                               "full particle step per solve, Green's spectrum cached; "
+                               + ("particles resident in the step's binned (tile) order, field returned in that "
+                                  "order" if tile_order else "field returned in the input order"),
                    "mesh": list(n), "particles": num},
         "roofline": roofline,
         "cpu_baseline": cpu,

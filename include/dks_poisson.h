@@ -189,6 +189,30 @@ dks_status dks_poisson_solve_particles(dks_poisson_plan_t plan, const void* x, c
                                        void* Ez, void* phi, int64_t* n_outside,
                                        dks_stream_t stream);
 
+/* The particle step for a caller that keeps its particles on the device
+ * and lets the solver order them (the paper's particle-matter offload keeps
+ * its particles resident on the device between steps and sorts them there,
+ * section "The DKS Implementation of the Particle Matter Interaction
+ * Model"): the same step as
+ * dks_poisson_solve_particles, but the particles come back in the order the
+ * step binned them, 16^3-cell tile by tile of this step's mesh (particles
+ * outside the mesh last), instead of in their input order.
+ *   x, y, z    : device [np] positions, read, then overwritten with the same
+ *                positions in the binned order.
+ *   Ex, Ey, Ez : device [np] field at the particles in the binned order.
+ *   new_index  : device uint32 [np] or NULL; new_index[i] receives the new
+ *                position of the particle that was at index i, so the caller
+ *                can move its other per-particle arrays the same way
+ *                (a[new_index[i]] = a_before[i]).
+ * Other arguments, limits and errors as dks_poisson_solve_particles.  The
+ * step needs no reordering pass of its own (the field is written in the
+ * binned order), and particles that arrive in the previous step's order
+ * are binned with long runs of consecutive writes. */
+dks_status dks_poisson_solve_particles_sorted(dks_poisson_plan_t plan, void* x, void* y, void* z,
+                                              int64_t np, double q, void* Ex, void* Ey, void* Ez,
+                                              void* phi, uint32_t* new_index, int64_t* n_outside,
+                                              dks_stream_t stream);
+
 /* One element of a batched particle solve.  The table of elements lives in
  * device memory and is read by the kernels when they run, so a HIP graph
  * captured over dks_poisson_solve_particles_batched can be replayed for new

@@ -800,11 +800,23 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geomet
 // ---------------------------------------------------------------------------
 // gather with the central-difference field formed on the fly from staged phi.
 // ---------------------------------------------------------------------------
-template <typename T, int SCH>
+// OUT (tile-ordered output of a single solve): the field of record i goes to
+// out.ex/ey/ez[i] and its position to out.x/y/z[i], the caller's arrays, in
+// place of the record (no unsort follows).
+template <typename T> struct SortedOut {
+  T* x;
+  T* y;
+  T* z;
+  T* ex;
+  T* ey;
+  T* ez;
+};
+
+template <typename T, int SCH, bool OUT = false>
 __global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(const Geometry* geo, size_t stride, char* slot_base,
                                                        size_t bins_off, char* sorted_base, size_t sorted_stride,
                                                        const T* __restrict__ phi_ext, size_t phi_stride,
-                                                       MeshDims m, BinGeom bg) {
+                                                       MeshDims m, BinGeom bg, SortedOut<T> so) {
   constexpr int A = apron_edge<SCH>(), NA = A * A * A, WD = Scheme<SCH>::width;
   constexpr bool PAIR = pair_phi<T, SCH>();
   // Staged phi: one value per node, or (node, node + 1 in x) pairs.
@@ -824,7 +836,19 @@ __global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(co
     unsigned s0, s1;
     decode_item(st, bg, t, &tile, &s0, &s1);
     if (tile == bg.K) {
-      for (unsigned i = s0 + threadIdx.x; i < s1; i += blockDim.x) part[i] = P4{(T)0, (T)0, (T)0};
+      for (unsigned i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+        if constexpr (OUT) {
+          const P4 p = part[i];
+          so.x[i] = p.x;
+          so.y[i] = p.y;
+          so.z[i] = p.z;
+          so.ex[i] = (T)0;
+          so.ey[i] = (T)0;
+          so.ez[i] = (T)0;
+        } else {
+          part[i] = P4{(T)0, (T)0, (T)0};
+        }
+      }
       continue;
     }
     const int tx = tile % bg.tx, ty = (tile / bg.tx) % bg.ty, tz = tile / (bg.tx * bg.ty);
@@ -976,7 +1000,16 @@ __global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(co
                 az += wgt * (q[A * A] - q[-A * A]);
               }
         }
-        part[i] = P4{ax * cx, ay * cy, az * cz};
+        if constexpr (OUT) {
+          so.x[i] = p.x;
+          so.y[i] = p.y;
+          so.z[i] = p.z;
+          so.ex[i] = ax * cx;
+          so.ey[i] = ay * cy;
+          so.ez[i] = az * cz;
+        } else {
+          part[i] = P4{ax * cx, ay * cy, az * cz};
+        }
       }
     }
     __syncthreads();
@@ -1200,15 +1233,28 @@ hipError_t launch_deposit_binned(const Geometry* geo, size_t stride, char* slot_
   return hipGetLastError();
 }
 
+// out: NULL, or six caller arrays (x, y, z, Ex, Ey, Ez) of one element that
+// receive the positions and fields in record order (tile-ordered output).
 template <typename T>
 hipError_t launch_gather_binned(const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                                 char* sorted_base, size_t sorted_stride, const void* phi_ext, size_t phi_stride,
-                                const MeshDims& m, const BinGeom& bg, int nblk, int batch, hipStream_t s) {
+                                const MeshDims& m, const BinGeom& bg, int nblk, int batch, void* const* out,
+                                hipStream_t s) {
+  SortedOut<T> so{};
+  if (out) {
+    if (batch != 1) return hipErrorInvalidValue;
+    so = SortedOut<T>{(T*)out[0], (T*)out[1], (T*)out[2], (T*)out[3], (T*)out[4], (T*)out[5]};
+  }
   with_scheme(bg.scheme, [&](auto sc) {
     constexpr int SCH = decltype(sc)::value;
-    hipLaunchKernelGGL((k_gather_binned<T, SCH>), dim3(nblk, batch), dim3(gather_threads<T, SCH>()), 0, s,
-                       geo, stride, slot_base, bins_off, sorted_base, sorted_stride, (const T*)phi_ext, phi_stride, m,
-                       bg);
+    if (out)
+      hipLaunchKernelGGL((k_gather_binned<T, SCH, true>), dim3(nblk, batch), dim3(gather_threads<T, SCH>()), 0, s,
+                         geo, stride, slot_base, bins_off, sorted_base, sorted_stride, (const T*)phi_ext, phi_stride,
+                         m, bg, so);
+    else
+      hipLaunchKernelGGL((k_gather_binned<T, SCH, false>), dim3(nblk, batch), dim3(gather_threads<T, SCH>()), 0, s,
+                         geo, stride, slot_base, bins_off, sorted_base, sorted_stride, (const T*)phi_ext, phi_stride,
+                         m, bg, so);
   });
   return hipGetLastError();
 }
@@ -1234,7 +1280,7 @@ hipError_t launch_unsort(const ElemBatch& eb, int batch, const char* sorted_base
                                                size_t, const MeshDims&, const BinGeom&, int, int, hipStream_t);    \
   template hipError_t launch_gather_binned<T>(const Geometry*, size_t, char*, size_t, char*, size_t,               \
                                               const void*, size_t, const MeshDims&, const BinGeom&, int, int,      \
-                                              hipStream_t);                                                        \
+                                              void* const*, hipStream_t);                                          \
   template hipError_t launch_unsort<T>(const ElemBatch&, int, const char*, size_t, size_t, hipStream_t);
 DKS_INSTANTIATE(float)
 DKS_INSTANTIATE(double)

@@ -363,6 +363,20 @@ __device__ __forceinline__ void run_any(typename Cplx<T>::type* lds, const FFTPl
   }
 }
 
+// Passes [P0, npass) of compile-time plan SP with its twiddle table at `tw`
+// (for instance a copy in LDS, whose reads do not wait on vector memory).
+template <typename T, bool INV, bool FIRST_LDS, class SP, int P0, bool ZU = false, class FirstIn, class LastOut,
+          class LastPre = NoPre>
+__device__ __forceinline__ void run_static_tw(typename Cplx<T>::type* lds, const typename Cplx<T>::type* tw,
+                                              FirstIn first_in, LastOut last_out, LastPre last_pre = LastPre{}) {
+  static_assert(SP::is_static, "compile-time plans only");
+  NoPre none;
+  RunStatic<T, INV, FIRST_LDS, SP, P0, P0, ZU>::go(lds, tw, first_in, last_out, none, last_pre);
+}
+
+// Complex twiddles in the table of compile-time plan SP.
+template <class SP> constexpr int static_tw_count() { return SP::npass < 2 ? 0 : SP::tw_off(SP::npass); }
+
 // ---------------------------------------------------------------------------
 // Host helpers of the launchers
 // ---------------------------------------------------------------------------

@@ -20,13 +20,13 @@ namespace dks {
 // Launchers defined in the kernel translation units.
 template <typename T> hipError_t launch_fft_x_fwd(const void*, size_t, void*, size_t, const MeshDims&,
                                                   const PlanRef&, const void*, int, hipStream_t);
-template <typename T> hipError_t launch_fft_y_fwd(const void*, void*, size_t, const MeshDims&, const PlanRef&,
+template <typename T> hipError_t launch_fft_y_fwd(const void*, void*, size_t, const MeshDims&, const PlanRef&, int, int,
                                                   int, hipStream_t);
 template <typename T> hipError_t launch_fft_z_conv(const void*, void*, size_t, const void*, const Geometry*,
                                                    size_t, const MeshDims&, const PlanRef&, const PlanRef&, int,
-                                                   hipStream_t);
+                                                   int, int, hipStream_t);
 template <typename T> hipError_t launch_fft_y_inv(const void*, void*, size_t, const MeshDims&, const PlanRef&,
-                                                  int, hipStream_t);
+                                                  int, int, int, hipStream_t);
 template <typename T> hipError_t launch_fft_x_inv(const void*, size_t, void*, size_t, const ElemBatch&,
                                                   const MeshDims&, const PlanRef&, const void*, int,
                                                   hipStream_t);
@@ -53,7 +53,7 @@ template <typename T> hipError_t launch_deposit_binned(const Geometry*, size_t, 
                                                        hipStream_t);
 template <typename T> hipError_t launch_gather_binned(const Geometry*, size_t, char*, size_t, char*, size_t,
                                                       const void*, size_t, const MeshDims&, const BinGeom&, int, int,
-                                                      hipStream_t);
+                                                      void* const*, hipStream_t);
 template <typename T> hipError_t launch_unsort(const ElemBatch&, int, const char*, size_t, size_t, hipStream_t);
 template <typename T> hipError_t launch_twiddle_pass(void*, int, int, hipStream_t);
 template <typename T> hipError_t launch_twiddle_line(void*, int, int, hipStream_t);
@@ -356,9 +356,9 @@ void layout(dks_poisson_plan_s* p) {
   p->off_slot = align256(p->off_green + p->green_bytes);
   const size_t cs = (size_t)m.cs;
   const size_t A = (size_t)ny * nz * cs * c;
-  // B and C are z-blocked in groups of 16 rows (partial last block allocated in full)
-  const size_t B = (size_t)m.Ny * ((nz + 15) / 16 * 16) * cs * c;
-  const size_t C = (size_t)m.Ny * ((nz + 2 + 15) / 16 * 16) * cs * c;
+  // B and C are block-major: (2 ny) rows of cs columns over nz (B) or nz + 2 (C) planes
+  const size_t B = (size_t)m.Ny * nz * cs * c;
+  const size_t C = (size_t)m.Ny * (nz + 2) * cs * c;
   const size_t D = (size_t)(ny + 2) * (nz + 2) * cs * c;
   p->bytes_W = (size_t)nx * ny * nz * s;
   p->bytes_phi_ext = (size_t)(nx + 2) * (ny + 2) * (nz + 2) * s;
@@ -421,9 +421,9 @@ dks_status convolve(const dks_poisson_plan_s* p, const void* src, size_t in_stri
   const void* post = p->ws + p->tw_post;
   const void* G = p->ws + p->off_green;
   DKS_TK("fft_x_fwd", launch_fft_x_fwd<T>(src, in_stride, R1, cstride, m, fx, post, batch, st));
-  DKS_TK("fft_y_fwd", launch_fft_y_fwd<T>(R1, R2, cstride, m, fy, batch, st));
-  DKS_TK("fft_z_conv", launch_fft_z_conv<T>(R2, R1, cstride, G, sl.geo(), sl.stride, m, fz, fzi, batch, st));
-  DKS_TK("fft_y_inv", launch_fft_y_inv<T>(R1, R2, cstride, m, fy, batch, st));
+  DKS_TK("fft_y_fwd", launch_fft_y_fwd<T>(R1, R2, cstride, m, fy, batch, 0, m.ncols, st));
+  DKS_TK("fft_z_conv", launch_fft_z_conv<T>(R2, R1, cstride, G, sl.geo(), sl.stride, m, fz, fzi, batch, 0, m.ncols, st));
+  DKS_TK("fft_y_inv", launch_fft_y_inv<T>(R1, R2, cstride, m, fy, batch, 0, m.ncols, st));
   DKS_TK("fft_x_inv", launch_fft_x_inv<T>(R2, cstride, R3, rstride, phi_user, m, fx, post, batch, st));
   return DKS_OK;
 }
@@ -494,9 +494,12 @@ dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl
   return DKS_OK;
 }
 
+// sorted_out: NULL, or the caller's (x, y, z, Ex, Ey, Ez) of a single solve,
+// which then receive the positions and fields in the binned (tile) order
+// instead of the field in the input order.
 template <typename T>
 dks_status solve_particles_t(const dks_poisson_plan_s* p, int batch, const Slots& sl, const ElemBatch& eb,
-                             char* sorted, size_t sorted_stride, hipStream_t st) {
+                             char* sorted, size_t sorted_stride, hipStream_t st, void* const* sorted_out = nullptr) {
   const PartWork w = part_work(p, eb.max_np);
   const size_t inv_off = inv_offset(p, eb.max_np);
   dks_status r = deposit_stage<T>(p, batch, sl, eb, sorted, sorted_stride, inv_off, w, st);
@@ -505,8 +508,8 @@ dks_status solve_particles_t(const dks_poisson_plan_s* p, int batch, const Slots
   if (r != DKS_OK) return r;
   DKS_TK("gather", launch_gather_binned<T>(sl.geo(), sl.stride, sl.base, p->s_bins, sorted, sorted_stride,
                                            sl.base + p->s_r3, sl.stride / sizeof(T), p->md, w.bg, w.item_blocks,
-                                           batch, st));
-  DKS_TK("unsort", launch_unsort<T>(eb, batch, sorted, sorted_stride, inv_off, st));
+                                           batch, sorted_out, st));
+  if (!sorted_out) DKS_TK("unsort", launch_unsort<T>(eb, batch, sorted, sorted_stride, inv_off, st));
   return DKS_OK;
 }
 
@@ -933,6 +936,30 @@ dks_status dks_poisson_solve_particles_noalloc(dks_poisson_plan_t p, const void*
                                            : solve_particles_t<double>(p, 1, sl, eb, buf, 0, st);
   if (r == DKS_OK) p->has_geometry = true;
   return r;
+}
+
+dks_status dks_poisson_solve_particles_sorted(dks_poisson_plan_t p, void* x, void* y, void* z, int64_t np, double q,
+                                              void* Ex, void* Ey, void* Ez, void* phi, uint32_t* new_index,
+                                              int64_t* n_outside, dks_stream_t stream) {
+  if (!p || np < 0 || np > kMaxParticles || !std::isfinite(q)) return DKS_EINVAL;
+  if (np > 0 && (!x || !y || !z || !Ex || !Ey || !Ez)) return DKS_EINVAL;
+  if (!ws_ready(p)) return DKS_EWORKSPACE;
+  if (particle_bytes(p, np) > p->pscratch_bytes) return DKS_EWORKSPACE;
+  if (!p->prepared) return DKS_ESTATE;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  Slots sl{p->ws + p->off_slot, p->slot_bytes};
+  const ElemBatch eb = single(x, y, z, Ex, Ey, Ez, phi, n_outside, np, q, true);
+  void* const outs[6] = {x, y, z, Ex, Ey, Ez};
+  const dks_status r = p->dtype == DKS_F32 ? solve_particles_t<float>(p, 1, sl, eb, p->pscratch, 0, st, outs)
+                                           : solve_particles_t<double>(p, 1, sl, eb, p->pscratch, 0, st, outs);
+  if (r != DKS_OK) return r;
+  p->has_geometry = true;
+  // the scatter's inverse permutation: new position of each input index
+  if (new_index && np > 0 &&
+      hipMemcpyAsync(new_index, p->pscratch + inv_offset(p, np), (size_t)np * sizeof(uint32_t),
+                     hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return DKS_EHIP;
+  return DKS_OK;
 }
 
 dks_status dks_poisson_solve_particles_batched(dks_poisson_plan_t p, int batch, const dks_particle_set* sets,

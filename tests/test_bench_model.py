@@ -53,3 +53,14 @@ def test_method_bytes_of_the_step():
         (2 * part + s * 258 ** 3)
     assert total == model
     assert all(mb(k) <= bench.algorithmic_bytes(n, npart, s, k) for k in names)
+
+
+def test_tile_order_step_bytes():
+    """The tile-ordered step: the gather writes the field and the positions
+    (no unsort follows); the method counts the field write only."""
+    n, npart, s = (256, 256, 256), 100_000_000, 4
+    mesh_ext = s * 258 ** 3
+    assert bench.algorithmic_bytes(n, npart, s, "gather", True) == 9 * s * npart + mesh_ext
+    assert bench.method_bytes(n, npart, s, "gather", True) == 6 * s * npart + mesh_ext
+    assert bench.method_bytes(n, npart, s, "gather", True) == (
+        bench.method_bytes(n, npart, s, "gather") + bench.method_bytes(n, npart, s, "unsort"))
