@@ -33,8 +33,9 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, vendor figure
 def algorithmic_bytes(n, num_particles, s, kernel, tile_order=False):
     """Bytes a kernel must move per launch in this design (its compulsory
     traffic: every array it reads and writes, once).  tile_order: the step
-    that returns the particles in binned order (the gather writes the field
-    and the positions, and there is no unsort)."""
+    that returns the particles in binned order (the scatter writes the binned
+    positions into the caller's arrays and no inverse permutation, the gather
+    reads them back and writes the field, and there is no unsort)."""
     nx, ny, nz = n
     c = 2 * s
     mesh = nx * ny * nz
@@ -43,7 +44,7 @@ def algorithmic_bytes(n, num_particles, s, kernel, tile_order=False):
         "geometry": s * mesh,          # the fit and the zero fill of the deposit mesh
         "bin_count": 3 * s * num_particles,
         "bin_scan": 0,
-        "bin_scatter": 3 * s * num_particles + 3 * s * num_particles + 4 * num_particles,
+        "bin_scatter": 3 * s * num_particles + 3 * s * num_particles + (0 if tile_order else 4 * num_particles),
         "deposit": 3 * s * num_particles + s * mesh,
         "fft_x_fwd": s * mesh + c * (nx + 1) * ny * nz,
         "fft_y_fwd": c * (nx + 1) * ny * nz + c * (nx + 1) * 2 * ny * nz,
@@ -52,7 +53,7 @@ def algorithmic_bytes(n, num_particles, s, kernel, tile_order=False):
         "fft_y_inv": c * (nx + 1) * 2 * ny * (nz + 2) + c * (nx + 1) * (ny + 2) * (nz + 2),
         "fft_x_inv": c * (nx + 1) * (ny + 2) * (nz + 2) + s * (nx + 2) * (ny + 2) * (nz + 2),
         "gradient": s * (nx + 2) * (ny + 2) * (nz + 2) + 3 * s * mesh,
-        "gather": ((9 if tile_order else 6) * s * num_particles + s * (nx + 2) * (ny + 2) * (nz + 2)),
+        "gather": 6 * s * num_particles + s * (nx + 2) * (ny + 2) * (nz + 2),
         "unsort": 4 * num_particles + 3 * s * num_particles + 3 * s * num_particles,
     }
     return model[kernel]
@@ -104,8 +105,8 @@ def measured_traffic(kernel, tile_order=False):
         return None
     doc = json.load(open(TRAFFIC_FILE))
     sym = KERNEL_SYMBOL.get(kernel, "")
-    if kernel == "gather" and tile_order:
-        sym = "k_gather_binned_tile"
+    if kernel in ("bin_scatter", "deposit", "gather") and tile_order:
+        sym += "_tile"          # the kernels' instances that work on the caller's arrays
     src = ("fft_kernels.hip" if sym.startswith("k_fft") else
            "particle_kernels.hip" if sym in ("k_bbox", "k_geometry_zero", "k_gradient") else "bin_kernels.hip")
     deps = (src, "dks_internal.h") + (("fft_engine.h",) if src == "fft_kernels.hip" else ())
@@ -123,8 +124,9 @@ def measured_traffic(kernel, tile_order=False):
     total = k["fetch_bytes"] + k["write_bytes"]
     # the scatter's whole chunks go through the pipelined kernel, a partial
     # last chunk through the one-chunk kernel launched after it
-    if sym == "k_bin_scatter_pipe" and "k_bin_scatter" in doc["kernels"]:
-        t = doc["kernels"]["k_bin_scatter"]
+    part = sym.replace("k_bin_scatter_pipe", "k_bin_scatter")
+    if sym.startswith("k_bin_scatter_pipe") and part in doc["kernels"]:
+        t = doc["kernels"][part]
         total += t["fetch_bytes"] + t["write_bytes"]
     return total
 
@@ -372,9 +374,14 @@ def main():
     # caller's input order is timed beside it (input_order_step).
     tile_order = args.order == "tile"
 
+    pos = [(tx, ty, tz), tuple(torch.empty_like(t) for t in (tx, ty, tz)) if tile_order else None]
+
     def step():
         if tile_order:
-            plan.solve_particles_sorted(tx, ty, tz, q, out=bufs)
+            # positions alternate between two sets of arrays, as a caller
+            # keeping its particles resident does
+            plan.solve_particles_sorted(*pos[0], q, pos_out=pos[1], out=bufs)
+            pos.reverse()
         else:
             plan.solve_particles(tx, ty, tz, q, out=bufs)
 
@@ -480,7 +487,7 @@ def main():
         # the same step with the field returned in the caller's input order
         # (binning, then an unsort pass through the inverse permutation)
         dks.dks_timing_enable(True)
-        io_ms = time_loop(torch, lambda: plan.solve_particles(tx, ty, tz, q, out=bufs), args.steps, 2)
+        io_ms = time_loop(torch, lambda: plan.solve_particles(*pos[0], q, out=bufs), args.steps, 2)
         kk = dks.dks_timing_read()
         dks.dks_timing_enable(False)
         io_k = {k: kk[k][1] / kk[k][0] for k in kk}
@@ -505,7 +512,7 @@ def main():
         dks.dks_poisson_set_scheme(plan.handle, dks.DKS_GREEN_INTEGRATED, dks.DKS_ASSIGN_CIC)
         extra["variants"] = variants
         progress("scheme variants done")
-        del tx, ty, tz, out, bufs, plan
+        del tx, ty, tz, out, bufs, plan, pos
         torch.cuda.empty_cache()
         # mesh-only solves (rho -> phi and E) at 256^3 in FP32 and FP64
         for dt_name, tdt in (("f32", torch.float32), ("f64", torch.float64)):

@@ -193,23 +193,32 @@ dks_status dks_poisson_solve_particles(dks_poisson_plan_t plan, const void* x, c
  * and lets the solver order them (the paper's particle-matter offload keeps
  * its particles resident on the device between steps and sorts them there,
  * section "The DKS Implementation of the Particle Matter Interaction
- * Model"): the same step as
- * dks_poisson_solve_particles, but the particles come back in the order the
- * step binned them, 16^3-cell tile by tile of this step's mesh (particles
- * outside the mesh last), instead of in their input order.
- *   x, y, z    : device [np] positions, read, then overwritten with the same
- *                positions in the binned order.
- *   Ex, Ey, Ez : device [np] field at the particles in the binned order.
- *   new_index  : device uint32 [np] or NULL; new_index[i] receives the new
- *                position of the particle that was at index i, so the caller
- *                can move its other per-particle arrays the same way
- *                (a[new_index[i]] = a_before[i]).
+ * Model"): the same step as dks_poisson_solve_particles, but the particles
+ * come back in the order the step binned them, 16^3-cell tile by tile of
+ * this step's mesh (particles outside the mesh last), instead of in their
+ * input order.
+ *   x, y, z             : device [np] positions, read only.
+ *   x_out, y_out, z_out : device [np], written with the same positions in
+ *                         the binned order (they hold the binned particles
+ *                         during the step); must not overlap x, y, z, the
+ *                         field outputs or each other (DKS_EINVAL).  A
+ *                         caller keeping its particles resident alternates
+ *                         between two sets of position arrays.
+ *   Ex, Ey, Ez          : device [np] field at the particles in the binned
+ *                         order.
+ *   new_index           : device uint32 [np] or NULL (then the step writes
+ *                         no permutation); new_index[i] receives the new
+ *                         position of the particle that was at index i, so
+ *                         the caller can move its other per-particle arrays
+ *                         the same way (a[new_index[i]] = a_before[i]).  It
+ *                         must not overlap the other arrays (DKS_EINVAL).
  * Other arguments, limits and errors as dks_poisson_solve_particles.  The
  * step needs no reordering pass of its own (the field is written in the
  * binned order), and particles that arrive in the previous step's order
  * are binned with long runs of consecutive writes. */
-dks_status dks_poisson_solve_particles_sorted(dks_poisson_plan_t plan, void* x, void* y, void* z,
-                                              int64_t np, double q, void* Ex, void* Ey, void* Ez,
+dks_status dks_poisson_solve_particles_sorted(dks_poisson_plan_t plan, const void* x, const void* y,
+                                              const void* z, int64_t np, double q, void* x_out,
+                                              void* y_out, void* z_out, void* Ex, void* Ey, void* Ez,
                                               void* phi, uint32_t* new_index, int64_t* n_outside,
                                               dks_stream_t stream);
 

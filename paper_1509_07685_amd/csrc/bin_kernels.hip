@@ -78,6 +78,49 @@ template <typename T> struct Rec {
   T x, y, z;
 };
 
+// Caller arrays of the tile-ordered step (one element): x, y, z receive the
+// positions in binned order and serve as the binned records themselves;
+// ex, ey, ez receive the field in that order; inv (or NULL: not written)
+// receives the new position of each input index.
+template <typename T> struct SortedOut {
+  T* x;
+  T* y;
+  T* z;
+  T* ex;
+  T* ey;
+  T* ez;
+  unsigned* inv;
+};
+
+// The binned records of one element: (x, y, z) records in the particle
+// scratch, or (SOA) the three position arrays of a SortedOut.
+template <typename T, bool SOA> struct Recs;
+template <typename T> struct Recs<T, false> {
+  Rec<T>* p;
+  __device__ __forceinline__ Rec<T> ld(size_t i) const { return p[i]; }
+  __device__ __forceinline__ void st(size_t i, Rec<T> r) const { p[i] = r; }
+};
+template <typename T> struct Recs<T, true> {
+  T* x;
+  T* y;
+  T* z;
+  __device__ __forceinline__ Rec<T> ld(size_t i) const { return Rec<T>{x[i], y[i], z[i]}; }
+  __device__ __forceinline__ void st(size_t i, Rec<T> r) const {
+    x[i] = r.x;
+    y[i] = r.y;
+    z[i] = r.z;
+  }
+};
+template <typename T, bool SOA>
+__device__ __forceinline__ Recs<T, SOA> recs_of(char* sorted_base, size_t sorted_stride, int b,
+                                                const SortedOut<T>& so) {
+  if constexpr (SOA) {
+    return Recs<T, true>{so.x, so.y, so.z};
+  } else {
+    return Recs<T, false>{reinterpret_cast<Rec<T>*>(sorted_base + (size_t)b * sorted_stride)};
+  }
+}
+
 // Fixed-point scale of the deposit accumulators: a weight is at most 1 and a
 // work item holds at most 2^16 (FP32) or 2^14 (FP64) particles, so a node sum
 // stays below 2^47 resp. 2^63 in 64 bits; the scale keeps 2^-31 resp. 2^-49
@@ -166,6 +209,36 @@ constexpr int kScatterThreads = 1024;
 constexpr int kUnsortThreads = 256;
 template <typename T, int THREADS> constexpr int chunk_per() { return (int)(scatter_chunk<T>() / THREADS); }
 
+// Counter increments of one particle per lane, with the lanes of a wavefront
+// that share one key served by a single atomic: in tile-ordered input most
+// wavefronts hold particles of one tile, and 64 atomics on one LDS address
+// serialise (the count pass took 338 us instead of 185 us on such input).
+// rank_add returns the counter's old value plus the lane's place among the
+// active lanes (lane order), or its own atomic's old value when the keys
+// differ; the order of equal keys is arbitrary either way.
+__device__ __forceinline__ unsigned rank_add(unsigned* ctr, int key) {
+  const int k0 = __builtin_amdgcn_readfirstlane(key);
+  if (__all(key == k0)) {
+    const unsigned long long act = __ballot(1);
+    const int leader = __ffsll((long long)act) - 1;
+    const int lane = (int)__lane_id();
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(&ctr[k0], (unsigned)__popcll(act));
+    base = __shfl(base, leader);
+    return base + (unsigned)__popcll(act & ((1ull << lane) - 1ull));
+  }
+  return atomicAdd(&ctr[key], 1u);
+}
+__device__ __forceinline__ void count_add(unsigned* ctr, int key) {
+  const int k0 = __builtin_amdgcn_readfirstlane(key);
+  if (__all(key == k0)) {
+    const unsigned long long act = __ballot(1);
+    if ((int)__lane_id() == __ffsll((long long)act) - 1) atomicAdd(&ctr[k0], (unsigned)__popcll(act));
+  } else {
+    atomicAdd(&ctr[key], 1u);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // count: per XCD group and tile.  Workgroup w walks the scatter chunks
 // c = w, w + G, ... (G = gridDim.x, a multiple of kXcd), which all fall in
@@ -192,8 +265,8 @@ __global__ __launch_bounds__(256) void k_bin_count(ElemBatch eb, const Geometry*
   for (int64_t c = blockIdx.x; c * CH < n; c += gridDim.x) {
     for_each_particle<T>(px, py, pz, c * CH, min(c * CH + CH, n), [&](T x, T y, T z, int64_t) {
       const int key = locate<T, SCH>(x, y, z, g, m, bg).key;
-      if (LDSHIST) atomicAdd(&hist[key], 1u);
-      else atomicAdd(&xc[key], 1u);
+      if constexpr (LDSHIST) count_add(hist, key);
+      else count_add(xc, key);
     });
   }
   if (LDSHIST) {
@@ -385,13 +458,13 @@ constexpr int kStageRun = 8;
 struct NoMid {
   __device__ void operator()() const {}
 };
-template <typename T, bool FULL, class Mid = NoMid, int PER = chunk_per<T, kScatterThreads>()>
+template <typename T, bool FULL, class RecOut, class Mid = NoMid, int PER = chunk_per<T, kScatterThreads>()>
 __device__ __forceinline__ void scatter_stage_chunk(unsigned* lcnt, unsigned* lbase, Rec<T>* srec,
                                                     unsigned short* skey, unsigned* wa, unsigned* wb,
                                                     unsigned* cursor, const BinGeom& bg, const int (&key)[PER],
                                                     const unsigned (&rank)[PER], const T (&xs)[PER],
                                                     const T (&ys)[PER], const T (&zs)[PER], int64_t c0, int64_t n,
-                                                    bool vec, Rec<T>* out, unsigned* inv, Mid mid = Mid{}) {
+                                                    bool vec, const RecOut& out, unsigned* inv, Mid mid = Mid{}) {
   using P4 = Rec<T>;
   constexpr int NV = Vec16<T>::n;
   constexpr int64_t CH = scatter_chunk<T>();
@@ -434,7 +507,9 @@ __device__ __forceinline__ void scatter_stage_chunk(unsigned* lcnt, unsigned* lb
       dv[j] = lp + lbase[key[j]];
     }
   }
-  if (FULL || vec) {
+  if (!inv) {
+    // no inverse permutation wanted
+  } else if (FULL || vec) {
     struct alignas(NV * sizeof(unsigned)) U { unsigned v[NV]; };
 #pragma unroll
     for (int q = 0; q < PER / NV; ++q) {
@@ -482,15 +557,15 @@ __device__ __forceinline__ void scatter_stage_chunk(unsigned* lcnt, unsigned* lb
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int j = 0; j < PER; ++j)
-    if (FULL || threadIdx.x + (unsigned)j * kScatterThreads < nv) out[dd[j]] = P4{rx[j], ry[j], rz[j]};
+    if (FULL || threadIdx.x + (unsigned)j * kScatterThreads < nv) out.st(dd[j], P4{rx[j], ry[j], rz[j]});
 }
 
-template <typename T, bool LDSHIST, bool STAGE, int SCH>
+template <typename T, bool LDSHIST, bool STAGE, int SCH, bool SOA>
 __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, const Geometry* geo, size_t stride,
                                                                  char* slot_base, size_t bins_off,
                                                                  char* sorted_base, size_t sorted_stride,
                                                                  size_t inv_off, MeshDims m, BinGeom bg,
-                                                                 int chunk0, int nchunk) {
+                                                                 int chunk0, int nchunk, SortedOut<T> so) {
   extern __shared__ unsigned lds[];
   __shared__ unsigned wa[16], wb[16];
   constexpr int PER = chunk_per<T, kScatterThreads>();
@@ -521,8 +596,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
   // the chunk's XCD group, as the count kernel assigned it
   unsigned* cursor = st.xcursor + (int)(((int64_t)b * nchunk + chunk) % kXcd) * (bg.K + 1);
-  P4* out = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
-  unsigned* inv = reinterpret_cast<unsigned*>(sorted_base + (size_t)b * sorted_stride + inv_off);
+  const Recs<T, SOA> out = recs_of<T, SOA>(sorted_base, sorted_stride, b, so);
+  unsigned* inv = SOA ? so.inv : reinterpret_cast<unsigned*>(sorted_base + (size_t)b * sorted_stride + inv_off);
   if (LDSHIST) {
     for (int k = threadIdx.x; k <= bg.K; k += kScatterThreads) lcnt[k] = 0;
   }
@@ -567,8 +642,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
   for (int j = 0; j < PER; ++j) {
     const int64_t i = chunk_index<T, kScatterThreads>(vec, c0, j);
     key[j] = i < n ? locate<T, SCH>(xs[j], ys[j], zs[j], g, m, bg).key : -1;
-    if (LDSHIST) rank[j] = key[j] >= 0 ? atomicAdd(&lcnt[key[j]], 1u) : 0u;
-    else rank[j] = key[j] >= 0 ? atomicAdd(&cursor[key[j]], 1u) : 0u;
+    if (LDSHIST) rank[j] = key[j] >= 0 ? rank_add(lcnt, key[j]) : 0u;
+    else rank[j] = key[j] >= 0 ? rank_add(cursor, key[j]) : 0u;
   }
   if constexpr (STAGE) {
     scatter_stage_chunk<T, false>(lcnt, lbase, srec, skey, wa, wb, cursor, bg, key, rank, xs, ys, zs, c0, n, vec, out,
@@ -601,7 +676,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
     // a whole chunk: no branches between the stores, so none waits for the last
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int j = 0; j < PER; ++j) out[dv[j]] = P4{xs[j], ys[j], zs[j]};
+    for (int j = 0; j < PER; ++j) out.st(dv[j], P4{xs[j], ys[j], zs[j]});
+    if (!inv) return;
     struct alignas(NV * sizeof(unsigned)) U { unsigned v[NV]; };
 #pragma unroll
     for (int q = 0; q < PER / NV; ++q) {
@@ -616,8 +692,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
   for (int j = 0; j < PER; ++j) {
     if (key[j] < 0) continue;
     const int64_t i = chunk_index<T, kScatterThreads>(vec, c0, j);
-    out[dv[j]] = P4{xs[j], ys[j], zs[j]};
-    inv[i] = dv[j];
+    out.st(dv[j], P4{xs[j], ys[j], zs[j]});
+    if (inv) inv[i] = dv[j];
   }
 }
 
@@ -626,12 +702,12 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter(ElemBatch eb, c
 // one workgroup per CU), and loads chunk c + G while chunk c is ranked,
 // staged and stored.  One element whose positions are 16-byte aligned; the
 // chunks are the first nfull (whole) ones.
-template <typename T, int SCH>
+template <typename T, int SCH, bool SOA>
 __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter_pipe(ElemBatch eb, const Geometry* geo, size_t stride,
                                                                       char* slot_base, size_t bins_off,
                                                                       char* sorted_base, size_t sorted_stride,
                                                                       size_t inv_off, MeshDims m, BinGeom bg,
-                                                                      int nchunk, int nfull) {
+                                                                      int nchunk, int nfull, SortedOut<T> so) {
   extern __shared__ unsigned lds[];
   __shared__ unsigned wa[16], wb[16];
   constexpr int PER = chunk_per<T, kScatterThreads>();
@@ -654,8 +730,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter_pipe(ElemBatch 
   const Geometry gcopy = *geo_of(geo, stride, b);
   const Geometry* g = &gcopy;
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
-  P4* out = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
-  unsigned* inv = reinterpret_cast<unsigned*>(sorted_base + (size_t)b * sorted_stride + inv_off);
+  const Recs<T, SOA> out = recs_of<T, SOA>(sorted_base, sorted_stride, b, so);
+  unsigned* inv = SOA ? so.inv : reinterpret_cast<unsigned*>(sorted_base + (size_t)b * sorted_stride + inv_off);
   auto load = [&](int ch, T (&x)[PER], T (&y)[PER], T (&z)[PER]) {
 #pragma unroll
     for (int q = 0; q < PER / NV; ++q) {
@@ -680,7 +756,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bin_scatter_pipe(ElemBatch 
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       key[j] = locate<T, SCH>(xs[j], ys[j], zs[j], g, m, bg).key;
-      rank[j] = atomicAdd(&lcnt[key[j]], 1u);
+      rank[j] = rank_add(lcnt, key[j]);
     }
     // the next chunk, loaded once the reservations are back (the last chunk
     // re-reads itself, so no load is conditional)
@@ -722,11 +798,11 @@ __device__ __forceinline__ void decode_item(const BinState& st, const BinGeom& b
 // ---------------------------------------------------------------------------
 // deposit: LDS-privatised accumulation per work item, then merge.
 // ---------------------------------------------------------------------------
-template <typename T, int SCH>
+template <typename T, int SCH, bool SOA>
 __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geometry* geo, size_t stride, char* slot_base,
                                                         size_t bins_off, const char* sorted_base,
                                                         size_t sorted_stride, T* W, size_t w_stride, MeshDims m,
-                                                        BinGeom bg) {
+                                                        BinGeom bg, SortedOut<T> so) {
   constexpr int A = acc_edge<SCH>(), NN = A * A * A, WD = Scheme<SCH>::width;
   __shared__ unsigned long long acc[NN];
   using P4 = Rec<T>;
@@ -734,7 +810,7 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geomet
   const Geometry gcopy = *geo_of(geo, stride, b);   // private copy: not reloaded after each store
   const Geometry* g = &gcopy;
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
-  const P4* part = reinterpret_cast<const P4*>(sorted_base + (size_t)b * sorted_stride);
+  const Recs<T, SOA> part = recs_of<T, SOA>(const_cast<char*>(sorted_base), sorted_stride, b, so);
   T* w = W + (size_t)b * w_stride;
   const unsigned nitems = min(st.misc[0], bg.max_items);
   for (unsigned t = blockIdx.x; t < nitems; t += gridDim.x) {
@@ -756,11 +832,11 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geomet
     P4 pr[kUnrollDeposit], nx[kUnrollDeposit];
     if (s1 > s0) {
 #pragma unroll
-      for (int u = 0; u < kUnrollDeposit; ++u) pr[u] = part[min(s0 + threadIdx.x + u * blockDim.x, s1 - 1)];
+      for (int u = 0; u < kUnrollDeposit; ++u) pr[u] = part.ld(min(s0 + threadIdx.x + u * blockDim.x, s1 - 1));
     }
     for (unsigned i0 = s0 + threadIdx.x; i0 < s1; i0 += kUnrollDeposit * blockDim.x) {
 #pragma unroll
-      for (int u = 0; u < kUnrollDeposit; ++u) nx[u] = part[min(i0 + (kUnrollDeposit + u) * blockDim.x, s1 - 1)];
+      for (int u = 0; u < kUnrollDeposit; ++u) nx[u] = part.ld(min(i0 + (kUnrollDeposit + u) * blockDim.x, s1 - 1));
 #pragma unroll
       for (int u = 0; u < kUnrollDeposit; ++u) {
         if (i0 + u * blockDim.x >= s1) break;
@@ -800,19 +876,11 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geomet
 // ---------------------------------------------------------------------------
 // gather with the central-difference field formed on the fly from staged phi.
 // ---------------------------------------------------------------------------
-// OUT (tile-ordered output of a single solve): the field of record i goes to
-// out.ex/ey/ez[i] and its position to out.x/y/z[i], the caller's arrays, in
-// place of the record (no unsort follows).
-template <typename T> struct SortedOut {
-  T* x;
-  T* y;
-  T* z;
-  T* ex;
-  T* ey;
-  T* ez;
-};
-
-template <typename T, int SCH, bool OUT = false>
+// SOA (tile-ordered step of a single solve): the records are the caller's
+// position arrays so.x/y/z, and the field of record i goes to
+// so.ex/ey/ez[i] (no unsort follows); otherwise the field overwrites the
+// record in the particle scratch.
+template <typename T, int SCH, bool SOA>
 __global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(const Geometry* geo, size_t stride, char* slot_base,
                                                        size_t bins_off, char* sorted_base, size_t sorted_stride,
                                                        const T* __restrict__ phi_ext, size_t phi_stride,
@@ -826,7 +894,7 @@ __global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(co
   const Geometry gcopy = *geo_of(geo, stride, b);   // private copy: not reloaded after each store
   const Geometry* g = &gcopy;
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
-  P4* part = reinterpret_cast<P4*>(sorted_base + (size_t)b * sorted_stride);
+  const Recs<T, SOA> part = recs_of<T, SOA>(sorted_base, sorted_stride, b, so);
   const T* phi = phi_ext + (size_t)b * phi_stride;
   const T cx = Geo<T>::grad(g, 0), cy = Geo<T>::grad(g, 1), cz = Geo<T>::grad(g, 2);
   const int nx2 = m.nx + 2, ny2 = m.ny + 2, nz2 = m.nz + 2;
@@ -837,16 +905,12 @@ __global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(co
     decode_item(st, bg, t, &tile, &s0, &s1);
     if (tile == bg.K) {
       for (unsigned i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-        if constexpr (OUT) {
-          const P4 p = part[i];
-          so.x[i] = p.x;
-          so.y[i] = p.y;
-          so.z[i] = p.z;
+        if constexpr (SOA) {
           so.ex[i] = (T)0;
           so.ey[i] = (T)0;
           so.ez[i] = (T)0;
         } else {
-          part[i] = P4{(T)0, (T)0, (T)0};
+          part.st(i, P4{(T)0, (T)0, (T)0});
         }
       }
       continue;
@@ -876,7 +940,7 @@ __global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(co
     for (unsigned i0 = s0 + threadIdx.x; i0 < s1; i0 += kUnrollGather * blockDim.x) {
       P4 pr[kUnrollGather];
 #pragma unroll
-      for (int u = 0; u < kUnrollGather; ++u) pr[u] = part[min(i0 + u * blockDim.x, s1 - 1)];
+      for (int u = 0; u < kUnrollGather; ++u) pr[u] = part.ld(min(i0 + u * blockDim.x, s1 - 1));
 #pragma unroll
       for (int u = 0; u < kUnrollGather; ++u) {
         const unsigned i = i0 + u * blockDim.x;
@@ -1000,15 +1064,12 @@ __global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(co
                 az += wgt * (q[A * A] - q[-A * A]);
               }
         }
-        if constexpr (OUT) {
-          so.x[i] = p.x;
-          so.y[i] = p.y;
-          so.z[i] = p.z;
+        if constexpr (SOA) {
           so.ex[i] = ax * cx;
           so.ey[i] = ay * cy;
           so.ez[i] = az * cz;
         } else {
-          part[i] = P4{ax * cx, ay * cy, az * cz};
+          part.st(i, P4{ax * cx, ay * cy, az * cz});
         }
       }
     }
@@ -1127,6 +1188,19 @@ __global__ __launch_bounds__(kUnsortThreads) void k_unsort(ElemBatch eb, const c
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
+template <typename T> static SortedOut<T> sorted_out(void* const* soa) {
+  if (!soa) return SortedOut<T>{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  return SortedOut<T>{(T*)soa[0], (T*)soa[1], (T*)soa[2], (T*)soa[3], (T*)soa[4], (T*)soa[5], (unsigned*)soa[6]};
+}
+
+// f(scheme constant, SOA constant)
+template <class F> static void with_scheme_soa(int scheme, bool soa, F&& f) {
+  with_scheme(scheme, [&](auto sc) {
+    if (soa) f(sc, std::true_type{});
+    else f(sc, std::false_type{});
+  });
+}
+
 template <typename T>
 hipError_t launch_bin_count(const ElemBatch& eb, int batch, const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                             const MeshDims& m, const BinGeom& bg, int nblk, hipStream_t s) {
@@ -1171,9 +1245,11 @@ static int compute_units() {
 template <typename T>
 hipError_t launch_bin_scatter(const ElemBatch& eb, int batch, const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                               char* sorted_base, size_t sorted_stride, size_t inv_off, const MeshDims& m,
-                              const BinGeom& bg, int nblk, hipStream_t s) {
+                              const BinGeom& bg, int nblk, void* const* soa, hipStream_t s) {
   (void)nblk;
   if (eb.max_np == 0) return hipSuccess;
+  if (soa && batch != 1) return hipErrorInvalidValue;
+  const SortedOut<T> so = sorted_out<T>(soa);
   const int64_t ch = scatter_chunk<T>();
   const unsigned nchunk = (unsigned)((eb.max_np + ch - 1) / ch);
   const bool lh = bg.lds_hist != 0;
@@ -1197,26 +1273,28 @@ hipError_t launch_bin_scatter(const ElemBatch& eb, int batch, const Geometry* ge
       G = std::max(kXcd, cus / kXcd * kXcd);
     }
   }
-  with_scheme(bg.scheme, [&](auto sc) {
+  with_scheme_soa(bg.scheme, soa != nullptr, [&](auto sc, auto sa) {
     constexpr int SCH = decltype(sc)::value;
+    constexpr bool SOA = decltype(sa)::value;
     if (nfull > 0) {
-      hipLaunchKernelGGL((k_bin_scatter_pipe<T, SCH>), dim3(G, 1), dim3(kScatterThreads), lds, s, eb, geo, stride,
-                         slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg, (int)nchunk, nfull);
+      hipLaunchKernelGGL((k_bin_scatter_pipe<T, SCH, SOA>), dim3(G, 1), dim3(kScatterThreads), lds, s, eb, geo, stride,
+                         slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg, (int)nchunk, nfull, so);
       if ((unsigned)nfull < nchunk)
-        hipLaunchKernelGGL((k_bin_scatter<T, true, true, SCH>), dim3(nchunk - nfull, 1), dim3(kScatterThreads), lds,
+        hipLaunchKernelGGL((k_bin_scatter<T, true, true, SCH, SOA>), dim3(nchunk - nfull, 1), dim3(kScatterThreads), lds,
                            s, eb, geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg,
-                           nfull, (int)nchunk);
+                           nfull, (int)nchunk, so);
     } else if (stage) {
-      hipLaunchKernelGGL((k_bin_scatter<T, true, true, SCH>), dim3(nchunk, batch), dim3(kScatterThreads), lds, s, eb,
-                         geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg, 0, (int)nchunk);
+      hipLaunchKernelGGL((k_bin_scatter<T, true, true, SCH, SOA>), dim3(nchunk, batch), dim3(kScatterThreads), lds, s, eb,
+                         geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg, 0, (int)nchunk,
+                         so);
     } else if (lh) {
-      hipLaunchKernelGGL((k_bin_scatter<T, true, false, SCH>), dim3(nchunk, batch), dim3(kScatterThreads), lds, s,
+      hipLaunchKernelGGL((k_bin_scatter<T, true, false, SCH, SOA>), dim3(nchunk, batch), dim3(kScatterThreads), lds, s,
                          eb, geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg, 0,
-                         (int)nchunk);
+                         (int)nchunk, so);
     } else {
-      hipLaunchKernelGGL((k_bin_scatter<T, false, false, SCH>), dim3(nchunk, batch), dim3(kScatterThreads), 0, s,
+      hipLaunchKernelGGL((k_bin_scatter<T, false, false, SCH, SOA>), dim3(nchunk, batch), dim3(kScatterThreads), 0, s,
                          eb, geo, stride, slot_base, bins_off, sorted_base, sorted_stride, inv_off, m, bg, 0,
-                         (int)nchunk);
+                         (int)nchunk, so);
     }
   });
   return hipGetLastError();
@@ -1225,36 +1303,32 @@ hipError_t launch_bin_scatter(const ElemBatch& eb, int batch, const Geometry* ge
 template <typename T>
 hipError_t launch_deposit_binned(const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                                  const char* sorted_base, size_t sorted_stride, void* W, size_t w_stride,
-                                 const MeshDims& m, const BinGeom& bg, int nblk, int batch, hipStream_t s) {
-  with_scheme(bg.scheme, [&](auto sc) {
-    hipLaunchKernelGGL((k_deposit_binned<T, decltype(sc)::value>), dim3(nblk, batch), dim3(kDepositThreads), 0, s,
-                       geo, stride, slot_base, bins_off, sorted_base, sorted_stride, (T*)W, w_stride, m, bg);
+                                 const MeshDims& m, const BinGeom& bg, int nblk, int batch, void* const* soa,
+                                 hipStream_t s) {
+  if (soa && batch != 1) return hipErrorInvalidValue;
+  const SortedOut<T> so = sorted_out<T>(soa);
+  with_scheme_soa(bg.scheme, soa != nullptr, [&](auto sc, auto sa) {
+    hipLaunchKernelGGL((k_deposit_binned<T, decltype(sc)::value, decltype(sa)::value>), dim3(nblk, batch),
+                       dim3(kDepositThreads), 0, s, geo, stride, slot_base, bins_off, sorted_base, sorted_stride,
+                       (T*)W, w_stride, m, bg, so);
   });
   return hipGetLastError();
 }
 
-// out: NULL, or six caller arrays (x, y, z, Ex, Ey, Ez) of one element that
-// receive the positions and fields in record order (tile-ordered output).
+// soa: NULL, or the caller arrays (x, y, z, Ex, Ey, Ez) of the tile-ordered
+// step of one element: the records are x, y, z and the field goes to Ex, Ey, Ez.
 template <typename T>
 hipError_t launch_gather_binned(const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                                 char* sorted_base, size_t sorted_stride, const void* phi_ext, size_t phi_stride,
-                                const MeshDims& m, const BinGeom& bg, int nblk, int batch, void* const* out,
+                                const MeshDims& m, const BinGeom& bg, int nblk, int batch, void* const* soa,
                                 hipStream_t s) {
-  SortedOut<T> so{};
-  if (out) {
-    if (batch != 1) return hipErrorInvalidValue;
-    so = SortedOut<T>{(T*)out[0], (T*)out[1], (T*)out[2], (T*)out[3], (T*)out[4], (T*)out[5]};
-  }
-  with_scheme(bg.scheme, [&](auto sc) {
+  if (soa && batch != 1) return hipErrorInvalidValue;
+  const SortedOut<T> so = sorted_out<T>(soa);
+  with_scheme_soa(bg.scheme, soa != nullptr, [&](auto sc, auto sa) {
     constexpr int SCH = decltype(sc)::value;
-    if (out)
-      hipLaunchKernelGGL((k_gather_binned<T, SCH, true>), dim3(nblk, batch), dim3(gather_threads<T, SCH>()), 0, s,
-                         geo, stride, slot_base, bins_off, sorted_base, sorted_stride, (const T*)phi_ext, phi_stride,
-                         m, bg, so);
-    else
-      hipLaunchKernelGGL((k_gather_binned<T, SCH, false>), dim3(nblk, batch), dim3(gather_threads<T, SCH>()), 0, s,
-                         geo, stride, slot_base, bins_off, sorted_base, sorted_stride, (const T*)phi_ext, phi_stride,
-                         m, bg, so);
+    hipLaunchKernelGGL((k_gather_binned<T, SCH, decltype(sa)::value>), dim3(nblk, batch),
+                       dim3(gather_threads<T, SCH>()), 0, s, geo, stride, slot_base, bins_off, sorted_base,
+                       sorted_stride, (const T*)phi_ext, phi_stride, m, bg, so);
   });
   return hipGetLastError();
 }
@@ -1275,9 +1349,10 @@ hipError_t launch_unsort(const ElemBatch& eb, int batch, const char* sorted_base
                                           const BinGeom&, int, hipStream_t);                                       \
   template hipError_t launch_bin_scatter<T>(const ElemBatch&, int, const Geometry*, size_t, char*, size_t,      \
                                             char*, size_t, size_t, const MeshDims&, const BinGeom&, int,           \
-                                            hipStream_t);                                                          \
+                                            void* const*, hipStream_t);                                            \
   template hipError_t launch_deposit_binned<T>(const Geometry*, size_t, char*, size_t, const char*, size_t, void*, \
-                                               size_t, const MeshDims&, const BinGeom&, int, int, hipStream_t);    \
+                                               size_t, const MeshDims&, const BinGeom&, int, int, void* const*,    \
+                                               hipStream_t);                                                       \
   template hipError_t launch_gather_binned<T>(const Geometry*, size_t, char*, size_t, char*, size_t,               \
                                               const void*, size_t, const MeshDims&, const BinGeom&, int, int,      \
                                               void* const*, hipStream_t);                                          \

@@ -47,9 +47,9 @@ hipError_t launch_bin_scan(const Geometry*, size_t, char*, size_t, const BinGeom
                            hipStream_t);
 template <typename T> hipError_t launch_bin_scatter(const ElemBatch&, int, const Geometry*, size_t, char*,
                                                     size_t, char*, size_t, size_t, const MeshDims&, const BinGeom&,
-                                                    int, hipStream_t);
+                                                    int, void* const*, hipStream_t);
 template <typename T> hipError_t launch_deposit_binned(const Geometry*, size_t, char*, size_t, const char*, size_t,
-                                                       void*, size_t, const MeshDims&, const BinGeom&, int, int,
+                                                       void*, size_t, const MeshDims&, const BinGeom&, int, int, void* const*,
                                                        hipStream_t);
 template <typename T> hipError_t launch_gather_binned(const Geometry*, size_t, char*, size_t, char*, size_t,
                                                       const void*, size_t, const MeshDims&, const BinGeom&, int, int,
@@ -470,11 +470,12 @@ PartWork part_work(const dks_poisson_plan_s* p, int64_t maxn) {
 }
 
 // Mesh fit (fitted plans), geometry, particle binning and the binned deposit:
-// leaves the weights W in R3 and the binned particles in `sorted`.
+// leaves the weights W in R3 and the binned particles in `sorted` (or, soa,
+// in the caller's output position arrays soa[0..2]).
 template <typename T>
 dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl, const ElemBatch& eb,
                          char* sorted, size_t sorted_stride, size_t inv_off, const PartWork& w,
-                         hipStream_t st) {
+                         hipStream_t st, void* const* soa = nullptr) {
   int nb = 0;
   double* bbox = reinterpret_cast<double*>(sl.base + p->s_bbox);
   if (p->fitted) DKS_TK("bbox", launch_bbox<T>(eb, batch, bbox, sl.stride / sizeof(double), &nb, st));
@@ -487,22 +488,24 @@ dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl
                                           w.count_blocks, st));
   DKS_TK("bin_scan", launch_bin_scan(sl.geo(), sl.stride, sl.base, p->s_bins, w.bg, eb, batch, st));
   DKS_TK("bin_scatter", launch_bin_scatter<T>(eb, batch, sl.geo(), sl.stride, sl.base, p->s_bins, sorted,
-                                              sorted_stride, inv_off, p->md, w.bg, w.count_blocks, st));
+                                              sorted_stride, inv_off, p->md, w.bg, w.count_blocks, soa, st));
   DKS_TK("deposit", launch_deposit_binned<T>(sl.geo(), sl.stride, sl.base, p->s_bins, sorted, sorted_stride,
                                              sl.base + p->s_r3, sl.stride / sizeof(T), p->md, w.bg, w.item_blocks,
-                                             batch, st));
+                                             batch, soa, st));
   return DKS_OK;
 }
 
-// sorted_out: NULL, or the caller's (x, y, z, Ex, Ey, Ez) of a single solve,
-// which then receive the positions and fields in the binned (tile) order
-// instead of the field in the input order.
+// sorted_out: NULL, or the caller's output arrays (x, y, z, Ex, Ey, Ez,
+// new_index or NULL) of a single solve, which then receive the positions
+// (written by the scatter, and read back as the binned records) and the
+// field in the binned (tile) order instead of the field in the input order,
+// and the scatter's inverse permutation.
 template <typename T>
 dks_status solve_particles_t(const dks_poisson_plan_s* p, int batch, const Slots& sl, const ElemBatch& eb,
                              char* sorted, size_t sorted_stride, hipStream_t st, void* const* sorted_out = nullptr) {
   const PartWork w = part_work(p, eb.max_np);
   const size_t inv_off = inv_offset(p, eb.max_np);
-  dks_status r = deposit_stage<T>(p, batch, sl, eb, sorted, sorted_stride, inv_off, w, st);
+  dks_status r = deposit_stage<T>(p, batch, sl, eb, sorted, sorted_stride, inv_off, w, st, sorted_out);
   if (r != DKS_OK) return r;
   r = convolve<T>(p, sl.base + p->s_r3, sl.stride / sizeof(T), batch, sl, eb, st);
   if (r != DKS_OK) return r;
@@ -938,27 +941,37 @@ dks_status dks_poisson_solve_particles_noalloc(dks_poisson_plan_t p, const void*
   return r;
 }
 
-dks_status dks_poisson_solve_particles_sorted(dks_poisson_plan_t p, void* x, void* y, void* z, int64_t np, double q,
-                                              void* Ex, void* Ey, void* Ez, void* phi, uint32_t* new_index,
+dks_status dks_poisson_solve_particles_sorted(dks_poisson_plan_t p, const void* x, const void* y, const void* z,
+                                              int64_t np, double q, void* x_out, void* y_out, void* z_out, void* Ex,
+                                              void* Ey, void* Ez, void* phi, uint32_t* new_index,
                                               int64_t* n_outside, dks_stream_t stream) {
   if (!p || np < 0 || np > kMaxParticles || !std::isfinite(q)) return DKS_EINVAL;
-  if (np > 0 && (!x || !y || !z || !Ex || !Ey || !Ez)) return DKS_EINVAL;
+  if (np > 0 && (!x || !y || !z || !x_out || !y_out || !z_out || !Ex || !Ey || !Ez)) return DKS_EINVAL;
+  if (np > 0) {
+    // the outputs are written while the inputs are still being read, and
+    // the position outputs are read back as the binned records
+    const void* arr[10] = {new_index, x_out, y_out, z_out, Ex, Ey, Ez, x, y, z};
+    auto bytes = [&](int i) { return (size_t)np * (i == 0 ? sizeof(uint32_t) : (size_t)p->rsize); };
+    for (int i = new_index ? 0 : 1; i < 7; ++i)
+      for (int j = i + 1; j < 10; ++j) {
+        const char* a = static_cast<const char*>(arr[i]);
+        const char* b = static_cast<const char*>(arr[j]);
+        if (a < b + bytes(j) && b < a + bytes(i)) return DKS_EINVAL;
+      }
+  }
   if (!ws_ready(p)) return DKS_EWORKSPACE;
   if (particle_bytes(p, np) > p->pscratch_bytes) return DKS_EWORKSPACE;
   if (!p->prepared) return DKS_ESTATE;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   Slots sl{p->ws + p->off_slot, p->slot_bytes};
   const ElemBatch eb = single(x, y, z, Ex, Ey, Ez, phi, n_outside, np, q, true);
-  void* const outs[6] = {x, y, z, Ex, Ey, Ez};
+  // the scatter writes the new position of each input index straight into
+  // new_index (and no inverse permutation at all when it is NULL)
+  void* const outs[7] = {x_out, y_out, z_out, Ex, Ey, Ez, new_index};
   const dks_status r = p->dtype == DKS_F32 ? solve_particles_t<float>(p, 1, sl, eb, p->pscratch, 0, st, outs)
                                            : solve_particles_t<double>(p, 1, sl, eb, p->pscratch, 0, st, outs);
   if (r != DKS_OK) return r;
   p->has_geometry = true;
-  // the scatter's inverse permutation: new position of each input index
-  if (new_index && np > 0 &&
-      hipMemcpyAsync(new_index, p->pscratch + inv_offset(p, np), (size_t)np * sizeof(uint32_t),
-                     hipMemcpyDeviceToDevice, st) != hipSuccess)
-    return DKS_EHIP;
   return DKS_OK;
 }
 

@@ -86,7 +86,7 @@ _SIGS = {
     "dks_poisson_solve_particles_batched": (_i, [_PLAN, _i, _vp, _i64, _vp, _sz, _vp]),
     "dks_poisson_solve_particles_noalloc": (_i, [_PLAN, _vp, _vp, _vp, _i64, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
     "dks_poisson_solve_particles_sorted": (_i, [_PLAN, _vp, _vp, _vp, _i64, _d, _vp, _vp, _vp, _vp, _vp, _vp,
-                                                _vp]),
+                                                _vp, _vp, _vp, _vp]),
     "dks_poisson_deposit": (_i, [_PLAN, _vp, _vp, _vp, _i64, _d, _vp, _vp, _vp]),
     "dks_poisson_gather": (_i, [_PLAN, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp]),
     "dks_poisson_geometry": (_i, [_PLAN, _vp, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
@@ -294,9 +294,11 @@ def dks_poisson_solve_particles_noalloc(plan, x, y, z, np_, q, Ex, Ey, Ez, phi, 
 NOALLOC_SCRATCH_BYTES = 64 << 20     # DKS_NOALLOC_SCRATCH_BYTES
 
 
-def dks_poisson_solve_particles_sorted(plan, x, y, z, np_, q, Ex, Ey, Ez, phi, new_index, n_outside, stream):
-    _check(_lib.dks_poisson_solve_particles_sorted(plan, x, y, z, np_, q, Ex, Ey, Ez, phi, new_index, n_outside,
-                                                   stream), "dks_poisson_solve_particles_sorted")
+def dks_poisson_solve_particles_sorted(plan, x, y, z, np_, q, x_out, y_out, z_out, Ex, Ey, Ez, phi, new_index,
+                                       n_outside, stream):
+    _check(_lib.dks_poisson_solve_particles_sorted(plan, x, y, z, np_, q, x_out, y_out, z_out, Ex, Ey, Ez, phi,
+                                                   new_index, n_outside, stream),
+           "dks_poisson_solve_particles_sorted")
 
 
 class dks_particle_set(ctypes.Structure):
@@ -505,15 +507,20 @@ class PoissonPlan:
                                     _ptr(Ey), _ptr(Ez), _ptr(phi), _ptr(cnt), _stream_handle(stream))
         return (Ex, Ey, Ez), phi, cnt
 
-    def solve_particles_sorted(self, x, y, z, q, want_phi=False, want_index=False, out=None, stream=None):
-        """The step with particles returned in binned order: x, y, z are
-        rewritten in place in that order and the field comes back in it;
-        with want_index, also each input index's new position (int32)."""
+    def solve_particles_sorted(self, x, y, z, q, want_phi=False, want_index=False, pos_out=None, out=None,
+                               stream=None):
+        """The step with particles returned in binned order: the positions in
+        that order go to pos_out (three new arrays unless given; they must
+        not overlap the inputs) and the field comes back in it; with
+        want_index, also each input index's new position (int32).
+        Returns ((x, y, z) in binned order, (Ex, Ey, Ez), phi, count, index)."""
         torch = _torch()
         npart = x.numel()
         self.reserve_particles(npart)
         for name, t in (("x", x), ("y", y), ("z", z)):
             self._check_tensor(t, (npart,), name)
+        if pos_out is None:
+            pos_out = tuple(torch.empty(npart, dtype=self.dtype, device=x.device) for _ in range(3))
         if out is None:
             Ex, Ey, Ez = (torch.empty(npart, dtype=self.dtype, device=x.device) for _ in range(3))
             cnt = torch.zeros(1, dtype=torch.int64, device=x.device)
@@ -521,10 +528,11 @@ class PoissonPlan:
             Ex, Ey, Ez, cnt = out
         phi = torch.empty(self.mesh_shape(), dtype=self.dtype, device=x.device) if want_phi else None
         idx = torch.empty(npart, dtype=torch.int32, device=x.device) if want_index else None
-        dks_poisson_solve_particles_sorted(self.handle, _ptr(x), _ptr(y), _ptr(z), npart, float(q), _ptr(Ex),
-                                           _ptr(Ey), _ptr(Ez), _ptr(phi), _ptr(idx), _ptr(cnt),
-                                           _stream_handle(stream))
-        return (Ex, Ey, Ez), phi, cnt, idx
+        xo, yo, zo = pos_out
+        dks_poisson_solve_particles_sorted(self.handle, _ptr(x), _ptr(y), _ptr(z), npart, float(q), _ptr(xo),
+                                           _ptr(yo), _ptr(zo), _ptr(Ex), _ptr(Ey), _ptr(Ez), _ptr(phi), _ptr(idx),
+                                           _ptr(cnt), _stream_handle(stream))
+        return (xo, yo, zo), (Ex, Ey, Ez), phi, cnt, idx
 
     def deposit(self, x, y, z, q, stream=None):
         torch = _torch()

@@ -56,11 +56,14 @@ def test_method_bytes_of_the_step():
 
 
 def test_tile_order_step_bytes():
-    """The tile-ordered step: the gather writes the field and the positions
-    (no unsort follows); the method counts the field write only."""
+    """The tile-ordered step: the scatter writes the binned positions into the
+    caller's arrays and no permutation, the gather reads them and writes the
+    field (no unsort follows)."""
     n, npart, s = (256, 256, 256), 100_000_000, 4
     mesh_ext = s * 258 ** 3
-    assert bench.algorithmic_bytes(n, npart, s, "gather", True) == 9 * s * npart + mesh_ext
+    assert bench.algorithmic_bytes(n, npart, s, "bin_scatter", True) == 6 * s * npart
+    assert bench.algorithmic_bytes(n, npart, s, "bin_scatter") == 6 * s * npart + 4 * npart
+    assert bench.algorithmic_bytes(n, npart, s, "gather", True) == 6 * s * npart + mesh_ext
     assert bench.method_bytes(n, npart, s, "gather", True) == 6 * s * npart + mesh_ext
     assert bench.method_bytes(n, npart, s, "gather", True) == (
         bench.method_bytes(n, npart, s, "gather") + bench.method_bytes(n, npart, s, "unsort"))

@@ -1,5 +1,6 @@
 """The particle step with tile-ordered output (dks_poisson_solve_particles_sorted)
-through the C ABI: the positions come back as a permutation of the input,
+through the C ABI: the positions come back (in separate output arrays) as a
+permutation of the input,
 tile by tile of the step's mesh (particles outside the mesh last), the field
 comes back in that order and equals the oracle's field of each particle, and
 new_index maps every input index to its new place.  Tolerances: relative L2
@@ -53,14 +54,17 @@ def test_sorted_step_matches_oracle_and_orders_by_tile(dt, mesh):
     x, y, z = wl.halo_gaussian(num, 1e-3, 0.1, 5e-3, 120, NP_DT[dt])
     q = wl.TOTAL_CHARGE / num
     plan = dks().PoissonPlan(n, h, dt)
-    tx, ty, tz = (torch.from_numpy(a.copy()).cuda() for a in (x, y, z))
-    (Ex, Ey, Ez), phi, cnt, idx = plan.solve_particles_sorted(tx, ty, tz, q, want_phi=True, want_index=True)
+    gx, gy, gz = (torch.from_numpy(a.copy()).cuda() for a in (x, y, z))
+    (tx, ty, tz), (Ex, Ey, Ez), phi, cnt, idx = plan.solve_particles_sorted(gx, gy, gz, q, want_phi=True,
+                                                                           want_index=True)
     ni = host(idx).astype(np.int64)
-    # new_index is a permutation, and the positions moved with it exactly
+    # new_index is a permutation, the positions moved with it exactly, and the
+    # input arrays are untouched
     assert np.array_equal(np.sort(ni), np.arange(num))
-    for before, after in ((x, tx), (y, ty), (z, tz)):
+    for before, after, inp in ((x, tx, gx), (y, ty, gy), (z, tz, gz)):
         a = host(after)
         assert np.array_equal(a[ni], before)
+        assert np.array_equal(host(inp), before)
     ref = orc.solve_particles(x, y, z, q, n, h, dtype=NP_DT[dt])
     E = np.stack([host(t)[ni] for t in (Ex, Ey, Ez)])
     assert int(host(cnt)[0]) == ref["n_outside"]
@@ -90,14 +94,17 @@ def test_sorted_steps_in_a_row_and_the_regular_step_agree():
     gx, gy, gz = (torch.from_numpy(a).cuda() for a in (x, y, z))
     (Rx, Ry, Rz), _, _ = plan.solve_particles(gx, gy, gz, q)
     regular = np.stack([host(t) for t in (Rx, Ry, Rz)])
-    tx, ty, tz = gx.clone(), gy.clone(), gz.clone()
+    cur = (gx.clone(), gy.clone(), gz.clone())
+    other = tuple(torch.empty_like(t) for t in cur)
     where = np.arange(num)                 # current position of each original particle
     for step in range(3):
-        (Ex, Ey, Ez), _, _, idx = plan.solve_particles_sorted(tx, ty, tz, q, want_index=True)
+        # two sets of position arrays used in turn, as a resident caller would
+        pos, (Ex, Ey, Ez), _, _, idx = plan.solve_particles_sorted(*cur, q, want_index=True, pos_out=other)
+        cur, other = pos, cur
         where = host(idx).astype(np.int64)[where]
         E = np.stack([host(t)[where] for t in (Ex, Ey, Ez)])
         assert rel_l2(E, regular) <= 1e-6, step
-        assert np.array_equal(host(tx)[where], x)
+        assert np.array_equal(host(cur[0])[where], x)
 
 
 def test_sorted_step_full_size_against_the_regular_step():
@@ -111,8 +118,7 @@ def test_sorted_step_full_size_against_the_regular_step():
     plan = dks().PoissonPlan(cfg.n, None, "f32")
     gx, gy, gz = (torch.from_numpy(a).cuda() for a in (x, y, z))
     (Rx, Ry, Rz), _, rc = plan.solve_particles(gx, gy, gz, q)
-    tx, ty, tz = gx.clone(), gy.clone(), gz.clone()
-    (Ex, Ey, Ez), _, sc, idx = plan.solve_particles_sorted(tx, ty, tz, q, want_index=True)
+    (tx, ty, tz), (Ex, Ey, Ez), _, sc, idx = plan.solve_particles_sorted(gx, gy, gz, q, want_index=True)
     torch.cuda.synchronize()
     assert int(rc.item()) == int(sc.item()) == 0
     ni = idx.long()
@@ -128,3 +134,37 @@ def test_sorted_step_full_size_against_the_regular_step():
     # both runs merge work items into the mesh with float atomics, in orders
     # that differ between runs: equal to FP32 rounding, held to the FP32 bar
     assert (num / den) ** 0.5 <= TOL["f32"]
+
+
+def test_sorted_step_refuses_overlapping_outputs():
+    d = dks()
+    plan = d.PoissonPlan((16, 16, 16), None, "f32")
+    x = torch.zeros(1000, dtype=torch.float32, device="cuda")
+    e = [torch.zeros(1000, dtype=torch.float32, device="cuda") for _ in range(5)]
+    plan.reserve_particles(1000)
+    st = d._lib.dks_poisson_solve_particles_sorted(plan.handle, d._ptr(x), d._ptr(e[0]), d._ptr(e[1]), 1000, 1e-15,
+                                                   d._ptr(x), d._ptr(e[2]), d._ptr(e[3]), d._ptr(e[4]),
+                                                   d._ptr(e[4]), d._ptr(e[4]), None, None, None, None)
+    assert st == d.DKS_EINVAL
+
+
+def test_sorted_step_refuses_outputs_that_overlap_each_other():
+    d = dks()
+    plan = d.PoissonPlan((16, 16, 16), None, "f32")
+    a = [torch.zeros(1000, dtype=torch.float32, device="cuda") for _ in range(8)]
+    plan.reserve_particles(1000)
+    p = [d._ptr(t) for t in a]
+    st = d._lib.dks_poisson_solve_particles_sorted(plan.handle, p[0], p[1], p[2], 1000, 1e-15, p[3], p[4], p[5],
+                                                   p[6], p[7], p[5], None, None, None, None)
+    assert st == d.DKS_EINVAL
+
+
+def test_sorted_step_refuses_index_that_overlaps_the_field():
+    d = dks()
+    plan = d.PoissonPlan((16, 16, 16), None, "f32")
+    a = [torch.zeros(1000, dtype=torch.float32, device="cuda") for _ in range(9)]
+    plan.reserve_particles(1000)
+    p = [d._ptr(t) for t in a]
+    st = d._lib.dks_poisson_solve_particles_sorted(plan.handle, p[0], p[1], p[2], 1000, 1e-15, p[3], p[4], p[5],
+                                                   p[6], p[7], p[8], None, p[8], None, None)
+    assert st == d.DKS_EINVAL
