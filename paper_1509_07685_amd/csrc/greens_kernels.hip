@@ -126,60 +126,102 @@ __global__ void k_cos_matrix(double* M, int n) {
 }
 
 // out(r, k) = sum_a M[k][a] in(r, a) along one axis of an [n2+1][n1+1][n0+1]
-// FP64 array.  Row r = (rh, rl) with rl < Llo addresses rh * Shi + rl * Slo;
-// the contracted index steps by Sa.  64 x 64 output tile per block, 4 x 4
-// per thread, 16-deep chunks of the contraction staged in LDS.
+// FP64 array: a dense (rows x L) by (L x L) product on the FP64 matrix cores.
+// Row r = (rh, rl) with rl < Llo addresses rh * Shi + rl * Slo; the
+// contracted index steps by Sa.  A workgroup of four wavefronts computes a
+// 64 x 64 output tile, each wavefront a 32 x 32 quarter as 2 x 2 tiles of
+// v_mfma_f64_16x16x4 (lane l holds A(l % 16, l / 16) and B(l / 16, l % 16)
+// of the 16 x 4 and 4 x 16 operands, and D(4 e + l / 16, l % 16) in element
+// e of the 16 x 16 result).  16-deep chunks of the contraction are staged in
+// LDS, zero-filled past L.  Workgroup b runs on XCD b % 8 (round-robin
+// dispatch); the k tiles of one row tile are consecutive on the same XCD, so
+// its input rows come from that XCD's L2 after the first.
+typedef double dks_dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kXcdGroups = 8;
+
+template <bool AFAST>
 __global__ __launch_bounds__(256) void k_apply_axis(const double* __restrict__ in, double* __restrict__ out,
                                                     const double* __restrict__ M, int L, long long nrows,
-                                                    int Llo, long long Shi, long long Slo, long long Sa) {
+                                                    int Llo, long long Shi, long long Slo, long long Sa, int nrb,
+                                                    int nkb) {
   __shared__ double sIn[16][64 + 1];
   __shared__ double sM[16][64 + 1];
+  const int b = blockIdx.x;
+  const int seq = b / kXcdGroups;
+  const int rb = (seq / nkb) * kXcdGroups + b % kXcdGroups, kb = seq % nkb;
+  if (rb >= nrb) return;
   const int tid = threadIdx.x;
-  const long long r0 = (long long)blockIdx.x * 64;
-  const int k0 = blockIdx.y * 64;
-  const int tr = tid >> 4, tk = tid & 15;
-  double acc[4][4] = {};
-  for (int a0 = 0; a0 < L; a0 += 16) {
-    for (int e = tid; e < 64 * 16; e += 256) {
-      const int rr = e & 63, aa = e >> 6;
-      const long long r = r0 + rr;
-      const int a = a0 + aa;
-      double v = 0.0;
-      if (r < nrows && a < L) {
-        const long long rh = r / Llo, rl = r - rh * Llo;
-        v = in[rh * Shi + rl * Slo + a * Sa];
-      }
-      sIn[aa][rr] = v;
-      const int kk = e & 63;
-      const int k = k0 + kk;
-      sM[aa][kk] = (k < L && a < L) ? M[(long long)k * L + a] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int aa = 0; aa < 16; ++aa) {
-      double vi[4], vm[4];
+  const long long r0 = (long long)rb * 64;
+  const int k0 = kb * 64;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wk = (wave & 1) * 32;
+  const int fi = lane & 15, fk = lane >> 4;
+  // Staging map, fixed per thread: AFAST (contracted index contiguous in
+  // memory) takes 16 consecutive a of four rows, otherwise 64 consecutive
+  // rows of four a; the matrix always 16 consecutive a of four k.
+  const int sa = AFAST ? (tid & 15) : (tid >> 6);
+  const int sr = AFAST ? (tid >> 4) : (tid & 63);
+  long long base[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) vi[i] = sIn[aa][tr * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) vm[j] = sM[aa][tk * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += vi[i] * vm[j];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const long long r = r0 + tr * 4 + i;
-    if (r >= nrows) continue;
+  for (int q = 0; q < 4; ++q) {
+    const long long r = r0 + (AFAST ? sr + 16 * q : sr);
     const long long rh = r / Llo, rl = r - rh * Llo;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = k0 + tk * 4 + j;
-      if (k < L) out[rh * Shi + rl * Slo + (long long)k * Sa] = acc[i][j];
-    }
+    base[q] = r < nrows ? rh * Shi + rl * Slo : -1;
   }
+  const int ma = tid & 15, mk = tid >> 4;
+  dks_dbl4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dks_dbl4{0.0, 0.0, 0.0, 0.0};
+  // chunk a0's operands are loaded into registers while chunk a0 - 16 is
+  // multiplied
+  double vIn[4], vM[4];
+  auto load = [&](int a0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int a = a0 + (AFAST ? sa : sa + 4 * q);
+      vIn[q] = (base[q] >= 0 && a < L) ? in[base[q] + a * Sa] : 0.0;
+      const int k = k0 + mk + 16 * q, am = a0 + ma;
+      vM[q] = (k < L && am < L) ? M[(long long)k * L + am] : 0.0;
+    }
+  };
+  load(0);
+  for (int a0 = 0; a0 < L; a0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sIn[AFAST ? sa : sa + 4 * q][AFAST ? sr + 16 * q : sr] = vIn[q];
+      sM[ma][mk + 16 * q] = vM[q];
+    }
+    __syncthreads();
+    if (a0 + 16 < L) load(a0 + 16);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      double af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) af[i] = sIn[kk + fk][wr + 16 * i + fi];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = sM[kk + fk][wk + 16 * j + fi];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const long long r = r0 + wr + 16 * i + 4 * e + fk;
+      if (r >= nrows) continue;
+      const long long rh = r / Llo, rl = r - rh * Llo;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int k = k0 + wk + 16 * j + fi;
+        if (k < L) out[rh * Shi + rl * Slo + (long long)k * Sa] = acc[i][j][e];
+      }
+    }
 }
 
 // Ghat (dtype) in the layout the z pass reads, times 1 / (Nx Ny Nz) formed
@@ -244,8 +286,15 @@ hipError_t launch_apply_axis(const double* in, double* out, const double* M, con
   } else {                  // rows (b, a)
     L = (int)L2; nrows = L0 * L1; Llo = (int)L0; Shi = L0; Slo = 1; Sa = L0 * L1;
   }
-  dim3 grid((unsigned)((nrows + 63) / 64), (unsigned)((L + 63) / 64));
-  hipLaunchKernelGGL(k_apply_axis, grid, dim3(256), 0, s, in, out, M, L, nrows, Llo, Shi, Slo, Sa);
+  const int nrb = (int)((nrows + 63) / 64), nkb = (L + 63) / 64;
+  const long long blocks = (long long)(nrb + kXcdGroups - 1) / kXcdGroups * kXcdGroups * nkb;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (Sa == 1)
+    hipLaunchKernelGGL(k_apply_axis<true>, dim3((unsigned)blocks), dim3(256), 0, s, in, out, M, L, nrows, Llo, Shi,
+                       Slo, Sa, nrb, nkb);
+  else
+    hipLaunchKernelGGL(k_apply_axis<false>, dim3((unsigned)blocks), dim3(256), 0, s, in, out, M, L, nrows, Llo, Shi,
+                       Slo, Sa, nrb, nkb);
   return hipGetLastError();
 }
 
