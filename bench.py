@@ -495,6 +495,17 @@ def main():
             "ms_per_step": io_ms, "mesh_pts_per_s": mesh_pts / (io_ms * 1e-3), "kernel_ms": io_k,
             "design_bytes": sum(algorithmic_bytes(n, num, 4, k) for k in kk)}
         progress(f"input-order step {io_ms:.3f} ms")
+    # the same step with the order-independent deposit (integer node totals)
+    plan.set_deterministic(True)
+    dks.dks_timing_enable(True)
+    det_ms = time_loop(torch, step, args.steps, 2)
+    kk = dks.dks_timing_read()
+    dks.dks_timing_enable(False)
+    plan.set_deterministic(False)
+    extra["deterministic_step"] = {
+        "ms_per_step": det_ms, "mesh_pts_per_s": mesh_pts / (det_ms * 1e-3),
+        "kernel_ms": {k: kk[k][1] / kk[k][0] for k in ("geometry", "deposit", "fixed_to_weights") if k in kk}}
+    progress(f"order-independent deposit step {det_ms:.3f} ms")
     if not args.no_extra:
         # the same full step with the other assignment schemes and the point kernel
         variants = {}

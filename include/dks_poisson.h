@@ -114,6 +114,20 @@ dks_status dks_poisson_set_origin(dks_poisson_plan_t plan, double x0, double y0,
  * again.  DKS_EINVAL for an unknown value. */
 dks_status dks_poisson_set_scheme(dks_poisson_plan_t plan, dks_green green, dks_assign assign);
 
+/* Order-independent deposit (default off): on = 1 makes the charge
+ * assignment (the deposit, in the paper's OPAL structure "NGP, CIC, TSI",
+ * section "The DKS Implementation of the Poisson Solver") independent of the
+ * order of the particles and of the scheduling of the work, so that a solve
+ * repeated on the same particles, in any order, gives bitwise the same phi
+ * and, particle for particle, the same field.  Each work item's fixed-point
+ * sum is added to an exact integer total per mesh node (64 bits in FP32,
+ * 128 in FP64) kept in the plan's workspace, and the weights are formed from
+ * the totals once; the default adds the items' sums in floating point, whose
+ * rounding depends on the order.  Costs one more pass over the mesh.
+ * Host-only; takes effect from the next solve.  DKS_EINVAL for on other than
+ * 0 or 1. */
+dks_status dks_poisson_set_deterministic(dks_poisson_plan_t plan, int on);
+
 /* Bytes of device workspace the plan needs: its resident state (Green's
  * spectrum octant, twiddle tables, geometry block) plus the scratch of one
  * solve.  The caller allocates it (section "DKS": memory management is left

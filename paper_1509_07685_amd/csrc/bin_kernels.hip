@@ -801,11 +801,28 @@ __device__ __forceinline__ void decode_item(const BinState& st, const BinGeom& b
 // ---------------------------------------------------------------------------
 // deposit: LDS-privatised accumulation per work item, then merge.
 // ---------------------------------------------------------------------------
+// iacc (the order-independent deposit): instead of adding each work item's
+// sum to W in floating point, add the fixed-point sum itself to a per-node
+// integer total (FP32: one 64-bit word, which holds 2^32 particles' weights;
+// FP64: two words, low and high, with the carry out of the low one), so that
+// the totals, and W formed from them afterwards, do not depend on the order
+// of the additions.
+template <typename T>
+__device__ __forceinline__ void add_fixed_total(unsigned long long* node, unsigned long long fv) {
+  if constexpr (sizeof(T) == 4) {
+    atomicAdd(node, fv);
+  } else {
+    const unsigned long long old = atomicAdd(node, fv);
+    if (old + fv < old) atomicAdd(node + 1, 1ull);
+  }
+}
+
 template <typename T, int SCH, bool SOA>
 __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geometry* geo, size_t stride, char* slot_base,
                                                         size_t bins_off, const char* sorted_base,
                                                         size_t sorted_stride, T* W, size_t w_stride, MeshDims m,
-                                                        BinGeom bg, SortedOut<T> so) {
+                                                        BinGeom bg, SortedOut<T> so,
+                                                        unsigned long long* iacc, size_t ia_stride) {
   constexpr int A = acc_edge<SCH>(), NN = A * A * A, WD = Scheme<SCH>::width;
   __shared__ unsigned long long acc[NN];
   using P4 = Rec<T>;
@@ -815,6 +832,7 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geomet
   BinState st = bin_state(slot_base, stride, bins_off, b, bg.K);
   const Recs<T, SOA> part = recs_of<T, SOA>(const_cast<char*>(sorted_base), sorted_stride, b, so);
   T* w = W + (size_t)b * w_stride;
+  unsigned long long* ia = iacc ? iacc + (size_t)b * ia_stride : nullptr;
   const unsigned nitems = min(st.misc[0], bg.max_items);
   for (unsigned t = blockIdx.x; t < nitems; t += gridDim.x) {
     int tile;
@@ -865,14 +883,35 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit_binned(const Geomet
     for (int e = threadIdx.x; e < NN; e += blockDim.x) {
       const unsigned long long fv = acc[e];
       if (fv != 0ull) {
-        const T v = Fixed<T>::from(fv);
         const int ex = e % A, ey = (e / A) % A, ez = e / (A * A);
         const int x = bx + ex, y = by + ey, z = bz + ez;
-        if (x >= 0 && y >= 0 && z >= 0 && x < m.nx && y < m.ny && z < m.nz)
-          unsafeAtomicAdd(&w[((size_t)z * m.ny + y) * m.nx + x], v);
+        if (x >= 0 && y >= 0 && z >= 0 && x < m.nx && y < m.ny && z < m.nz) {
+          const size_t node = ((size_t)z * m.ny + y) * m.nx + x;
+          if (ia) add_fixed_total<T>(ia + node * (sizeof(T) == 4 ? 1 : 2), fv);
+          else unsafeAtomicAdd(&w[node], Fixed<T>::from(fv));
+        }
       }
     }
     __syncthreads();
+  }
+}
+
+// The order-independent deposit's totals -> W: one conversion of each exact
+// integer total (FP64: high word times 2^64 plus the low word, in units of
+// the fixed-point scale).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fixed_to_weights(const unsigned long long* __restrict__ iacc,
+                                                          size_t ia_stride, T* __restrict__ W, size_t w_stride,
+                                                          size_t nmesh) {
+  const unsigned long long* ia = iacc + (size_t)blockIdx.y * ia_stride;
+  T* w = W + (size_t)blockIdx.y * w_stride;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nmesh; i += (size_t)gridDim.x * blockDim.x) {
+    if constexpr (sizeof(T) == 4) {
+      w[i] = Fixed<T>::from(ia[i]);
+    } else {
+      const unsigned long long lo = ia[2 * i], hi = ia[2 * i + 1];
+      w[i] = (double)hi * 32768.0 + Fixed<T>::from(lo);     // 2^64 * 2^-49 = 2^15
+    }
   }
 }
 
@@ -1404,14 +1443,24 @@ template <typename T>
 hipError_t launch_deposit_binned(const Geometry* geo, size_t stride, char* slot_base, size_t bins_off,
                                  const char* sorted_base, size_t sorted_stride, void* W, size_t w_stride,
                                  const MeshDims& m, const BinGeom& bg, int nblk, int batch, void* const* soa,
-                                 hipStream_t s) {
+                                 void* iacc, size_t ia_stride, hipStream_t s) {
   if (soa && batch != 1) return hipErrorInvalidValue;
   const SortedOut<T> so = sorted_out<T>(soa);
   with_scheme_soa(bg.scheme, soa != nullptr, [&](auto sc, auto sa) {
     hipLaunchKernelGGL((k_deposit_binned<T, decltype(sc)::value, decltype(sa)::value>), dim3(nblk, batch),
                        dim3(kDepositThreads), 0, s, geo, stride, slot_base, bins_off, sorted_base, sorted_stride,
-                       (T*)W, w_stride, m, bg, so);
+                       (T*)W, w_stride, m, bg, so, (unsigned long long*)iacc, ia_stride);
   });
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fixed_to_weights(const void* iacc, size_t ia_stride, void* W, size_t w_stride, size_t nmesh,
+                                   int batch, hipStream_t s) {
+  if (nmesh == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>((nmesh + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_fixed_to_weights<T>, dim3(blocks, batch), dim3(256), 0, s,
+                     (const unsigned long long*)iacc, ia_stride, (T*)W, w_stride, nmesh);
   return hipGetLastError();
 }
 
@@ -1465,7 +1514,8 @@ hipError_t launch_unsort(const ElemBatch& eb, int batch, const char* sorted_base
                                             void* const*, hipStream_t);                                            \
   template hipError_t launch_deposit_binned<T>(const Geometry*, size_t, char*, size_t, const char*, size_t, void*, \
                                                size_t, const MeshDims&, const BinGeom&, int, int, void* const*,    \
-                                               hipStream_t);                                                       \
+                                               void*, size_t, hipStream_t);                                        \
+  template hipError_t launch_fixed_to_weights<T>(const void*, size_t, void*, size_t, size_t, int, hipStream_t);   \
   template hipError_t launch_gather_binned<T>(const Geometry*, size_t, char*, size_t, char*, size_t,               \
                                               const void*, size_t, const MeshDims&, const BinGeom&, int, int,      \
                                               void* const*, hipStream_t);                                          \

@@ -50,7 +50,8 @@ template <typename T> hipError_t launch_bin_scatter(const ElemBatch&, int, const
                                                     int, void* const*, hipStream_t);
 template <typename T> hipError_t launch_deposit_binned(const Geometry*, size_t, char*, size_t, const char*, size_t,
                                                        void*, size_t, const MeshDims&, const BinGeom&, int, int, void* const*,
-                                                       hipStream_t);
+                                                       void*, size_t, hipStream_t);
+template <typename T> hipError_t launch_fixed_to_weights(const void*, size_t, void*, size_t, size_t, int, hipStream_t);
 template <typename T> hipError_t launch_gather_binned(const Geometry*, size_t, char*, size_t, char*, size_t,
                                                       const void*, size_t, const MeshDims&, const BinGeom&, int, int,
                                                       void* const*, hipStream_t);
@@ -208,6 +209,7 @@ struct dks_poisson_plan_s {
   size_t pscratch_bytes;
   bool prepared;
   bool has_geometry;
+  bool deterministic = false;   // order-independent deposit (integer node totals)
   HostPipe hp;         // host-resident solves
 };
 
@@ -366,7 +368,9 @@ void layout(dks_poisson_plan_s* p) {
   const size_t COS = ((size_t)(nx + 1) * (nx + 1) + (size_t)(ny + 1) * (ny + 1) + (size_t)(nz + 1) * (nz + 1)) *
                      sizeof(double);
   const size_t r1 = std::max({A, C, G64});
-  const size_t r2 = std::max({B, D, G64});
+  // R2 also holds the order-independent deposit's integer node totals (8 or
+  // 16 bytes per node; B alone always covers them)
+  const size_t r2 = std::max({B, D, G64, (size_t)nx * ny * nz * 2 * s});
   const size_t r3 = std::max({p->bytes_W, p->bytes_phi_ext, COS + 256});
   BinGeom& bg = p->bg;
   bg.tx = (nx + 15) / 16;        // 16 nodes per tile edge (CIC files by cell, NGP/TSC by node)
@@ -482,8 +486,14 @@ dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl
   GeoArgs ga = geo_args(p, 1, nb);
   ga.zero_off = p->s_bins;                  // the per-group tile counts
   ga.zero_len = kXcd * (p->bg.K + 1);
+  // The order-independent deposit sums into integer node totals in R2
+  // (free until the forward y pass) and forms W from them afterwards.
+  const size_t nmesh = (size_t)p->n[0] * p->n[1] * p->n[2];
+  char* iacc = p->deterministic ? sl.base + p->s_r2 : nullptr;
+  const size_t iacc_bytes = nmesh * (sizeof(T) == 4 ? 8 : 16);
   DKS_TK("geometry", launch_geometry_zero(bbox, sl.stride / sizeof(double), sl.geo(), sl.stride, ga, eb, batch,
-                                          sl.base + p->s_r3, sl.stride, p->bytes_W, st));
+                                          iacc ? iacc : sl.base + p->s_r3, sl.stride, iacc ? iacc_bytes : p->bytes_W,
+                                          st));
   DKS_TK("bin_count", launch_bin_count<T>(eb, batch, sl.geo(), sl.stride, sl.base, p->s_bins, p->md, w.bg,
                                           w.count_blocks, st));
   DKS_TK("bin_scan", launch_bin_scan(sl.geo(), sl.stride, sl.base, p->s_bins, w.bg, eb, batch, st));
@@ -491,7 +501,11 @@ dks_status deposit_stage(const dks_poisson_plan_s* p, int batch, const Slots& sl
                                               sorted_stride, inv_off, p->md, w.bg, w.count_blocks, soa, st));
   DKS_TK("deposit", launch_deposit_binned<T>(sl.geo(), sl.stride, sl.base, p->s_bins, sorted, sorted_stride,
                                              sl.base + p->s_r3, sl.stride / sizeof(T), p->md, w.bg, w.item_blocks,
-                                             batch, soa, st));
+                                             batch, soa, iacc, sl.stride / sizeof(unsigned long long), st));
+  if (iacc)
+    DKS_TK("fixed_to_weights", launch_fixed_to_weights<T>(iacc, sl.stride / sizeof(unsigned long long),
+                                                          sl.base + p->s_r3, sl.stride / sizeof(T), nmesh, batch,
+                                                          st));
   return DKS_OK;
 }
 
@@ -769,6 +783,12 @@ dks_status dks_poisson_set_scheme(dks_poisson_plan_t p, dks_green green, dks_ass
     p->prepared = false;           // the spectrum must be rebuilt
   }
   p->bg.scheme = assign == DKS_ASSIGN_NGP ? kSchemeNGP : assign == DKS_ASSIGN_TSC ? kSchemeTSC : kSchemeCIC;
+  return DKS_OK;
+}
+
+dks_status dks_poisson_set_deterministic(dks_poisson_plan_t p, int on) {
+  if (!p || (on != 0 && on != 1)) return DKS_EINVAL;
+  p->deterministic = on == 1;
   return DKS_OK;
 }
 

@@ -35,7 +35,8 @@ GREENS = {"integrated": DKS_GREEN_INTEGRATED, "point": DKS_GREEN_POINT}
 SCHEMES = {"cic": DKS_ASSIGN_CIC, "ngp": DKS_ASSIGN_NGP, "tsc": DKS_ASSIGN_TSC}
 
 EXPORTS = (
-    "dks_poisson_plan", "dks_poisson_set_origin", "dks_poisson_set_scheme", "dks_poisson_workspace_bytes",
+    "dks_poisson_plan", "dks_poisson_set_origin", "dks_poisson_set_scheme", "dks_poisson_set_deterministic",
+    "dks_poisson_workspace_bytes",
     "dks_poisson_batch_scratch_bytes", "dks_poisson_particle_scratch_bytes",
     "dks_poisson_set_particle_scratch", "dks_poisson_set_workspace", "dks_poisson_prepare",
     "dks_poisson_solve_rho", "dks_poisson_solve_particles", "dks_poisson_solve_particles_batched",
@@ -75,6 +76,7 @@ _SIGS = {
     "dks_poisson_plan": (_i, [_i, _i, _i, _d, _d, _d, _i, ctypes.POINTER(_PLAN)]),
     "dks_poisson_set_origin": (_i, [_PLAN, _d, _d, _d]),
     "dks_poisson_set_scheme": (_i, [_PLAN, _i, _i]),
+    "dks_poisson_set_deterministic": (_i, [_PLAN, _i]),
     "dks_poisson_workspace_bytes": (_i, [_PLAN, ctypes.POINTER(_sz)]),
     "dks_poisson_batch_scratch_bytes": (_i, [_PLAN, _i, _i64, ctypes.POINTER(_sz)]),
     "dks_poisson_particle_scratch_bytes": (_i, [_PLAN, _i64, ctypes.POINTER(_sz)]),
@@ -148,6 +150,10 @@ def dks_poisson_set_origin(plan, x0, y0, z0):
 
 def dks_poisson_set_scheme(plan, green, assign):
     _check(_lib.dks_poisson_set_scheme(plan, green, assign), "dks_poisson_set_scheme")
+
+
+def dks_poisson_set_deterministic(plan, on):
+    _check(_lib.dks_poisson_set_deterministic(plan, 1 if on else 0), "dks_poisson_set_deterministic")
 
 
 def dks_poisson_workspace_bytes(plan):
@@ -407,7 +413,7 @@ class PoissonPlan:
     """
 
     def __init__(self, n, h=None, dtype="f32", device="cuda", stream=None, prepare=True, scheme="cic",
-                 green="integrated"):
+                 green="integrated", deterministic=False):
         torch = _torch()
         self.n = tuple(int(v) for v in n)
         self.fitted = h is None
@@ -416,6 +422,8 @@ class PoissonPlan:
         self.device = torch.device(device)
         self.handle = dks_poisson_plan(*self.n, *self.h, self.code)
         dks_poisson_set_scheme(self.handle, GREENS[green], SCHEMES[scheme])
+        if deterministic:
+            dks_poisson_set_deterministic(self.handle, True)
         self.workspace_bytes = dks_poisson_workspace_bytes(self.handle)
         self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
         dks_poisson_set_workspace(self.handle, _ptr(self.workspace), self.workspace_bytes)
@@ -425,6 +433,9 @@ class PoissonPlan:
 
     def prepare(self, stream=None):
         dks_poisson_prepare(self.handle, _stream_handle(stream))
+
+    def set_deterministic(self, on):
+        dks_poisson_set_deterministic(self.handle, on)
 
     def set_origin(self, origin):
         dks_poisson_set_origin(self.handle, *[float(v) for v in origin])

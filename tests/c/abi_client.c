@@ -22,6 +22,7 @@ int main(void) {
   CHECK(dks_poisson_plan(64, 64, 64, 1e-4, 1e-4, 1e-4, DKS_F32, &p) == DKS_OK && p != NULL);
   CHECK(dks_poisson_workspace_bytes(p, &bytes) == DKS_OK && bytes > 0);
   CHECK(dks_poisson_set_scheme(p, DKS_GREEN_POINT, DKS_ASSIGN_TSC) == DKS_OK);
+  CHECK(dks_poisson_set_deterministic(p, 1) == DKS_OK && dks_poisson_set_deterministic(p, 2) == DKS_EINVAL);
   CHECK(dks_poisson_solve_rho(p, NULL, NULL, NULL, NULL) == DKS_EINVAL);
   CHECK(dks_poisson_host_staging_bytes(p, &bytes) == DKS_OK && bytes >= 10u * 64 * 64 * 64 * 4);
   CHECK(dks_poisson_destroy(p) == DKS_OK);

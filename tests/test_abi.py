@@ -123,6 +123,10 @@ def test_workspace_and_state_checks(dks):
         assert lib.dks_poisson_set_scheme(None, 0, 0) == dks.DKS_EINVAL
         assert lib.dks_poisson_set_scheme(plan, dks.DKS_GREEN_POINT, dks.DKS_ASSIGN_TSC) == dks.DKS_OK
         assert lib.dks_poisson_set_scheme(plan, dks.DKS_GREEN_INTEGRATED, dks.DKS_ASSIGN_CIC) == dks.DKS_OK
+        assert lib.dks_poisson_set_deterministic(None, 1) == dks.DKS_EINVAL
+        assert lib.dks_poisson_set_deterministic(plan, 2) == dks.DKS_EINVAL
+        assert lib.dks_poisson_set_deterministic(plan, 1) == dks.DKS_OK
+        assert lib.dks_poisson_set_deterministic(plan, 0) == dks.DKS_OK
         # attached but not prepared: solves are refused before touching the device
         assert lib.dks_poisson_solve_rho(plan, fake, fake, None, None) == dks.DKS_ESTATE
         assert lib.dks_poisson_solve_particles(plan, fake, fake, fake, 10, 1e-15, fake, fake, fake,
