@@ -11,10 +11,12 @@ synthetic, seeded, resident in HBM before the clock starts.
 
 Prints one JSON line: value = mesh points per second of the full step
 (256^3 x steps / time).  It also carries the per-kernel breakdown measured
-with HIP events on the library's stream, the roofline of the dominant
-kernel, the mesh-only solve rates in FP32 and FP64, the CPU oracle timed on
-a bounded sample of the same workload, and, when the serving loop is
-available, the mixed-size request stream.
+with HIP events on the library's stream (recorded around every kernel
+launch over as many steps again, right after the timed ones: events
+between the kernels would otherwise add to the timed steps), the roofline
+of the 256^3 convolution from those durations, the mesh-only solve rates
+in FP32 and FP64, the CPU oracle timed on a bounded sample of the same
+workload, and the mixed-size request stream.
 """
 
 import argparse
@@ -134,6 +136,20 @@ def measured_traffic(kernel, tile_order=False):
 def conv_bytes(n, s):
     return sum(algorithmic_bytes(n, 0, s, k) for k in
                ("fft_x_fwd", "fft_y_fwd", "fft_z_conv", "fft_y_inv", "fft_x_inv"))
+
+
+def timed_and_kernels(torch, dks, fn, steps, warmup):
+    """ms per call of fn over `steps` calls without the library's per-kernel
+    timing, then {kernel: (launches, total_ms, min_ms, max_ms)} over as many
+    calls with it (its events between the kernels are not in the first)."""
+    ms = time_loop(torch, fn, steps, warmup)
+    dks.dks_timing_enable(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    kk = dks.dks_timing_read()
+    dks.dks_timing_enable(False)
+    return ms, kk
 
 
 def time_loop(torch, fn, steps, warmup):
@@ -388,7 +404,8 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    dks.dks_timing_enable(True)
+    # the timed steps run without the library's per-kernel timing (its events
+    # between the kernels would be part of the measured time) ...
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -399,6 +416,11 @@ def main():
     torch.cuda.synchronize()
     ms_per_step = a.elapsed_time(b) / args.steps
     progress(f"full step {ms_per_step:.3f} ms")
+    # ... which the same number of steps then measures, kernel by kernel
+    dks.dks_timing_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
     kt = dks.dks_timing_read()
     dks.dks_timing_enable(False)
     mesh_pts = n[0] * n[1] * n[2]
@@ -486,10 +508,7 @@ def main():
     if tile_order:
         # the same step with the field returned in the caller's input order
         # (binning, then an unsort pass through the inverse permutation)
-        dks.dks_timing_enable(True)
-        io_ms = time_loop(torch, lambda: plan.solve_particles(*pos[0], q, out=bufs), args.steps, 2)
-        kk = dks.dks_timing_read()
-        dks.dks_timing_enable(False)
+        io_ms, kk = timed_and_kernels(torch, dks, lambda: plan.solve_particles(*pos[0], q, out=bufs), args.steps, 2)
         io_k = {k: kk[k][1] / kk[k][0] for k in kk}
         extra["input_order_step"] = {
             "ms_per_step": io_ms, "mesh_pts_per_s": mesh_pts / (io_ms * 1e-3), "kernel_ms": io_k,
@@ -497,10 +516,7 @@ def main():
         progress(f"input-order step {io_ms:.3f} ms")
     # the same step with the order-independent deposit (integer node totals)
     plan.set_deterministic(True)
-    dks.dks_timing_enable(True)
-    det_ms = time_loop(torch, step, args.steps, 2)
-    kk = dks.dks_timing_read()
-    dks.dks_timing_enable(False)
+    det_ms, kk = timed_and_kernels(torch, dks, step, args.steps, 2)
     plan.set_deterministic(False)
     extra["deterministic_step"] = {
         "ms_per_step": det_ms, "mesh_pts_per_s": mesh_pts / (det_ms * 1e-3),
@@ -512,10 +528,7 @@ def main():
         for green, scheme in (("integrated", "ngp"), ("integrated", "tsc"), ("point", "cic")):
             dks.dks_poisson_set_scheme(plan.handle, dks.GREENS[green], dks.SCHEMES[scheme])
             plan.prepare()
-            dks.dks_timing_enable(True)
-            ms = time_loop(torch, step, 10, 2)
-            kk = dks.dks_timing_read()
-            dks.dks_timing_enable(False)
+            ms, kk = timed_and_kernels(torch, dks, step, 10, 2)
             variants[f"{scheme}_{green}"] = {
                 "ms_per_step": ms, "mesh_pts_per_s": mesh_pts / (ms * 1e-3),
                 "kernel_ms": {k: kk[k][1] / kk[k][0] for k in ("bin_scatter", "deposit", "gather", "unsort")
@@ -530,11 +543,8 @@ def main():
             mp = dks.PoissonPlan(n, (1e-5, 1e-5, 1e-5), dt_name)
             rho = torch.rand((n[2], n[1], n[0]), dtype=tdt, device="cuda")
             phi = torch.empty_like(rho)
-            dks.dks_timing_enable(True)
-            ms = time_loop(torch, lambda: dks.dks_poisson_solve_rho(
+            ms, kk = timed_and_kernels(torch, dks, lambda: dks.dks_poisson_solve_rho(
                 mp.handle, dks._ptr(rho), dks._ptr(phi), None, dks._stream_handle(None)), 10, 2)
-            kk = dks.dks_timing_read()
-            dks.dks_timing_enable(False)
             s = 4 if dt_name == "f32" else 8
             cms = sum(kk[k][1] / kk[k][0] for k in conv_names if k in kk)
             extra[f"solve_{dt_name}"] = {"ms": ms, "mesh_pts_per_s": mesh_pts / (ms * 1e-3), "conv_ms": cms,
