@@ -69,7 +69,7 @@ template <typename T, int SCH> constexpr bool pair_phi() {
 // per CU: 1024 lanes each keep the CU's wave slots filled.
 template <typename T, int SCH> constexpr int gather_threads() { return pair_phi<T, SCH>() ? 1024 : kGatherThreads; }
 
-// FP32 CIC gather from node differences staged per tile (k_gather_binned_field).
+// FP32 gather from node differences staged per tile (k_gather_binned_field).
 constexpr bool kFieldGather = true;
 
 // Binned records each lane loads before using any.
@@ -1120,23 +1120,28 @@ __global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(co
 }
 
 // ---------------------------------------------------------------------------
-// FP32 CIC gather from the field at the tile's nodes.  A workgroup first
-// forms the central differences (phi(+1) - phi(-1) per axis) at the 17^3
-// nodes a 16^3-cell tile's particles touch, straight from phi (the reads of
-// neighbouring nodes hit L2), as one 16-byte LDS entry per node; a particle
-// then needs 8 entries and 36 multiply-adds (trilinear weights of its cell
-// times the node differences), against 32 node values and about twice the
-// arithmetic when the differences are formed per particle.  The entries take
-// 77 KB of LDS: two 1024-lane workgroups per CU.
+// FP32 gather from the field differences at the tile's nodes.  A workgroup
+// first forms the central differences (phi(+1) - phi(-1) per axis) at the
+// E^3 nodes a 16^3-node tile's particles touch (E = 16 + width - 1: 17 CIC,
+// 16 NGP, 18 TSC), straight from phi (the reads of neighbouring nodes hit
+// L2), as one 16-byte LDS entry per node; a CIC particle then needs 8
+// entries and 36 multiply-adds (trilinear weights of its cell times the
+// node differences), against 32 node values and about twice the arithmetic
+// when the differences are formed per particle.  The entries take 77 KB
+// (CIC) or 64 KB (NGP): two 1024-lane workgroups per CU.  (TSC would need
+// 91 KB, one workgroup per CU; it keeps k_gather_binned.)
 // ---------------------------------------------------------------------------
-constexpr int kFieldEdge = kTile + 1;
-template <bool SOA>
+template <int SCH> constexpr int field_edge() { return acc_edge<SCH>(); }
+template <int SCH> constexpr size_t field_lds_bytes() {
+  return (size_t)field_edge<SCH>() * field_edge<SCH>() * field_edge<SCH>() * sizeof(float4);
+}
+template <int SCH, bool SOA>
 __global__ __launch_bounds__(1024) void k_gather_binned_field(const Geometry* geo, size_t stride, char* slot_base,
                                                               size_t bins_off, char* sorted_base,
                                                               size_t sorted_stride, const float* __restrict__ phi_ext,
                                                               size_t phi_stride, MeshDims m, BinGeom bg,
                                                               SortedOut<float> so) {
-  constexpr int SCH = kSchemeCIC, E = kFieldEdge;
+  constexpr int E = field_edge<SCH>(), WD = Scheme<SCH>::width;
   __shared__ float4 ef[E * E * E];
   using P4 = Rec<float>;
   const int b = blockIdx.y;
@@ -1165,9 +1170,10 @@ __global__ __launch_bounds__(1024) void k_gather_binned_field(const Geometry* ge
       continue;
     }
     const int tx = tile % bg.tx, ty = (tile / bg.tx) % bg.ty, tz = tile / (bg.tx * bg.ty);
-    // entry e holds node (bx, by, bz) + (e % E, e / E % E, e / E^2), whose
-    // phi_ext index is node + 1 per axis; phi outside phi_ext reads as 0
-    const int bx = tx * kTile, by = ty * kTile, bz = tz * kTile;
+    // entry e holds node (bx, by, bz) + (e % E, e / E % E, e / E^2), the
+    // tile's first stencil node onwards; its phi_ext index is node + 1 per
+    // axis, and phi outside phi_ext reads as 0
+    const int bx = tx * kTile + Scheme<SCH>::lo, by = ty * kTile + Scheme<SCH>::lo, bz = tz * kTile + Scheme<SCH>::lo;
     for (int e = threadIdx.x; e < E * E * E; e += blockDim.x) {
       const int x = bx + e % E + 1, y = by + (e / E) % E + 1, z = bz + e / (E * E) + 1;
       auto at = [&](int xx, int yy, int zz) {
@@ -1194,14 +1200,21 @@ __global__ __launch_bounds__(1024) void k_gather_binned_field(const Geometry* ge
         const float4* o = ef + ((c.bz - bz) * E + (c.by - by)) * E + (c.bx - bx);
         float ax = 0.f, ay = 0.f, az = 0.f;
 #pragma unroll
-        for (int kz = 0; kz < 2; ++kz)
+        for (int kz = 0; kz < WD; ++kz)
 #pragma unroll
-          for (int ky = 0; ky < 2; ++ky) {
-            const float4 e0 = o[(kz * E + ky) * E], e1 = o[(kz * E + ky) * E + 1];
+          for (int ky = 0; ky < WD; ++ky) {
             const float w = c.wz[kz] * c.wy[ky];
-            ax += w * (c.wx[0] * e0.x + c.wx[1] * e1.x);
-            ay += w * (c.wx[0] * e0.y + c.wx[1] * e1.y);
-            az += w * (c.wx[0] * e0.z + c.wx[1] * e1.z);
+            float rx = 0.f, ry = 0.f, rz = 0.f;
+#pragma unroll
+            for (int kx = 0; kx < WD; ++kx) {
+              const float4 d = o[(kz * E + ky) * E + kx];
+              rx += c.wx[kx] * d.x;
+              ry += c.wx[kx] * d.y;
+              rz += c.wx[kx] * d.z;
+            }
+            ax += w * rx;
+            ay += w * ry;
+            az += w * rz;
           }
         if constexpr (SOA) {
           so.ex[i] = ax * cx;
@@ -1474,15 +1487,30 @@ hipError_t launch_gather_binned(const Geometry* geo, size_t stride, char* slot_b
   if (soa && batch != 1) return hipErrorInvalidValue;
   const SortedOut<T> so = sorted_out<T>(soa);
   if constexpr (sizeof(T) == 4) {
-    if (kFieldGather && bg.scheme == kSchemeCIC) {
-      if (soa)
-        hipLaunchKernelGGL((k_gather_binned_field<true>), dim3(nblk, batch), dim3(1024), 0, s, geo, stride,
-                           slot_base, bins_off, sorted_base, sorted_stride, (const float*)phi_ext, phi_stride, m, bg,
-                           so);
-      else
-        hipLaunchKernelGGL((k_gather_binned_field<false>), dim3(nblk, batch), dim3(1024), 0, s, geo, stride,
-                           slot_base, bins_off, sorted_base, sorted_stride, (const float*)phi_ext, phi_stride, m, bg,
-                           so);
+    // TSC's 91 KB of node differences leave one workgroup per CU, and that
+    // gather measured slower (1851 against 1675 us at 256^3 / 1e8) than
+    // forming the differences per particle
+    if (kFieldGather && bg.scheme != kSchemeTSC) {
+      const bool ngp = bg.scheme == kSchemeNGP;
+      if (soa) {
+        if (ngp)
+          hipLaunchKernelGGL((k_gather_binned_field<kSchemeNGP, true>), dim3(nblk, batch), dim3(1024), 0, s, geo,
+                             stride, slot_base, bins_off, sorted_base, sorted_stride, (const float*)phi_ext,
+                             phi_stride, m, bg, so);
+        else
+          hipLaunchKernelGGL((k_gather_binned_field<kSchemeCIC, true>), dim3(nblk, batch), dim3(1024), 0, s, geo,
+                             stride, slot_base, bins_off, sorted_base, sorted_stride, (const float*)phi_ext,
+                             phi_stride, m, bg, so);
+      } else {
+        if (ngp)
+          hipLaunchKernelGGL((k_gather_binned_field<kSchemeNGP, false>), dim3(nblk, batch), dim3(1024), 0, s, geo,
+                             stride, slot_base, bins_off, sorted_base, sorted_stride, (const float*)phi_ext,
+                             phi_stride, m, bg, so);
+        else
+          hipLaunchKernelGGL((k_gather_binned_field<kSchemeCIC, false>), dim3(nblk, batch), dim3(1024), 0, s, geo,
+                             stride, slot_base, bins_off, sorted_base, sorted_stride, (const float*)phi_ext,
+                             phi_stride, m, bg, so);
+      }
       return hipGetLastError();
     }
   }
