@@ -28,6 +28,30 @@ int main(void) {
   CHECK(dks_poisson_destroy(p) == DKS_OK);
   CHECK(dks_poisson_plan(5, 8, 8, 1.0, 1.0, 1.0, DKS_F64, &p) == DKS_EUNSUPPORTED);
 
+  /* runtime and compile-time plans of both dtypes, fitted and explicit: the
+   * host-side layout, validation and scratch queries */
+  {
+    const int shapes[4][3] = {{96, 96, 192}, {48, 36, 64}, {256, 256, 256}, {4, 6, 9}};
+    for (int s = 0; s < 4; ++s)
+      for (int d = 0; d < 2; ++d)
+        for (int f = 0; f < 2; ++f) {
+          const double h = f ? 0.0 : 1e-4;
+          p = NULL;
+          CHECK(dks_poisson_plan(shapes[s][0], shapes[s][1], shapes[s][2], h, h, h, d ? DKS_F64 : DKS_F32, &p) ==
+                    DKS_OK && p != NULL);
+          CHECK(dks_poisson_workspace_bytes(p, &bytes) == DKS_OK && bytes > 0);
+          CHECK(dks_poisson_particle_scratch_bytes(p, 1000000, &bytes) == DKS_OK && bytes >= 16000000u);
+          CHECK(dks_poisson_batch_scratch_bytes(p, 3, 1000, &bytes) == DKS_OK && bytes > 0);
+          CHECK(dks_poisson_set_origin(p, 0.0, 0.0, 0.0) == (f ? DKS_ESTATE : DKS_OK));
+          CHECK(dks_poisson_set_scheme(p, DKS_GREEN_INTEGRATED, DKS_ASSIGN_NGP) == DKS_OK);
+          CHECK(dks_poisson_set_deterministic(p, 1) == DKS_OK);
+          CHECK(dks_poisson_solve_particles(p, NULL, NULL, NULL, 10, 1.0, NULL, NULL, NULL, NULL, NULL, NULL) ==
+                DKS_EINVAL);
+          CHECK(dks_poisson_destroy(p) == DKS_OK);
+        }
+  }
+  for (int st = -8; st <= 0; ++st) CHECK(dks_status_string((dks_status)st) != NULL);
+
   dks_fft_plan_t f = NULL;
   CHECK(dks_fft_plan(512, 512, 256, 1, DKS_FFT_C2C, DKS_F32, &f) == DKS_OK);
   CHECK(dks_fft_workspace_bytes(f, &bytes) == DKS_OK && bytes > 0);
