@@ -58,20 +58,6 @@ template <int SCH> constexpr int apron_edge() { return acc_edge<SCH>() + 2; }
 constexpr int kDepositThreads = 1024;
 constexpr int kGatherThreads = 512;
 
-// FP32 CIC gather: phi staged as (phi(x), phi(x + 1)) pairs, so that the 32
-// node values of a particle come in 16 eight-byte LDS reads instead of 32
-// four-byte ones (the gather is bound by the bank conflicts of these reads).
-constexpr bool kPairPhi = true;
-template <typename T, int SCH> constexpr bool pair_phi() {
-  return kPairPhi && SCH == kSchemeCIC && sizeof(T) == 4;
-}
-// The paired tile takes 54 KB of LDS, which leaves room for two workgroups
-// per CU: 1024 lanes each keep the CU's wave slots filled.
-template <typename T, int SCH> constexpr int gather_threads() { return pair_phi<T, SCH>() ? 1024 : kGatherThreads; }
-
-// FP32 gather from node differences staged per tile (k_gather_binned_field).
-constexpr bool kFieldGather = true;
-
 // Binned records each lane loads before using any.
 constexpr int kUnrollDeposit = 4;
 constexpr int kUnrollGather = 2;
@@ -181,8 +167,11 @@ __device__ __forceinline__ Cell<T, SCH> locate(T x, T y, T z, const Geometry* g,
   const T sy = cc(y, Geo<T>::origin(g, 1), Geo<T>::inv_h(g, 1));
   const T sz = cc(z, Geo<T>::origin(g, 2), Geo<T>::inv_h(g, 2));
   int kx, ky, kz;
-  const bool in = axis_stencil<T, SCH>(sx, m.nx, kx, c.wx) & axis_stencil<T, SCH>(sy, m.ny, ky, c.wy) &
-                  axis_stencil<T, SCH>(sz, m.nz, kz, c.wz);
+  // every axis is evaluated (its node and weights are set either way)
+  const bool inx = axis_stencil<T, SCH>(sx, m.nx, kx, c.wx);
+  const bool iny = axis_stencil<T, SCH>(sy, m.ny, ky, c.wy);
+  const bool inz = axis_stencil<T, SCH>(sz, m.nz, kz, c.wz);
+  const bool in = inx && iny && inz;
   if (in) {
     // node indices are >= 0 here: unsigned division by the tile edge is a shift
     c.key = (int)((((unsigned)kz / kTile) * bg.ty + ((unsigned)ky / kTile)) * bg.tx + ((unsigned)kx / kTile));
@@ -916,21 +905,20 @@ __global__ __launch_bounds__(256) void k_fixed_to_weights(const unsigned long lo
 }
 
 // ---------------------------------------------------------------------------
-// gather with the central-difference field formed on the fly from staged phi.
+// gather with the central-difference field formed on the fly from staged phi
+// (FP64, and FP32 TSC; FP32 CIC and NGP use k_gather_binned_field below).
 // ---------------------------------------------------------------------------
 // SOA (tile-ordered step of a single solve): the records are the caller's
 // position arrays so.x/y/z, and the field of record i goes to
 // so.ex/ey/ez[i] (no unsort follows); otherwise the field overwrites the
 // record in the particle scratch.
 template <typename T, int SCH, bool SOA>
-__global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(const Geometry* geo, size_t stride, char* slot_base,
+__global__ __launch_bounds__(kGatherThreads) void k_gather_binned(const Geometry* geo, size_t stride, char* slot_base,
                                                        size_t bins_off, char* sorted_base, size_t sorted_stride,
                                                        const T* __restrict__ phi_ext, size_t phi_stride,
                                                        MeshDims m, BinGeom bg, SortedOut<T> so) {
   constexpr int A = apron_edge<SCH>(), NA = A * A * A, WD = Scheme<SCH>::width;
-  constexpr bool PAIR = pair_phi<T, SCH>();
-  // Staged phi: one value per node, or (node, node + 1 in x) pairs.
-  __shared__ typename std::conditional<PAIR, float2, T>::type ph[NA];
+  __shared__ T ph[NA];
   using P4 = Rec<T>;
   const int b = blockIdx.y;
   const Geometry gcopy = *geo_of(geo, stride, b);   // private copy: not reloaded after each store
@@ -966,14 +954,7 @@ __global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(co
       const int x = bx + ex, y = by + ey, z = bz + ez;
       const bool in_yz = y >= 0 && z >= 0 && y < ny2 && z < nz2;
       const T* row = phi + ((size_t)z * ny2 + y) * nx2;
-      const T v0 = (in_yz && x >= 0 && x < nx2) ? row[x] : (T)0;
-      if constexpr (PAIR) {
-        // the second value of the last pair of a row is never read
-        const T v1 = (in_yz && ex + 1 < A && x + 1 >= 0 && x + 1 < nx2) ? row[x + 1] : (T)0;
-        ph[e] = make_float2(v0, v1);
-      } else {
-        ph[e] = v0;
-      }
+      ph[e] = (in_yz && x >= 0 && x < nx2) ? row[x] : (T)0;
     }
     __syncthreads();
     // Unconditional loads (past the item's end they re-read its last record;
@@ -992,58 +973,7 @@ __global__ __launch_bounds__((gather_threads<T, SCH>())) void k_gather_binned(co
         // staged index of the first stencil node: (node - tile's first node) + 1 per axis
         const int o_idx = ((c.bz - bz + 1) * A + (c.by - by + 1)) * A + (c.bx - bx + 1);
         T ax = 0, ay = 0, az = 0;
-        if constexpr (PAIR) {
-          const float2* o = ph + o_idx;
-          const float* wx = c.wx;
-          const float* wy = c.wy;
-          const float* wz = c.wz;
-          // the same 32 values as the scalar CIC path below, two per read
-          float r[2][2][4], ym[2][2], yp[2][2], zm[2][2], zp[2][2];
-#pragma unroll
-          for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-            for (int ky = 0; ky < 2; ++ky) {
-              const float2 lo = o[(kz * A + ky) * A - 1], hi = o[(kz * A + ky) * A + 1];
-              r[kz][ky][0] = lo.x;
-              r[kz][ky][1] = lo.y;
-              r[kz][ky][2] = hi.x;
-              r[kz][ky][3] = hi.y;
-            }
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            const float2 qym = o[(a * A - 1) * A], qyp = o[(a * A + 2) * A];
-            const float2 qzm = o[(-A + a) * A], qzp = o[(2 * A + a) * A];
-            ym[a][0] = qym.x;
-            ym[a][1] = qym.y;
-            yp[a][0] = qyp.x;
-            yp[a][1] = qyp.y;
-            zm[a][0] = qzm.x;
-            zm[a][1] = qzm.y;
-            zp[a][0] = qzp.x;
-            zp[a][1] = qzp.y;
-          }
-#pragma unroll
-          for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-            for (int ky = 0; ky < 2; ++ky) {
-              const float d0 = r[kz][ky][2] - r[kz][ky][0], d1 = r[kz][ky][3] - r[kz][ky][1];
-              ax += wz[kz] * wy[ky] * (wx[0] * d0 + wx[1] * d1);
-            }
-#pragma unroll
-          for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-            for (int kx = 0; kx < 2; ++kx) {
-              const float d0 = r[kz][1][kx + 1] - ym[kz][kx], d1 = yp[kz][kx] - r[kz][0][kx + 1];
-              ay += wz[kz] * wx[kx] * (wy[0] * d0 + wy[1] * d1);
-            }
-#pragma unroll
-          for (int ky = 0; ky < 2; ++ky)
-#pragma unroll
-            for (int kx = 0; kx < 2; ++kx) {
-              const float d0 = r[1][ky][kx + 1] - zm[ky][kx], d1 = zp[ky][kx] - r[0][ky][kx + 1];
-              az += wy[ky] * wx[kx] * (wz[0] * d0 + wz[1] * d1);
-            }
-        } else if constexpr (SCH == kSchemeCIC) {
+        if constexpr (SCH == kSchemeCIC) {
           const T* o = ph + o_idx;
           const T* wx = c.wx;
           const T* wy = c.wy;
@@ -1490,7 +1420,7 @@ hipError_t launch_gather_binned(const Geometry* geo, size_t stride, char* slot_b
     // TSC's 91 KB of node differences leave one workgroup per CU, and that
     // gather measured slower (1851 against 1675 us at 256^3 / 1e8) than
     // forming the differences per particle
-    if (kFieldGather && bg.scheme != kSchemeTSC) {
+    if (bg.scheme != kSchemeTSC) {
       const bool ngp = bg.scheme == kSchemeNGP;
       if (soa) {
         if (ngp)
@@ -1517,7 +1447,7 @@ hipError_t launch_gather_binned(const Geometry* geo, size_t stride, char* slot_b
   with_scheme_soa(bg.scheme, soa != nullptr, [&](auto sc, auto sa) {
     constexpr int SCH = decltype(sc)::value;
     hipLaunchKernelGGL((k_gather_binned<T, SCH, decltype(sa)::value>), dim3(nblk, batch),
-                       dim3(gather_threads<T, SCH>()), 0, s, geo, stride, slot_base, bins_off, sorted_base,
+                       dim3(kGatherThreads), 0, s, geo, stride, slot_base, bins_off, sorted_base,
                        sorted_stride, (const T*)phi_ext, phi_stride, m, bg, so);
   });
   return hipGetLastError();

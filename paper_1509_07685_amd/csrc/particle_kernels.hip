@@ -233,9 +233,11 @@ __global__ __launch_bounds__(256) void k_gather(const T* __restrict__ E, const T
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     T wx[WD], wy[WD], wz[WD];
     int kx, ky, kz;
-    const bool in = axis_stencil<T, SCH>(cell_coord(px[i], ox, ix), nx, kx, wx) &
-                    axis_stencil<T, SCH>(cell_coord(py[i], oy, iy), ny, ky, wy) &
-                    axis_stencil<T, SCH>(cell_coord(pz[i], oz, iz), nz, kz, wz);
+    // every axis is evaluated (its node and weights are set either way)
+    const bool inx = axis_stencil<T, SCH>(cell_coord(px[i], ox, ix), nx, kx, wx);
+    const bool iny = axis_stencil<T, SCH>(cell_coord(py[i], oy, iy), ny, ky, wy);
+    const bool inz = axis_stencil<T, SCH>(cell_coord(pz[i], oz, iz), nz, kz, wz);
+    const bool in = inx && iny && inz;
     T ax = 0, ay = 0, az = 0;
     if (in) {
       const int bx = kx + Scheme<SCH>::lo, by = ky + Scheme<SCH>::lo, bz = kz + Scheme<SCH>::lo;
