@@ -32,6 +32,15 @@ template <typename T> struct RegCfg {
 // forward x pass stages nx reals per row of nx complex slots.
 constexpr int kTileReals = 16;
 
+// Twiddle tables in device memory, addressed as global rather than generic
+// memory: a generic (flat) load also counts in the LDS counter, so each
+// pass's wait for its LDS writes before the barrier would wait for the
+// twiddles' round trip to memory as well.
+template <typename C> using GlobalPtr = const __attribute__((address_space(1))) C*;
+template <typename C> __device__ __forceinline__ GlobalPtr<C> as_global(const void* p) {
+  return (GlobalPtr<C>)p;
+}
+
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
   return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
@@ -124,7 +133,7 @@ __device__ __forceinline__ void fft_pass(const FFTPlan* __restrict__ P, int p, I
   constexpr int TH = RegCfg<T>::THREADS;
   constexpr int K = (RegCfg<T>::EMAX + R - 1) / R;
   const int W = P->W, logW = P->logW, NR = P->N / R, nbf = W * NR, Ns = P->Ns[p];
-  const C* tw = (const C*)P->tw + P->tw_off[p];
+  const GlobalPtr<C> tw = as_global<C>(P->tw) + P->tw_off[p];
   const unsigned magic = P->magic[p];
   C v[K * R];
   C w[K * (R - 1)];   // twiddles, fetched with the inputs so their latency hides under the barrier
@@ -138,9 +147,9 @@ __device__ __forceinline__ void fft_pass(const FFTPlan* __restrict__ P, int p, I
       pre(std::integral_constant<int, R>{}, k, c, j);
       if (Ns > 1) {
         const int q = (int)__umulhi((unsigned)j, magic);
-        const C* wt = tw + (j - q * Ns) * (R - 1);
+        const GlobalPtr<C> wt = tw + (j - q * Ns) * (R - 1);
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[k * (R - 1) + r - 1] = wt[r - 1];
+        for (int r = 1; r < R; ++r) w[k * (R - 1) + r - 1] = C{wt[r - 1].x, wt[r - 1].y};
       }
     }
   }
@@ -264,14 +273,17 @@ template <class SP> __device__ __forceinline__ int plan_npass(const FFTPlan* P) 
 // fft_pass with every plan value a constant.
 // ZU: the transform's upper half inputs are zero (a zero-padded forward
 // transform): inputs r >= R/2 of the first pass are not read.
-template <typename T, bool INV, class SP, int p, bool SYNC, bool ZU, class In, class Out, class Pre>
-__device__ __forceinline__ void fft_pass_s(const typename Cplx<T>::type* __restrict__ twb, In in, Out out, Pre pre) {
+// in(c, idx, slot): slot numbers the thread's inputs of the pass, k R + r
+// (k (R / 2) + r with ZU), for callers that hold them in registers.
+// TwP: pointer to the plan's twiddle table (global memory or an LDS copy).
+template <typename T, bool INV, class SP, int p, bool SYNC, bool ZU, class TwP, class In, class Out, class Pre>
+__device__ __forceinline__ void fft_pass_s(TwP twb, In in, Out out, Pre pre) {
   using C = typename Cplx<T>::type;
   constexpr int R = SP::R(p), Ns = SP::Ns(p), NR = SP::N / R, W = SP::W, logW = SP::logW;
   constexpr int TH = RegCfg<T>::THREADS, nbf = W * NR;
   constexpr int K = cmin((RegCfg<T>::EMAX + R - 1) / R, (nbf + TH - 1) / TH);
   constexpr bool guard = K * TH > nbf;
-  const C* tw = twb + SP::tw_off(p);
+  const TwP tw = twb + SP::tw_off(p);
   C v[K * R];
   C w[K * (R - 1)];
 #pragma unroll
@@ -280,12 +292,13 @@ __device__ __forceinline__ void fft_pass_s(const typename Cplx<T>::type* __restr
     if (!guard || b < nbf) {
       const int c = b & (W - 1), j = b >> logW;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[k * R + r] = (ZU && 2 * r >= R) ? C{0, 0} : in(c, j + r * NR, k * (R / 2) + r);
+      for (int r = 0; r < R; ++r)
+        v[k * R + r] = (ZU && 2 * r >= R) ? C{0, 0} : in(c, j + r * NR, ZU ? k * (R / 2) + r : k * R + r);
       pre(std::integral_constant<int, R>{}, k, c, j);
       if constexpr (Ns > 1) {
-        const C* wt = tw + (j & (Ns - 1)) * (R - 1);
+        const TwP wt = tw + (j & (Ns - 1)) * (R - 1);
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[k * (R - 1) + r - 1] = wt[r - 1];
+        for (int r = 1; r < R; ++r) w[k * (R - 1) + r - 1] = C{wt[r - 1].x, wt[r - 1].y};
       }
     }
   }
@@ -316,8 +329,8 @@ __device__ __forceinline__ void fft_pass_s(const typename Cplx<T>::type* __restr
 
 template <typename T, bool INV, bool FIRST_LDS, class SP, int p, int p0, bool ZU>
 struct RunStatic {
-  template <class FirstIn, class LastOut, class FirstPre, class LastPre>
-  static __device__ __forceinline__ void go(typename Cplx<T>::type* lds, const typename Cplx<T>::type* tw,
+  template <class TwP, class FirstIn, class LastOut, class FirstPre, class LastPre>
+  static __device__ __forceinline__ void go(typename Cplx<T>::type* lds, TwP tw,
                                             FirstIn& first_in, LastOut& last_out, FirstPre& first_pre,
                                             LastPre& last_pre) {
     using C = typename Cplx<T>::type;
@@ -356,7 +369,7 @@ __device__ __forceinline__ void run_any(typename Cplx<T>::type* lds, const FFTPl
                                         FirstIn first_in, LastOut last_out, LastPre last_pre = LastPre{}) {
   if constexpr (SP::is_static) {
     NoPre none;
-    RunStatic<T, INV, FIRST_LDS, SP, P0, P0, ZU>::go(lds, (const typename Cplx<T>::type*)P->tw, first_in, last_out,
+    RunStatic<T, INV, FIRST_LDS, SP, P0, P0, ZU>::go(lds, as_global<typename Cplx<T>::type>(P->tw), first_in, last_out,
                                                      none, last_pre);
   } else {
     run_fft<T, INV, FIRST_LDS>(lds, P, P0, first_in, last_out, last_pre);

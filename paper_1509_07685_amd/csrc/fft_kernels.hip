@@ -203,7 +203,10 @@ __device__ __forceinline__ void keep_outputs(int base, int Ns, int N, const C* v
 
 // ---------------------------------------------------------------------------
 // y forward: pencils along y of the x-transformed rows.  Input A[z][y][kx]
-// (y < ny), output B (ky < 2 ny, tile-major).  Grid: (column tiles, nz, batch).
+// (y < ny), output B (ky < 2 ny, tile-major).  Grid: (column tiles, nz, batch):
+// consecutive workgroups read adjacent segments of one A row (the loads are
+// what a workgroup waits on; ordering by z instead, so that the stores to B
+// are adjacent, measured slower).
 // ---------------------------------------------------------------------------
 template <typename T, class SP>
 __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_fwd(const typename Cplx<T>::type* __restrict__ A,
@@ -493,7 +496,10 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS, PipeOcc<T>::waves_per_simd) voi
 
 // ---------------------------------------------------------------------------
 // y inverse: C (tile-major) -> D[z'][y + 1][kx] for y in [-1, ny].
-// Grid: (column tiles, nz + 2, batch).
+// Grid: (nz + 2, column tiles, batch): consecutive workgroups read adjacent
+// segments of each C row (one column block holds the rows of every z'), which
+// measured faster than ordering by column tile, where the stores to D are the
+// adjacent ones.
 // ---------------------------------------------------------------------------
 template <typename T, class SP>
 __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_inv(const typename Cplx<T>::type* __restrict__ Cin,
@@ -504,8 +510,8 @@ __global__ __launch_bounds__(RegCfg<T>::THREADS) void k_fft_y_inv(const typename
   extern __shared__ __align__(16) unsigned char smem[];
   C* lds = reinterpret_cast<C*>(smem);
   constexpr int WB = kBlockCols<T>;
-  const int c0 = (tile0 + (int)blockIdx.x) * plan_W<SP>(P);
-  const int zp = blockIdx.y;
+  const int c0 = (tile0 + (int)blockIdx.y) * plan_W<SP>(P);
+  const int zp = blockIdx.x;
   using Off = OffT<SP>;
   const C* src = Cin + blockIdx.z * stride + ((size_t)(c0 / WB) * (m.nz + 2) + zp) * WB + c0 % WB;
   C* dst = D + blockIdx.z * stride + (size_t)zp * (m.ny + 2) * m.cs + c0;
@@ -803,7 +809,7 @@ hipError_t launch_fft_y_inv(const void* Cin, void* D, size_t stride, const MeshD
                             int col0, int col1, hipStream_t s) {
   using C = typename Cplx<T>::type;
   const int W = P.host.W, t0 = col0 / W;
-  dim3 grid((col1 + W - 1) / W - t0, m.nz + 2, batch);
+  dim3 grid(m.nz + 2, (col1 + W - 1) / W - t0, batch);
   with_plan<T, 0>(P.host, [&](auto sp) {
     hipLaunchKernelGGL((k_fft_y_inv<T, decltype(sp)>), grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s,
                        (const C*)Cin, (C*)D, stride, m, P.dev, t0);
