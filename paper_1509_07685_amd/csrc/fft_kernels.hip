@@ -723,19 +723,202 @@ template <typename T, int PAD, class F> static void with_plan(const FFTPlan& h, 
   else f(DynPlan{});
 }
 
-// Workgroups of the persistent z pass: four per CU (two are resident at a
-// time, the LDS tile bounds it; the second round evens out the tiles left
-// at the end of the first).  Measured at 256^3: two per CU 203 us, four 196 us
-// (FP32); 303 and 300 us (FP64).
-static int z_pipe_blocks() {
-  static const int nb = [] {
+static int device_cus() {
+  static const int n = [] {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
                                                 hipSuccess || cus <= 0)
       cus = 256;
-    return 4 * cus;
+    return cus;
   }();
-  return nb;
+  return n;
+}
+
+// Workgroups of the persistent z pass: four per CU (two are resident at a
+// time, the LDS tile bounds it; the second round evens out the tiles left
+// at the end of the first).  Measured at 256^3: two per CU 203 us, four 196 us
+// (FP32); 303 and 300 us (FP64).
+static int z_pipe_blocks() { return 4 * device_cus(); }
+
+// The value held by lane (lane xor H) of the wavefront, H = 1, 2, ..., 32.
+// Within a 16-lane row by DPP, one or two VALU operations: quad permutations
+// (H = 1, 2) and row rotations (H = 8; H = 4 as two rotations, lane + 4
+// written to banks 0 and 2 and lane - 4 to banks 1 and 3).  Across rows by
+// the LDS crossbar (ds_bpermute), which costs no VALU work: gfx950's half-row
+// and half-wavefront swaps do the same exchange but cost two copies, the swap
+// and a select in VALU operations.
+template <int H> __device__ __forceinline__ unsigned lane_xor_dpp_u32(unsigned v) {
+  static_assert(H == 1 || H == 2 || H == 4 || H == 8, "xor distance within a 16-lane row");
+  if constexpr (H == 1) {
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);            // quad_perm [1, 0, 3, 2]
+  } else if constexpr (H == 2) {
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);            // quad_perm [2, 3, 0, 1]
+  } else if constexpr (H == 4) {
+    const unsigned t = __builtin_amdgcn_update_dpp(v, v, 0x12C, 0xF, 0x5, false);   // row_ror 12
+    return __builtin_amdgcn_update_dpp(t, v, 0x124, 0xF, 0xA, false);               // row_ror 4
+  } else {
+    return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);           // row_ror 8
+  }
+}
+template <int H> __device__ __forceinline__ unsigned lane_xor_u32(unsigned v, int lane) {
+  if constexpr (H <= 8) return lane_xor_dpp_u32<H>(v);
+  else return (unsigned)__builtin_amdgcn_ds_bpermute((lane ^ H) << 2, (int)v);
+}
+template <int H> __device__ __forceinline__ float lane_xor(float v, int lane) {
+  return __uint_as_float(lane_xor_u32<H>(__float_as_uint(v), lane));
+}
+template <int H> __device__ __forceinline__ double lane_xor(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = lane_xor_u32<H>((unsigned)b, lane), hi = lane_xor_u32<H>((unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// ---------------------------------------------------------------------------
+// x inverse with one wavefront per row, for nx = 64 P (P = 1, 2, 4, 8): no
+// LDS tile and no barriers; the radix stages across lanes exchange values
+// with wavefront shuffles.  Lane l holds Z'[k] (as in k_fft_x_inv) for
+// k = l + 64 i, i < P, so its loads are row-contiguous.  With m = m1 + P m2
+// the inverse transform z[m] = sum_k Z'[k] e^{+2 pi i k m / nx} splits into a
+// length-P transform over i in registers, the twiddle e^{+2 pi i l m1 / nx},
+// and for each m1 a length-64 transform over the lanes: six radix-2
+// decimation-in-frequency stages (spans h = 32, 16, ..., 1) in which lane l
+// takes its partner's value from lane l xor h (lane_xor).  That leaves
+// z[m1 + P rev(l)] in lane l (rev the 6-bit reversal); one permutation across
+// the lanes puts z[m1 + P l] in lane l, so each lane stores P adjacent output
+// pairs.  Every twiddle is an entry of the post table e^{-2 pi i k / (2 nx)},
+// k <= nx.
+// ---------------------------------------------------------------------------
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_fft_x_inv_wave(const typename Cplx<T>::type* __restrict__ D,
+                                                        size_t in_stride, T* __restrict__ phi_ext,
+                                                        size_t out_stride, ElemBatch phi_user, MeshDims m,
+                                                        const typename Cplx<T>::type* __restrict__ post, int nrows) {
+  using C = typename Cplx<T>::type;
+  constexpr int N = 64 * P;
+  const int lane = (int)threadIdx.x & 63;
+  const int rl = (int)(__builtin_bitreverse32((unsigned)lane) >> 26);
+  const C* src = D + blockIdx.y * in_stride;
+  T* dst = phi_ext + blockIdx.y * out_stride;
+  T* user = reinterpret_cast<T*>(phi_user.at(blockIdx.y).phi);
+  const bool user_pairs = (reinterpret_cast<uintptr_t>(user) & (sizeof(C) - 1)) == 0;
+  // the wavefront's row of z, for lane-contiguous stores (no barrier: only
+  // this wavefront touches it, and its LDS operations complete in order)
+  __shared__ C zrow[4][N];
+  C* zb = zrow[threadIdx.x >> 6];
+  // e^{+2 pi i t / N}, 0 <= t < N
+  auto wpow = [&](int t) {
+    const C w = 2 * t <= N ? post[2 * t] : C{-post[2 * t - N].x, -post[2 * t - N].y};
+    return C{w.x, -w.y};
+  };
+  C wz[P], w2[P], ws[6];
+  T sg[6];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const C w = post[lane + 64 * i];
+    wz[i] = C{w.x, -w.y};
+    w2[i] = wpow(lane * i);
+  }
+#pragma unroll
+  for (int st = 0; st < 6; ++st) {
+    const int h = 1 << st;
+    const bool upper = (lane & h) != 0;
+    ws[st] = upper ? wpow((lane & (h - 1)) * (N / (2 * h))) : C{(T)1, (T)0};
+    sg[st] = upper ? (T)-1 : (T)1;
+  }
+  // Rows r = wid, wid + nw, ... of this wavefront, two register sets: the
+  // next row's loads are issued before this row is transformed (a scheduling
+  // barrier keeps them there), and no branch separates them from their use
+  // (a row past the end is loaded as row 0 and transformed but not stored).
+  // wavefront index, uniform (scalar registers, so the row bases are too)
+  const int wid = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  const int nw = (int)((gridDim.x * blockDim.x) >> 6);
+  // byte offsets of the lane's elements in a row (the row base is uniform)
+  const unsigned ok0 = (unsigned)(lane * (int)sizeof(C)), oc0 = (unsigned)((N - lane) * (int)sizeof(C));
+  auto load = [&](C* xk, C* xc, int r) {
+    const char* row = reinterpret_cast<const char*>(src + (size_t)(r < nrows ? r : 0) * m.cs);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      xk[i] = *reinterpret_cast<const C*>(row + (ok0 + (unsigned)(64 * i * (int)sizeof(C))));
+      xc[i] = *reinterpret_cast<const C*>(row + (oc0 - (unsigned)(64 * i * (int)sizeof(C))));
+    }
+  };
+  auto transform = [&](const C* xk, const C* xc, int r) {
+    C v[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const C c{xc[i].x, -xc[i].y};
+      const C sm = cadd(xk[i], c), d = csub(xk[i], c);
+      const C wd = cmul(wz[i], d);
+      v[i] = C{sm.x - wd.y, sm.y + wd.x};
+    }
+    if constexpr (P > 1) dft<P, true>(v);
+#pragma unroll
+    for (int i = 1; i < P; ++i) v[i] = cmul(v[i], w2[i]);
+    // stage of span h: the lower lane of a pair keeps a + b, the upper one
+    // (a - b) w^j, j = l mod h, w = e^{+2 pi i / (2 h)}
+    auto stage = [&](auto STC) {
+      constexpr int st = decltype(STC)::value, h = 1 << st;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const T px = lane_xor<h>(v[i].x, lane), py = lane_xor<h>(v[i].y, lane);
+        const C t{sg[st] * v[i].x + px, sg[st] * v[i].y + py};
+        v[i] = st == 0 ? t : cmul(t, ws[st]);    // span 1: every twiddle is 1
+      }
+    };
+    stage(std::integral_constant<int, 5>{});
+    stage(std::integral_constant<int, 4>{});
+    stage(std::integral_constant<int, 3>{});
+    stage(std::integral_constant<int, 2>{});
+    stage(std::integral_constant<int, 1>{});
+    stage(std::integral_constant<int, 0>{});
+    // lane l holds z[i + P rev(l)]
+#pragma unroll
+    for (int i = 0; i < P; ++i) zb[i + P * rl] = v[i];
+    if (r >= nrows) return;
+    // pair q is (x = 2q - 1, x = 2q) = (z[q - 1].y, z[q].x), q = 0 .. N/2
+    C* orow = reinterpret_cast<C*>(dst + (size_t)r * (N + 2));
+#pragma unroll
+    for (int j = 0; j <= (N / 2) / 64; ++j) {
+      const int q = lane + 64 * j;
+      if (j < (N / 2) / 64 || q <= N / 2) orow[q] = C{zb[(q + N - 1) & (N - 1)].y, zb[q].x};
+    }
+    if (user) {
+      const int zq = r / (m.ny + 2), yq = r - zq * (m.ny + 2);
+      if (zq >= 1 && zq <= m.nz && yq >= 1 && yq <= m.ny) {
+        // physical x = 0 .. N - 1: pair (2q, 2q + 1) is z[q], q < N/2.  Global
+        // (not generic) stores: a pending flat store would make the compiler
+        // wait for every outstanding load, the prefetch included.
+        using GT = __attribute__((address_space(1))) T;
+        using GC = __attribute__((address_space(1))) C;
+        GT* urow = (GT*)user + ((size_t)(zq - 1) * m.ny + (yq - 1)) * N;
+#pragma unroll
+        for (int j = 0; j < (N / 2 + 63) / 64; ++j) {
+          const int q = lane + 64 * j;
+          if (q < N / 2) {
+            const C zv = zb[q];
+            if (user_pairs) {
+              GC* up = reinterpret_cast<GC*>(urow) + q;
+              up->x = zv.x;
+              up->y = zv.y;
+            } else {
+              urow[2 * q] = zv.x;
+              urow[2 * q + 1] = zv.y;
+            }
+          }
+        }
+      }
+    }
+  };
+  C ak[P], ac[P], bk[P], bc[P];
+  load(ak, ac, wid);
+  for (int r = wid; r < nrows; r += 2 * nw) {      // uniform over the wavefront
+    load(bk, bc, r + nw);
+    __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of the transform
+    transform(ak, ac, r);
+    load(ak, ac, r + 2 * nw);
+    __builtin_amdgcn_sched_barrier(0);
+    transform(bk, bc, r + nw);
+  }
 }
 
 template <typename T>
@@ -824,6 +1007,19 @@ hipError_t launch_fft_x_inv(const void* D, size_t in_stride, void* phi_ext, size
   using C = typename Cplx<T>::type;
   const int nrows = (m.ny + 2) * (m.nz + 2);
   if ((size_t)P.host.W * P.host.N > (size_t)kTileReals * RegCfg<T>::THREADS) return hipErrorInvalidValue;
+  // FP32 rows of 256: one wavefront per row (four per workgroup, a few rows
+  // each).  Measured at 256^3: 55 against 66 us for the LDS-tile kernel, 69
+  // against 79 us when phi is also written; the LDS-tile kernel stays as
+  // fast or faster in FP64 (111 against 110 us at 256^3, more registers per
+  // lane) and for shorter rows (128^3, 64^3).
+  if constexpr (sizeof(T) == 4) {
+    if (m.nx == 256) {
+      dim3 gw((unsigned)std::min((nrows + 3) / 4, 5 * device_cus()), batch);   // about the resident wavefronts
+      hipLaunchKernelGGL((k_fft_x_inv_wave<T, 4>), gw, dim3(256), 0, s, (const C*)D, in_stride, (T*)phi_ext,
+                         out_stride, phi_user, m, (const C*)post, nrows);
+      return hipGetLastError();
+    }
+  }
   dim3 grid((nrows + P.host.W - 1) / P.host.W, batch);
   with_plan<T, 1>(P.host, [&](auto sp) {
     hipLaunchKernelGGL((k_fft_x_inv<T, decltype(sp)>), grid, dim3(RegCfg<T>::THREADS), lds_bytes<T>(P.host), s,
