@@ -773,6 +773,33 @@ template <int H> __device__ __forceinline__ double lane_xor(double v, int lane) 
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Six radix-2 decimation-in-frequency stages (spans h = 32, 16, ..., 1) of a
+// length-64 transform over the lanes of a wavefront, applied to each of the
+// P values per lane: of a lane pair (l, l xor h) the lower lane keeps a + b
+// and the upper one (a - b) w^j, j = l mod h.  ws[st] is that lane's w^j for
+// span 2^st (1 on lower lanes), sg[st] is -1 on upper lanes and +1 on lower
+// ones.  Lane l ends with the output at index rev(l), rev the 6-bit reversal.
+template <typename T, int P>
+__device__ __forceinline__ void wave_dif64(typename Cplx<T>::type* v, const typename Cplx<T>::type* ws,
+                                           const T* sg, int lane) {
+  using C = typename Cplx<T>::type;
+  auto stage = [&](auto STC) {
+    constexpr int st = decltype(STC)::value, h = 1 << st;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const T px = lane_xor<h>(v[i].x, lane), py = lane_xor<h>(v[i].y, lane);
+      const C t{sg[st] * v[i].x + px, sg[st] * v[i].y + py};
+      v[i] = st == 0 ? t : cmul(t, ws[st]);    // span 1: every twiddle is 1
+    }
+  };
+  stage(std::integral_constant<int, 5>{});
+  stage(std::integral_constant<int, 4>{});
+  stage(std::integral_constant<int, 3>{});
+  stage(std::integral_constant<int, 2>{});
+  stage(std::integral_constant<int, 1>{});
+  stage(std::integral_constant<int, 0>{});
+}
+
 // ---------------------------------------------------------------------------
 // x inverse with one wavefront per row, for nx = 64 P (P = 1, 2, 4, 8): no
 // LDS tile and no barriers; the radix stages across lanes exchange values
@@ -854,23 +881,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv_wave(const typename Cplx<T>::
     if constexpr (P > 1) dft<P, true>(v);
 #pragma unroll
     for (int i = 1; i < P; ++i) v[i] = cmul(v[i], w2[i]);
-    // stage of span h: the lower lane of a pair keeps a + b, the upper one
-    // (a - b) w^j, j = l mod h, w = e^{+2 pi i / (2 h)}
-    auto stage = [&](auto STC) {
-      constexpr int st = decltype(STC)::value, h = 1 << st;
-#pragma unroll
-      for (int i = 0; i < P; ++i) {
-        const T px = lane_xor<h>(v[i].x, lane), py = lane_xor<h>(v[i].y, lane);
-        const C t{sg[st] * v[i].x + px, sg[st] * v[i].y + py};
-        v[i] = st == 0 ? t : cmul(t, ws[st]);    // span 1: every twiddle is 1
-      }
-    };
-    stage(std::integral_constant<int, 5>{});
-    stage(std::integral_constant<int, 4>{});
-    stage(std::integral_constant<int, 3>{});
-    stage(std::integral_constant<int, 2>{});
-    stage(std::integral_constant<int, 1>{});
-    stage(std::integral_constant<int, 0>{});
+    wave_dif64<T, P>(v, ws, sg, lane);    // w = e^{+2 pi i / (2 h)}
     // lane l holds z[i + P rev(l)]
 #pragma unroll
     for (int i = 0; i < P; ++i) zb[i + P * rl] = v[i];
