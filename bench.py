@@ -86,12 +86,13 @@ def method_bytes(n, num_particles, s, kernel, tile_order=False):
     }[kernel]
 
 
-# Library timing names -> kernel symbols as rocprofv3 reports them.
+# Library timing names -> kernel symbols as rocprofv3 reports them (the
+# 256^3 FP32 workload's instances).
 KERNEL_SYMBOL = {
     "bbox": "k_bbox", "geometry": "k_geometry_zero", "bin_count": "k_bin_count",
     "bin_scan": "k_bin_scan", "bin_scatter": "k_bin_scatter_pipe", "deposit": "k_deposit_binned",
     "fft_x_fwd": "k_fft_x_fwd", "fft_y_fwd": "k_fft_y_fwd", "fft_z_conv": "k_fft_z_conv_pipe",
-    "fft_y_inv": "k_fft_y_inv", "fft_x_inv": "k_fft_x_inv", "gradient": "k_gradient",
+    "fft_y_inv": "k_fft_y_inv", "fft_x_inv": "k_fft_x_inv_wave", "gradient": "k_gradient",
     "gather": "k_gather_binned_field", "unsort": "k_unsort",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_halo_gaussian_256cubed_1e8_f32.json")
