@@ -383,13 +383,14 @@ def test_repeated_solves_reuse_state():
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-@pytest.mark.parametrize("scheme,green", [("cic", "integrated"), ("tsc", "integrated"), ("ngp", "point")])
-def test_batched_solve_matches_single_solves(dt, scheme, green):
+@pytest.mark.parametrize("scheme,green,n", [("cic", "integrated", (32, 24, 36)), ("tsc", "integrated", (32, 24, 36)),
+                                            ("ngp", "point", (32, 24, 36)),
+                                            ("cic", "integrated", (256, 12, 8))])   # rows of 256: x inverse per wavefront
+def test_batched_solve_matches_single_solves(dt, scheme, green, n):
     """One batched launch over elements with different particle counts and
     charges equals the elements solved one by one (and the oracle), for each
     assignment scheme and kernel."""
     d = dks()
-    n = (32, 24, 36)
     plan = d.PoissonPlan(n, None, dt, scheme=scheme, green=green)
     counts = [5000, 0, 12345, 1, 30000]
     charges = [1e-13, 2e-13, 5e-14, 1e-12, 3e-14]
