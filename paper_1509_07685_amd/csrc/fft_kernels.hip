@@ -852,16 +852,17 @@ __global__ __launch_bounds__(256) void k_fft_x_inv_wave(const typename Cplx<T>::
     ws[st] = upper ? wpow((lane & (h - 1)) * (N / (2 * h))) : C{(T)1, (T)0};
     sg[st] = upper ? (T)-1 : (T)1;
   }
-  // Rows r = wid, wid + nw, ... of this wavefront, two register sets: the
-  // next row's loads are issued before this row is transformed (a scheduling
-  // barrier keeps them there), and no branch separates them from their use
-  // (a row past the end is loaded as row 0 and transformed but not stored).
-  // wavefront index, uniform (scalar registers, so the row bases are too)
+  // Rows r = wid, wid + nw, ... of this wavefront.  A row's inputs are used
+  // up by the Z' formation at the start of its transform; the next row's
+  // loads are issued into the same registers right after (a scheduling
+  // barrier keeps them there), so they are in flight for the rest of the
+  // transform.  A row past the end is loaded as row 0 and never used.
   const int wid = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
   const int nw = (int)((gridDim.x * blockDim.x) >> 6);
   // byte offsets of the lane's elements in a row (the row base is uniform)
   const unsigned ok0 = (unsigned)(lane * (int)sizeof(C)), oc0 = (unsigned)((N - lane) * (int)sizeof(C));
-  auto load = [&](C* xk, C* xc, int r) {
+  C xk[P], xc[P];
+  auto load = [&](int r) {
     const char* row = reinterpret_cast<const char*>(src + (size_t)(r < nrows ? r : 0) * m.cs);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
@@ -869,7 +870,8 @@ __global__ __launch_bounds__(256) void k_fft_x_inv_wave(const typename Cplx<T>::
       xc[i] = *reinterpret_cast<const C*>(row + (oc0 - (unsigned)(64 * i * (int)sizeof(C))));
     }
   };
-  auto transform = [&](const C* xk, const C* xc, int r) {
+  load(wid);
+  for (int r = wid; r < nrows; r += nw) {      // uniform over the wavefront
     C v[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
@@ -878,6 +880,8 @@ __global__ __launch_bounds__(256) void k_fft_x_inv_wave(const typename Cplx<T>::
       const C wd = cmul(wz[i], d);
       v[i] = C{sm.x - wd.y, sm.y + wd.x};
     }
+    load(r + nw);
+    __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of the transform
     if constexpr (P > 1) dft<P, true>(v);
 #pragma unroll
     for (int i = 1; i < P; ++i) v[i] = cmul(v[i], w2[i]);
@@ -885,7 +889,6 @@ __global__ __launch_bounds__(256) void k_fft_x_inv_wave(const typename Cplx<T>::
     // lane l holds z[i + P rev(l)]
 #pragma unroll
     for (int i = 0; i < P; ++i) zb[i + P * rl] = v[i];
-    if (r >= nrows) return;
     // pair q is (x = 2q - 1, x = 2q) = (z[q - 1].y, z[q].x), q = 0 .. N/2
     C* orow = reinterpret_cast<C*>(dst + (size_t)r * (N + 2));
 #pragma unroll
@@ -919,16 +922,6 @@ __global__ __launch_bounds__(256) void k_fft_x_inv_wave(const typename Cplx<T>::
         }
       }
     }
-  };
-  C ak[P], ac[P], bk[P], bc[P];
-  load(ak, ac, wid);
-  for (int r = wid; r < nrows; r += 2 * nw) {      // uniform over the wavefront
-    load(bk, bc, r + nw);
-    __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of the transform
-    transform(ak, ac, r);
-    load(ak, ac, r + 2 * nw);
-    __builtin_amdgcn_sched_barrier(0);
-    transform(bk, bc, r + nw);
   }
 }
 
