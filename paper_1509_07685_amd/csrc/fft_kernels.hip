@@ -810,10 +810,10 @@ __device__ __forceinline__ void wave_dif64(typename Cplx<T>::type* v, const type
 // and for each m1 a length-64 transform over the lanes: six radix-2
 // decimation-in-frequency stages (spans h = 32, 16, ..., 1) in which lane l
 // takes its partner's value from lane l xor h (lane_xor).  That leaves
-// z[m1 + P rev(l)] in lane l (rev the 6-bit reversal); one permutation across
-// the lanes puts z[m1 + P l] in lane l, so each lane stores P adjacent output
-// pairs.  Every twiddle is an entry of the post table e^{-2 pi i k / (2 nx)},
-// k <= nx.
+// z[m1 + P rev(l)] in lane l (rev the 6-bit reversal); the lanes write z to
+// the wavefront's own LDS row at those places and read it back so that lane
+// l forms the outputs l, l + 64, ...: both stores are lane-contiguous.  Every
+// twiddle is an entry of the post table e^{-2 pi i k / (2 nx)}, k <= nx.
 // ---------------------------------------------------------------------------
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_fft_x_inv_wave(const typename Cplx<T>::type* __restrict__ D,
